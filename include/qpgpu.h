@@ -1,0 +1,171 @@
+/*
+ * qpgpu -- C ABI of the MI355X (gfx950) implementation of the preconditioned
+ * inexact interior point method of Karim & Solomonik, "Efficient
+ * Preconditioners for Interior Point Methods via a new Schur Complement-Based
+ * Strategy" (arXiv 2104.12916).
+ *
+ * Problem (eq. qp, Sec. 1):
+ *     minimize 1/2 x^T H x + c^T x   subject to  A x = b,  C x >= d,
+ * with H (n x n) symmetric positive definite, A (m1 x n) of full row rank,
+ * 0 < m1 <= n, C (m2 x n), m2 >= 1.  Multipliers follow the Lagrangian of
+ * eq. lagrangian: lambda (free) for A x = b, nu >= 0 for C x >= d, and
+ * H x + c - A^T lambda - C^T nu = 0 at the optimum.
+ *
+ * Method.  Each IPM iteration solves the inequality-constraint reduced system
+ * K_F dnu = r_nu (eq. ineq-const-reduced) by preconditioned CG in implicit form,
+ * using one factorization of the fixed KKT block done once per QP (Sec. 3.1).
+ * This library factorizes K0 = [H A^T; A 0] (the paper's F = [-H A^T; A 0] up to
+ * the sign change K0 = -J F J, J = diag(-I_n, I_m1)), so that
+ *     K_F = D + [C 0] K0^{-1} [C^T; 0],  D = V^{-1} S (eq. diag-d).
+ *
+ * Conventions shared by every entry point
+ *   Layout     dense, row-major, float64; the leading dimension equals the
+ *              number of columns (H: n, A: n, C: n).  Vectors are contiguous.
+ *   Memory     `where` says whether caller pointers are host (QP_MEM_HOST) or
+ *              device (QP_MEM_DEVICE, on the context's device) memory.  Inputs
+ *              are copied into device memory owned by the context and are only
+ *              read during the call; outputs are written to caller buffers.
+ *   Streams    all device work runs on the stream given to qp_setup (a
+ *              hipStream_t, or NULL for a stream owned by the context); calls
+ *              return after their results are complete.
+ *   Errors     status codes only; no C++ exception crosses the ABI.  The text
+ *              of the last error of a context is available from qp_last_error.
+ *   Threads    a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef QPGPU_H
+#define QPGPU_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QPGPU_ABI_VERSION 1
+
+typedef struct qp_ctx qp_ctx;
+
+typedef enum {
+  QP_OK = 0,
+  QP_E_INVALID = 1, /* bad sizes, NaN/Inf input, non-symmetric H, bad option    */
+  QP_E_NOT_SPD = 2, /* Cholesky of H failed: H is not positive definite (Sec. 1) */
+  QP_E_RANK = 3,    /* Cholesky of A H^{-1} A^T failed: A is rank deficient      */
+  QP_E_NOCONV = 4,  /* iteration limit reached (PCG or IPM); outputs are filled  */
+  QP_E_NOMEM = 5,   /* device allocation failed                                  */
+  QP_E_DEVICE = 6,  /* HIP runtime error                                         */
+  QP_E_STATE = 7    /* call order violated (e.g. solve before qp_factor_K0)      */
+} qp_status;
+
+typedef enum {
+  QP_PREC_NONE = 0,    /* unpreconditioned CG (the paper's U-KF variant)           */
+  QP_PREC_LOW_DOF = 1, /* P_L = D, eq. preconditioner-1                            */
+  QP_PREC_FEW_EQ = 2,  /* P_H = D + C H^{-1} C^T, eq. preconditioner-2 (exact H)   */
+  QP_PREC_AUTO = 3     /* P_L if min(m2, n-m1) <= min(m2, m1), else P_H: the
+                          smaller of the bounds of Theorems thm1 and thm2          */
+} qp_precond;
+
+typedef enum {
+  QP_FP64 = 0, /* every kernel in float64                                        */
+  QP_MIXED = 1 /* CG operator and preconditioner applies in float32 with float32
+                  accumulation; factorization, IPM residuals and an iterative
+                  refinement of each reduced solve stay float64                  */
+} qp_precision;
+
+typedef enum { QP_MEM_HOST = 0, QP_MEM_DEVICE = 1 } qp_mem;
+
+typedef struct {
+  double rtol_kkt;  /* IPM stops when the relative KKT score <= rtol_kkt (1e-9)   */
+  double cg_theta;  /* IPM's CG stop: max_i |nu_i r_i| <= cg_theta * mu (0.1)     */
+  double cg_rtol;   /* CG relative residual floor inside the IPM (1e-12)          */
+  double tau;       /* fraction of the step to the boundary (0.995)              */
+  int max_ipm;      /* IPM iteration limit (200)                                 */
+  int max_pcg;      /* CG iterations per reduced solve; 0: 10 * m2               */
+  int poll_every;   /* CG steps launched between host polls of the stop flag (32) */
+  qp_precond prec;  /* preconditioner used by qp_ipm_solve (QP_PREC_AUTO)        */
+  qp_precision precision; /* QP_FP64                                              */
+  int verbose;      /* 1: one line per IPM iteration on stderr                    */
+} qp_options;
+
+typedef struct {
+  int iters;           /* CG steps taken (all refinement sweeps together)         */
+  int status;          /* qp_status of the solve                                  */
+  double rel_res;      /* ||r_nu - K_F dnu||_2 / ||r_nu||_2, recomputed in float64 */
+  int refinements;     /* float64 refinement sweeps (QP_MIXED), else 0            */
+  int fp64_fallback;   /* 1 if a mixed solve fell back to float64 CG             */
+} qp_pcg_info;
+
+typedef struct {
+  int ipm_iters;
+  long long pcg_iters_total;
+  double rel_kkt;          /* max of the parts below (computed on the device)     */
+  double rel_kkt_parts[5]; /* dual, equality, inequality violation, gap, nu < 0   */
+  double obj;              /* 1/2 x^T H x + c^T x                                  */
+  double mu;               /* s^T nu / m2 at the returned point                    */
+  int status;
+  int refinements_total;
+  double t_solve_ms;       /* wall time of qp_ipm_solve on the device stream      */
+} qp_ipm_info;
+
+/* Defaults listed in the field comments above. */
+void qp_default_options(qp_options* opt);
+
+/* Create a context for one QP and copy its data to the device.
+ *   out        receives the context (NULL on failure)
+ *   n, m1, m2  sizes; require 0 < m1 <= n and m2 >= 1 (Sec. 1)
+ *   H (n x n, symmetric within 1e-14 ||H||_F), c (n), A (m1 x n), b (m1),
+ *   C (m2 x n), d (m2): the data of eq. qp
+ *   opt        options (NULL: defaults)
+ *   hip_stream hipStream_t to run on, or NULL for a stream owned by the context
+ * Allocates every device buffer the solves need; later calls allocate nothing
+ * except qp_factor_K0's setup scratch, which it frees before returning. */
+qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const double* c, const double* A,
+                   const double* b, const double* C, const double* d, qp_mem where, const qp_options* opt,
+                   void* hip_stream);
+
+/* Factorize K0 = L Sigma L^T once (Sec. 3.1, single factorization), Sigma =
+ * diag(I_n, -I_m1), L = [L_H 0; W^T L_S] with L_H L_H^T = H, W = L_H^{-1} A^T,
+ * L_S L_S^T = A H^{-1} A^T, and store the inverse factor L^{-1} for the solves.
+ * Also forms C H^{-1} C^T when the options' preconditioner resolves to P_H.
+ * QP_E_NOT_SPD / QP_E_RANK when a Cholesky pivot is not positive. */
+qp_status qp_factor_K0(qp_ctx* ctx);
+
+/* out = K0^{-1} rhs (both n + m1 long) with the stored factor.  Requires
+ * qp_factor_K0.  Used by the IPM for r_nu and the recovery of eq. schur-delta-x. */
+qp_status qp_k0_solve(qp_ctx* ctx, const double* rhs, double* out, qp_mem where);
+
+/* q = K_F p = D p + [C 0] K0^{-1} [C^T p; 0] (m2 vectors, dvec = diag(D) > 0),
+ * the implicit product of one CG step, in float64. */
+qp_status qp_kf_apply(qp_ctx* ctx, const double* dvec, const double* p, double* q, qp_mem where);
+
+/* Solve K_F dnu = rhs (eq. ineq-const-reduced) by PCG from a zero initial guess
+ * (Sec. 6 protocol) until ||r||_2 <= rtol ||rhs||_2 or maxit steps (maxit <= 0:
+ * 10 * m2).  dvec (m2, all > 0) is diag(D); prec selects P_L, P_H or none (AUTO
+ * resolves as documented above).  In QP_MIXED precision the CG runs in float32
+ * inside float64 iterative refinement.  info may be NULL.  Returns QP_E_NOCONV
+ * (with dnu and info filled) when the tolerance is not met. */
+qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, double* dnu, qp_mem where,
+                       qp_precond prec, double rtol, int maxit, qp_pcg_info* info);
+
+/* Run the interior point method (Mehrotra predictor-corrector, both directions
+ * from the reduced system with the preconditioner of the options) and write the
+ * final iterate: x (n), lambda (m1), nu (m2), s (m2).  info may be NULL.
+ * Returns QP_E_NOCONV (outputs filled) if rtol_kkt is not met in max_ipm. */
+qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, double* s, qp_mem where,
+                       qp_ipm_info* info);
+
+/* Device bytes held by the context (all buffers, factor included). */
+size_t qp_ctx_bytes(const qp_ctx* ctx);
+
+/* Free every resource of the context.  NULL is accepted. */
+void qp_destroy(qp_ctx* ctx);
+
+/* Static description of a status code. */
+const char* qp_status_str(qp_status st);
+
+/* Message of the last failure on this context ("" if none; never NULL). */
+const char* qp_last_error(const qp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPGPU_H */

@@ -1,0 +1,186 @@
+// Device-side building blocks of the streaming matrix-vector kernels: wave
+// reductions, 16-byte row dot products against an LDS-staged vector, and the
+// last-workgroup completion counter used for deterministic grid reductions.
+#pragma once
+#include "common.hpp"
+
+namespace qpg {
+
+// ---------------------------------------------------------------------------
+// wave-level helpers
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = v2d_t;
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = v4f_t;
+  static constexpr int n = 4;
+};
+
+template <typename V, typename T>
+__device__ __forceinline__ T dot16(const V& a, const T* x);
+template <>
+__device__ __forceinline__ double dot16<v2d_t, double>(const v2d_t& a, const double* x) {
+  return a.x * x[0] + a.y * x[1];
+}
+template <>
+__device__ __forceinline__ float dot16<v4f_t, float>(const v4f_t& a, const float* x) {
+  return a.x * x[0] + a.y * x[1] + a.z * x[2] + a.w * x[3];
+}
+
+// Dot product of one matrix row (len elements, already rounded to whole
+// 64-lane x 16-byte chunks, zeros past the true length) with x staged in LDS.
+// Returns the full sum in every lane.
+template <typename T>
+__device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int lenR, int lane) {
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CH = kWave * VE;  // elements per wave-wide 16 B load
+  constexpr int U = 4;
+  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  int j = lane * VE;
+  const V* av = reinterpret_cast<const V*>(a);
+  for (; j + (U - 1) * CH < lenR; j += U * CH) {
+    V v0 = __builtin_nontemporal_load(av + (j) / VE);
+    V v1 = __builtin_nontemporal_load(av + (j + CH) / VE);
+    V v2 = __builtin_nontemporal_load(av + (j + 2 * CH) / VE);
+    V v3 = __builtin_nontemporal_load(av + (j + 3 * CH) / VE);
+    acc0 += dot16<V, T>(v0, xs + j);
+    acc1 += dot16<V, T>(v1, xs + j + CH);
+    acc2 += dot16<V, T>(v2, xs + j + 2 * CH);
+    acc3 += dot16<V, T>(v3, xs + j + 3 * CH);
+  }
+  for (; j < lenR; j += CH) {
+    V v0 = __builtin_nontemporal_load(av + j / VE);
+    acc0 += dot16<V, T>(v0, xs + j);
+  }
+  return wave_sum<T>((acc0 + acc1) + (acc2 + acc3));
+}
+
+template <typename T>
+__device__ __forceinline__ int round_chunk(int len, int ld) {
+  constexpr int CH = kWave * Vec16<T>::n;
+  int r = (len + CH - 1) / CH * CH;
+  return r < ld ? r : ld;
+}
+
+// Stage x[0..len) into LDS, zero-filled up to lenR.
+template <typename T>
+__device__ __forceinline__ void stage_x(T* xs, const T* __restrict__ x, int len, int lenR) {
+  for (int j = threadIdx.x; j < lenR; j += blockDim.x) xs[j] = (j < len) ? x[j] : T(0);
+  __syncthreads();
+}
+
+// Arrive at a grid-wide counter; returns true in exactly one (the last) block.
+// The release fence publishes this block's global writes, the acquire fence in
+// the last block makes every other block's writes visible to it.
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned expected) {
+  __shared__ int am_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    am_last = (prev + 1u == expected);
+    if (am_last) atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  if (am_last) __threadfence();
+  return am_last != 0;
+}
+
+
+// Per-workgroup partial of y_j = sum_i A_ij x_i over rows [r0, r1) for the
+// column tile starting at c0 (64 lanes x 16 B).  The four waves of the block
+// split the rows; the result for column c0 + jj is returned through LDS `red`.
+// Shape kLower skips rows that lie entirely above the diagonal of the tile.
+template <typename T>
+__device__ __forceinline__ void cols_block_partial(const T* __restrict__ A, int lda, int r0, int r1, int c0, int shape,
+                                                   const T* __restrict__ x, T (*red)[kWave * Vec16<T>::n]) {
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  T acc[VE];
+#pragma unroll
+  for (int e = 0; e < VE; ++e) acc[e] = 0;
+  const int j = c0 + lane * VE;
+  constexpr int U = 4;
+  const int step = 4 * U;
+  int i = r0 + wave * U;
+  if (shape == kLower && r0 < c0) i += (c0 - r0) / step * step;
+  for (; i < r1; i += step) {
+    V a[U];
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int ii = i + u;
+      if (ii < r1) {
+        a[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(A + (size_t)ii * lda + j));
+        xv[u] = x[ii];
+      } else {
+        xv[u] = 0;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) reinterpret_cast<T*>(&a[u])[e] = 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[e] += reinterpret_cast<const T*>(&a[u])[e] * xv[u];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < VE; ++e) red[wave][lane * VE + e] = acc[e];
+  __syncthreads();
+}
+
+// Block-wide sum (and max) helpers for 256-thread blocks.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh /* >= 4 */) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  v = wave_sum<T>(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  T s = 0;
+  for (int w = 0; w < nw; ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_max(T v, T* sh) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  v = wave_max<T>(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  T s = sh[0];
+  for (int w = 1; w < nw; ++w) s = fmax(s, sh[w]);
+  __syncthreads();
+  return s;
+}
+
+}  // namespace qpg

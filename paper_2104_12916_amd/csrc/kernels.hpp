@@ -1,0 +1,30 @@
+// Internal launcher declarations (not part of the C ABI).
+#pragma once
+#include "common.hpp"
+
+namespace qpg {
+
+// gemv.hip -----------------------------------------------------------------
+template <typename T>
+hipError_t launch_gemv_rows(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha,
+                            T beta, const T* y0, int nsplit, const int* skip);
+template <typename T>
+hipError_t launch_gemv_cols(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha,
+                            T beta, const T* y0, const GemvWork<T>& w, const int* skip);
+template <typename T>
+void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks);
+
+// blas.hip -----------------------------------------------------------------
+// Tile skip rules for GEMM operands with known zero blocks (indices in op()
+// space): kALower: op(A) lower triangular (k <= i); kBLower: op(B) lower (k >= j);
+// kAUpper: op(A) upper (k >= i); kBUpper: op(B) upper (k <= j); kOutLower: only
+// output tiles that touch the lower triangle are computed.
+enum TriFlags : int { kNone = 0, kALower = 1, kBLower = 2, kAUpper = 4, kBUpper = 8, kOutLower = 16 };
+hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double beta, double* C, int ldc, int flags);
+hipError_t fill2d_f64(hipStream_t st, double* X, int ld, int rows, int cols, double v);
+hipError_t chol_inv_f64(hipStream_t st, double* A, int lda, double* X, int ldx, int n, double* tmp, int* info,
+                        int code);
+size_t chol_inv_tmp_elems(int n);
+
+}  // namespace qpg

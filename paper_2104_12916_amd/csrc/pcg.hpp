@@ -1,0 +1,70 @@
+// Launchers of the fused CG-step kernels (pcg.hip) and the IPM vector kernels
+// (ipm.hip).  Internal to the library.
+#pragma once
+#include "common.hpp"
+
+namespace qpg {
+
+enum PrecMode : int { kPrecNone = 0, kPrecL = 1, kPrecH = 2 };
+
+template <typename T>
+hipError_t pcg_init(hipStream_t st, int m2, const T* b, const T* dvec, const T* wts, T* x, T* r, T* z, T* p, int prec,
+                    double rtol, double wtol, int maxit, PcgScalars* sc);
+template <typename T>
+int pcg_q_grid(int m2);
+template <typename T>
+hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, T* p, T* q, T* x, T* r,
+                 T* z, const T* wts, int prec, PcgScalars* sc, double* bpart, unsigned* counter);
+template <typename T>
+hipError_t pcg_prec_cols(hipStream_t st, const T* XP, int ldp, int m2, const T* t, const T* r, T* z, T* p, int init,
+                         PcgScalars* sc, const GemvWork<T>& w, double* tpart);
+
+// ---- IPM (ipm.hip) -------------------------------------------------------
+// Scalars of one IPM iteration, resident in device memory.
+struct IpmScalars {
+  double mu;        // s^T nu / m2 at the current iterate
+  double sigma;     // centering parameter from the predictor
+  double alpha_aff;
+  double mu_aff;
+  double alpha;     // step taken
+  double alpha_max;
+  double tau;
+  double pad;
+};
+
+// Stats of the current iterate used for the relative KKT score.
+enum StatIdx : int {
+  kRdInf = 0, kHxInf, kCInf, kAtlInf, kCtnInf,   // dual residual and its terms
+  kReInf, kAxInf, kBInf,                         // equality residual
+  kViolInf, kDInf,                               // inequality violation max(d - Cx, 0)
+  kXHx, kCx, kBl, kDn,                           // objective pieces
+  kNuMin, kNuInf, kSNu, kRiInf, kSMin,
+  kNumStats
+};
+
+hipError_t ipm_stats(hipStream_t st, int n, int m1, int m2, const double* Hx, const double* Atl, const double* Ctn,
+                     const double* Ax, const double* Cx, const double* x, const double* c, const double* lam,
+                     const double* b, const double* nu, const double* s, const double* d, double* rg, double* re,
+                     double* ri, double* stats);
+hipError_t ipm_rhs(hipStream_t st, int m2, int corrector, const double* ri, const double* s, const double* nu,
+                   const double* Cw, const double* dsa, const double* dna, const IpmScalars* isc, double* rc,
+                   double* rhs, double* dvec);
+hipError_t ipm_neg_copy(hipStream_t st, int m, const double* src, double* dst);
+hipError_t ipm_dirs(hipStream_t st, int n, int m1, int m2, const double* sol, const double* rc, const double* nu,
+                    const double* dvec, const double* dnu, double* dx, double* dlam, double* ds);
+hipError_t ipm_step(hipStream_t st, int n, int m1, int m2, int corrector, double* x, double* lam, double* nu,
+                    double* s, const double* dx, const double* dlam, const double* dnu, const double* ds,
+                    IpmScalars* isc);
+hipError_t ipm_init_point(hipStream_t st, int n, int m1, int m2, const double* sol, const double* Cx,
+                          const double* d, double* x, double* lam, double* nu, double* s);
+hipError_t ew_mul(hipStream_t st, int m, const double* a, const double* b, double* out);
+hipError_t ir_accumulate(hipStream_t st, int m, const float* fx, double* x);
+hipError_t ir_residual(hipStream_t st, int m, const double* rhs, const double* Kx, const double* w, double* r,
+                       PcgScalars* sc);
+hipError_t add_diag_copy(hipStream_t st, int m, const double* T, int ldt, const double* dvec, double* P, int ldp);
+template <typename S, typename D>
+hipError_t convert_2d(hipStream_t st, const S* src, int lds, D* dst, int ldd, int rows, int cols);
+template <typename S, typename D>
+hipError_t convert_1d(hipStream_t st, const S* src, D* dst, int n);
+
+}  // namespace qpg

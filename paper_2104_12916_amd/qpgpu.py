@@ -1,0 +1,242 @@
+"""ctypes binding of libqpgpu.so (include/qpgpu.h), same names as the C ABI.
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Arrays are either NumPy float64 arrays (host memory, QP_MEM_HOST) or
+torch float64 CUDA tensors (device memory, QP_MEM_DEVICE); the library is
+loaded from the package directory and a missing build raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpgpu.so")
+
+QP_OK, QP_E_INVALID, QP_E_NOT_SPD, QP_E_RANK, QP_E_NOCONV, QP_E_NOMEM, QP_E_DEVICE, QP_E_STATE = range(8)
+QP_PREC_NONE, QP_PREC_LOW_DOF, QP_PREC_FEW_EQ, QP_PREC_AUTO = range(4)
+QP_FP64, QP_MIXED = 0, 1
+QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = (
+    "qp_default_options", "qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply",
+    "qp_pcg_solve", "qp_ipm_solve", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
+    "qp_last_error",
+)
+
+
+class qp_options(ct.Structure):
+    _fields_ = [
+        ("rtol_kkt", ct.c_double), ("cg_theta", ct.c_double), ("cg_rtol", ct.c_double),
+        ("tau", ct.c_double), ("max_ipm", ct.c_int), ("max_pcg", ct.c_int),
+        ("poll_every", ct.c_int), ("prec", ct.c_int), ("precision", ct.c_int),
+        ("verbose", ct.c_int),
+    ]
+
+
+class qp_pcg_info(ct.Structure):
+    _fields_ = [
+        ("iters", ct.c_int), ("status", ct.c_int), ("rel_res", ct.c_double),
+        ("refinements", ct.c_int), ("fp64_fallback", ct.c_int),
+    ]
+
+
+class qp_ipm_info(ct.Structure):
+    _fields_ = [
+        ("ipm_iters", ct.c_int), ("pcg_iters_total", ct.c_longlong), ("rel_kkt", ct.c_double),
+        ("rel_kkt_parts", ct.c_double * 5), ("obj", ct.c_double), ("mu", ct.c_double),
+        ("status", ct.c_int), ("refinements_total", ct.c_int), ("t_solve_ms", ct.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqpgpu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2104_12916_amd.build")
+    L = ct.CDLL(LIB_PATH)
+    P, I, D = ct.c_void_p, ct.c_int, ct.c_double
+    L.qp_default_options.argtypes = [ct.POINTER(qp_options)]
+    L.qp_default_options.restype = None
+    L.qp_setup.argtypes = [ct.POINTER(P), I, I, I, P, P, P, P, P, P, I, ct.POINTER(qp_options), P]
+    L.qp_factor_K0.argtypes = [P]
+    L.qp_k0_solve.argtypes = [P, P, P, I]
+    L.qp_kf_apply.argtypes = [P, P, P, P, I]
+    L.qp_pcg_solve.argtypes = [P, P, P, P, I, I, D, I, ct.POINTER(qp_pcg_info)]
+    L.qp_ipm_solve.argtypes = [P, P, P, P, P, I, ct.POINTER(qp_ipm_info)]
+    L.qp_ctx_bytes.argtypes = [P]
+    L.qp_ctx_bytes.restype = ct.c_size_t
+    L.qp_destroy.argtypes = [P]
+    L.qp_destroy.restype = None
+    L.qp_status_str.argtypes = [I]
+    L.qp_status_str.restype = ct.c_char_p
+    L.qp_last_error.argtypes = [P]
+    L.qp_last_error.restype = ct.c_char_p
+    for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve"):
+        getattr(L, name).restype = I
+    _lib = L
+    return L
+
+
+# --- marshalling ------------------------------------------------------------
+def _ptr(a):
+    """(pointer, where) for a float64 NumPy array or torch CUDA tensor."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError("host arrays must be C-contiguous float64")
+        return a.ctypes.data_as(ct.c_void_p), QP_MEM_HOST
+    try:
+        import torch
+    except ImportError as e:  # pragma: no cover
+        raise TypeError("expected a numpy array") from e
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError("device tensors must be contiguous float64")
+        if not a.is_cuda:
+            raise TypeError("torch tensors must live on the GPU (use NumPy for host data)")
+        return ct.c_void_p(a.data_ptr()), QP_MEM_DEVICE
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _where(*arrs):
+    ws = {_ptr(a)[1] for a in arrs}
+    if len(ws) != 1:
+        raise TypeError("mix of host and device arrays in one call")
+    return ws.pop()
+
+
+class QpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{qp_status_str(status)}: {msg}")
+        self.status = status
+
+
+def qp_default_options(**overrides) -> qp_options:
+    o = qp_options()
+    lib().qp_default_options(ct.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def qp_status_str(st: int) -> str:
+    return lib().qp_status_str(int(st)).decode()
+
+
+def qp_last_error(ctx) -> str:
+    return lib().qp_last_error(ctx).decode()
+
+
+def qp_setup(H, c, A, b, C, d, opt: qp_options | None = None, stream=None):
+    """Returns (status, ctx).  stream: hipStream_t as int, or None."""
+    n, m1, m2 = H.shape[0], A.shape[0], C.shape[0]
+    where = _where(H, c, A, b, C, d)
+    ctx = ct.c_void_p()
+    if opt is None:
+        opt = qp_default_options()
+    st = lib().qp_setup(ct.byref(ctx), n, m1, m2, *(_ptr(a)[0] for a in (H, c, A, b, C, d)), where,
+                        ct.byref(opt), ct.c_void_p(stream) if stream else None)
+    return st, ctx
+
+
+def qp_factor_K0(ctx) -> int:
+    return lib().qp_factor_K0(ctx)
+
+
+def qp_k0_solve(ctx, rhs, out) -> int:
+    return lib().qp_k0_solve(ctx, _ptr(rhs)[0], _ptr(out)[0], _where(rhs, out))
+
+
+def qp_kf_apply(ctx, dvec, p, q) -> int:
+    return lib().qp_kf_apply(ctx, _ptr(dvec)[0], _ptr(p)[0], _ptr(q)[0], _where(dvec, p, q))
+
+
+def qp_pcg_solve(ctx, dvec, rhs, dnu, prec: int, rtol: float, maxit: int = 0):
+    info = qp_pcg_info()
+    st = lib().qp_pcg_solve(ctx, _ptr(dvec)[0], _ptr(rhs)[0], _ptr(dnu)[0], _where(dvec, rhs, dnu), int(prec),
+                            float(rtol), int(maxit), ct.byref(info))
+    return st, info
+
+
+def qp_ipm_solve(ctx, x, lam, nu, s):
+    info = qp_ipm_info()
+    st = lib().qp_ipm_solve(ctx, _ptr(x)[0], _ptr(lam)[0], _ptr(nu)[0], _ptr(s)[0], _where(x, lam, nu, s),
+                            ct.byref(info))
+    return st, info
+
+
+def qp_ctx_bytes(ctx) -> int:
+    return int(lib().qp_ctx_bytes(ctx))
+
+
+def qp_destroy(ctx) -> None:
+    lib().qp_destroy(ctx)
+
+
+# --- convenience wrapper used by tests and the benchmark --------------------
+class Solver:
+    """Owns one context; raises QpError on any non-OK status it is not told to accept."""
+
+    def __init__(self, H, c, A, b, C, d, **opts):
+        self.n, self.m1, self.m2 = H.shape[0], A.shape[0], C.shape[0]
+        stream = opts.pop("stream", None)
+        self.opt = qp_default_options(**opts)
+        st, ctx = qp_setup(H, c, A, b, C, d, self.opt, stream)
+        if st != QP_OK:
+            raise QpError(st, "qp_setup failed")
+        self.ctx = ctx
+
+    def check(self, st, accept=(QP_OK,)):
+        if st not in accept:
+            raise QpError(st, qp_last_error(self.ctx))
+        return st
+
+    def factor(self):
+        return self.check(qp_factor_K0(self.ctx))
+
+    def k0_solve(self, rhs):
+        out = np.empty_like(rhs)
+        self.check(qp_k0_solve(self.ctx, rhs, out))
+        return out
+
+    def kf_apply(self, dvec, p):
+        q = np.empty_like(p)
+        self.check(qp_kf_apply(self.ctx, dvec, p, q))
+        return q
+
+    def pcg(self, dvec, rhs, prec=QP_PREC_LOW_DOF, rtol=1e-10, maxit=0, accept=(QP_OK,)):
+        dnu = np.empty_like(rhs)
+        st, info = qp_pcg_solve(self.ctx, dvec, rhs, dnu, prec, rtol, maxit)
+        self.check(st, accept)
+        return dnu, info
+
+    def ipm(self, accept=(QP_OK,)):
+        x = np.empty(self.n)
+        lam = np.empty(self.m1)
+        nu = np.empty(self.m2)
+        s = np.empty(self.m2)
+        st, info = qp_ipm_solve(self.ctx, x, lam, nu, s)
+        self.check(st, accept)
+        return x, lam, nu, s, info
+
+    def bytes(self):
+        return qp_ctx_bytes(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            qp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

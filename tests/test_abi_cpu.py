@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol declared in include/qpgpu.h.
+
+No compute call is made here (no GPU): only symbol lookup, static strings,
+option defaults and argument validation that returns before touching a device.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_12916_amd import qpgpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "qpgpu.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_[a-zA-Z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = qpgpu.lib()
+    names = header_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(qpgpu.EXPORTS)
+
+
+def test_status_strings_and_defaults():
+    assert qpgpu.qp_status_str(qpgpu.QP_OK) == "ok"
+    assert "positive definite" in qpgpu.qp_status_str(qpgpu.QP_E_NOT_SPD)
+    assert qpgpu.qp_status_str(99) == "unknown status"
+    o = qpgpu.qp_default_options()
+    assert o.rtol_kkt == 1e-9 and o.tau == 0.995 and o.max_ipm == 200
+    assert o.prec == qpgpu.QP_PREC_AUTO and o.precision == qpgpu.QP_FP64
+    assert qpgpu.lib().qp_last_error(None) == b""
+    qpgpu.lib().qp_destroy(None)
+
+
+def _qp(n=6, m1=2, m2=4):
+    rng = np.random.default_rng(0)
+    Q = rng.standard_normal((n, n))
+    H = Q.T @ Q / n + np.eye(n)
+    return (np.ascontiguousarray(H), rng.standard_normal(n), rng.standard_normal((m1, n)),
+            rng.standard_normal(m1), rng.standard_normal((m2, n)), rng.standard_normal(m2))
+
+
+@pytest.mark.parametrize("case", ["m1_zero", "m1_gt_n", "m2_zero", "nan", "asym", "bad_tau"])
+def test_setup_rejects_invalid_input_before_device_work(case):
+    H, c, A, b, C, d = _qp()
+    L = qpgpu.lib()
+    ctx = ct.c_void_p()
+    n, m1, m2 = 6, 2, 4
+    opt = qpgpu.qp_default_options()
+    if case == "m1_zero":
+        m1 = 0
+    elif case == "m1_gt_n":
+        m1 = 7
+    elif case == "m2_zero":
+        m2 = 0
+    elif case == "nan":
+        c = c.copy()
+        c[3] = np.nan
+    elif case == "asym":
+        H = H.copy()
+        H[0, 1] += 1e-6
+    elif case == "bad_tau":
+        opt.tau = 1.5
+    ptrs = [a.ctypes.data_as(ct.c_void_p) for a in (H, c, A, b, C, d)]
+    st = L.qp_setup(ct.byref(ctx), n, m1, m2, *ptrs, qpgpu.QP_MEM_HOST, ct.byref(opt), None)
+    assert st == qpgpu.QP_E_INVALID
+    assert not ctx.value
+
+
+def test_null_context_calls_are_rejected():
+    L = qpgpu.lib()
+    assert L.qp_factor_K0(None) == qpgpu.QP_E_INVALID
+    assert L.qp_ipm_solve(None, None, None, None, None, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_pcg_solve(None, None, None, None, 0, 1, 1e-8, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_ctx_bytes(None) == 0
+
+
+def test_binding_marshalling_rejects_wrong_dtypes():
+    with pytest.raises(TypeError):
+        qpgpu._ptr(np.zeros(3, dtype=np.float32))
+    with pytest.raises(TypeError):
+        qpgpu._ptr(np.zeros((3, 3))[:, :2])
