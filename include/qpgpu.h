@@ -84,6 +84,8 @@ typedef struct {
   qp_precond prec;  /* preconditioner used by qp_ipm_solve (QP_PREC_AUTO)        */
   qp_precision precision; /* QP_FP64                                              */
   int verbose;      /* 1: one line per IPM iteration on stderr                    */
+  int profile;      /* 1: time the operator kernels of the first CG step of every
+                       poll chunk with HIP events (read with qp_profile_get)     */
 } qp_options;
 
 typedef struct {
@@ -152,6 +154,24 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
  * Returns QP_E_NOCONV (outputs filled) if rtol_kkt is not met in max_ipm. */
 qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, double* s, qp_mem where,
                        qp_ipm_info* info);
+
+/* Diagnostic: average device time (ms) of one launch of a CG-step operator
+ * kernel, measured with HIP events around `reps` back-to-back launches on the
+ * context's stream, in the launch configuration qp_pcg_solve uses:
+ *   op 0  u = C^T p            (column sweep over C)
+ *   op 1  v = Sigma M u        (row sweep over M = L^{-1}[:, :n])
+ *   op 2  w = M^T v            (column sweep over M)
+ *   op 3  q = C w              (row sweep over C)
+ *   op 4  one whole P_L CG step (ops 0-2 and the fused q/update kernel)
+ * precision QP_MIXED times the float32 copies (context created QP_MIXED).
+ * Overwrites the context's CG work vectors.  Requires qp_factor_K0. */
+qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, double* avg_ms);
+
+/* Average device time (ms) per launch and sample counts of the CG-step kernels
+ * sampled while options.profile is set, in the order: C^T p column sweep,
+ * Sigma M u row sweep, M^T v column sweep, q = C w + D p row sweep, and for
+ * P_H the X_P r row sweep and X_P^T t column sweep.  reset != 0 clears them. */
+qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset);
 
 /* Device bytes held by the context (all buffers, factor included). */
 size_t qp_ctx_bytes(const qp_ctx* ctx);

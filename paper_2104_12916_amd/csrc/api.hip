@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 #include <chrono>
+#include <cstdlib>
 
 #include "../../include/qpgpu.h"
 #include "kernels.hpp"
@@ -36,6 +37,8 @@ static int ld_for(int cols) { return ((cols > 0 ? cols : 1) + 255) / 256 * 256; 
 }  // namespace qpg
 
 using namespace qpg;
+
+constexpr int kProfOps = 6;
 
 struct qp_ctx {
   int dev = 0;
@@ -77,13 +80,18 @@ struct qp_ctx {
   // workspaces
   GemvWork<double> w64{};
   GemvWork<float> w32{};
-  double* bpart = nullptr;
-  double* tpart = nullptr;
-  unsigned* cnt_q = nullptr;
+  double* bpart = nullptr;  // per-workgroup partials of p^T q
+  int bpart_cap = 0;
   PcgScalars* sc = nullptr;
   IpmScalars* isc = nullptr;
   double* stats = nullptr;
   int* info = nullptr;
+  // sampled kernel durations (options.profile): CG-step sweeps in the order
+  // C^T p, Sigma M u, M^T v, q = C w + D p, X_P r, X_P^T t
+  EventPair prof_ev[kProfOps] = {};
+  double prof_ms[kProfOps] = {};
+  long long prof_n[kProfOps] = {};
+  bool prof_ready = false;
   // pinned host mirrors
   PcgScalars* h_sc = nullptr;
   IpmScalars* h_isc = nullptr;
@@ -191,9 +199,9 @@ void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN) {
 template <typename T>
 void k0_top_apply(qp_ctx* ctx, const T* Linv, const T* u, T* v, T* w, const GemvWork<T>& wk, const int* skip) {
   HIPCHK(ctx, launch_gemv_rows<T>(ctx->stream, Linv, ctx->ldN, ctx->N, ctx->n, kLower, u, v, T(1), T(0), nullptr,
-                                  ctx->n, skip));
+                                  ctx->n, skip, 2));
   HIPCHK(ctx, launch_gemv_cols<T>(ctx->stream, Linv, ctx->ldN, ctx->N, ctx->n, kLower, v, w, T(1), T(0), nullptr, wk,
-                                  skip));
+                                  skip, 3));
 }
 
 // ---- factorization --------------------------------------------------------
@@ -285,13 +293,26 @@ PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, doub
   const int n = ctx->n, m2 = ctx->m2;
   const int* skip = &ctx->sc->done;
   HIPCHK(ctx, pcg_init<T>(st, m2, rhs, B.dvec, B.wts, B.x, B.r, B.z, B.p, prec, rtol, wtol, maxit, ctx->sc));
-  if (prec == kPrecH) {
-    HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip));
-    HIPCHK(ctx, pcg_prec_cols<T>(st, B.XP, ctx->ldm2, m2, B.t, B.r, B.z, B.p, 1, ctx->sc, *B.wk, ctx->tpart));
-  }
+  auto ph_apply = [&](int init, const EventPair* ev) {
+    HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip, 4,
+                                    ev ? &ev[4] : nullptr));
+    HIPCHK(ctx, launch_gemv_cols<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.t, B.z, T(1), T(0), nullptr, *B.wk, skip,
+                                    5, ev ? &ev[5] : nullptr));
+    HIPCHK(ctx, pcg_ph_update<T>(st, m2, B.r, B.z, B.p, init, ctx->sc));
+  };
+  if (prec == kPrecH) ph_apply(1, nullptr);
   const int poll = ctx->opt.poll_every > 0 ? ctx->opt.poll_every : 32;
   PcgResult res;
   long long launched = 0;
+  const bool prof = ctx->opt.profile != 0;
+  if (prof && !ctx->prof_ready) {
+    for (int o = 0; o < kProfOps; ++o) {
+      HIPCHK(ctx, hipEventCreate(&ctx->prof_ev[o].begin));
+      HIPCHK(ctx, hipEventCreate(&ctx->prof_ev[o].end));
+    }
+    ctx->prof_ready = true;
+  }
+  int iter_before = 0;
   for (;;) {
     // the device stops at maxit; a host bound guards against a stop flag that never arrives
     if (launched > (long long)maxit + 2LL * poll) {
@@ -300,17 +321,32 @@ PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, doub
     }
     launched += poll;
     for (int k = 0; k < poll; ++k) {
-      HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip));
-      k0_top_apply<T>(ctx, B.Linv, B.u, B.v, B.w, *B.wk, skip);
-      HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc,
-                           ctx->bpart, ctx->cnt_q));
-      if (prec == kPrecH) {
-        HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip));
-        HIPCHK(ctx, pcg_prec_cols<T>(st, B.XP, ctx->ldm2, m2, B.t, B.r, B.z, B.p, 0, ctx->sc, *B.wk, ctx->tpart));
-      }
+      const EventPair* ev = (prof && k == 0) ? ctx->prof_ev : nullptr;
+      HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip, 1,
+                                      ev ? &ev[0] : nullptr));
+      HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n, skip,
+                                      2, ev ? &ev[1] : nullptr));
+      HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr, *B.wk,
+                                      skip, 3, ev ? &ev[2] : nullptr));
+      HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
+                           ev ? &ev[3] : nullptr));
+      HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc));
+      if (prec == kPrecH) ph_apply(0, ev);
     }
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_sc, ctx->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
     sync(ctx);
+    if (prof && ctx->h_sc->iter > iter_before) {
+      // the sampled step ran (it was the first of the chunk and the solve had not stopped)
+      const int nops = (prec == kPrecH) ? 6 : 4;
+      for (int o = 0; o < nops; ++o) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ctx->prof_ev[o].begin, ctx->prof_ev[o].end) == hipSuccess) {
+          ctx->prof_ms[o] += ms;
+          ctx->prof_n[o] += 1;
+        }
+      }
+    }
+    iter_before = ctx->h_sc->iter;
     if (ctx->h_sc->done) break;
   }
   res.iters = ctx->h_sc->iter;
@@ -574,17 +610,14 @@ void alloc_all(qp_ctx* ctx) {
     *v = dalloc<double>(ctx, m2);
   for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) *v = dalloc<double>(ctx, N);
   // gemv_cols partial workspace: chunks * ld with chunks <= 4 * CUs / tiles
+  // gemv_cols_plan keeps chunks <= 4 CUs / tiles (and >= 1), so chunks * tiles * tile_width
+  // <= (4 CUs + tiles) * 256 elements for either precision
   int maxld = std::max(std::max(ctx->ldn, ctx->ldN), ctx->ldm2);
-  size_t part = (size_t)(dev_info().cu_count * 4 + 64) * 256 + (size_t)4 * maxld;
-  part = std::max(part, (size_t)((ctx->m2 + 31) / 32 + 1) * ctx->ldm2);
-  part = std::max(part, (size_t)((N + 31) / 32 + 1) * 256);
+  size_t part = (size_t)(dev_info().cu_count * 4) * 256 + (size_t)2 * maxld + 4096;
   ctx->w64.part = dalloc<double>(ctx, part);
   ctx->w64.part_elems = part;
-  ctx->w64.n_counters = 4096;
-  ctx->w64.counters = dalloc<unsigned>(ctx, 4096);
-  ctx->bpart = dalloc<double>(ctx, 8192);
-  ctx->tpart = dalloc<double>(ctx, 8192);
-  ctx->cnt_q = dalloc<unsigned>(ctx, 64);
+  ctx->bpart_cap = 2 * dev_info().cu_count + 64;
+  ctx->bpart = dalloc<double>(ctx, ctx->bpart_cap);
   ctx->sc = dalloc<PcgScalars>(ctx, 1);
   ctx->isc = dalloc<IpmScalars>(ctx, 1);
   ctx->stats = dalloc<double>(ctx, 64);
@@ -608,8 +641,6 @@ void alloc_all(qp_ctx* ctx) {
     ctx->fv = dalloc<float>(ctx, N);
     ctx->w32.part = dalloc<float>(ctx, part);
     ctx->w32.part_elems = part;
-    ctx->w32.n_counters = 4096;
-    ctx->w32.counters = ctx->w64.counters;
   }
   HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_sc, sizeof(PcgScalars), hipHostMallocDefault));
   HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_isc, sizeof(IpmScalars), hipHostMallocDefault));
@@ -650,6 +681,7 @@ void qp_default_options(qp_options* opt) {
   opt->prec = QP_PREC_AUTO;
   opt->precision = QP_FP64;
   opt->verbose = 0;
+  opt->profile = 0;
 }
 
 const char* qp_status_str(qp_status st) {
@@ -670,9 +702,27 @@ const char* qp_last_error(const qp_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 
 size_t qp_ctx_bytes(const qp_ctx* ctx) { return ctx ? ctx->bytes : 0; }
 
+qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset) {
+  if (!ctx || !avg_ms || !samples) return QP_E_INVALID;
+  for (int o = 0; o < kProfOps; ++o) {
+    samples[o] = ctx->prof_n[o];
+    avg_ms[o] = ctx->prof_n[o] ? ctx->prof_ms[o] / (double)ctx->prof_n[o] : 0.0;
+    if (reset) {
+      ctx->prof_ms[o] = 0;
+      ctx->prof_n[o] = 0;
+    }
+  }
+  return QP_OK;
+}
+
 void qp_destroy(qp_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->prof_ready)
+    for (int o = 0; o < kProfOps; ++o) {
+      (void)hipEventDestroy(ctx->prof_ev[o].begin);
+      (void)hipEventDestroy(ctx->prof_ev[o].end);
+    }
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (void* p : {(void*)ctx->h_sc, (void*)ctx->h_isc, (void*)ctx->h_stats, (void*)ctx->h_info})
     if (p) (void)hipHostFree(p);
@@ -851,6 +901,96 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
   if (info) info->status = st;
   (void)code;
   return st;
+}
+
+qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, double* avg_ms) {
+  if (!ctx || !avg_ms || reps <= 0 || op < 0 || op > 4) return QP_E_INVALID;
+  if (precision != QP_FP64 && precision != QP_MIXED) return QP_E_INVALID;
+  if (precision == QP_MIXED && ctx->opt.precision != QP_MIXED) {
+    set_err(ctx, "float32 operator copies exist only in a QP_MIXED context");
+    return QP_E_STATE;
+  }
+  if (!ctx->factored) {
+    set_err(ctx, "qp_op_time before qp_factor_K0");
+    return QP_E_STATE;
+  }
+  ctx->err.clear();
+  return guarded(ctx, [&] {
+    hipStream_t st = ctx->stream;
+    const int n = ctx->n, m2 = ctx->m2;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      PcgBufs<T> B;
+      if constexpr (sizeof(T) == 8) {
+        B = bufs64(ctx, ctx->dvec, nullptr, ctx->dnu);
+      } else {
+        B = bufs32(ctx);
+        B.wts = nullptr;
+      }
+      // deterministic operands: p = 1, d = 1, a CG state that is far from convergence
+      HIPCHK(ctx, fill_vec<T>(st, m2, T(1), const_cast<T*>(B.dvec)));
+      HIPCHK(ctx, fill_vec<T>(st, m2, T(1), B.q));
+      HIPCHK(ctx, pcg_init<T>(st, m2, B.q, B.dvec, nullptr, B.x, B.r, B.z, B.p, kPrecL, 0.0, -1.0, 1 << 30,
+                              ctx->sc));
+      HIPCHK(ctx, fill_vec<T>(st, n, T(1), B.u));
+      HIPCHK(ctx, fill_vec<T>(st, ctx->N, T(1), B.v));
+      HIPCHK(ctx, fill_vec<T>(st, n, T(1), B.w));
+      auto launch = [&]() {
+        switch (op) {
+          case 0:
+            HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk,
+                                            nullptr, 1));
+            break;
+          case 1:
+            HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n,
+                                            nullptr, 2));
+            break;
+          case 2:
+            HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr,
+                                            *B.wk, nullptr, 3));
+            break;
+          case 3:
+            HIPCHK(ctx, launch_gemv_rows<T>(st, B.C, ctx->ldn, m2, n, kDense, B.w, B.q, T(1), T(0), nullptr, m2,
+                                            nullptr, 0));
+            break;
+          case 4: {
+            const int* skip = &ctx->sc->done;
+            HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk,
+                                            skip, 1));
+            k0_top_apply<T>(ctx, B.Linv, B.u, B.v, B.w, *B.wk, skip);
+            HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart,
+                                 ctx->bpart_cap));
+            HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, nullptr, kPrecL, ctx->sc));
+            break;
+          }
+        }
+      };
+      launch();  // warm-up
+      HIPCHK(ctx, hipEventRecord(e0, st));
+      for (int k = 0; k < reps; ++k) launch();
+      HIPCHK(ctx, hipEventRecord(e1, st));
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+      *avg_ms = ms / reps;
+      if (op == 4) {
+        HIPCHK(ctx, hipMemcpy(ctx->h_sc, ctx->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost));
+        if (ctx->h_sc->done) {
+          set_err(ctx, "CG state stopped during the timing loop (done=%d)", ctx->h_sc->done);
+          throw Fail{QP_E_NOCONV};
+        }
+      }
+    };
+    if (precision == QP_MIXED)
+      run(float(0));
+    else
+      run(double(0));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
 }
 
 qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, double* s, qp_mem where,

@@ -40,12 +40,18 @@ struct DevInfo {
 };
 DevInfo& dev_info();
 
+// Optional pair of events recorded around the main kernel of a launch (used to
+// sample kernel durations during a solve).
+struct EventPair {
+  hipEvent_t begin;
+  hipEvent_t end;
+};
+
+// Workspace of the two-pass column sweep: per-chunk partial sums.
 template <typename T>
 struct GemvWork {
-  T* part;            // partial sums, at least chunks * ncols elements
-  unsigned* counters; // zero-initialised, one per column tile (+1 global)
+  T* part;
   size_t part_elems;
-  int n_counters;
 };
 
 }  // namespace qpg

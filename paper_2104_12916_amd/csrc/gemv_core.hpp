@@ -1,6 +1,6 @@
-// Device-side building blocks of the streaming matrix-vector kernels: wave
-// reductions, 16-byte row dot products against an LDS-staged vector, and the
-// last-workgroup completion counter used for deterministic grid reductions.
+// Device-side building blocks of the streaming matrix-vector kernels: wave and
+// workgroup reductions, 16-byte row dot products against an LDS-staged vector,
+// and the per-workgroup partial of a column sweep.
 #pragma once
 #include "common.hpp"
 
@@ -91,24 +91,6 @@ __device__ __forceinline__ void stage_x(T* xs, const T* __restrict__ x, int len,
   for (int j = threadIdx.x; j < lenR; j += blockDim.x) xs[j] = (j < len) ? x[j] : T(0);
   __syncthreads();
 }
-
-// Arrive at a grid-wide counter; returns true in exactly one (the last) block.
-// The release fence publishes this block's global writes, the acquire fence in
-// the last block makes every other block's writes visible to it.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned expected) {
-  __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    am_last = (prev + 1u == expected);
-    if (am_last) atomicExch(counter, 0u);
-  }
-  __syncthreads();
-  if (am_last) __threadfence();
-  return am_last != 0;
-}
-
 
 // Per-workgroup partial of y_j = sum_i A_ij x_i over rows [r0, r1) for the
 // column tile starting at c0 (64 lanes x 16 B).  The four waves of the block

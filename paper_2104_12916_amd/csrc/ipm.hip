@@ -329,6 +329,21 @@ hipError_t convert_1d(hipStream_t st, const S* src, D* dst, int n) {
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ void fill_vec_kernel(int n, T v, T* __restrict__ x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+template <typename T>
+hipError_t fill_vec(hipStream_t st, int n, T v, T* x) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_vec_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, v, x);
+  return hipGetLastError();
+}
+template hipError_t fill_vec<double>(hipStream_t, int, double, double*);
+template hipError_t fill_vec<float>(hipStream_t, int, float, float*);
+
 template hipError_t convert_2d<double, float>(hipStream_t, const double*, int, float*, int, int, int);
 template hipError_t convert_2d<double, double>(hipStream_t, const double*, int, double*, int, int, int);
 template hipError_t convert_1d<double, float>(hipStream_t, const double*, float*, int);

@@ -7,10 +7,12 @@ namespace qpg {
 // gemv.hip -----------------------------------------------------------------
 template <typename T>
 hipError_t launch_gemv_rows(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha,
-                            T beta, const T* y0, int nsplit, const int* skip);
+                            T beta, const T* y0, int nsplit, const int* skip, int tag = 0,
+                            const EventPair* ev = nullptr);
 template <typename T>
 hipError_t launch_gemv_cols(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha,
-                            T beta, const T* y0, const GemvWork<T>& w, const int* skip);
+                            T beta, const T* y0, const GemvWork<T>& w, const int* skip, int tag = 0,
+                            const EventPair* ev = nullptr);
 template <typename T>
 void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks);
 

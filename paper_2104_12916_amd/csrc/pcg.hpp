@@ -13,11 +13,13 @@ hipError_t pcg_init(hipStream_t st, int m2, const T* b, const T* dvec, const T* 
 template <typename T>
 int pcg_q_grid(int m2);
 template <typename T>
-hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, T* p, T* q, T* x, T* r,
-                 T* z, const T* wts, int prec, PcgScalars* sc, double* bpart, unsigned* counter);
+hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, const T* p, T* q,
+                 const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev = nullptr);
 template <typename T>
-hipError_t pcg_prec_cols(hipStream_t st, const T* XP, int ldp, int m2, const T* t, const T* r, T* z, T* p, int init,
-                         PcgScalars* sc, const GemvWork<T>& w, double* tpart);
+hipError_t pcg_update(hipStream_t st, int m2, const double* bpart, const T* dvec, T* p, const T* q, T* x, T* r, T* z,
+                      const T* wts, int prec, PcgScalars* sc);
+template <typename T>
+hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, int init, PcgScalars* sc);
 
 // ---- IPM (ipm.hip) -------------------------------------------------------
 // Scalars of one IPM iteration, resident in device memory.
@@ -62,6 +64,8 @@ hipError_t ir_accumulate(hipStream_t st, int m, const float* fx, double* x);
 hipError_t ir_residual(hipStream_t st, int m, const double* rhs, const double* Kx, const double* w, double* r,
                        PcgScalars* sc);
 hipError_t add_diag_copy(hipStream_t st, int m, const double* T, int ldt, const double* dvec, double* P, int ldp);
+template <typename T>
+hipError_t fill_vec(hipStream_t st, int n, T v, T* x);
 template <typename S, typename D>
 hipError_t convert_2d(hipStream_t st, const S* src, int lds, D* dst, int ldd, int rows, int cols);
 template <typename S, typename D>

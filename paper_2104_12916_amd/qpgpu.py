@@ -23,7 +23,7 @@ QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "qp_default_options", "qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply",
-    "qp_pcg_solve", "qp_ipm_solve", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
+    "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
     "qp_last_error",
 )
 
@@ -33,7 +33,7 @@ class qp_options(ct.Structure):
         ("rtol_kkt", ct.c_double), ("cg_theta", ct.c_double), ("cg_rtol", ct.c_double),
         ("tau", ct.c_double), ("max_ipm", ct.c_int), ("max_pcg", ct.c_int),
         ("poll_every", ct.c_int), ("prec", ct.c_int), ("precision", ct.c_int),
-        ("verbose", ct.c_int),
+        ("verbose", ct.c_int), ("profile", ct.c_int),
     ]
 
 
@@ -72,6 +72,8 @@ def lib():
     L.qp_kf_apply.argtypes = [P, P, P, P, I]
     L.qp_pcg_solve.argtypes = [P, P, P, P, I, I, D, I, ct.POINTER(qp_pcg_info)]
     L.qp_ipm_solve.argtypes = [P, P, P, P, P, I, ct.POINTER(qp_ipm_info)]
+    L.qp_op_time.argtypes = [P, I, I, I, ct.POINTER(D)]
+    L.qp_profile_get.argtypes = [P, ct.POINTER(D), ct.POINTER(ct.c_longlong), I]
     L.qp_ctx_bytes.argtypes = [P]
     L.qp_ctx_bytes.restype = ct.c_size_t
     L.qp_destroy.argtypes = [P]
@@ -80,7 +82,8 @@ def lib():
     L.qp_status_str.restype = ct.c_char_p
     L.qp_last_error.argtypes = [P]
     L.qp_last_error.restype = ct.c_char_p
-    for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve"):
+    for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
+                 "qp_op_time", "qp_profile_get"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -173,6 +176,21 @@ def qp_ipm_solve(ctx, x, lam, nu, s):
     return st, info
 
 
+def qp_op_time(ctx, op: int, precision: int = QP_FP64, reps: int = 20):
+    """Returns (status, average milliseconds per launch)."""
+    ms = ct.c_double(0.0)
+    st = lib().qp_op_time(ctx, int(op), int(precision), int(reps), ct.byref(ms))
+    return st, ms.value
+
+
+def qp_profile_get(ctx, reset: bool = False):
+    """Returns (status, [avg ms per launch] * 6, [samples] * 6)."""
+    ms = (ct.c_double * 6)()
+    cnt = (ct.c_longlong * 6)()
+    st = lib().qp_profile_get(ctx, ms, cnt, int(reset))
+    return st, list(ms), list(cnt)
+
+
 def qp_ctx_bytes(ctx) -> int:
     return int(lib().qp_ctx_bytes(ctx))
 
@@ -226,6 +244,16 @@ class Solver:
         st, info = qp_ipm_solve(self.ctx, x, lam, nu, s)
         self.check(st, accept)
         return x, lam, nu, s, info
+
+    def op_time(self, op, precision=QP_FP64, reps=20):
+        st, ms = qp_op_time(self.ctx, op, precision, reps)
+        self.check(st)
+        return ms
+
+    def profile(self, reset=False):
+        st, ms, cnt = qp_profile_get(self.ctx, reset)
+        self.check(st)
+        return ms, cnt
 
     def bytes(self):
         return qp_ctx_bytes(self.ctx)
