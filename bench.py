@@ -51,7 +51,7 @@ def op_bytes(n, m1, m2, elem):
 
 def kernel_src_hash():
     h = hashlib.sha256()
-    for f in ("gemv.hip", "gemv_core.hpp", "pcg.hip"):
+    for f in ("gemv.hip", "gemv_core.hpp", "pcg.hip", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2104_12916_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

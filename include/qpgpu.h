@@ -79,7 +79,7 @@ typedef struct {
   double cg_rtol;   /* CG relative residual floor inside the IPM (1e-12)          */
   double tau;       /* fraction of the step to the boundary (0.995)              */
   int max_ipm;      /* IPM iteration limit (200)                                 */
-  int max_pcg;      /* CG iterations per reduced solve; 0: 10 * m2               */
+  int max_pcg;      /* CG iterations per reduced solve in the IPM; 0: 20 * m2     */
   int poll_every;   /* CG steps launched between host polls of the stop flag (32) */
   qp_precond prec;  /* preconditioner used by qp_ipm_solve (QP_PREC_AUTO)        */
   qp_precision precision; /* QP_FP64                                              */

@@ -32,7 +32,9 @@ DevInfo& dev_info() {
   return info;
 }
 
-static int ld_for(int cols) { return ((cols > 0 ? cols : 1) + 255) / 256 * 256; }
+// Leading dimension of a matrix with `cols` columns: whole 256-element rows
+// (every sweep reads full 64-lane x 16-byte chunks) plus tune().ld_pad.
+static int ld_for(int cols) { return ((cols > 0 ? cols : 1) + 255) / 256 * 256 + tune().ld_pad; }
 
 }  // namespace qpg
 
@@ -511,7 +513,7 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
   const qp_precond pc = resolve_prec(ctx, ctx->opt.prec);
   const int prec = prec_mode(pc);
   if (prec == kPrecH) ph_setup(ctx);
-  const int maxit = ctx->opt.max_pcg > 0 ? ctx->opt.max_pcg : 10 * m2;
+  const int maxit = ctx->opt.max_pcg > 0 ? ctx->opt.max_pcg : 20 * m2;
   // initial point: K0 [x0; -lam0] = [-c; b]; s0 = max(C x0 - d, 1); nu0 = 1
   HIPCHK(ctx, ipm_neg_copy(st, n, ctx->c, ctx->vN1));
   HIPCHK(ctx, hipMemcpyAsync(ctx->vN1 + n, ctx->b, (size_t)m1 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -610,13 +612,11 @@ void alloc_all(qp_ctx* ctx) {
     *v = dalloc<double>(ctx, m2);
   for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) *v = dalloc<double>(ctx, N);
   // gemv_cols partial workspace: chunks * ld with chunks <= 4 * CUs / tiles
-  // gemv_cols_plan keeps chunks <= 4 CUs / tiles (and >= 1), so chunks * tiles * tile_width
-  // <= (4 CUs + tiles) * 256 elements for either precision
   int maxld = std::max(std::max(ctx->ldn, ctx->ldN), ctx->ldm2);
-  size_t part = (size_t)(dev_info().cu_count * 4) * 256 + (size_t)2 * maxld + 4096;
+  size_t part = gemv_cols_part_elems(maxld);
   ctx->w64.part = dalloc<double>(ctx, part);
   ctx->w64.part_elems = part;
-  ctx->bpart_cap = 2 * dev_info().cu_count + 64;
+  ctx->bpart_cap = kMaxRowsBpc * dev_info().cu_count + 64;
   ctx->bpart = dalloc<double>(ctx, ctx->bpart_cap);
   ctx->sc = dalloc<PcgScalars>(ctx, 1);
   ctx->isc = dalloc<IpmScalars>(ctx, 1);

@@ -5,6 +5,7 @@
 // explicit zeros above the diagonal; kernels skip those regions by tile.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 #include <cstddef>
 
@@ -40,12 +41,39 @@ struct DevInfo {
 };
 DevInfo& dev_info();
 
+// Launch shapes of the streaming sweeps.  Defaults were chosen by timing on
+// gfx950 (qp_op_time); the environment variable QPGPU_TUNE
+// ("rows_bpc=4,rows_unroll=8,cols_wide=1,cols_bpc=8") overrides them.
+struct Tune {
+  int rows_bpc = 2;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
+  int rows_unroll = 4;  // 16-byte loads in flight per lane: 4 or 8
+  int cols_wide = 0;    // gemv_cols: 0 four waves split the rows of one 64-lane column tile,
+                        //            1 each wave owns its own column tile (4 per workgroup)
+  int cols_bpc = 2;     // gemv_cols: target workgroups per CU
+  int cols_unroll = 8;  // gemv_cols: rows in flight per wave: 4 or 8
+  int ld_pad = 64;      // elements added to every matrix leading dimension (multiple of 64);
+                        // breaks the power-of-two row stride of n = 4096 matrices
+};
+Tune& tune();
+constexpr int kMaxRowsBpc = 8;
+constexpr int kMaxColsBpc = 8;
+
 // Optional pair of events recorded around the main kernel of a launch (used to
 // sample kernel durations during a solve).
 struct EventPair {
   hipEvent_t begin;
   hipEvent_t end;
 };
+
+// Launch a kernel; when ev is non-null the runtime stamps the kernel's own
+// start and stop times into ev->begin / ev->end (no marker packets around it).
+#define QPG_LAUNCH(kernel, grid, block, smem, st, ev, ...)                                              \
+  do {                                                                                                   \
+    if (ev)                                                                                              \
+      hipExtLaunchKernelGGL(kernel, grid, block, smem, st, (ev)->begin, (ev)->end, 0u, __VA_ARGS__);     \
+    else                                                                                                 \
+      hipLaunchKernelGGL(kernel, grid, block, smem, st, __VA_ARGS__);                                    \
+  } while (0)
 
 // Workspace of the two-pass column sweep: per-chunk partial sums.
 template <typename T>

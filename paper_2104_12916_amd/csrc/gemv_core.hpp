@@ -52,30 +52,26 @@ __device__ __forceinline__ float dot16<v4f_t, float>(const v4f_t& a, const float
 // Dot product of one matrix row (len elements, already rounded to whole
 // 64-lane x 16-byte chunks, zeros past the true length) with x staged in LDS.
 // Returns the full sum in every lane.
-template <typename T>
+template <typename T, int U = 4>
 __device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int lenR, int lane) {
   using V = typename Vec16<T>::type;
   constexpr int VE = Vec16<T>::n;
   constexpr int CH = kWave * VE;  // elements per wave-wide 16 B load
-  constexpr int U = 4;
-  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  T acc[4] = {0, 0, 0, 0};
   int j = lane * VE;
   const V* av = reinterpret_cast<const V*>(a);
   for (; j + (U - 1) * CH < lenR; j += U * CH) {
-    V v0 = __builtin_nontemporal_load(av + (j) / VE);
-    V v1 = __builtin_nontemporal_load(av + (j + CH) / VE);
-    V v2 = __builtin_nontemporal_load(av + (j + 2 * CH) / VE);
-    V v3 = __builtin_nontemporal_load(av + (j + 3 * CH) / VE);
-    acc0 += dot16<V, T>(v0, xs + j);
-    acc1 += dot16<V, T>(v1, xs + j + CH);
-    acc2 += dot16<V, T>(v2, xs + j + 2 * CH);
-    acc3 += dot16<V, T>(v3, xs + j + 3 * CH);
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(av + (j + u * CH) / VE);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u % 4] += dot16<V, T>(v[u], xs + j + u * CH);
   }
   for (; j < lenR; j += CH) {
     V v0 = __builtin_nontemporal_load(av + j / VE);
-    acc0 += dot16<V, T>(v0, xs + j);
+    acc[0] += dot16<V, T>(v0, xs + j);
   }
-  return wave_sum<T>((acc0 + acc1) + (acc2 + acc3));
+  return wave_sum<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 template <typename T>
@@ -96,7 +92,7 @@ __device__ __forceinline__ void stage_x(T* xs, const T* __restrict__ x, int len,
 // column tile starting at c0 (64 lanes x 16 B).  The four waves of the block
 // split the rows; the result for column c0 + jj is returned through LDS `red`.
 // Shape kLower skips rows that lie entirely above the diagonal of the tile.
-template <typename T>
+template <typename T, int U = 4>
 __device__ __forceinline__ void cols_block_partial(const T* __restrict__ A, int lda, int r0, int r1, int c0, int shape,
                                                    const T* __restrict__ x, T (*red)[kWave * Vec16<T>::n]) {
   using V = typename Vec16<T>::type;
@@ -106,7 +102,6 @@ __device__ __forceinline__ void cols_block_partial(const T* __restrict__ A, int 
 #pragma unroll
   for (int e = 0; e < VE; ++e) acc[e] = 0;
   const int j = c0 + lane * VE;
-  constexpr int U = 4;
   const int step = 4 * U;
   int i = r0 + wave * U;
   if (shape == kLower && r0 < c0) i += (c0 - r0) / step * step;
@@ -134,6 +129,44 @@ __device__ __forceinline__ void cols_block_partial(const T* __restrict__ A, int 
 #pragma unroll
   for (int e = 0; e < VE; ++e) red[wave][lane * VE + e] = acc[e];
   __syncthreads();
+}
+
+// Per-wave partial of y_j = sum_i A_ij x_i over rows [r0, r1) for the column
+// tile starting at c0 (64 lanes x 16 B), U rows in flight; the result is
+// returned in acc (each lane its 16 bytes of columns).  Shape kLower skips rows
+// above the diagonal of the tile.
+template <typename T, int U>
+__device__ __forceinline__ void cols_wave_partial(const T* __restrict__ A, int lda, int r0, int r1, int c0, int shape,
+                                                  const T* __restrict__ x, T* acc) {
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int e = 0; e < VE; ++e) acc[e] = 0;
+  const int j = c0 + lane * VE;
+  int i = r0;
+  if (shape == kLower && i < c0) i = c0;
+  for (; i < r1; i += U) {
+    V a[U];
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int ii = i + u;
+      if (ii < r1) {
+        a[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(A + (size_t)ii * lda + j));
+        xv[u] = x[ii];
+      } else {
+        xv[u] = 0;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) a[u][e] = 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[e] += a[u][e] * xv[u];
+    }
+  }
 }
 
 // Block-wide sum (and max) helpers for 256-thread blocks.

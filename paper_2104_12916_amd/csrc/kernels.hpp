@@ -14,7 +14,10 @@ hipError_t launch_gemv_cols(hipStream_t st, const T* A, int lda, int m, int k, i
                             T beta, const T* y0, const GemvWork<T>& w, const int* skip, int tag = 0,
                             const EventPair* ev = nullptr);
 template <typename T>
-void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks);
+void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& bw);
+template <typename T>
+int gemv_rows_grid(int m);
+size_t gemv_cols_part_elems(int max_ld);
 
 // blas.hip -----------------------------------------------------------------
 // Tile skip rules for GEMM operands with known zero blocks (indices in op()

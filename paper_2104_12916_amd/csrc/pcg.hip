@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kUpd) pcg_init_kernel(int m2, const T* __restr
 // --------------------------------------------------------------------------
 // q = C w + D p over rows of C (one wavefront per row, w staged in LDS), and
 // the workgroup's partial of p^T q.
-template <typename T>
+template <typename T, int U>
 __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int ldc, int m2, int n,
                                                     const T* __restrict__ w, const T* __restrict__ dvec,
                                                     const T* __restrict__ p, T* __restrict__ q,
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int
   stage_x<T>(ws, w, n, lenR);
   double pq = 0;
   for (int i = blockIdx.x * waves + wave; i < m2; i += gridDim.x * waves) {
-    T v = row_dot<T>(C + (size_t)i * ldc, ws, lenR, lane);
+    T v = row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane);
     if (lane == 0) {
       T pi = p[i];
       T qi = v + dvec[i] * pi;
@@ -201,9 +201,7 @@ hipError_t pcg_init(hipStream_t st, int m2, const T* b, const T* dvec, const T* 
 
 template <typename T>
 int pcg_q_grid(int m2) {
-  int blocks = (m2 + 3) / 4;
-  int cap = dev_info().cu_count * 2;
-  return blocks < cap ? blocks : cap;
+  return gemv_rows_grid<T>(m2);
 }
 
 template <typename T>
@@ -216,11 +214,13 @@ hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w,
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   const int grid = pcg_q_grid<T>(m2);
   if (grid > bpart_cap) return hipErrorInvalidValue;
-  if (ev) (void)hipEventRecord(ev->begin, st);
-  hipLaunchKernelGGL(pcg_q_kernel<T>, dim3(grid), dim3(256), smem, st, C, ldc, m2, n, w, dvec, p, q, sc, bpart);
-  hipError_t e = hipGetLastError();
-  if (ev) (void)hipEventRecord(ev->end, st);
-  return e;
+  if (tune().rows_unroll == 8)
+    QPG_LAUNCH((pcg_q_kernel<T, 8>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
+               bpart);
+  else
+    QPG_LAUNCH((pcg_q_kernel<T, 4>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
+               bpart);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -1,0 +1,52 @@
+"""Kernel-level timing run for profilers (rocprofv3 --kernel-trace / --pmc).
+
+Sets up one workload instance, factorizes it, then launches each CG-step sweep
+`reps` times through qp_op_time (same kernels and launch shapes as inside the
+solver) and, for counter calibration, one plain device-to-device copy of a known
+size.  Prints the event-timed averages.
+
+Usage: python -m paper_2104_12916_amd.profile_ops [--workload lowdof] [--reps 10]
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+COPY_BYTES = 256 << 20
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="lowdof")
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    args = ap.parse_args()
+
+    import torch
+    import synth
+    from paper_2104_12916_amd import qpgpu
+
+    torch.cuda.set_device(0)
+    qp = synth.workload(args.workload, seed=args.seed)
+    mixed = args.precision == "mixed"
+    s = qpgpu.Solver(*qp.arrays(), prec=qpgpu.QP_PREC_LOW_DOF,
+                     precision=qpgpu.QP_MIXED if mixed else qpgpu.QP_FP64)
+    s.factor()
+    # calibration copy: COPY_BYTES read and COPY_BYTES written by one elementwise kernel
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copy kernel: {COPY_BYTES} bytes read, {COPY_BYTES} bytes written", flush=True)
+    names = ["C^T p", "Sigma M u", "M^T v", "C w", "CG step"]
+    for op in range(5):
+        ms = s.op_time(op, qpgpu.QP_MIXED if mixed else qpgpu.QP_FP64, args.reps)
+        print(f"op {op} ({names[op]}): {ms * 1e3:.2f} us per launch", flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()
