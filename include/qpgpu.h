@@ -104,8 +104,9 @@ typedef struct {
   double obj;              /* 1/2 x^T H x + c^T x                                  */
   double mu;               /* s^T nu / m2 at the returned point                    */
   int status;
-  int refinements_total;
-  double t_solve_ms;       /* wall time of qp_ipm_solve on the device stream      */
+  int refinements_total;   /* float64 refinement sweeps over all reduced solves   */
+  int fp64_fallbacks;      /* mixed reduced solves finished by float64 CG          */
+  double t_solve_ms;       /* wall time of qp_ipm_solve (host clock)              */
 } qp_ipm_info;
 
 /* Defaults listed in the field comments above. */

@@ -75,7 +75,7 @@ struct qp_ctx {
   // PCG vectors (float64)
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *pt = nullptr;
   double *pu = nullptr, *pv = nullptr, *pw = nullptr;
-  double *ir_r = nullptr, *ir_x = nullptr;  // refinement residual / correction
+  double *ir_r = nullptr, *ir_x = nullptr, *ir_d = nullptr;  // refinement residual, K_F dnu, correction
   // PCG vectors (float32)
   float *fr = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr, *ft = nullptr, *fx = nullptr, *fb = nullptr;
   float *fu = nullptr, *fv = nullptr, *fw = nullptr, *fd = nullptr, *fwts = nullptr;
@@ -410,30 +410,39 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
 // Reduced solve used by both qp_pcg_solve and the IPM.  dvec, rhs, dnu, wts are
 // device float64 vectors.  Returns CG steps; sets *done to the PCG stop code.
 int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, double* dnu, const double* wts,
-                  double rtol, double wtol, int maxit, int* done, int* refinements) {
+                  double rtol, double wtol, int maxit, int* done, int* refinements, int* fallback) {
   *refinements = 0;
+  *fallback = 0;
   if (ctx->opt.precision != QP_MIXED) {
     PcgBufs<double> B = bufs64(ctx, dvec, wts, dnu);
     PcgResult r = run_pcg<double>(ctx, B, rhs, prec, rtol, wtol, maxit);
     *done = r.done;
     return r.iters;
   }
-  // Mixed: float32 PCG on the residual equation inside float64 refinement.
+  // Mixed: float32 PCG sweeps on the residual equation K_F delta = r inside a
+  // float64 refinement loop (r = rhs - K_F dnu recomputed with the float64
+  // operator).  When a sweep does not converge within its cap or fails to
+  // shrink ||r||_2 tenfold (the float32 recurrence stalls on ill-conditioned
+  // systems) the remaining correction is solved by float64 PCG, which also sees
+  // the total residual, so the stop tests are the same as in the float64 path.
   hipStream_t st = ctx->stream;
   const int m2 = ctx->m2;
+  const int bound = prec == kPrecL ? std::min(m2, ctx->n - ctx->m1) : (prec == kPrecH ? std::min(m2, ctx->m1) : m2);
+  const int inner_cap = std::max(200, 2 * (bound + 1));
+  const double inner_rtol = 1e-5;
   int total = 0;
   HIPCHK(ctx, (convert_1d<double, float>(st, dvec, ctx->fd, m2)));
   if (wts) HIPCHK(ctx, (convert_1d<double, float>(st, wts, ctx->fwts, m2)));
-  HIPCHK(ctx, hipMemsetAsync(dnu, 0, (size_t)m2 * sizeof(double), st));
+  HIPCHK(ctx, fill_vec<double>(st, m2, 0.0, dnu));
   HIPCHK(ctx, hipMemcpyAsync(ctx->ir_r, rhs, (size_t)m2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  const double inner_rtol = 1e-5;
   int sweeps = 0;
+  double prev_rr = -1.0;
   *done = 2;
-  for (; sweeps < 30; ++sweeps) {
+  for (; sweeps < 30 && total < maxit; ++sweeps) {
     HIPCHK(ctx, (convert_1d<double, float>(st, ctx->ir_r, ctx->fb, m2)));
     PcgBufs<float> B = bufs32(ctx);
     B.wts = wts ? ctx->fwts : nullptr;
-    PcgResult r = run_pcg<float>(ctx, B, ctx->fb, prec, inner_rtol, -1.0, maxit - total > 0 ? maxit - total : 1);
+    PcgResult r = run_pcg<float>(ctx, B, ctx->fb, prec, inner_rtol, -1.0, std::min(inner_cap, maxit - total));
     total += r.iters;
     HIPCHK(ctx, ir_accumulate(st, m2, ctx->fx, dnu));
     // float64 residual r = rhs - K_F dnu, with its stop statistics
@@ -441,18 +450,27 @@ int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, 
     HIPCHK(ctx, ir_residual(st, m2, rhs, ctx->ir_x, wts, ctx->ir_r, ctx->sc));
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_sc, ctx->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
     sync(ctx);
-    const PcgScalars& h = *ctx->h_sc;
-    bool ok = (h.rr <= rtol * rtol * h.bb) || (wtol >= 0.0 && h.wmax <= wtol) || h.bb == 0.0;
-    if (ok) {
+    const PcgScalars h = *ctx->h_sc;
+    if (h.bb == 0.0 || h.rr <= rtol * rtol * h.bb || (wtol >= 0.0 && h.wmax <= wtol)) {
       *done = 1;
       ++sweeps;
       break;
     }
-    if (total >= maxit) {
-      *done = 2;
+    const double ref_rr = prev_rr >= 0.0 ? prev_rr : h.bb;
+    const bool stalled = r.done != 1 || h.rr > 1e-2 * ref_rr || !std::isfinite(h.rr);
+    if (stalled && total < maxit) {
+      // float64 PCG on the remaining correction, zero start, same stop tests
+      PcgBufs<double> B64 = bufs64(ctx, dvec, wts, ctx->ir_d);
+      const double rtol64 = h.rr > 0.0 ? rtol * std::sqrt(h.bb / h.rr) : rtol;
+      PcgResult r64 = run_pcg<double>(ctx, B64, ctx->ir_r, prec, rtol64, wtol, maxit - total);
+      total += r64.iters;
+      HIPCHK(ctx, vec_add(st, m2, ctx->ir_d, dnu));
+      *done = r64.done;
+      *fallback = 1;
       ++sweeps;
       break;
     }
+    prev_rr = h.rr;
   }
   *refinements = sweeps;
   return total;
@@ -526,6 +544,7 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
   HIPCHK(ctx, hipMemcpyAsync(ctx->isc, &hs, sizeof(IpmScalars), hipMemcpyHostToDevice, st));
   long long cg_total = 0;
   int refin_total = 0;
+  int fallbacks = 0;
   int it = 0;
   double parts[5] = {0, 0, 0, 0, 0};
   double score = 0;
@@ -555,10 +574,11 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
                         ctx->dvec));
     if (prec == kPrecH) ph_factor(ctx, ctx->dvec);
     const double wtol = ctx->opt.cg_theta * mu;
-    int done = 0, refin = 0;
+    int done = 0, refin = 0, fb = 0;
     int k1 = reduced_solve(ctx, prec, ctx->dvec, ctx->rhs, ctx->dnu_a, ctx->nu, ctx->opt.cg_rtol, wtol, maxit, &done,
-                           &refin);
+                           &refin, &fb);
     refin_total += refin;
+    fallbacks += fb;
     recover(ctx, ctx->dnu_a, ctx->dx_a, ctx->dlam_a, ctx->ds_a);
     HIPCHK(ctx, ipm_step(st, n, m1, m2, 0, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx_a, ctx->dlam_a, ctx->dnu_a,
                          ctx->ds_a, ctx->isc));
@@ -566,8 +586,9 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
     HIPCHK(ctx, ipm_rhs(st, m2, 1, ctx->ri, ctx->s, ctx->nu, ctx->Cw, ctx->ds_a, ctx->dnu_a, ctx->isc, ctx->rc,
                         ctx->rhs, ctx->dvec));
     int k2 = reduced_solve(ctx, prec, ctx->dvec, ctx->rhs, ctx->dnu, ctx->nu, ctx->opt.cg_rtol, wtol, maxit, &done,
-                           &refin);
+                           &refin, &fb);
     refin_total += refin;
+    fallbacks += fb;
     recover(ctx, ctx->dnu, ctx->dx, ctx->dlam, ctx->ds);
     HIPCHK(ctx, ipm_step(st, n, m1, m2, 1, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx, ctx->dlam, ctx->dnu, ctx->ds,
                          ctx->isc));
@@ -576,8 +597,8 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
     if (ctx->opt.verbose) {
       HIPCHK(ctx, hipMemcpyAsync(ctx->h_isc, ctx->isc, sizeof(IpmScalars), hipMemcpyDeviceToHost, st));
       sync(ctx);
-      fprintf(stderr, "[qpgpu] it %3d mu %.3e sigma %.2e alpha %.4f cg %d+%d rel_kkt %.3e\n", it, mu,
-              ctx->h_isc->sigma, ctx->h_isc->alpha, k1, k2, score);
+      fprintf(stderr, "[qpgpu] it %3d mu %.3e sigma %.2e alpha %.4f cg %d+%d rel_kkt %.3e fallbacks %d\n", it, mu,
+              ctx->h_isc->sigma, ctx->h_isc->alpha, k1, k2, score, fallbacks);
     }
   }
   if (info) {
@@ -589,6 +610,7 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
     info->mu = ctx->h_stats[kSNu] / m2;
     info->status = status;
     info->refinements_total = refin_total;
+    info->fp64_fallbacks = fallbacks;
   }
   if (status != QP_OK && ctx->err.empty()) set_err(ctx, "IPM stopped at rel_kkt %.3e after %d iterations", score, it);
   if (status != QP_OK) throw Fail{(qp_status)status};
@@ -608,7 +630,7 @@ void alloc_all(qp_ctx* ctx) {
   for (double** v : {&ctx->lam, &ctx->Ax, &ctx->re, &ctx->dlam, &ctx->dlam_a}) *v = dalloc<double>(ctx, m1);
   for (double** v : {&ctx->nu, &ctx->s, &ctx->Cx, &ctx->ri, &ctx->dvec, &ctx->rc, &ctx->rhs, &ctx->Cw, &ctx->dnu,
                      &ctx->ds, &ctx->dnu_a, &ctx->ds_a, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pq, &ctx->pt, &ctx->ir_r,
-                     &ctx->ir_x})
+                     &ctx->ir_x, &ctx->ir_d})
     *v = dalloc<double>(ctx, m2);
   for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) *v = dalloc<double>(ctx, N);
   // gemv_cols partial workspace: chunks * ld with chunks <= 4 * CUs / tiles
@@ -873,8 +895,8 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
       }
     }
     int mi = maxit > 0 ? maxit : 10 * m2;
-    int done = 0, refin = 0;
-    int iters = reduced_solve(ctx, mode, ctx->dvec, ctx->rhs, ctx->dnu, nullptr, rtol, -1.0, mi, &done, &refin);
+    int done = 0, refin = 0, fb = 0;
+    int iters = reduced_solve(ctx, mode, ctx->dvec, ctx->rhs, ctx->dnu, nullptr, rtol, -1.0, mi, &done, &refin, &fb);
     // true residual in float64
     kf_apply_dev(ctx, ctx->dvec, ctx->dnu, ctx->ir_x);
     HIPCHK(ctx, ir_residual(ctx->stream, m2, ctx->rhs, ctx->ir_x, nullptr, ctx->ir_r, ctx->sc));
@@ -886,7 +908,7 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
       info->iters = iters;
       info->rel_res = rel;
       info->refinements = refin;
-      info->fp64_fallback = 0;
+      info->fp64_fallback = fb;
     }
     code = done;
     if (done == 3) {

@@ -263,6 +263,17 @@ __global__ void ir_accumulate_kernel(int m, const float* __restrict__ fx, double
   if (i < m) x[i] += (double)fx[i];
 }
 
+__global__ void vec_add_kernel(int m, const double* __restrict__ a, double* __restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) y[i] += a[i];
+}
+
+hipError_t vec_add(hipStream_t st, int m, const double* a, double* y) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_add_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, a, y);
+  return hipGetLastError();
+}
+
 hipError_t ir_accumulate(hipStream_t st, int m, const float* fx, double* x) {
   hipLaunchKernelGGL(ir_accumulate_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, fx, x);
   return hipGetLastError();

@@ -61,6 +61,7 @@ hipError_t ipm_init_point(hipStream_t st, int n, int m1, int m2, const double* s
                           const double* d, double* x, double* lam, double* nu, double* s);
 hipError_t ew_mul(hipStream_t st, int m, const double* a, const double* b, double* out);
 hipError_t ir_accumulate(hipStream_t st, int m, const float* fx, double* x);
+hipError_t vec_add(hipStream_t st, int m, const double* a, double* y);
 hipError_t ir_residual(hipStream_t st, int m, const double* rhs, const double* Kx, const double* w, double* r,
                        PcgScalars* sc);
 hipError_t add_diag_copy(hipStream_t st, int m, const double* T, int ldt, const double* dvec, double* P, int ldp);

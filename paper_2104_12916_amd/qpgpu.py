@@ -48,7 +48,8 @@ class qp_ipm_info(ct.Structure):
     _fields_ = [
         ("ipm_iters", ct.c_int), ("pcg_iters_total", ct.c_longlong), ("rel_kkt", ct.c_double),
         ("rel_kkt_parts", ct.c_double * 5), ("obj", ct.c_double), ("mu", ct.c_double),
-        ("status", ct.c_int), ("refinements_total", ct.c_int), ("t_solve_ms", ct.c_double),
+        ("status", ct.c_int), ("refinements_total", ct.c_int), ("fp64_fallbacks", ct.c_int),
+        ("t_solve_ms", ct.c_double),
     ]
 
 

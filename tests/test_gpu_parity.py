@@ -197,3 +197,34 @@ def test_device_pointer_path(gpu):
     ref = reduced.k0_solve(qp, rhs.cpu().numpy())
     assert relerr(out.cpu().numpy(), ref) <= 1e-10
     s.close()
+
+
+# --- mixed precision (float32 CG inside float64 refinement) ------------------
+@pytest.mark.parametrize("prec", [PL, PH])
+@pytest.mark.parametrize("n,m1,m2", [(70, 30, 40), (200, 50, 100), (300, 130, 170)])
+def test_mixed_pcg_matches_direct_reduced_solve(gpu, prec, n, m1, m2):
+    qp = synth.gaussian_qp(5000 + n, n, m1, m2)
+    s = make(qp, precision=qpgpu.QP_MIXED)
+    s.factor()
+    dvec = synth.log_uniform(9, m2, 1e-2, 1e2)
+    rhs = np.random.default_rng(3).standard_normal(m2)
+    dnu, info = s.pcg(dvec, rhs, prec=prec, rtol=1e-10)
+    ref = sla.cho_solve(sla.cho_factor(reduced.kf_explicit(qp, dvec)), rhs)
+    # the refinement drives the float64 residual to rtol; cond(K_F) <= ~1e4 here
+    assert info.rel_res <= 1e-10
+    assert relerr(dnu, ref) <= 1e-6
+    assert info.refinements >= 1
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [PL, PH])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_mixed_ipm_small_workload_matches_oracle(gpu, seed, prec):
+    qp = synth.gaussian_qp(seed, 200, 50, 100)
+    ref = ipm.solve(qp)
+    s = make(qp, prec=prec, precision=qpgpu.QP_MIXED)
+    s.factor()
+    x, lam, nu, sl, info = s.ipm()
+    _check_ipm(qp, x, lam, nu, ref.obj)
+    assert info.refinements_total >= 2 * info.ipm_iters
+    s.close()
