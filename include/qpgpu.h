@@ -186,6 +186,70 @@ const char* qp_status_str(qp_status st);
 /* Message of the last failure on this context ("" if none; never NULL). */
 const char* qp_last_error(const qp_ctx* ctx);
 
+/* ---- Batches of independent QPs ------------------------------------------
+ * A batch keeps many QPs of different sizes in flight on one stream and runs
+ * the interior point method of qp_ipm_solve for all of them, one iteration of
+ * every QP per round.  The CG steps of all reduced solves of a round (eq.
+ * ineq-const-reduced, one per QP, predictor and corrector) run together: one
+ * launch per operator sweep covers every QP still iterating.  A QP's arithmetic
+ * and launch shapes depend only on that QP, so its result does not depend on
+ * the other QPs of the batch.  Preconditioner and precision come from the
+ * batch options (QP_PREC_AUTO resolves per QP).
+ *
+ * Memory: the batch takes one device allocation of hbm_budget_bytes at
+ * creation (0: 80% of the free device memory) and gives every admitted QP its
+ * buffers from it; a QP's memory returns as soon as it finishes.  Admission is
+ * refused with QP_E_NOMEM while the QP does not fit (qp_batch_footprint tells
+ * its size), or when 4096 QPs are in flight.
+ *
+ * Flow: qp_batch_admit (any time between steps) -> qp_batch_step (factors the
+ * new QPs at the start of a round, then advances every QP one iteration per
+ * round) -> qp_batch_finished lists finished tickets -> qp_batch_collect copies
+ * a result out and forgets the ticket.  Calls on one batch must not overlap. */
+typedef struct qp_batch qp_batch;
+
+/* Create a batch.  opt: NULL for defaults; hip_stream: hipStream_t or NULL for
+ * a stream owned by the batch. */
+qp_status qp_batch_create(qp_batch** out, const qp_options* opt, size_t hbm_budget_bytes, void* hip_stream);
+
+/* Admit one QP (arguments as for qp_setup) and receive its ticket (> 0).  The
+ * data is copied to the device before the call returns.  QP_E_NOMEM: no room
+ * now, retry after qp_batch_step has retired QPs; QP_E_INVALID: bad problem. */
+qp_status qp_batch_admit(qp_batch* b, int n, int m1, int m2, const double* H, const double* c, const double* A,
+                         const double* b_eq, const double* C, const double* d, qp_mem where, long long* ticket);
+
+/* Run up to max_rounds rounds (fewer when nothing is in flight).  n_done (may
+ * be NULL) receives the number of finished, uncollected QPs.  A QP that fails
+ * (H not SPD, A rank deficient, no convergence) finishes with that status and
+ * does not affect the others; a device error fails the call. */
+qp_status qp_batch_step(qp_batch* b, int max_rounds, int* n_done);
+
+/* Tickets of finished, uncollected QPs in increasing order (at most cap). */
+qp_status qp_batch_finished(qp_batch* b, long long* tickets, int cap, int* count);
+
+/* Copy the final iterate of a finished QP: x (n), lambda (m1), nu (m2), s (m2),
+ * host or device memory per `where`; info (may be NULL) as for qp_ipm_solve,
+ * with t_solve_ms measured from admission to completion.  Returns the QP's own
+ * status (QP_OK, QP_E_NOCONV, QP_E_NOT_SPD, ...); QP_E_STATE if the ticket has
+ * not finished, QP_E_INVALID if it is unknown.  The ticket is then forgotten
+ * (outputs are left untouched when the QP failed before its first iterate). */
+qp_status qp_batch_collect(qp_batch* b, long long ticket, double* x, double* lambda, double* nu, double* s,
+                           qp_mem where, qp_ipm_info* info);
+
+/* Counters: QPs admitted and not finished, finished and not collected, arena
+ * bytes in use and in total, rounds run.  Any pointer may be NULL. */
+qp_status qp_batch_query(const qp_batch* b, int* in_flight, int* finished, size_t* bytes_used,
+                         size_t* bytes_capacity, long long* rounds);
+
+/* Arena bytes a QP of these sizes takes under these options (0 if invalid). */
+size_t qp_batch_footprint(const qp_options* opt, int n, int m1, int m2);
+
+/* Message of the last batch-level failure ("" if none; never NULL). */
+const char* qp_batch_last_error(const qp_batch* b);
+
+/* Free the batch, its arena and every result not collected.  NULL accepted. */
+void qp_batch_destroy(qp_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

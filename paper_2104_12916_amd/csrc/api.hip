@@ -1,19 +1,16 @@
-// C ABI of the library: the per-QP context (device buffers, stream, factor),
-// the PCG driver and the interior point driver.  Every arithmetic step runs in
-// the kernels of gemv.hip, blas.hip, pcg.hip and ipm.hip; this file only orders
-// launches, polls convergence flags and copies small scalar records.
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
+// C ABI of the library for one QP: the per-QP context (device buffers, stream,
+// factor), the PCG driver and the interior point driver.  Every arithmetic step
+// runs in the kernels of gemv.hip, blas.hip, pcg.hip and ipm.hip; this file
+// only orders launches, polls convergence flags and copies small scalar
+// records.  The interior point method is split into phases (ctx.hpp) that the
+// batch driver (batch.hip) runs for many QPs between batched CG solves.
 #include <chrono>
+#include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
-#include "../../include/qpgpu.h"
-#include "kernels.hpp"
-#include "pcg.hpp"
+#include "ctx.hpp"
 
 namespace qpg {
 
@@ -32,80 +29,78 @@ DevInfo& dev_info() {
   return info;
 }
 
-// Leading dimension of a matrix with `cols` columns: whole 256-element rows
-// (every sweep reads full 64-lane x 16-byte chunks) plus tune().ld_pad.
-static int ld_for(int cols) { return ((cols > 0 ? cols : 1) + 255) / 256 * 256 + tune().ld_pad; }
+// ---- Arena ------------------------------------------------------------------
+static constexpr size_t kGranule = 256;
 
-}  // namespace qpg
+hipError_t Arena::init(size_t bytes) {
+  bytes = (bytes + kGranule - 1) / kGranule * kGranule;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return e;
+  base_ = static_cast<char*>(p);
+  cap_ = bytes;
+  used_bytes_ = 0;
+  free_.clear();
+  live_.clear();
+  free_[0] = bytes;
+  return hipSuccess;
+}
 
-using namespace qpg;
+void Arena::release() {
+  if (base_) (void)hipFree(base_);
+  base_ = nullptr;
+  cap_ = used_bytes_ = 0;
+  free_.clear();
+  live_.clear();
+}
 
-constexpr int kProfOps = 6;
+void* Arena::alloc(size_t bytes) {
+  bytes = ((bytes ? bytes : 1) + kGranule - 1) / kGranule * kGranule;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, sz = it->second;
+    free_.erase(it);
+    if (sz > bytes) free_[off + bytes] = sz - bytes;
+    live_[off] = bytes;
+    used_bytes_ += bytes;
+    return base_ + off;
+  }
+  return nullptr;
+}
 
-struct qp_ctx {
-  int dev = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int n = 0, m1 = 0, m2 = 0, N = 0;
-  int ldn = 0, ldN = 0, ldm2 = 0, ldm1 = 0;
-  qp_options opt{};
-  std::string err;
-  size_t bytes = 0;
-  std::vector<void*> allocs;
+void Arena::free(void* p) {
+  if (!p) return;
+  const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
+  auto lv = live_.find(off);
+  if (lv == live_.end()) return;
+  size_t sz = lv->second;
+  live_.erase(lv);
+  used_bytes_ -= sz;
+  size_t start = off;
+  auto next = free_.lower_bound(off);
+  if (next != free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      start = prev->first;
+      sz += prev->second;
+      free_.erase(prev);
+    }
+  }
+  next = free_.lower_bound(start);
+  if (next != free_.end() && start + sz == next->first) {
+    sz += next->second;
+    free_.erase(next);
+  }
+  free_[start] = sz;
+}
 
-  // problem data (float64)
-  double *H = nullptr, *c = nullptr, *A = nullptr, *b = nullptr, *C = nullptr, *d = nullptr;
-  // inverse factor L^{-1} of K0 = L Sigma L^T (N x ldN, lower, explicit zeros above)
-  double* Linv = nullptr;
-  bool factored = false;
-  // P_H data: T = C H^{-1} C^T (fixed), P = D + T and X_P = chol(P)^{-1} (per D)
-  double *T = nullptr, *P = nullptr, *XP = nullptr, *ptmp = nullptr;
-  bool ph_ready = false;
-  // float32 copies for the mixed path
-  float *Linv32 = nullptr, *C32 = nullptr, *XP32 = nullptr;
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (const auto& kv : free_) m = kv.second > m ? kv.second : m;
+  return m;
+}
 
-  // vectors (float64)
-  double *x = nullptr, *lam = nullptr, *nu = nullptr, *s = nullptr;
-  double *Hx = nullptr, *Atl = nullptr, *Ctn = nullptr, *Ax = nullptr, *Cx = nullptr;
-  double *rg = nullptr, *re = nullptr, *ri = nullptr;
-  double *dvec = nullptr, *rc = nullptr, *rhs = nullptr, *Cw = nullptr;
-  double *vN1 = nullptr, *vN2 = nullptr, *vN3 = nullptr;  // N-long scratch
-  double *dx = nullptr, *dlam = nullptr, *dnu = nullptr, *ds = nullptr;
-  double *dx_a = nullptr, *dlam_a = nullptr, *dnu_a = nullptr, *ds_a = nullptr;
-  // PCG vectors (float64)
-  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *pt = nullptr;
-  double *pu = nullptr, *pv = nullptr, *pw = nullptr;
-  double *ir_r = nullptr, *ir_x = nullptr, *ir_d = nullptr;  // refinement residual, K_F dnu, correction
-  // PCG vectors (float32)
-  float *fr = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr, *ft = nullptr, *fx = nullptr, *fb = nullptr;
-  float *fu = nullptr, *fv = nullptr, *fw = nullptr, *fd = nullptr, *fwts = nullptr;
-  // workspaces
-  GemvWork<double> w64{};
-  GemvWork<float> w32{};
-  double* bpart = nullptr;  // per-workgroup partials of p^T q
-  int bpart_cap = 0;
-  PcgScalars* sc = nullptr;
-  IpmScalars* isc = nullptr;
-  double* stats = nullptr;
-  int* info = nullptr;
-  // sampled kernel durations (options.profile): CG-step sweeps in the order
-  // C^T p, Sigma M u, M^T v, q = C w + D p, X_P r, X_P^T t
-  EventPair prof_ev[kProfOps] = {};
-  double prof_ms[kProfOps] = {};
-  long long prof_n[kProfOps] = {};
-  bool prof_ready = false;
-  // pinned host mirrors
-  PcgScalars* h_sc = nullptr;
-  IpmScalars* h_isc = nullptr;
-  double* h_stats = nullptr;
-  int* h_info = nullptr;
-};
-
-namespace {
-
-struct Fail {
-  qp_status st;
-};
+namespace detail {
 
 void set_err(qp_ctx* ctx, const char* fmt, ...) {
   char buf[512];
@@ -116,26 +111,38 @@ void set_err(qp_ctx* ctx, const char* fmt, ...) {
   if (ctx) ctx->err = buf;
 }
 
-#define HIPCHK(ctx, expr)                                                                                   \
-  do {                                                                                                      \
-    hipError_t e_ = (expr);                                                                                 \
-    if (e_ != hipSuccess) {                                                                                 \
-      set_err(ctx, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__);              \
-      throw Fail{e_ == hipErrorOutOfMemory ? QP_E_NOMEM : QP_E_DEVICE};                                      \
-    }                                                                                                       \
-  } while (0)
+void set_err_str(std::string& dst, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  dst = buf;
+}
 
-template <typename T>
-T* dalloc(qp_ctx* ctx, size_t elems) {
-  if (elems == 0) elems = 1;
+// Leading dimension of a matrix with `cols` columns: whole 256-element rows
+// (every sweep reads full 64-lane x 16-byte chunks) plus tune().ld_pad.
+int ld_for(int cols) { return ((cols > 0 ? cols : 1) + 255) / 256 * 256 + tune().ld_pad; }
+
+static size_t round_bytes(size_t bytes) { return ((bytes ? bytes : 1) + kGranule - 1) / kGranule * kGranule; }
+
+void* dalloc_bytes(qp_ctx* ctx, size_t bytes) {
+  bytes = round_bytes(bytes);
   void* p = nullptr;
-  size_t bytes = elems * sizeof(T);
-  bytes = (bytes + 255) / 256 * 256;
-  HIPCHK(ctx, hipMalloc(&p, bytes));
+  if (ctx->arena) {
+    p = ctx->arena->alloc(bytes);
+    if (!p) {
+      set_err(ctx, "batch memory budget exhausted (%zu bytes requested, largest free range %zu)", bytes,
+              ctx->arena->largest_free());
+      throw Fail{QP_E_NOMEM};
+    }
+  } else {
+    HIPCHK(ctx, hipMalloc(&p, bytes));
+  }
   HIPCHK(ctx, hipMemsetAsync(p, 0, bytes, ctx->stream));
   ctx->allocs.push_back(p);
   ctx->bytes += bytes;
-  return static_cast<T*>(p);
+  return p;
 }
 
 void dfree(qp_ctx* ctx, void* p) {
@@ -145,7 +152,20 @@ void dfree(qp_ctx* ctx, void* p) {
       ctx->allocs.erase(ctx->allocs.begin() + i);
       break;
     }
-  (void)hipFree(p);
+  if (ctx->arena)
+    ctx->arena->free(p);
+  else
+    (void)hipFree(p);
+}
+
+void free_all(qp_ctx* ctx) {
+  for (void* p : ctx->allocs) {
+    if (ctx->arena)
+      ctx->arena->free(p);
+    else
+      (void)hipFree(p);
+  }
+  ctx->allocs.clear();
 }
 
 // Copy a dense rows x cols row-major caller matrix (ld = cols) into a padded
@@ -177,15 +197,200 @@ bool finite_all(const double* v, size_t n) {
   return true;
 }
 
-qp_precond resolve_prec(const qp_ctx* ctx, qp_precond p) {
+qp_status check_problem(int n, int m1, int m2, const double* H, const double* c, const double* A, const double* b,
+                        const double* C, const double* d, qp_mem where) {
+  if (n <= 0 || m1 <= 0 || m1 > n || m2 <= 0) return QP_E_INVALID;
+  if (!H || !c || !A || !b || !C || !d) return QP_E_INVALID;
+  if (where != QP_MEM_HOST && where != QP_MEM_DEVICE) return QP_E_INVALID;
+  if ((long long)(n + m1) * (n + m1) > (1LL << 31) || (long long)m2 * m2 > (1LL << 31)) return QP_E_INVALID;
+  if (where == QP_MEM_HOST) {
+    // finiteness and symmetry checks on the caller's host arrays
+    if (!finite_all(H, (size_t)n * n) || !finite_all(c, n) || !finite_all(A, (size_t)m1 * n) ||
+        !finite_all(b, m1) || !finite_all(C, (size_t)m2 * n) || !finite_all(d, m2))
+      return QP_E_INVALID;
+    double fro = 0, asym = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double h = H[(size_t)i * n + j];
+        double t = h - H[(size_t)j * n + i];
+        fro += h * h;
+        asym += t * t;
+      }
+    if (std::sqrt(asym) > 1e-14 * std::max(1.0, std::sqrt(fro))) return QP_E_INVALID;
+  }
+  return QP_OK;
+}
+
+qp_status check_options(const qp_options& o) {
+  if (!(o.tau > 0 && o.tau < 1) || o.max_ipm < 0 || !(o.rtol_kkt > 0) || o.prec < QP_PREC_NONE ||
+      o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED))
+    return QP_E_INVALID;
+  return QP_OK;
+}
+
+static qp_precond resolve_prec_dims(int n, int m1, int m2, qp_precond p) {
   if (p != QP_PREC_AUTO) return p;
-  int bl = std::min(ctx->m2, ctx->n - ctx->m1);
-  int bh = std::min(ctx->m2, ctx->m1);
+  int bl = std::min(m2, n - m1);
+  int bh = std::min(m2, m1);
   return bl <= bh ? QP_PREC_LOW_DOF : QP_PREC_FEW_EQ;
 }
 
+qp_precond resolve_prec(const qp_ctx* ctx, qp_precond p) { return resolve_prec_dims(ctx->n, ctx->m1, ctx->m2, p); }
+
 int prec_mode(qp_precond p) {
   return p == QP_PREC_LOW_DOF ? kPrecL : (p == QP_PREC_FEW_EQ ? kPrecH : kPrecNone);
+}
+
+void init_dims(qp_ctx* ctx, int n, int m1, int m2, const qp_options& o) {
+  ctx->n = n;
+  ctx->m1 = m1;
+  ctx->m2 = m2;
+  ctx->N = n + m1;
+  ctx->ldn = ld_for(n);
+  ctx->ldN = ld_for(n + m1);
+  ctx->ldm2 = ld_for(m2);
+  ctx->ldm1 = ld_for(m1);
+  ctx->opt = o;
+}
+
+// ---- buffer layout ------------------------------------------------------------
+// One description of every device buffer, walked either to allocate or to add
+// up the footprint.  Pooled (batch) contexts get exact column-sweep workspaces
+// and P_H / float32 buffers only when their options use them; a stand-alone
+// context keeps the P_H buffers because qp_pcg_solve may ask for P_H whatever
+// the options say.
+template <typename Get>
+static void layout_buffers(qp_ctx* ctx, Get&& get) {
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2, N = ctx->N;
+  auto D = [&](double*& p, size_t elems) { p = static_cast<double*>(get(elems * sizeof(double))); };
+  auto F = [&](float*& p, size_t elems) { p = static_cast<float*>(get(elems * sizeof(float))); };
+  D(ctx->H, (size_t)n * ctx->ldn);
+  D(ctx->c, n);
+  D(ctx->A, (size_t)m1 * ctx->ldn);
+  D(ctx->b, m1);
+  D(ctx->C, (size_t)m2 * ctx->ldn);
+  D(ctx->d, m2);
+  D(ctx->Linv, (size_t)N * ctx->ldN);
+  for (double** v : {&ctx->x, &ctx->Hx, &ctx->Atl, &ctx->Ctn, &ctx->rg, &ctx->dx, &ctx->dx_a, &ctx->pu, &ctx->pw})
+    D(*v, n);
+  for (double** v : {&ctx->lam, &ctx->Ax, &ctx->re, &ctx->dlam, &ctx->dlam_a}) D(*v, m1);
+  for (double** v : {&ctx->nu, &ctx->s, &ctx->Cx, &ctx->ri, &ctx->dvec, &ctx->rc, &ctx->rhs, &ctx->Cw, &ctx->dnu,
+                     &ctx->ds, &ctx->dnu_a, &ctx->ds_a, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pq, &ctx->pt, &ctx->ir_r,
+                     &ctx->ir_x, &ctx->ir_d})
+    D(*v, m2);
+  for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) D(*v, N);
+  const bool mixed = ctx->opt.precision == QP_MIXED;
+  const bool need_ph = !ctx->pooled || resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ;
+  size_t part64, part32;
+  if (!ctx->pooled) {
+    int maxld = std::max(std::max(ctx->ldn, ctx->ldN), ctx->ldm2);
+    part64 = part32 = gemv_cols_part_elems(maxld);
+    ctx->bpart_cap = kMaxRowsBpc * dev_info().cu_count + 64;
+  } else {
+    // every column sweep a pooled context launches: C, A, L^{-1} (k0 solve and
+    // M^T v) and X_P, in the single-launch and in the batched shape
+    auto need = [&](auto tag) {
+      using T = decltype(tag);
+      const int shapes[5][2] = {{m2, n}, {m1, n}, {N, N}, {N, n}, {m2, m2}};
+      size_t mx = 0;
+      for (int k = 0; k < 5; ++k) {
+        if (k == 4 && !need_ph) continue;
+        mx = std::max(mx, gemv_cols_need<T>(shapes[k][0], shapes[k][1]));
+        mx = std::max(mx, bgemv_cols_need<T>(shapes[k][0], shapes[k][1]));
+      }
+      return mx;
+    };
+    part64 = need(double(0));
+    part32 = need(float(0));
+    ctx->bpart_cap = std::max(std::max(pcg_q_grid<double>(m2), pcg_q_grid<float>(m2)), bpcg_q_blocks(m2));
+  }
+  D(ctx->w64.part, part64);
+  ctx->w64.part_elems = part64;
+  D(ctx->bpart, ctx->bpart_cap);
+  ctx->isc = static_cast<IpmScalars*>(get(sizeof(IpmScalars)));
+  if (!ctx->pooled) {
+    ctx->sc = static_cast<PcgScalars*>(get(sizeof(PcgScalars)));
+    D(ctx->stats, kStatsStride);
+    ctx->info = static_cast<int*>(get(16 * sizeof(int)));
+  }
+  if (need_ph) {
+    D(ctx->T, (size_t)m2 * ctx->ldm2);
+    D(ctx->P, (size_t)m2 * ctx->ldm2);
+    D(ctx->XP, (size_t)m2 * ctx->ldm2);
+    D(ctx->ptmp, chol_inv_tmp_elems(m2));
+  }
+  if (mixed) {
+    F(ctx->Linv32, (size_t)N * ctx->ldN);
+    F(ctx->C32, (size_t)m2 * ctx->ldn);
+    if (need_ph) F(ctx->XP32, (size_t)m2 * ctx->ldm2);
+    for (float** v : {&ctx->fr, &ctx->fz, &ctx->fp, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts})
+      F(*v, m2);
+    for (float** v : {&ctx->fu, &ctx->fw}) F(*v, n);
+    F(ctx->fv, N);
+    F(ctx->w32.part, part32);
+    ctx->w32.part_elems = part32;
+  }
+}
+
+template <typename Get>
+static void layout_factor_scratch(qp_ctx* ctx, Get&& get) {
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
+  auto D = [&](double*& p, size_t elems) { p = static_cast<double*>(get(elems * sizeof(double))); };
+  D(ctx->fHw, (size_t)n * ctx->ldn);
+  D(ctx->fWt, (size_t)m1 * ctx->ldn);
+  D(ctx->fS, (size_t)m1 * ctx->ldm1);
+  D(ctx->fG, (size_t)m1 * ctx->ldn);
+  D(ctx->ftmp, chol_inv_tmp_elems(n > m1 ? n : m1));
+  if (resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ) D(ctx->fYt, (size_t)m2 * ctx->ldn);
+}
+
+void alloc_all(qp_ctx* ctx) {
+  layout_buffers(ctx, [&](size_t bytes) { return dalloc_bytes(ctx, bytes); });
+  if (!ctx->pooled) {
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_sc, sizeof(PcgScalars), hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_isc, sizeof(IpmScalars), hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_stats, kStatsStride * sizeof(double), hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_info, 16 * sizeof(int), hipHostMallocDefault));
+  }
+}
+
+void alloc_factor_scratch(qp_ctx* ctx) {
+  layout_factor_scratch(ctx, [&](size_t bytes) { return dalloc_bytes(ctx, bytes); });
+}
+
+void free_factor_scratch(qp_ctx* ctx) {
+  for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fYt}) {
+    dfree(ctx, *p);
+    *p = nullptr;
+  }
+}
+
+size_t footprint_bytes(int n, int m1, int m2, const qp_options& o, bool pooled, bool with_scratch) {
+  qp_ctx tmp;
+  init_dims(&tmp, n, m1, m2, o);
+  tmp.pooled = pooled;
+  size_t total = 0;
+  static char dummy;
+  auto sum = [&](size_t bytes) -> void* {
+    total += round_bytes(bytes);
+    return &dummy;
+  };
+  layout_buffers(&tmp, sum);
+  if (with_scratch) layout_factor_scratch(&tmp, sum);
+  return total;
+}
+
+void upload_problem(qp_ctx* ctx, const double* H, const double* c, const double* A, const double* b,
+                    const double* C, const double* d, qp_mem where) {
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
+  upload_matrix(ctx, ctx->H, ctx->ldn, H, n, n, where);
+  upload_vec(ctx, ctx->c, c, n, where);
+  upload_matrix(ctx, ctx->A, ctx->ldn, A, m1, n, where);
+  upload_vec(ctx, ctx->b, b, m1, where);
+  upload_matrix(ctx, ctx->C, ctx->ldn, C, m2, n, where);
+  upload_vec(ctx, ctx->d, d, m2, where);
+  if (ctx->opt.precision == QP_MIXED)
+    HIPCHK(ctx, (convert_2d<double, float>(ctx->stream, ctx->C, ctx->ldn, ctx->C32, ctx->ldn, m2, n)));
 }
 
 // ---- K0 solves ------------------------------------------------------------
@@ -199,7 +404,8 @@ void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN) {
 
 // w = [I 0] K0^{-1} [u; 0] = M^T Sigma M u with M = L^{-1}[:, :n].
 template <typename T>
-void k0_top_apply(qp_ctx* ctx, const T* Linv, const T* u, T* v, T* w, const GemvWork<T>& wk, const int* skip) {
+static void k0_top_apply(qp_ctx* ctx, const T* Linv, const T* u, T* v, T* w, const GemvWork<T>& wk,
+                         const int* skip) {
   HIPCHK(ctx, launch_gemv_rows<T>(ctx->stream, Linv, ctx->ldN, ctx->N, ctx->n, kLower, u, v, T(1), T(0), nullptr,
                                   ctx->n, skip, 2));
   HIPCHK(ctx, launch_gemv_cols<T>(ctx->stream, Linv, ctx->ldN, ctx->N, ctx->n, kLower, v, w, T(1), T(0), nullptr, wk,
@@ -210,11 +416,22 @@ void k0_top_apply(qp_ctx* ctx, const T* Linv, const T* u, T* v, T* w, const Gemv
 void factor(qp_ctx* ctx) {
   const int n = ctx->n, m1 = ctx->m1, N = ctx->N, ldn = ctx->ldn, ldN = ctx->ldN, ldm1 = ctx->ldm1;
   hipStream_t st = ctx->stream;
-  double* Hw = dalloc<double>(ctx, (size_t)n * ldn);
-  double* Wt = dalloc<double>(ctx, (size_t)m1 * ldn);
-  double* S = dalloc<double>(ctx, (size_t)m1 * ldm1);
-  double* tmpG = dalloc<double>(ctx, (size_t)m1 * ldn);
-  double* tmp = dalloc<double>(ctx, chol_inv_tmp_elems(n > m1 ? n : m1));
+  const bool own_scratch = ctx->fHw == nullptr;
+  if (own_scratch) {
+    ctx->fHw = dalloc<double>(ctx, (size_t)n * ldn);
+    ctx->fWt = dalloc<double>(ctx, (size_t)m1 * ldn);
+    ctx->fS = dalloc<double>(ctx, (size_t)m1 * ldm1);
+    ctx->fG = dalloc<double>(ctx, (size_t)m1 * ldn);
+    ctx->ftmp = dalloc<double>(ctx, chol_inv_tmp_elems(n > m1 ? n : m1));
+  }
+  double *Hw = ctx->fHw, *Wt = ctx->fWt, *S = ctx->fS, *tmpG = ctx->fG, *tmp = ctx->ftmp;
+  auto drop = [&] {
+    if (!own_scratch) return;
+    for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp}) {
+      dfree(ctx, *p);
+      *p = nullptr;
+    }
+  };
   HIPCHK(ctx, hipMemsetAsync(ctx->info, 0, sizeof(int), st));
   HIPCHK(ctx, hipMemcpyAsync(Hw, ctx->H, (size_t)n * ldn * sizeof(double), hipMemcpyDeviceToDevice, st));
   double* XH = ctx->Linv;                        // rows 0..n-1, cols 0..n-1
@@ -229,7 +446,7 @@ void factor(qp_ctx* ctx) {
   sync(ctx);
   if (*ctx->h_info != 0) {
     set_err(ctx, "Cholesky factorization of H failed: H is not positive definite");
-    for (void* p : {(void*)Hw, (void*)Wt, (void*)S, (void*)tmpG, (void*)tmp}) dfree(ctx, p);
+    drop();
     throw Fail{QP_E_NOT_SPD};
   }
   // X_S = L_S^{-1}
@@ -240,12 +457,11 @@ void factor(qp_ctx* ctx) {
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_info, ctx->info, sizeof(int), hipMemcpyDeviceToHost, st));
   sync(ctx);
   int bad = *ctx->h_info;
+  drop();
   if (bad != 0) {
     set_err(ctx, "Cholesky factorization of A H^{-1} A^T failed: A is rank deficient");
-    for (void* p : {(void*)Hw, (void*)Wt, (void*)S, (void*)tmpG, (void*)tmp}) dfree(ctx, p);
     throw Fail{QP_E_RANK};
   }
-  for (void* p : {(void*)Hw, (void*)Wt, (void*)S, (void*)tmpG, (void*)tmp}) dfree(ctx, p);
   if (ctx->opt.precision == QP_MIXED) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->Linv, ldN, ctx->Linv32, ldN, N, N)));
   }
@@ -257,11 +473,12 @@ void ph_setup(qp_ctx* ctx) {
   if (ctx->ph_ready) return;
   const int n = ctx->n, m2 = ctx->m2;
   hipStream_t st = ctx->stream;
-  double* Yt = dalloc<double>(ctx, (size_t)m2 * ctx->ldn);
+  const bool own = ctx->fYt == nullptr;
+  double* Yt = own ? dalloc<double>(ctx, (size_t)m2 * ctx->ldn) : ctx->fYt;
   HIPCHK(ctx, gemm_f64(st, 0, 1, m2, n, n, 1.0, ctx->C, ctx->ldn, ctx->Linv, ctx->ldN, 0.0, Yt, ctx->ldn, kBUpper));
   HIPCHK(ctx, gemm_f64(st, 0, 1, m2, m2, n, 1.0, Yt, ctx->ldn, Yt, ctx->ldn, 0.0, ctx->T, ctx->ldm2, kOutLower));
   sync(ctx);
-  dfree(ctx, Yt);
+  if (own) dfree(ctx, Yt);
   ctx->ph_ready = true;
 }
 
@@ -276,21 +493,62 @@ void ph_factor(qp_ctx* ctx, const double* dvec) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->XP, ctx->ldm2, ctx->XP32, ctx->ldm2, m2, m2)));
 }
 
-// ---- PCG driver -------------------------------------------------------------
+// ---- CG buffers -------------------------------------------------------------
+PcgBufs<double> bufs64(qp_ctx* ctx, const double* dvec, const double* wts, double* x) {
+  PcgBufs<double> B;
+  B.Linv = ctx->Linv;
+  B.C = ctx->C;
+  B.XP = ctx->XP;
+  B.dvec = dvec;
+  B.wts = wts;
+  B.r = ctx->pr;
+  B.z = ctx->pz;
+  B.p = ctx->pp;
+  B.q = ctx->pq;
+  B.t = ctx->pt;
+  B.u = ctx->pu;
+  B.v = ctx->pv;
+  B.w = ctx->pw;
+  B.x = x;
+  B.wk = &ctx->w64;
+  return B;
+}
+
+PcgBufs<float> bufs32(qp_ctx* ctx) {
+  PcgBufs<float> B;
+  B.Linv = ctx->Linv32;
+  B.C = ctx->C32;
+  B.XP = ctx->XP32;
+  B.dvec = ctx->fd;
+  B.wts = ctx->fwts;
+  B.r = ctx->fr;
+  B.z = ctx->fz;
+  B.p = ctx->fp;
+  B.q = ctx->fq;
+  B.t = ctx->ft;
+  B.u = ctx->fu;
+  B.v = ctx->fv;
+  B.w = ctx->fw;
+  B.x = ctx->fx;
+  B.wk = &ctx->w32;
+  return B;
+}
+
+int mixed_inner_cap(const qp_ctx* ctx, int prec) {
+  const int m2 = ctx->m2;
+  const int bound = prec == kPrecL ? std::min(m2, ctx->n - ctx->m1) : (prec == kPrecH ? std::min(m2, ctx->m1) : m2);
+  return std::max(200, 2 * (bound + 1));
+}
+
+// ---- PCG driver (one QP) ------------------------------------------------------
 struct PcgResult {
   int iters = 0;
   int done = 0;
 };
 
 template <typename T>
-struct PcgBufs {
-  const T *Linv, *C, *XP, *dvec, *wts;
-  T *r, *z, *p, *q, *t, *u, *v, *w, *x;
-  const GemvWork<T>* wk;
-};
-
-template <typename T>
-PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, double rtol, double wtol, int maxit) {
+static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, double rtol, double wtol,
+                         int maxit) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m2 = ctx->m2;
   const int* skip = &ctx->sc->done;
@@ -356,46 +614,6 @@ PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, doub
   return res;
 }
 
-PcgBufs<double> bufs64(qp_ctx* ctx, const double* dvec, const double* wts, double* x) {
-  PcgBufs<double> B;
-  B.Linv = ctx->Linv;
-  B.C = ctx->C;
-  B.XP = ctx->XP;
-  B.dvec = dvec;
-  B.wts = wts;
-  B.r = ctx->pr;
-  B.z = ctx->pz;
-  B.p = ctx->pp;
-  B.q = ctx->pq;
-  B.t = ctx->pt;
-  B.u = ctx->pu;
-  B.v = ctx->pv;
-  B.w = ctx->pw;
-  B.x = x;
-  B.wk = &ctx->w64;
-  return B;
-}
-
-PcgBufs<float> bufs32(qp_ctx* ctx) {
-  PcgBufs<float> B;
-  B.Linv = ctx->Linv32;
-  B.C = ctx->C32;
-  B.XP = ctx->XP32;
-  B.dvec = ctx->fd;
-  B.wts = ctx->fwts;
-  B.r = ctx->fr;
-  B.z = ctx->fz;
-  B.p = ctx->fp;
-  B.q = ctx->fq;
-  B.t = ctx->ft;
-  B.u = ctx->fu;
-  B.v = ctx->fv;
-  B.w = ctx->fw;
-  B.x = ctx->fx;
-  B.wk = &ctx->w32;
-  return B;
-}
-
 // q = K_F p in float64 (used by qp_kf_apply and the refinement residual).
 void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
   hipStream_t st = ctx->stream;
@@ -409,8 +627,9 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
 
 // Reduced solve used by both qp_pcg_solve and the IPM.  dvec, rhs, dnu, wts are
 // device float64 vectors.  Returns CG steps; sets *done to the PCG stop code.
-int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, double* dnu, const double* wts,
-                  double rtol, double wtol, int maxit, int* done, int* refinements, int* fallback) {
+static int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, double* dnu,
+                         const double* wts, double rtol, double wtol, int maxit, int* done, int* refinements,
+                         int* fallback) {
   *refinements = 0;
   *fallback = 0;
   if (ctx->opt.precision != QP_MIXED) {
@@ -427,8 +646,7 @@ int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, 
   // the total residual, so the stop tests are the same as in the float64 path.
   hipStream_t st = ctx->stream;
   const int m2 = ctx->m2;
-  const int bound = prec == kPrecL ? std::min(m2, ctx->n - ctx->m1) : (prec == kPrecH ? std::min(m2, ctx->m1) : m2);
-  const int inner_cap = std::max(200, 2 * (bound + 1));
+  const int inner_cap = mixed_inner_cap(ctx, prec);
   const double inner_rtol = 1e-5;
   int total = 0;
   HIPCHK(ctx, (convert_1d<double, float>(st, dvec, ctx->fd, m2)));
@@ -476,7 +694,8 @@ int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, 
   return total;
 }
 
-double host_rel_kkt(const double* S, int m2, double parts[5]) {
+// ---- interior point phases ----------------------------------------------------
+double host_rel_kkt(const double* S, double parts[5]) {
   double pobj = 0.5 * S[kXHx] + S[kCx];
   double dobj = -0.5 * S[kXHx] + S[kBl] + S[kDn];
   double rho_d = S[kRdInf] / (1.0 + std::max(std::max(S[kHxInf], S[kCInf]), std::max(S[kAtlInf], S[kCtnInf])));
@@ -489,12 +708,10 @@ double host_rel_kkt(const double* S, int m2, double parts[5]) {
   parts[2] = rho_p;
   parts[3] = rho_g;
   parts[4] = rho_n;
-  (void)m2;
   return std::max(std::max(std::max(rho_d, rho_e), std::max(rho_p, rho_g)), rho_n);
 }
 
-// Residuals and statistics of the current iterate (x, lam, nu, s) -> host stats.
-void eval_iterate(qp_ctx* ctx) {
+void ipm_eval_launch(qp_ctx* ctx, bool copy) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
   HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->H, ctx->ldn, n, n, kDense, ctx->x, ctx->Hx, 1.0, 0.0, nullptr, n,
@@ -509,12 +726,12 @@ void eval_iterate(qp_ctx* ctx) {
                                        ctx->w64, nullptr));
   HIPCHK(ctx, ipm_stats(st, n, m1, m2, ctx->Hx, ctx->Atl, ctx->Ctn, ctx->Ax, ctx->Cx, ctx->x, ctx->c, ctx->lam, ctx->b,
                         ctx->nu, ctx->s, ctx->d, ctx->rg, ctx->re, ctx->ri, ctx->stats));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->h_stats, ctx->stats, kNumStats * sizeof(double), hipMemcpyDeviceToHost, st));
-  sync(ctx);
+  if (copy)
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_stats, ctx->stats, kNumStats * sizeof(double), hipMemcpyDeviceToHost, st));
 }
 
 // Recovery of eq. schur-delta-x (K0 form) and eq. delz for a given dnu.
-void recover(qp_ctx* ctx, const double* dnu, double* dx, double* dlam, double* ds) {
+static void recover(qp_ctx* ctx, const double* dnu, double* dx, double* dlam, double* ds) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
   // rhs = [r_g + C^T dnu; -r_e]
@@ -525,13 +742,13 @@ void recover(qp_ctx* ctx, const double* dnu, double* dx, double* dlam, double* d
   HIPCHK(ctx, ipm_dirs(st, n, m1, m2, ctx->vN2, ctx->rc, ctx->nu, ctx->dvec, dnu, dx, dlam, ds));
 }
 
-void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
+void ipm_start(qp_ctx* ctx, IpmRun& R) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
-  const qp_precond pc = resolve_prec(ctx, ctx->opt.prec);
-  const int prec = prec_mode(pc);
-  if (prec == kPrecH) ph_setup(ctx);
-  const int maxit = ctx->opt.max_pcg > 0 ? ctx->opt.max_pcg : 20 * m2;
+  R = IpmRun{};
+  R.prec = prec_mode(resolve_prec(ctx, ctx->opt.prec));
+  if (R.prec == kPrecH) ph_setup(ctx);
+  R.maxit = ctx->opt.max_pcg > 0 ? ctx->opt.max_pcg : 20 * m2;
   // initial point: K0 [x0; -lam0] = [-c; b]; s0 = max(C x0 - d, 1); nu0 = 1
   HIPCHK(ctx, ipm_neg_copy(st, n, ctx->c, ctx->vN1));
   HIPCHK(ctx, hipMemcpyAsync(ctx->vN1 + n, ctx->b, (size_t)m1 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -539,154 +756,118 @@ void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
   HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->C, ctx->ldn, m2, n, kDense, ctx->vN2, ctx->Cx, 1.0, 0.0, nullptr, m2,
                                        nullptr));
   HIPCHK(ctx, ipm_init_point(st, n, m1, m2, ctx->vN2, ctx->Cx, ctx->d, ctx->x, ctx->lam, ctx->nu, ctx->s));
-  IpmScalars hs{};
-  hs.tau = ctx->opt.tau;
-  HIPCHK(ctx, hipMemcpyAsync(ctx->isc, &hs, sizeof(IpmScalars), hipMemcpyHostToDevice, st));
-  long long cg_total = 0;
-  int refin_total = 0;
-  int fallbacks = 0;
-  int it = 0;
-  double parts[5] = {0, 0, 0, 0, 0};
-  double score = 0;
-  int status = QP_E_NOCONV;
+  // IPM scalars: only tau is read before the first step sets the rest
+  *ctx->h_isc = IpmScalars{};
+  ctx->h_isc->tau = ctx->opt.tau;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->isc, ctx->h_isc, sizeof(IpmScalars), hipMemcpyHostToDevice, st));
+}
+
+bool ipm_check(qp_ctx* ctx, IpmRun& R) {
+  R.score = host_rel_kkt(ctx->h_stats, R.parts);
+  if (!std::isfinite(R.score)) {
+    set_err(ctx, "non-finite iterate at IPM iteration %d", R.it);
+    R.status = QP_E_NOCONV;
+    return false;
+  }
+  if (R.score <= ctx->opt.rtol_kkt) {
+    R.status = QP_OK;
+    return false;
+  }
+  if (R.it >= ctx->opt.max_ipm) {
+    R.status = QP_E_NOCONV;
+    return false;
+  }
+  R.mu = ctx->h_stats[kSNu] / ctx->m2;
+  R.wtol = ctx->opt.cg_theta * R.mu;
+  return true;
+}
+
+void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R) {
+  hipStream_t st = ctx->stream;
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
+  // w = [I 0] K0^{-1} [-r_g; r_e];  C w feeds r_nu
+  HIPCHK(ctx, ipm_neg_copy(st, n, ctx->rg, ctx->vN1));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->vN1 + n, ctx->re, (size_t)m1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k0_solve_dev(ctx, ctx->vN1, ctx->vN2, ctx->vN3);
+  HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->C, ctx->ldn, m2, n, kDense, ctx->vN2, ctx->Cw, 1.0, 0.0, nullptr, m2,
+                                       nullptr));
+  // predictor right-hand side and D
+  HIPCHK(ctx, ipm_rhs(st, m2, 0, ctx->ri, ctx->s, ctx->nu, ctx->Cw, nullptr, nullptr, ctx->isc, ctx->rc, ctx->rhs,
+                      ctx->dvec));
+  if (R.prec == kPrecH) ph_factor(ctx, ctx->dvec);
+}
+
+void ipm_after_predictor(qp_ctx* ctx) {
+  hipStream_t st = ctx->stream;
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
+  recover(ctx, ctx->dnu_a, ctx->dx_a, ctx->dlam_a, ctx->ds_a);
+  HIPCHK(ctx, ipm_step(st, n, m1, m2, 0, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx_a, ctx->dlam_a, ctx->dnu_a,
+                       ctx->ds_a, ctx->isc));
+  // corrector right-hand side
+  HIPCHK(ctx, ipm_rhs(st, m2, 1, ctx->ri, ctx->s, ctx->nu, ctx->Cw, ctx->ds_a, ctx->dnu_a, ctx->isc, ctx->rc, ctx->rhs,
+                      ctx->dvec));
+}
+
+void ipm_after_corrector(qp_ctx* ctx, IpmRun& R) {
+  hipStream_t st = ctx->stream;
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
+  recover(ctx, ctx->dnu, ctx->dx, ctx->dlam, ctx->ds);
+  HIPCHK(ctx, ipm_step(st, n, m1, m2, 1, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx, ctx->dlam, ctx->dnu, ctx->ds,
+                       ctx->isc));
+  R.cg_total += R.k1 + R.k2;
+  ++R.it;
+  if (ctx->opt.verbose) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_isc, ctx->isc, sizeof(IpmScalars), hipMemcpyDeviceToHost, st));
+    sync(ctx);
+    fprintf(stderr, "[qpgpu] it %3d mu %.3e sigma %.2e alpha %.4f cg %d+%d rel_kkt %.3e fallbacks %d\n", R.it, R.mu,
+            ctx->h_isc->sigma, ctx->h_isc->alpha, R.k1, R.k2, R.score, R.fallbacks);
+  }
+}
+
+void ipm_fill_info(const qp_ctx* ctx, const IpmRun& R, qp_ipm_info* info) {
+  if (!info) return;
+  info->ipm_iters = R.it;
+  info->pcg_iters_total = R.cg_total;
+  info->rel_kkt = R.score;
+  for (int k = 0; k < 5; ++k) info->rel_kkt_parts[k] = R.parts[k];
+  info->obj = 0.5 * ctx->h_stats[kXHx] + ctx->h_stats[kCx];
+  info->mu = ctx->h_stats[kSNu] / ctx->m2;
+  info->status = R.status;
+  info->refinements_total = R.refin_total;
+  info->fp64_fallbacks = R.fallbacks;
+}
+
+static void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
+  IpmRun R;
+  ipm_start(ctx, R);
   for (;;) {
-    eval_iterate(ctx);
-    score = host_rel_kkt(ctx->h_stats, m2, parts);
-    if (!std::isfinite(score)) {
-      set_err(ctx, "non-finite iterate at IPM iteration %d", it);
-      status = QP_E_NOCONV;
-      break;
-    }
-    if (score <= ctx->opt.rtol_kkt) {
-      status = QP_OK;
-      break;
-    }
-    if (it >= ctx->opt.max_ipm) break;
-    const double mu = ctx->h_stats[kSNu] / m2;
-    // w = [I 0] K0^{-1} [-r_g; r_e];  C w feeds r_nu
-    HIPCHK(ctx, ipm_neg_copy(st, n, ctx->rg, ctx->vN1));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->vN1 + n, ctx->re, (size_t)m1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    k0_solve_dev(ctx, ctx->vN1, ctx->vN2, ctx->vN3);
-    HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->C, ctx->ldn, m2, n, kDense, ctx->vN2, ctx->Cw, 1.0, 0.0, nullptr,
-                                         m2, nullptr));
-    // predictor
-    HIPCHK(ctx, ipm_rhs(st, m2, 0, ctx->ri, ctx->s, ctx->nu, ctx->Cw, nullptr, nullptr, ctx->isc, ctx->rc, ctx->rhs,
-                        ctx->dvec));
-    if (prec == kPrecH) ph_factor(ctx, ctx->dvec);
-    const double wtol = ctx->opt.cg_theta * mu;
+    ipm_eval_launch(ctx, true);
+    sync(ctx);
+    if (!ipm_check(ctx, R)) break;
+    ipm_predictor_setup(ctx, R);
     int done = 0, refin = 0, fb = 0;
-    int k1 = reduced_solve(ctx, prec, ctx->dvec, ctx->rhs, ctx->dnu_a, ctx->nu, ctx->opt.cg_rtol, wtol, maxit, &done,
-                           &refin, &fb);
-    refin_total += refin;
-    fallbacks += fb;
-    recover(ctx, ctx->dnu_a, ctx->dx_a, ctx->dlam_a, ctx->ds_a);
-    HIPCHK(ctx, ipm_step(st, n, m1, m2, 0, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx_a, ctx->dlam_a, ctx->dnu_a,
-                         ctx->ds_a, ctx->isc));
-    // corrector
-    HIPCHK(ctx, ipm_rhs(st, m2, 1, ctx->ri, ctx->s, ctx->nu, ctx->Cw, ctx->ds_a, ctx->dnu_a, ctx->isc, ctx->rc,
-                        ctx->rhs, ctx->dvec));
-    int k2 = reduced_solve(ctx, prec, ctx->dvec, ctx->rhs, ctx->dnu, ctx->nu, ctx->opt.cg_rtol, wtol, maxit, &done,
-                           &refin, &fb);
-    refin_total += refin;
-    fallbacks += fb;
-    recover(ctx, ctx->dnu, ctx->dx, ctx->dlam, ctx->ds);
-    HIPCHK(ctx, ipm_step(st, n, m1, m2, 1, ctx->x, ctx->lam, ctx->nu, ctx->s, ctx->dx, ctx->dlam, ctx->dnu, ctx->ds,
-                         ctx->isc));
-    cg_total += k1 + k2;
-    ++it;
-    if (ctx->opt.verbose) {
-      HIPCHK(ctx, hipMemcpyAsync(ctx->h_isc, ctx->isc, sizeof(IpmScalars), hipMemcpyDeviceToHost, st));
-      sync(ctx);
-      fprintf(stderr, "[qpgpu] it %3d mu %.3e sigma %.2e alpha %.4f cg %d+%d rel_kkt %.3e fallbacks %d\n", it, mu,
-              ctx->h_isc->sigma, ctx->h_isc->alpha, k1, k2, score, fallbacks);
-    }
+    R.k1 = reduced_solve(ctx, R.prec, ctx->dvec, ctx->rhs, ctx->dnu_a, ctx->nu, ctx->opt.cg_rtol, R.wtol, R.maxit,
+                         &done, &refin, &fb);
+    R.refin_total += refin;
+    R.fallbacks += fb;
+    ipm_after_predictor(ctx);
+    R.k2 = reduced_solve(ctx, R.prec, ctx->dvec, ctx->rhs, ctx->dnu, ctx->nu, ctx->opt.cg_rtol, R.wtol, R.maxit,
+                         &done, &refin, &fb);
+    R.refin_total += refin;
+    R.fallbacks += fb;
+    ipm_after_corrector(ctx, R);
   }
-  if (info) {
-    info->ipm_iters = it;
-    info->pcg_iters_total = cg_total;
-    info->rel_kkt = score;
-    for (int k = 0; k < 5; ++k) info->rel_kkt_parts[k] = parts[k];
-    info->obj = 0.5 * ctx->h_stats[kXHx] + ctx->h_stats[kCx];
-    info->mu = ctx->h_stats[kSNu] / m2;
-    info->status = status;
-    info->refinements_total = refin_total;
-    info->fp64_fallbacks = fallbacks;
-  }
-  if (status != QP_OK && ctx->err.empty()) set_err(ctx, "IPM stopped at rel_kkt %.3e after %d iterations", score, it);
-  if (status != QP_OK) throw Fail{(qp_status)status};
+  ipm_fill_info(ctx, R, info);
+  if (R.status != QP_OK && ctx->err.empty())
+    set_err(ctx, "IPM stopped at rel_kkt %.3e after %d iterations", R.score, R.it);
+  if (R.status != QP_OK) throw Fail{(qp_status)R.status};
 }
 
-void alloc_all(qp_ctx* ctx) {
-  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2, N = ctx->N;
-  ctx->H = dalloc<double>(ctx, (size_t)n * ctx->ldn);
-  ctx->c = dalloc<double>(ctx, n);
-  ctx->A = dalloc<double>(ctx, (size_t)m1 * ctx->ldn);
-  ctx->b = dalloc<double>(ctx, m1);
-  ctx->C = dalloc<double>(ctx, (size_t)m2 * ctx->ldn);
-  ctx->d = dalloc<double>(ctx, m2);
-  ctx->Linv = dalloc<double>(ctx, (size_t)N * ctx->ldN);
-  for (double** v : {&ctx->x, &ctx->Hx, &ctx->Atl, &ctx->Ctn, &ctx->rg, &ctx->dx, &ctx->dx_a, &ctx->pu, &ctx->pw})
-    *v = dalloc<double>(ctx, n);
-  for (double** v : {&ctx->lam, &ctx->Ax, &ctx->re, &ctx->dlam, &ctx->dlam_a}) *v = dalloc<double>(ctx, m1);
-  for (double** v : {&ctx->nu, &ctx->s, &ctx->Cx, &ctx->ri, &ctx->dvec, &ctx->rc, &ctx->rhs, &ctx->Cw, &ctx->dnu,
-                     &ctx->ds, &ctx->dnu_a, &ctx->ds_a, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pq, &ctx->pt, &ctx->ir_r,
-                     &ctx->ir_x, &ctx->ir_d})
-    *v = dalloc<double>(ctx, m2);
-  for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) *v = dalloc<double>(ctx, N);
-  // gemv_cols partial workspace: chunks * ld with chunks <= 4 * CUs / tiles
-  int maxld = std::max(std::max(ctx->ldn, ctx->ldN), ctx->ldm2);
-  size_t part = gemv_cols_part_elems(maxld);
-  ctx->w64.part = dalloc<double>(ctx, part);
-  ctx->w64.part_elems = part;
-  ctx->bpart_cap = kMaxRowsBpc * dev_info().cu_count + 64;
-  ctx->bpart = dalloc<double>(ctx, ctx->bpart_cap);
-  ctx->sc = dalloc<PcgScalars>(ctx, 1);
-  ctx->isc = dalloc<IpmScalars>(ctx, 1);
-  ctx->stats = dalloc<double>(ctx, 64);
-  ctx->info = dalloc<int>(ctx, 16);
-  const qp_precond pc = resolve_prec(ctx, ctx->opt.prec);
-  const bool need_ph = true;  // qp_pcg_solve may ask for P_H whatever the options say
-  (void)pc;
-  if (need_ph) {
-    ctx->T = dalloc<double>(ctx, (size_t)m2 * ctx->ldm2);
-    ctx->P = dalloc<double>(ctx, (size_t)m2 * ctx->ldm2);
-    ctx->XP = dalloc<double>(ctx, (size_t)m2 * ctx->ldm2);
-    ctx->ptmp = dalloc<double>(ctx, chol_inv_tmp_elems(m2));
-  }
-  if (ctx->opt.precision == QP_MIXED) {
-    ctx->Linv32 = dalloc<float>(ctx, (size_t)N * ctx->ldN);
-    ctx->C32 = dalloc<float>(ctx, (size_t)m2 * ctx->ldn);
-    ctx->XP32 = dalloc<float>(ctx, (size_t)m2 * ctx->ldm2);
-    for (float** v : {&ctx->fr, &ctx->fz, &ctx->fp, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts})
-      *v = dalloc<float>(ctx, m2);
-    for (float** v : {&ctx->fu, &ctx->fw}) *v = dalloc<float>(ctx, n);
-    ctx->fv = dalloc<float>(ctx, N);
-    ctx->w32.part = dalloc<float>(ctx, part);
-    ctx->w32.part_elems = part;
-  }
-  HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_sc, sizeof(PcgScalars), hipHostMallocDefault));
-  HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_isc, sizeof(IpmScalars), hipHostMallocDefault));
-  HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_stats, 64 * sizeof(double), hipHostMallocDefault));
-  HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_info, 16 * sizeof(int), hipHostMallocDefault));
-}
+}  // namespace detail
+}  // namespace qpg
 
-template <typename F>
-qp_status guarded(qp_ctx* ctx, F&& f) {
-  try {
-    f();
-    return QP_OK;
-  } catch (const Fail& e) {
-    return e.st;
-  } catch (const std::exception& e) {
-    set_err(ctx, "internal error: %s", e.what());
-    return QP_E_DEVICE;
-  } catch (...) {
-    set_err(ctx, "internal error");
-    return QP_E_DEVICE;
-  }
-}
-
-}  // namespace
+using namespace qpg;
+using namespace qpg::detail;
 
 // ============================================================================
 extern "C" {
@@ -745,9 +926,10 @@ void qp_destroy(qp_ctx* ctx) {
       (void)hipEventDestroy(ctx->prof_ev[o].begin);
       (void)hipEventDestroy(ctx->prof_ev[o].end);
     }
-  for (void* p : ctx->allocs) (void)hipFree(p);
-  for (void* p : {(void*)ctx->h_sc, (void*)ctx->h_isc, (void*)ctx->h_stats, (void*)ctx->h_info})
-    if (p) (void)hipHostFree(p);
+  free_all(ctx);
+  if (!ctx->pooled)
+    for (void* p : {(void*)ctx->h_sc, (void*)ctx->h_isc, (void*)ctx->h_stats, (void*)ctx->h_info})
+      if (p) (void)hipHostFree(p);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -757,41 +939,14 @@ qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const d
                    void* hip_stream) {
   if (!out) return QP_E_INVALID;
   *out = nullptr;
-  if (n <= 0 || m1 <= 0 || m1 > n || m2 <= 0) return QP_E_INVALID;
-  if (!H || !c || !A || !b || !C || !d) return QP_E_INVALID;
-  if (where != QP_MEM_HOST && where != QP_MEM_DEVICE) return QP_E_INVALID;
-  if ((long long)(n + m1) * (n + m1) > (1LL << 31) || (long long)m2 * m2 > (1LL << 31)) return QP_E_INVALID;
+  qp_status pst = check_problem(n, m1, m2, H, c, A, b, C, d, where);
+  if (pst != QP_OK) return pst;
   qp_options o;
   qp_default_options(&o);
   if (opt) o = *opt;
-  if (!(o.tau > 0 && o.tau < 1) || o.max_ipm < 0 || !(o.rtol_kkt > 0) || o.prec < QP_PREC_NONE ||
-      o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED))
-    return QP_E_INVALID;
-  if (where == QP_MEM_HOST) {
-    // finiteness and symmetry checks on the caller's host arrays
-    if (!finite_all(H, (size_t)n * n) || !finite_all(c, n) || !finite_all(A, (size_t)m1 * n) ||
-        !finite_all(b, m1) || !finite_all(C, (size_t)m2 * n) || !finite_all(d, m2))
-      return QP_E_INVALID;
-    double fro = 0, asym = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        double h = H[(size_t)i * n + j];
-        double t = h - H[(size_t)j * n + i];
-        fro += h * h;
-        asym += t * t;
-      }
-    if (std::sqrt(asym) > 1e-14 * std::max(1.0, std::sqrt(fro))) return QP_E_INVALID;
-  }
+  if (check_options(o) != QP_OK) return QP_E_INVALID;
   qp_ctx* ctx = new qp_ctx();
-  ctx->n = n;
-  ctx->m1 = m1;
-  ctx->m2 = m2;
-  ctx->N = n + m1;
-  ctx->ldn = ld_for(n);
-  ctx->ldN = ld_for(n + m1);
-  ctx->ldm2 = ld_for(m2);
-  ctx->ldm1 = ld_for(m1);
-  ctx->opt = o;
+  init_dims(ctx, n, m1, m2, o);
   qp_status st = guarded(ctx, [&] {
     HIPCHK(ctx, hipGetDevice(&ctx->dev));
     (void)dev_info();
@@ -802,14 +957,7 @@ qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const d
       ctx->own_stream = true;
     }
     alloc_all(ctx);
-    upload_matrix(ctx, ctx->H, ctx->ldn, H, n, n, where);
-    upload_vec(ctx, ctx->c, c, n, where);
-    upload_matrix(ctx, ctx->A, ctx->ldn, A, m1, n, where);
-    upload_vec(ctx, ctx->b, b, m1, where);
-    upload_matrix(ctx, ctx->C, ctx->ldn, C, m2, n, where);
-    upload_vec(ctx, ctx->d, d, m2, where);
-    if (o.precision == QP_MIXED)
-      HIPCHK(ctx, (convert_2d<double, float>(ctx->stream, ctx->C, ctx->ldn, ctx->C32, ctx->ldn, m2, n)));
+    upload_problem(ctx, H, c, A, b, C, d, where);
     sync(ctx);
   });
   if (st != QP_OK) {
@@ -870,7 +1018,6 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
     return QP_E_STATE;
   }
   ctx->err.clear();
-  int code = 0;
   qp_status st = guarded(ctx, [&] {
     const int m2 = ctx->m2;
     if (where == QP_MEM_HOST) {
@@ -910,7 +1057,6 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
       info->refinements = refin;
       info->fp64_fallback = fb;
     }
-    code = done;
     if (done == 3) {
       set_err(ctx, "PCG breakdown (p^T q <= 0)");
       throw Fail{QP_E_NOCONV};
@@ -921,7 +1067,6 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
     }
   });
   if (info) info->status = st;
-  (void)code;
   return st;
 }
 

@@ -1,0 +1,801 @@
+// Batch driver: many independent QPs of different sizes in flight on one
+// stream, advanced together one interior point iteration per round.
+//
+// A round runs, for every QP in flight, the steps of one IPM iteration (Sec. 2
+// predictor-corrector on the reduced system of eq. ineq-const-reduced), with the
+// two reduced solves of all QPs done together: each CG step is one launch per
+// sweep over a descriptor list (desc.hpp) that covers every QP still iterating,
+// so the K0 inverse factors, the C matrices and the P_H factors of all QPs
+// stream through HBM in the same launches.  A QP's stop flag lives in device
+// memory; stopped QPs skip their share of a launch and are dropped from the
+// lists at the next host poll.  Each QP's launch shapes depend only on its own
+// sizes, so its result does not depend on which other QPs share the batch.
+//
+// Admission is by memory: every QP's buffers come from one arena of the
+// budget given at creation, so admitting and retiring QPs never calls hipMalloc
+// or hipFree.  New QPs are factored at the start of the next round and join
+// the running set there (continuous batching at iteration granularity).
+// Results are copied to host memory when a QP finishes and its device memory
+// returns to the arena at once.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <unordered_map>
+
+#include "ctx.hpp"
+
+using namespace qpg;
+using namespace qpg::detail;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum SlotState : int { kQueued = 0, kRunning = 1, kFinished = 2 };
+
+struct Slot {
+  qp_ctx* ctx = nullptr;
+  long long ticket = 0;
+  int pool = -1;
+  int state = kQueued;
+  IpmRun R;
+  qp_status status = QP_OK;
+  std::string err;
+  int n = 0, m1 = 0, m2 = 0;
+  std::vector<double> x, lam, nu, s;
+  qp_ipm_info info{};
+  Clock::time_point t_admit, t_done;
+};
+
+constexpr int kMaxSlots = 4096;  // QPs in flight at once (scalar pool entries)
+constexpr int kInfoStride = 16;
+
+}  // namespace
+
+struct qp_batch {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int dev = 0;
+  qp_options opt{};
+  Arena arena;
+  qp_ctx sink;  // error text and stream for batch-level failures
+  // scalar pools indexed by Slot::pool
+  PcgScalars *d_sc = nullptr, *h_sc = nullptr;
+  double *d_stats = nullptr, *h_stats = nullptr;
+  int *d_info = nullptr, *h_info = nullptr;
+  IpmScalars* h_isc = nullptr;
+  std::vector<int> free_pools;
+  std::vector<Slot*> live;                          // queued and running, admission order
+  std::unordered_map<long long, Slot*> finished;    // waiting for qp_batch_collect
+  long long next_ticket = 1;
+  // descriptor staging (pinned host and device copies)
+  char *h_stage = nullptr, *d_stage = nullptr;
+  size_t stage_cap = 0;
+  long long rounds = 0;
+  long long cg_launched = 0;  // batched CG steps launched
+};
+
+namespace {
+
+// ---- descriptor staging ---------------------------------------------------------
+struct Packer {
+  std::vector<std::pair<const void*, size_t>> parts;
+  size_t total = 0;
+  size_t add(const void* p, size_t bytes) {
+    size_t off = total;
+    parts.emplace_back(p, bytes);
+    total += (bytes + 255) / 256 * 256;
+    return off;
+  }
+};
+
+// Copy the packed sections to the device.  Only called right after the stream
+// was synchronized, so the pinned staging area is no longer being read.
+void stage_upload(qp_batch* B, Packer& pk) {
+  qp_ctx* sk = &B->sink;
+  if (pk.total > B->stage_cap) {
+    HIPCHK(sk, hipStreamSynchronize(B->stream));
+    if (B->h_stage) (void)hipHostFree(B->h_stage);
+    if (B->d_stage) (void)hipFree(B->d_stage);
+    B->h_stage = B->d_stage = nullptr;
+    size_t cap = std::max(pk.total * 2, (size_t)1 << 20);
+    HIPCHK(sk, hipHostMalloc((void**)&B->h_stage, cap, hipHostMallocDefault));
+    HIPCHK(sk, hipMalloc((void**)&B->d_stage, cap));
+    B->stage_cap = cap;
+  }
+  size_t off = 0;
+  for (auto& pr : pk.parts) {
+    if (pr.second) memcpy(B->h_stage + off, pr.first, pr.second);
+    off += (pr.second + 255) / 256 * 256;
+  }
+  HIPCHK(sk, hipMemcpyAsync(B->d_stage, B->h_stage, pk.total, hipMemcpyHostToDevice, B->stream));
+}
+
+void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
+  qp_ctx* sk = &B->sink;
+  if (hi >= lo) {
+    HIPCHK(sk, hipMemcpyAsync(B->h_sc + lo, B->d_sc + lo, (size_t)(hi - lo + 1) * sizeof(PcgScalars),
+                              hipMemcpyDeviceToHost, B->stream));
+    if (stats) {
+      HIPCHK(sk, hipMemcpyAsync(B->h_stats + (size_t)lo * kStatsStride, B->d_stats + (size_t)lo * kStatsStride,
+                                (size_t)(hi - lo + 1) * kStatsStride * sizeof(double), hipMemcpyDeviceToHost,
+                                B->stream));
+      HIPCHK(sk, hipMemcpyAsync(B->h_info + (size_t)lo * kInfoStride, B->d_info + (size_t)lo * kInfoStride,
+                                (size_t)(hi - lo + 1) * kInfoStride * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    }
+  }
+  HIPCHK(sk, hipStreamSynchronize(B->stream));
+}
+
+// ---- batched PCG ------------------------------------------------------------------
+template <typename T>
+struct BItem {
+  qp_ctx* ctx;
+  PcgBufs<T> bufs;
+  const T* rhs;
+  int prec;
+  double rtol, wtol;
+  int maxit;
+  int iters = 0, done = 0;
+};
+
+template <typename T>
+struct StepLists {
+  std::vector<ColsDesc<T>> c1, c3, c5;  // C^T p, M^T v, X_P^T t
+  std::vector<RowsDesc<T>> r2, r4;      // Sigma M u, X_P r
+  std::vector<PcgDesc<T>> pd, ph;       // all solves; the P_H ones
+  std::vector<int> c1p, c1r, c3p, c3r, c5p, c5r, r2p, r4p, qp;
+  int c1pt = 0, c1rt = 0, c3pt = 0, c3rt = 0, c5pt = 0, c5rt = 0, r2t = 0, r4t = 0, qt = 0;
+  size_t r2smem = 0, r4smem = 0, qsmem = 0;
+  // device addresses after upload
+  const ColsDesc<T>*dc1, *dc3, *dc5;
+  const RowsDesc<T>*dr2, *dr4;
+  const PcgDesc<T>*dpd, *dph;
+  const int *dc1p, *dc1r, *dc3p, *dc3r, *dc5p, *dc5r, *dr2p, *dr4p, *dqp;
+};
+
+template <typename T>
+void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
+  qp_ctx* sk = &B->sink;
+  L = StepLists<T>{};
+  for (BItem<T>* it : act) {
+    qp_ctx* c = it->ctx;
+    const PcgBufs<T>& b = it->bufs;
+    const int* skip = &c->sc->done;
+    const int n = c->n, m2 = c->m2, N = c->N;
+    ColsDesc<T> cd;
+    RowsDesc<T> rd;
+    GemvWork<T> wk = *b.wk;
+    if (!fill_cols_desc<T>(cd, b.C, c->ldn, m2, n, kDense, b.p, b.u, T(1), T(0), nullptr, wk.part, wk.part_elems,
+                           skip)) {
+      set_err(sk, "column sweep over C does not fit its workspace (m2=%d n=%d)", m2, n);
+      throw Fail{QP_E_DEVICE};
+    }
+    L.c1p.push_back(L.c1pt);
+    L.c1r.push_back(L.c1rt);
+    L.c1pt += cd.nblocks;
+    L.c1rt += cd.rblocks;
+    L.c1.push_back(cd);
+    fill_rows_desc<T>(rd, b.Linv, c->ldN, N, n, kLower, b.u, b.v, T(1), T(0), nullptr, n, skip);
+    L.r2p.push_back(L.r2t);
+    L.r2t += rd.nblocks;
+    L.r2.push_back(rd);
+    L.r2smem = std::max(L.r2smem, rows_smem_bytes<T>(N, n, kLower, c->ldN));
+    if (!fill_cols_desc<T>(cd, b.Linv, c->ldN, N, n, kLower, b.v, b.w, T(1), T(0), nullptr, wk.part, wk.part_elems,
+                           skip)) {
+      set_err(sk, "column sweep over the inverse factor does not fit its workspace (N=%d n=%d)", N, n);
+      throw Fail{QP_E_DEVICE};
+    }
+    L.c3p.push_back(L.c3pt);
+    L.c3r.push_back(L.c3rt);
+    L.c3pt += cd.nblocks;
+    L.c3rt += cd.rblocks;
+    L.c3.push_back(cd);
+    PcgDesc<T> pd;
+    pd.C = b.C;
+    pd.w = b.w;
+    pd.dvec = b.dvec;
+    pd.wts = b.wts;
+    pd.b = it->rhs;
+    pd.x = b.x;
+    pd.r = b.r;
+    pd.z = b.z;
+    pd.p = b.p;
+    pd.q = b.q;
+    pd.bpart = c->bpart;
+    pd.sc = c->sc;
+    pd.rtol = it->rtol;
+    pd.wtol = it->wtol;
+    pd.maxit = it->maxit;
+    pd.ldc = c->ldn;
+    pd.n = n;
+    pd.m2 = m2;
+    pd.prec = it->prec;
+    pd.qblocks = std::min(bpcg_q_blocks(m2), c->bpart_cap);
+    L.qp.push_back(L.qt);
+    L.qt += pd.qblocks;
+    L.pd.push_back(pd);
+    L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, n, kDense, c->ldn));
+    if (it->prec == kPrecH) {
+      fill_rows_desc<T>(rd, b.XP, c->ldm2, m2, m2, kLower, b.r, b.t, T(1), T(0), nullptr, m2, skip);
+      L.r4p.push_back(L.r4t);
+      L.r4t += rd.nblocks;
+      L.r4.push_back(rd);
+      L.r4smem = std::max(L.r4smem, rows_smem_bytes<T>(m2, m2, kLower, c->ldm2));
+      if (!fill_cols_desc<T>(cd, b.XP, c->ldm2, m2, m2, kLower, b.t, b.z, T(1), T(0), nullptr, wk.part,
+                             wk.part_elems, skip)) {
+        set_err(sk, "column sweep over X_P does not fit its workspace (m2=%d)", m2);
+        throw Fail{QP_E_DEVICE};
+      }
+      L.c5p.push_back(L.c5pt);
+      L.c5r.push_back(L.c5rt);
+      L.c5pt += cd.nblocks;
+      L.c5rt += cd.rblocks;
+      L.c5.push_back(cd);
+      L.ph.push_back(pd);
+    }
+  }
+  Packer pk;
+  auto V = [&](auto& v) { return pk.add(v.data(), v.size() * sizeof(v[0])); };
+  size_t o_c1 = V(L.c1), o_c3 = V(L.c3), o_c5 = V(L.c5), o_r2 = V(L.r2), o_r4 = V(L.r4), o_pd = V(L.pd),
+         o_ph = V(L.ph);
+  size_t o_c1p = V(L.c1p), o_c1r = V(L.c1r), o_c3p = V(L.c3p), o_c3r = V(L.c3r), o_c5p = V(L.c5p),
+         o_c5r = V(L.c5r), o_r2p = V(L.r2p), o_r4p = V(L.r4p), o_qp = V(L.qp);
+  stage_upload(B, pk);
+  char* base = B->d_stage;
+  L.dc1 = reinterpret_cast<const ColsDesc<T>*>(base + o_c1);
+  L.dc3 = reinterpret_cast<const ColsDesc<T>*>(base + o_c3);
+  L.dc5 = reinterpret_cast<const ColsDesc<T>*>(base + o_c5);
+  L.dr2 = reinterpret_cast<const RowsDesc<T>*>(base + o_r2);
+  L.dr4 = reinterpret_cast<const RowsDesc<T>*>(base + o_r4);
+  L.dpd = reinterpret_cast<const PcgDesc<T>*>(base + o_pd);
+  L.dph = reinterpret_cast<const PcgDesc<T>*>(base + o_ph);
+  L.dc1p = reinterpret_cast<const int*>(base + o_c1p);
+  L.dc1r = reinterpret_cast<const int*>(base + o_c1r);
+  L.dc3p = reinterpret_cast<const int*>(base + o_c3p);
+  L.dc3r = reinterpret_cast<const int*>(base + o_c3r);
+  L.dc5p = reinterpret_cast<const int*>(base + o_c5p);
+  L.dc5r = reinterpret_cast<const int*>(base + o_c5r);
+  L.dr2p = reinterpret_cast<const int*>(base + o_r2p);
+  L.dr4p = reinterpret_cast<const int*>(base + o_r4p);
+  L.dqp = reinterpret_cast<const int*>(base + o_qp);
+}
+
+// P_H apply z = X_P^T (X_P r) and the p update for the P_H solves of the lists.
+template <typename T>
+void launch_ph_apply(qp_batch* B, const StepLists<T>& L, int init) {
+  qp_ctx* sk = &B->sink;
+  const int nph = (int)L.ph.size();
+  if (!nph) return;
+  HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nph, L.r4t, L.r4smem, 4));
+  HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nph, 5));
+  HIPCHK(sk, bpcg_ph_update<T>(B->stream, L.dph, nph, init));
+}
+
+// Run PCG for every item at once; returns when all have stopped.
+template <typename T>
+void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
+  qp_ctx* sk = &B->sink;
+  if (items.empty()) return;
+  std::vector<BItem<T>*> act;
+  int maxit_all = 0;
+  for (auto& it : items) {
+    act.push_back(&it);
+    maxit_all = std::max(maxit_all, it.maxit);
+  }
+  StepLists<T> L;
+  // the staging area may still feed an earlier copy: wait before rewriting it
+  HIPCHK(sk, hipStreamSynchronize(B->stream));
+  build_lists<T>(B, act, L);
+  const int nall = (int)act.size();
+  HIPCHK(sk, bpcg_init<T>(B->stream, L.dpd, nall));
+  launch_ph_apply<T>(B, L, 1);
+  const int poll = B->opt.poll_every > 0 ? B->opt.poll_every : 32;
+  long long launched = 0;
+  for (;;) {
+    if (launched > (long long)maxit_all + 2LL * poll) {
+      set_err(sk, "batched PCG made no progress after %lld launched steps", launched);
+      throw Fail{QP_E_DEVICE};
+    }
+    const int na = (int)act.size();
+    for (int k = 0; k < poll; ++k) {
+      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1));
+      HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2));
+      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3));
+      HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem));
+      HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
+      launch_ph_apply<T>(B, L, 0);
+    }
+    launched += poll;
+    B->cg_launched += poll;
+    int lo = kMaxSlots, hi = -1;
+    for (BItem<T>* it : act) {
+      const int pool = (int)(it->ctx->sc - B->d_sc);
+      lo = std::min(lo, pool);
+      hi = std::max(hi, pool);
+    }
+    sync_pools(B, lo, hi, false);
+    std::vector<BItem<T>*> still;
+    for (BItem<T>* it : act) {
+      const PcgScalars& h = B->h_sc[it->ctx->sc - B->d_sc];
+      if (h.done) {
+        it->iters = h.iter;
+        it->done = h.done;
+      } else {
+        still.push_back(it);
+      }
+    }
+    if (still.empty()) break;
+    if (still.size() != act.size()) {
+      act.swap(still);
+      build_lists<T>(B, act, L);  // the stream was just synchronized
+    }
+  }
+}
+
+// ---- batched reduced solve ----------------------------------------------------------
+struct RsItem {
+  Slot* slot;
+  const double* dvec;
+  const double* rhs;
+  double* dnu;
+  const double* wts;
+  double rtol, wtol;
+  int maxit;
+  int iters = 0, done = 0, refin = 0, fb = 0;
+  // mixed-precision sweep state
+  double prev_rr = -1.0;
+  bool sweeping = true;
+  bool to_fp64 = false;
+  double rtol64 = 0;
+  int last_done = 0;
+};
+
+void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items) {
+  qp_ctx* sk = &B->sink;
+  if (items.empty()) return;
+  if (B->opt.precision != QP_MIXED) {
+    std::vector<BItem<double>> bi;
+    for (auto& it : items) {
+      qp_ctx* c = it.slot->ctx;
+      bi.push_back(BItem<double>{c, bufs64(c, it.dvec, it.wts, it.dnu), it.rhs, it.slot->R.prec, it.rtol, it.wtol,
+                                 it.maxit});
+    }
+    run_bpcg<double>(B, bi);
+    for (size_t k = 0; k < items.size(); ++k) {
+      items[k].iters = bi[k].iters;
+      items[k].done = bi[k].done;
+    }
+    return;
+  }
+  // Mixed precision: the same refinement as the single-QP solve, with the
+  // float32 sweeps of all QPs batched and the float64 residuals per QP.
+  const double inner_rtol = 1e-5;
+  for (auto& it : items) {
+    qp_ctx* c = it.slot->ctx;
+    const int m2 = c->m2;
+    HIPCHK(c, (convert_1d<double, float>(B->stream, it.dvec, c->fd, m2)));
+    if (it.wts) HIPCHK(c, (convert_1d<double, float>(B->stream, it.wts, c->fwts, m2)));
+    HIPCHK(c, fill_vec<double>(B->stream, m2, 0.0, it.dnu));
+    HIPCHK(c, hipMemcpyAsync(c->ir_r, it.rhs, (size_t)m2 * sizeof(double), hipMemcpyDeviceToDevice, B->stream));
+    it.done = 2;
+  }
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    std::vector<RsItem*> act;
+    for (auto& it : items)
+      if (it.sweeping && it.iters < it.maxit) act.push_back(&it);
+    if (act.empty()) break;
+    std::vector<BItem<float>> bi;
+    for (RsItem* it : act) {
+      qp_ctx* c = it->slot->ctx;
+      HIPCHK(c, (convert_1d<double, float>(B->stream, c->ir_r, c->fb, c->m2)));
+      PcgBufs<float> bf = bufs32(c);
+      bf.wts = it->wts ? c->fwts : nullptr;
+      const int cap = mixed_inner_cap(c, it->slot->R.prec);
+      bi.push_back(BItem<float>{c, bf, c->fb, it->slot->R.prec, inner_rtol, -1.0, std::min(cap, it->maxit - it->iters)});
+    }
+    run_bpcg<float>(B, bi);
+    int lo = kMaxSlots, hi = -1;
+    for (size_t k = 0; k < act.size(); ++k) {
+      RsItem* it = act[k];
+      qp_ctx* c = it->slot->ctx;
+      it->iters += bi[k].iters;
+      it->last_done = bi[k].done;
+      HIPCHK(c, ir_accumulate(B->stream, c->m2, c->fx, it->dnu));
+      kf_apply_dev(c, it->dvec, it->dnu, c->ir_x);
+      HIPCHK(c, ir_residual(B->stream, c->m2, it->rhs, c->ir_x, it->wts, c->ir_r, c->sc));
+      lo = std::min(lo, it->slot->pool);
+      hi = std::max(hi, it->slot->pool);
+    }
+    sync_pools(B, lo, hi, false);
+    for (RsItem* it : act) {
+      const PcgScalars h = B->h_sc[it->slot->pool];
+      it->refin += 1;
+      if (h.bb == 0.0 || h.rr <= it->rtol * it->rtol * h.bb || (it->wtol >= 0.0 && h.wmax <= it->wtol)) {
+        it->done = 1;
+        it->sweeping = false;
+        continue;
+      }
+      const double ref_rr = it->prev_rr >= 0.0 ? it->prev_rr : h.bb;
+      const bool stalled = it->last_done != 1 || h.rr > 1e-2 * ref_rr || !std::isfinite(h.rr);
+      if (stalled && it->iters < it->maxit) {
+        it->to_fp64 = true;
+        it->rtol64 = h.rr > 0.0 ? it->rtol * std::sqrt(h.bb / h.rr) : it->rtol;
+        it->sweeping = false;
+        continue;
+      }
+      it->prev_rr = h.rr;
+    }
+  }
+  // float64 PCG on the remaining correction of the solves whose float32 sweeps stalled
+  std::vector<BItem<double>> bi;
+  std::vector<RsItem*> fbk;
+  for (auto& it : items) {
+    if (!it.to_fp64) continue;
+    qp_ctx* c = it.slot->ctx;
+    bi.push_back(BItem<double>{c, bufs64(c, it.dvec, it.wts, c->ir_d), c->ir_r, it.slot->R.prec, it.rtol64, it.wtol,
+                               it.maxit - it.iters});
+    fbk.push_back(&it);
+  }
+  run_bpcg<double>(B, bi);
+  for (size_t k = 0; k < fbk.size(); ++k) {
+    RsItem* it = fbk[k];
+    qp_ctx* c = it->slot->ctx;
+    it->iters += bi[k].iters;
+    HIPCHK(c, vec_add(B->stream, c->m2, c->ir_d, it->dnu));
+    it->done = bi[k].done;
+    it->fb = 1;
+  }
+  (void)sk;
+}
+
+// ---- slots ------------------------------------------------------------------------------
+void release_slot_memory(qp_batch* B, Slot* s) {
+  if (s->ctx) {
+    free_all(s->ctx);  // stream-ordered reuse: later work on the stream runs after this QP's
+    delete s->ctx;
+    s->ctx = nullptr;
+  }
+  if (s->pool >= 0) {
+    B->free_pools.push_back(s->pool);
+    s->pool = -1;
+  }
+}
+
+// Copy the final iterate to host memory and free the QP's device memory.
+void finish_slot(qp_batch* B, Slot* s, qp_status st) {
+  qp_ctx* c = s->ctx;
+  s->status = st;
+  if (st != QP_OK && s->err.empty()) s->err = c && !c->err.empty() ? c->err : qp_status_str(st);
+  if (c && s->state == kRunning) {
+    s->x.resize(c->n);
+    s->lam.resize(c->m1);
+    s->nu.resize(c->m2);
+    s->s.resize(c->m2);
+    HIPCHK(c, hipMemcpyAsync(s->x.data(), c->x, (size_t)c->n * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    HIPCHK(c, hipMemcpyAsync(s->lam.data(), c->lam, (size_t)c->m1 * sizeof(double), hipMemcpyDeviceToHost,
+                             B->stream));
+    HIPCHK(c, hipMemcpyAsync(s->nu.data(), c->nu, (size_t)c->m2 * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    HIPCHK(c, hipMemcpyAsync(s->s.data(), c->s, (size_t)c->m2 * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    HIPCHK(c, hipStreamSynchronize(B->stream));
+    ipm_fill_info(c, s->R, &s->info);
+  }
+  s->info.status = st;
+  s->t_done = Clock::now();
+  s->info.t_solve_ms = std::chrono::duration<double, std::milli>(s->t_done - s->t_admit).count();
+  s->state = kFinished;
+  release_slot_memory(B, s);
+  B->finished[s->ticket] = s;
+}
+
+// Run one per-QP phase; a failure of this QP alone (not of the device) retires it.
+template <typename F>
+bool per_qp(qp_batch* B, Slot* s, F&& f) {
+  try {
+    f();
+    return true;
+  } catch (const Fail& e) {
+    if (e.st == QP_E_DEVICE) throw;
+    s->err = s->ctx ? s->ctx->err : "";
+    finish_slot(B, s, e.st);
+    return false;
+  }
+}
+
+// One IPM iteration for every QP in flight (and the set-up of new ones).
+void run_round(qp_batch* B) {
+  // factor and start the QPs admitted since the last round
+  for (Slot* s : std::vector<Slot*>(B->live)) {
+    if (s->state != kQueued) continue;
+    per_qp(B, s, [&] {
+      factor(s->ctx);
+      ipm_start(s->ctx, s->R);
+      free_factor_scratch(s->ctx);
+      s->state = kRunning;
+    });
+  }
+  auto prune = [&] {
+    std::vector<Slot*> keep;
+    for (Slot* s : B->live)
+      if (s->state != kFinished) keep.push_back(s);
+    B->live.swap(keep);
+  };
+  prune();
+  if (B->live.empty()) return;
+  // residuals and statistics of every iterate, one copy and one wait for all
+  int lo = kMaxSlots, hi = -1;
+  for (Slot* s : B->live) {
+    ipm_eval_launch(s->ctx, false);
+    lo = std::min(lo, s->pool);
+    hi = std::max(hi, s->pool);
+  }
+  sync_pools(B, lo, hi, true);
+  std::vector<Slot*> go;
+  for (Slot* s : B->live) {
+    if (!ipm_check(s->ctx, s->R)) {
+      qp_status st = (qp_status)s->R.status;
+      if (st != QP_OK && s->ctx->err.empty())
+        set_err(s->ctx, "IPM stopped at rel_kkt %.3e after %d iterations", s->R.score, s->R.it);
+      finish_slot(B, s, st);
+      continue;
+    }
+    if (per_qp(B, s, [&] { ipm_predictor_setup(s->ctx, s->R); })) go.push_back(s);
+  }
+  prune();
+  if (go.empty()) return;
+  auto solve = [&](bool corrector) {
+    std::vector<RsItem> items;
+    for (Slot* s : go) {
+      qp_ctx* c = s->ctx;
+      RsItem it{};
+      it.slot = s;
+      it.dvec = c->dvec;
+      it.rhs = c->rhs;
+      it.dnu = corrector ? c->dnu : c->dnu_a;
+      it.wts = c->nu;
+      it.rtol = c->opt.cg_rtol;
+      it.wtol = s->R.wtol;
+      it.maxit = s->R.maxit;
+      items.push_back(it);
+    }
+    batched_reduced_solve(B, items);
+    for (auto& it : items) {
+      IpmRun& R = it.slot->R;
+      (corrector ? R.k2 : R.k1) = it.iters;
+      R.refin_total += it.refin;
+      R.fallbacks += it.fb;
+    }
+  };
+  solve(false);
+  for (Slot* s : go) ipm_after_predictor(s->ctx);
+  solve(true);
+  for (Slot* s : go) ipm_after_corrector(s->ctx, s->R);
+  B->rounds += 1;
+}
+
+template <typename F>
+qp_status batch_guard(qp_batch* B, F&& f) {
+  try {
+    f();
+    return QP_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::exception& e) {
+    set_err(&B->sink, "internal error: %s", e.what());
+    return QP_E_DEVICE;
+  } catch (...) {
+    set_err(&B->sink, "internal error");
+    return QP_E_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void qp_batch_destroy(qp_batch* B) {
+  if (!B) return;
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  for (Slot* s : B->live) {
+    release_slot_memory(B, s);
+    delete s;
+  }
+  for (auto& kv : B->finished) delete kv.second;
+  B->arena.release();
+  for (void* p : {(void*)B->d_sc, (void*)B->d_stats, (void*)B->d_info, (void*)B->d_stage})
+    if (p) (void)hipFree(p);
+  for (void* p : {(void*)B->h_sc, (void*)B->h_stats, (void*)B->h_info, (void*)B->h_isc, (void*)B->h_stage})
+    if (p) (void)hipHostFree(p);
+  if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+}
+
+qp_status qp_batch_create(qp_batch** out, const qp_options* opt, size_t hbm_budget_bytes, void* hip_stream) {
+  if (!out) return QP_E_INVALID;
+  *out = nullptr;
+  qp_options o;
+  qp_default_options(&o);
+  if (opt) o = *opt;
+  if (check_options(o) != QP_OK) return QP_E_INVALID;
+  qp_batch* B = new qp_batch();
+  B->opt = o;
+  qp_status st = batch_guard(B, [&] {
+    qp_ctx* sk = &B->sink;
+    HIPCHK(sk, hipGetDevice(&B->dev));
+    (void)dev_info();
+    if (hip_stream) {
+      B->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      HIPCHK(sk, hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
+      B->own_stream = true;
+    }
+    sk->stream = B->stream;
+    size_t budget = hbm_budget_bytes;
+    if (budget == 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(sk, hipMemGetInfo(&fr, &tot));
+      budget = fr / 10 * 8;
+    }
+    HIPCHK(sk, B->arena.init(budget));
+    HIPCHK(sk, hipMalloc((void**)&B->d_sc, kMaxSlots * sizeof(PcgScalars)));
+    HIPCHK(sk, hipMalloc((void**)&B->d_stats, (size_t)kMaxSlots * kStatsStride * sizeof(double)));
+    HIPCHK(sk, hipMalloc((void**)&B->d_info, (size_t)kMaxSlots * kInfoStride * sizeof(int)));
+    HIPCHK(sk, hipMemsetAsync(B->d_sc, 0, kMaxSlots * sizeof(PcgScalars), B->stream));
+    HIPCHK(sk, hipMemsetAsync(B->d_stats, 0, (size_t)kMaxSlots * kStatsStride * sizeof(double), B->stream));
+    HIPCHK(sk, hipMemsetAsync(B->d_info, 0, (size_t)kMaxSlots * kInfoStride * sizeof(int), B->stream));
+    HIPCHK(sk, hipHostMalloc((void**)&B->h_sc, kMaxSlots * sizeof(PcgScalars), hipHostMallocDefault));
+    HIPCHK(sk, hipHostMalloc((void**)&B->h_stats, (size_t)kMaxSlots * kStatsStride * sizeof(double),
+                             hipHostMallocDefault));
+    HIPCHK(sk, hipHostMalloc((void**)&B->h_info, (size_t)kMaxSlots * kInfoStride * sizeof(int),
+                             hipHostMallocDefault));
+    HIPCHK(sk, hipHostMalloc((void**)&B->h_isc, kMaxSlots * sizeof(IpmScalars), hipHostMallocDefault));
+    for (int k = kMaxSlots - 1; k >= 0; --k) B->free_pools.push_back(k);
+    HIPCHK(sk, hipStreamSynchronize(B->stream));
+  });
+  if (st != QP_OK) {
+    qp_batch_destroy(B);
+    return st;
+  }
+  *out = B;
+  return QP_OK;
+}
+
+qp_status qp_batch_admit(qp_batch* B, int n, int m1, int m2, const double* H, const double* c, const double* A,
+                         const double* b, const double* C, const double* d, qp_mem where, long long* ticket) {
+  if (!B || !ticket) return QP_E_INVALID;
+  *ticket = 0;
+  qp_status pst = check_problem(n, m1, m2, H, c, A, b, C, d, where);
+  if (pst != QP_OK) {
+    set_err(&B->sink, "invalid QP (n=%d m1=%d m2=%d)", n, m1, m2);
+    return pst;
+  }
+  const size_t need = footprint_bytes(n, m1, m2, B->opt, true, true);
+  if (B->free_pools.empty() || need > B->arena.capacity() - B->arena.used()) {
+    set_err(&B->sink, "not enough batch memory for the QP (%zu bytes needed, %zu free)", need,
+            B->arena.capacity() - B->arena.used());
+    return QP_E_NOMEM;
+  }
+  Slot* s = new Slot();
+  s->pool = B->free_pools.back();
+  B->free_pools.pop_back();
+  s->n = n;
+  s->m1 = m1;
+  s->m2 = m2;
+  qp_ctx* ctx = new qp_ctx();
+  s->ctx = ctx;
+  init_dims(ctx, n, m1, m2, B->opt);
+  ctx->dev = B->dev;
+  ctx->stream = B->stream;
+  ctx->arena = &B->arena;
+  ctx->pooled = true;
+  ctx->sc = B->d_sc + s->pool;
+  ctx->h_sc = B->h_sc + s->pool;
+  ctx->stats = B->d_stats + (size_t)s->pool * kStatsStride;
+  ctx->h_stats = B->h_stats + (size_t)s->pool * kStatsStride;
+  ctx->info = B->d_info + (size_t)s->pool * kInfoStride;
+  ctx->h_info = B->h_info + (size_t)s->pool * kInfoStride;
+  ctx->h_isc = B->h_isc + s->pool;
+  qp_status st = guarded(ctx, [&] {
+    alloc_all(ctx);
+    alloc_factor_scratch(ctx);
+    upload_problem(ctx, H, c, A, b, C, d, where);
+    // the caller's arrays may be released when this call returns
+    sync(ctx);
+  });
+  if (st != QP_OK) {
+    B->sink.err = ctx->err;
+    release_slot_memory(B, s);
+    delete s;
+    return st;
+  }
+  s->ticket = B->next_ticket++;
+  s->t_admit = Clock::now();
+  s->state = kQueued;
+  B->live.push_back(s);
+  *ticket = s->ticket;
+  return QP_OK;
+}
+
+qp_status qp_batch_step(qp_batch* B, int max_rounds, int* n_done) {
+  if (!B || max_rounds <= 0) return QP_E_INVALID;
+  B->sink.err.clear();
+  qp_status st = batch_guard(B, [&] {
+    for (int r = 0; r < max_rounds && !B->live.empty(); ++r) run_round(B);
+  });
+  if (n_done) *n_done = (int)B->finished.size();
+  return st;
+}
+
+qp_status qp_batch_finished(qp_batch* B, long long* tickets, int cap, int* count) {
+  if (!B || !count || cap < 0 || (cap > 0 && !tickets)) return QP_E_INVALID;
+  std::vector<long long> t;
+  for (auto& kv : B->finished) t.push_back(kv.first);
+  std::sort(t.begin(), t.end());
+  int k = 0;
+  for (; k < cap && k < (int)t.size(); ++k) tickets[k] = t[k];
+  *count = k;
+  return QP_OK;
+}
+
+qp_status qp_batch_collect(qp_batch* B, long long ticket, double* x, double* lambda, double* nu, double* s,
+                           qp_mem where, qp_ipm_info* info) {
+  if (!B || !x || !lambda || !nu || !s) return QP_E_INVALID;
+  if (where != QP_MEM_HOST && where != QP_MEM_DEVICE) return QP_E_INVALID;
+  auto f = B->finished.find(ticket);
+  if (f == B->finished.end()) {
+    for (Slot* l : B->live)
+      if (l->ticket == ticket) {
+        set_err(&B->sink, "ticket %lld has not finished", ticket);
+        return QP_E_STATE;
+      }
+    set_err(&B->sink, "unknown ticket %lld", ticket);
+    return QP_E_INVALID;
+  }
+  Slot* sl = f->second;
+  qp_status st = batch_guard(B, [&] {
+    auto put = [&](double* dst, const std::vector<double>& v) {
+      if (v.empty()) return;
+      if (where == QP_MEM_HOST)
+        memcpy(dst, v.data(), v.size() * sizeof(double));
+      else
+        HIPCHK(&B->sink, hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    put(x, sl->x);
+    put(lambda, sl->lam);
+    put(nu, sl->nu);
+    put(s, sl->s);
+  });
+  if (st != QP_OK) return st;
+  if (info) *info = sl->info;
+  qp_status result = sl->status;
+  if (result != QP_OK) B->sink.err = sl->err;
+  B->finished.erase(f);
+  delete sl;
+  return result;
+}
+
+qp_status qp_batch_query(const qp_batch* B, int* in_flight, int* finished, size_t* bytes_used,
+                         size_t* bytes_capacity, long long* rounds) {
+  if (!B) return QP_E_INVALID;
+  if (in_flight) *in_flight = (int)B->live.size();
+  if (finished) *finished = (int)B->finished.size();
+  if (bytes_used) *bytes_used = B->arena.used();
+  if (bytes_capacity) *bytes_capacity = B->arena.capacity();
+  if (rounds) *rounds = B->rounds;
+  return QP_OK;
+}
+
+size_t qp_batch_footprint(const qp_options* opt, int n, int m1, int m2) {
+  qp_options o;
+  qp_default_options(&o);
+  if (opt) o = *opt;
+  if (n <= 0 || m1 <= 0 || m1 > n || m2 <= 0 || check_options(o) != QP_OK) return 0;
+  return footprint_bytes(n, m1, m2, o, true, true);
+}
+
+const char* qp_batch_last_error(const qp_batch* B) { return B ? B->sink.err.c_str() : ""; }
+
+}  // extern "C"

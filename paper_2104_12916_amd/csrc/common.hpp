@@ -43,12 +43,10 @@ DevInfo& dev_info();
 
 // Launch shapes of the streaming sweeps.  Defaults were chosen by timing on
 // gfx950 (qp_op_time); the environment variable QPGPU_TUNE
-// ("rows_bpc=4,rows_unroll=8,cols_wide=1,cols_bpc=8") overrides them.
+// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0") overrides them.
 struct Tune {
   int rows_bpc = 2;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
   int rows_unroll = 4;  // 16-byte loads in flight per lane: 4 or 8
-  int cols_wide = 0;    // gemv_cols: 0 four waves split the rows of one 64-lane column tile,
-                        //            1 each wave owns its own column tile (4 per workgroup)
   int cols_bpc = 2;     // gemv_cols: target workgroups per CU
   int cols_unroll = 8;  // gemv_cols: rows in flight per wave: 4 or 8
   int ld_pad = 64;      // elements added to every matrix leading dimension (multiple of 64);

@@ -1,0 +1,226 @@
+// Per-QP context of the library and the host-side steps shared by the
+// single-QP entry points (api.hip) and the batch driver (batch.hip).  Every
+// arithmetic step runs in the kernels of gemv.hip, blas.hip, pcg.hip and
+// ipm.hip; these functions only order launches and copy scalar records.
+#pragma once
+#include <algorithm>
+#include <cstdarg>
+#include <iterator>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qpgpu.h"
+#include "kernels.hpp"
+#include "pcg.hpp"
+
+namespace qpg {
+
+// First-fit sub-allocator over one device allocation (256-byte granules).
+// Used by the batch so that admitting and retiring QPs never calls hipMalloc /
+// hipFree (which synchronize the device) and so that admission can be decided
+// by the bytes still free.  Host-side bookkeeping only; not thread-safe.
+class Arena {
+ public:
+  hipError_t init(size_t bytes);
+  void release();
+  void* alloc(size_t bytes);  // nullptr when no free range is large enough
+  void free(void* p);
+  size_t capacity() const { return cap_; }
+  size_t used() const { return used_bytes_; }
+  size_t largest_free() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_bytes_ = 0;
+  std::map<size_t, size_t> free_;               // offset -> size, coalesced
+  std::unordered_map<size_t, size_t> live_;     // offset -> size
+};
+
+constexpr int kProfOps = 6;
+constexpr int kStatsStride = 64;  // doubles per QP in the stats record
+
+}  // namespace qpg
+
+struct qp_ctx {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n = 0, m1 = 0, m2 = 0, N = 0;
+  int ldn = 0, ldN = 0, ldm2 = 0, ldm1 = 0;
+  qp_options opt{};
+  std::string err;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  // batch member: buffers come from the batch arena and the scalar records
+  // (sc, stats, info and their pinned mirrors) live in the batch's pools
+  qpg::Arena* arena = nullptr;
+  bool pooled = false;
+
+  // problem data (float64)
+  double *H = nullptr, *c = nullptr, *A = nullptr, *b = nullptr, *C = nullptr, *d = nullptr;
+  // inverse factor L^{-1} of K0 = L Sigma L^T (N x ldN, lower, explicit zeros above)
+  double* Linv = nullptr;
+  bool factored = false;
+  // P_H data: T = C H^{-1} C^T (fixed), P = D + T and X_P = chol(P)^{-1} (per D)
+  double *T = nullptr, *P = nullptr, *XP = nullptr, *ptmp = nullptr;
+  bool ph_ready = false;
+  // float32 copies for the mixed path
+  float *Linv32 = nullptr, *C32 = nullptr, *XP32 = nullptr;
+  // factorization scratch allocated ahead of time (batch admission); null: allocated by factor()
+  double *fHw = nullptr, *fWt = nullptr, *fS = nullptr, *fG = nullptr, *ftmp = nullptr, *fYt = nullptr;
+
+  // vectors (float64)
+  double *x = nullptr, *lam = nullptr, *nu = nullptr, *s = nullptr;
+  double *Hx = nullptr, *Atl = nullptr, *Ctn = nullptr, *Ax = nullptr, *Cx = nullptr;
+  double *rg = nullptr, *re = nullptr, *ri = nullptr;
+  double *dvec = nullptr, *rc = nullptr, *rhs = nullptr, *Cw = nullptr;
+  double *vN1 = nullptr, *vN2 = nullptr, *vN3 = nullptr;  // N-long scratch
+  double *dx = nullptr, *dlam = nullptr, *dnu = nullptr, *ds = nullptr;
+  double *dx_a = nullptr, *dlam_a = nullptr, *dnu_a = nullptr, *ds_a = nullptr;
+  // PCG vectors (float64)
+  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *pt = nullptr;
+  double *pu = nullptr, *pv = nullptr, *pw = nullptr;
+  double *ir_r = nullptr, *ir_x = nullptr, *ir_d = nullptr;  // refinement residual, K_F dnu, correction
+  // PCG vectors (float32)
+  float *fr = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr, *ft = nullptr, *fx = nullptr, *fb = nullptr;
+  float *fu = nullptr, *fv = nullptr, *fw = nullptr, *fd = nullptr, *fwts = nullptr;
+  // workspaces
+  qpg::GemvWork<double> w64{};
+  qpg::GemvWork<float> w32{};
+  double* bpart = nullptr;  // per-workgroup partials of p^T q
+  int bpart_cap = 0;
+  qpg::PcgScalars* sc = nullptr;
+  qpg::IpmScalars* isc = nullptr;
+  double* stats = nullptr;
+  int* info = nullptr;
+  // sampled kernel durations (options.profile): CG-step sweeps in the order
+  // C^T p, Sigma M u, M^T v, q = C w + D p, X_P r, X_P^T t
+  qpg::EventPair prof_ev[qpg::kProfOps] = {};
+  double prof_ms[qpg::kProfOps] = {};
+  long long prof_n[qpg::kProfOps] = {};
+  bool prof_ready = false;
+  // pinned host mirrors
+  qpg::PcgScalars* h_sc = nullptr;
+  qpg::IpmScalars* h_isc = nullptr;
+  double* h_stats = nullptr;
+  int* h_info = nullptr;
+};
+
+namespace qpg {
+namespace detail {
+
+struct Fail {
+  qp_status st;
+};
+
+void set_err(qp_ctx* ctx, const char* fmt, ...);
+void set_err_str(std::string& dst, const char* fmt, ...);
+
+#define HIPCHK(ctx, expr)                                                                                   \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess) {                                                                                 \
+      ::qpg::detail::set_err(ctx, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      throw ::qpg::detail::Fail{e_ == hipErrorOutOfMemory ? QP_E_NOMEM : QP_E_DEVICE};                       \
+    }                                                                                                       \
+  } while (0)
+
+void* dalloc_bytes(qp_ctx* ctx, size_t bytes);
+template <typename T>
+T* dalloc(qp_ctx* ctx, size_t elems) {
+  return static_cast<T*>(dalloc_bytes(ctx, (elems ? elems : 1) * sizeof(T)));
+}
+void dfree(qp_ctx* ctx, void* p);
+void free_all(qp_ctx* ctx);
+
+int ld_for(int cols);
+void upload_matrix(qp_ctx* ctx, double* dst, int ldd, const double* src, int rows, int cols, qp_mem where);
+void upload_vec(qp_ctx* ctx, double* dst, const double* src, int n, qp_mem where);
+void download_vec(qp_ctx* ctx, double* dst, const double* src, int n, qp_mem where);
+void sync(qp_ctx* ctx);
+bool finite_all(const double* v, size_t n);
+qp_status check_problem(int n, int m1, int m2, const double* H, const double* c, const double* A, const double* b,
+                        const double* C, const double* d, qp_mem where);
+qp_status check_options(const qp_options& o);
+qp_precond resolve_prec(const qp_ctx* ctx, qp_precond p);
+int prec_mode(qp_precond p);
+
+// Context set-up: sizes and leading dimensions, then every device buffer.
+void init_dims(qp_ctx* ctx, int n, int m1, int m2, const qp_options& o);
+void alloc_all(qp_ctx* ctx);
+// Factorization scratch held from admission until the factor is done (batch).
+void alloc_factor_scratch(qp_ctx* ctx);
+void free_factor_scratch(qp_ctx* ctx);
+// Device bytes alloc_all (+ the factorization scratch) takes, rounded as dalloc rounds.
+size_t footprint_bytes(int n, int m1, int m2, const qp_options& o, bool pooled, bool with_scratch);
+void upload_problem(qp_ctx* ctx, const double* H, const double* c, const double* A, const double* b,
+                    const double* C, const double* d, qp_mem where);
+
+// K0 = L Sigma L^T and its inverse factor; throws Fail on a bad pivot.
+void factor(qp_ctx* ctx);
+void ph_setup(qp_ctx* ctx);
+void ph_factor(qp_ctx* ctx, const double* dvec);
+void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN);
+void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q);
+
+// ---- CG buffers -----------------------------------------------------------
+template <typename T>
+struct PcgBufs {
+  const T *Linv, *C, *XP, *dvec, *wts;
+  T *r, *z, *p, *q, *t, *u, *v, *w, *x;
+  const GemvWork<T>* wk;
+};
+PcgBufs<double> bufs64(qp_ctx* ctx, const double* dvec, const double* wts, double* x);
+PcgBufs<float> bufs32(qp_ctx* ctx);
+// Iteration cap of one float32 sweep of the mixed solve: a little above the
+// distinct-eigenvalue bound of the preconditioned operator.
+int mixed_inner_cap(const qp_ctx* ctx, int prec);
+
+// ---- interior point phases ------------------------------------------------
+// Host-side bookkeeping of one QP's IPM run.
+struct IpmRun {
+  int prec = 0, maxit = 0, it = 0;
+  long long cg_total = 0;
+  int refin_total = 0, fallbacks = 0;
+  int k1 = 0, k2 = 0;
+  double score = 0, parts[5] = {0, 0, 0, 0, 0};
+  double mu = 0, wtol = 0;
+  int status = QP_E_NOCONV;
+};
+// Preconditioner, CG cap, P_H set-up and the initial point (launches only).
+void ipm_start(qp_ctx* ctx, IpmRun& R);
+// Residual products and statistics of the current iterate; with copy, also the
+// asynchronous copy of the statistics to ctx->h_stats.
+void ipm_eval_launch(qp_ctx* ctx, bool copy);
+// After the statistics reached the host: KKT score and stop decision.
+// Returns true when another iteration is due (then R.mu and R.wtol are set).
+bool ipm_check(qp_ctx* ctx, IpmRun& R);
+// r_nu pieces, D and the predictor right-hand side; P_H factor (launches only).
+void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R);
+// Recovery and step of the predictor, then the corrector right-hand side.
+void ipm_after_predictor(qp_ctx* ctx);
+// Recovery and step of the corrector; closes the iteration.
+void ipm_after_corrector(qp_ctx* ctx, IpmRun& R);
+void ipm_fill_info(const qp_ctx* ctx, const IpmRun& R, qp_ipm_info* info);
+double host_rel_kkt(const double* S, double parts[5]);
+
+template <typename F>
+qp_status guarded(qp_ctx* ctx, F&& f) {
+  try {
+    f();
+    return QP_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::exception& e) {
+    set_err(ctx, "internal error: %s", e.what());
+    return QP_E_DEVICE;
+  } catch (...) {
+    set_err(ctx, "internal error");
+    return QP_E_DEVICE;
+  }
+}
+
+}  // namespace detail
+}  // namespace qpg

@@ -15,6 +15,9 @@
 //               release/acquire pair per workgroup, measured 4-6x slower than
 //               the extra launch on gfx950.)
 //
+// Each sweep exists as a single-problem kernel and as a batched kernel that
+// walks a list of descriptors (desc.hpp), one per QP, so one launch streams the
+// matrices of many QPs of different sizes.  Both call the same device bodies.
 // Lower-triangular operands (row i holds columns 0..i, zeros above) are read
 // only up to the tile containing the diagonal.  Launch shapes come from tune().
 #include <cstdlib>
@@ -22,6 +25,7 @@
 
 #include "kernels.hpp"
 #include "gemv_core.hpp"
+#include "desc.hpp"
 
 namespace qpg {
 
@@ -40,7 +44,6 @@ Tune& tune() {
       int val = atoi(eq + 1);
       if (!strcmp(tok, "rows_bpc") && val >= 1 && val <= kMaxRowsBpc) v.rows_bpc = val;
       if (!strcmp(tok, "rows_unroll") && (val == 4 || val == 8)) v.rows_unroll = val;
-      if (!strcmp(tok, "cols_wide") && (val == 0 || val == 1)) v.cols_wide = val;
       if (!strcmp(tok, "cols_bpc") && val >= 1 && val <= kMaxColsBpc) v.cols_bpc = val;
       if (!strcmp(tok, "cols_unroll") && (val == 4 || val == 8)) v.cols_unroll = val;
       if (!strcmp(tok, "ld_pad") && val >= 0 && val <= 1024 && val % 64 == 0) v.ld_pad = val;
@@ -51,27 +54,21 @@ Tune& tune() {
 }
 
 // ---------------------------------------------------------------------------
-// gemv_rows: y_i = alpha * (A x)_i [* sign_i] + beta * y0_i
-//   shape kLower: row i uses columns [0, min(i + 1, k)).
-//   sign: rows i >= nsplit are negated (applies Sigma = diag(I, -I)).
-// TAG only separates launch sites in profiles (same code for every value):
-// 0 generic, 1 C^T p, 2 Sigma M u, 3 M^T v (the CG-step operator sweeps),
-// 4 X_P r, 5 X_P^T t (the P_H apply).
-template <typename T, int TAG, int U>
-__global__ void __launch_bounds__(256) gemv_rows_kernel(
-    const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x,
-    T* __restrict__ y, T alpha, T beta, const T* __restrict__ y0, int nsplit, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);
+// device bodies
+
+// Rows bid, bid + nb, ... (in units of 4 waves) of y = alpha A x (+ beta y0),
+// rows >= nsplit negated.  xs: LDS of at least round_chunk(min(m,k) or k) elements.
+template <typename T, int U>
+__device__ __forceinline__ void rows_body(const T* __restrict__ A, int lda, int m, int k, int shape,
+                                          const T* __restrict__ x, T* __restrict__ y, T alpha, T beta,
+                                          const T* __restrict__ y0, int nsplit, int bid, int nb, T* xs) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int waves = blockDim.x / kWave;
-  // rows are dealt round-robin over all waves of the grid, so every block sees
-  // rows up to the last one
+  // rows are dealt round-robin over all waves, so every block sees rows up to the last one
   const int maxlen = (shape == kLower) ? min(m, k) : k;
   const int lenR_max = round_chunk<T>(maxlen, lda);
   stage_x<T>(xs, x, k, lenR_max);
-  for (int i = blockIdx.x * waves + wave; i < m; i += gridDim.x * waves) {
+  for (int i = bid * waves + wave; i < m; i += nb * waves) {
     int len = (shape == kLower) ? min(i + 1, k) : k;
     int lenR = round_chunk<T>(len, lda);
     T v = row_dot<T, U>(A + (size_t)i * lda, xs, lenR, lane);
@@ -84,67 +81,45 @@ __global__ void __launch_bounds__(256) gemv_rows_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------
-// gemv_cols first pass.
-//   WIDE = 0: the 4 waves of a workgroup split the rows of one 64-lane column
-//             tile and are combined through LDS (block width = 1 tile).
-//   WIDE = 1: each wave owns its own column tile (block width = 4 tiles) and
-//             streams all rows of the chunk; no LDS.
-// part[chunk * ps + col] receives the chunk's partial sum of column col.
-template <typename T, int TAG, int WIDE, int U>
-__global__ void __launch_bounds__(256) gemv_cols_part_kernel(
-    const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x, T* __restrict__ part,
-    int rows_per_chunk, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  constexpr int VE = Vec16<T>::n;
-  constexpr int CW = kWave * VE;
-  constexpr int BW = WIDE ? 4 * CW : CW;
-  const int tile = blockIdx.x, chunk = blockIdx.y;
-  const size_t ps = (size_t)gridDim.x * BW;
-  const int b0 = tile * BW;
-  const int first_chunk = (shape == kLower) ? (b0 / rows_per_chunk) : 0;
-  if (chunk < first_chunk) return;
-  const int r0 = chunk * rows_per_chunk;
-  const int r1 = min(m, r0 + rows_per_chunk);
-  if (WIDE) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int c0 = b0 + wave * CW;
-    if (c0 >= k) return;  // this wave's tile lies past the last column (no further barrier)
-    T acc[VE];
-    cols_wave_partial<T, 8>(A, lda, r0, r1, c0, shape, x, acc);
-#pragma unroll
-    for (int e = 0; e < VE; ++e) part[(size_t)chunk * ps + c0 + lane * VE + e] = acc[e];
-  } else {
-    __shared__ T red[4][CW];
-    cols_block_partial<T, U>(A, lda, r0, r1, b0, shape, x, red);
-    if (threadIdx.x < CW) {
-      const int jj = threadIdx.x;
-      part[(size_t)chunk * ps + b0 + jj] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
-    }
+// First pass of a column sweep for one (tile, chunk) block.
+template <typename T, int U>
+__device__ __forceinline__ void cols_part_body(const T* __restrict__ A, int lda, int m, int shape,
+                                               const T* __restrict__ x, T* __restrict__ part, int rpc, int tile,
+                                               int chunk, int ntiles) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  const size_t ps = (size_t)ntiles * CW;
+  const int c0 = tile * CW;
+  const int first_chunk = (shape == kLower) ? (c0 / rpc) : 0;
+  if (chunk < first_chunk) return;  // whole block above the diagonal (uniform exit, before any barrier)
+  const int r0 = chunk * rpc;
+  const int r1 = min(m, r0 + rpc);
+  __shared__ T red[4][CW];
+  cols_block_partial<T, U>(A, lda, r0, r1, c0, shape, x, red);
+  if (threadIdx.x < CW) {
+    const int jj = threadIdx.x;
+    part[(size_t)chunk * ps + c0 + jj] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
   }
 }
 
-// Second pass: y_j = alpha * sum over chunks + beta * y0_j.  A 256-thread
-// workgroup handles 16 columns; the 16 threads of a column load chunks
-// ch = t, t + 16, ... (coalesced across columns) and combine them with a fixed
-// butterfly, so the summation order is the same on every run.
+// Second pass: y_j = alpha * sum over chunks + beta * y0_j for the 16 columns
+// of group `grp`.  The 16 threads of a column load chunks t, t + 16, ...
+// (coalesced across columns) and combine them with a fixed butterfly, so the
+// summation order is the same on every run.
 constexpr int kRedCols = 16;
 template <typename T>
-__global__ void __launch_bounds__(256) gemv_cols_reduce_kernel(int k, int ps, int bw, int shape,
-                                                               const T* __restrict__ part, int rows_per_chunk,
-                                                               int nchunks, T* __restrict__ y, T alpha, T beta,
-                                                               const T* __restrict__ y0,
-                                                               const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int c = threadIdx.x % kRedCols, t = threadIdx.x / kRedCols;  // column in block, chunk lane
-  const int col = blockIdx.x * kRedCols + c;
+__device__ __forceinline__ void cols_reduce_body(int k, int ps, int shape, const T* __restrict__ part, int rpc,
+                                                 int nchunks, T* __restrict__ y, T alpha, T beta,
+                                                 const T* __restrict__ y0, int grp) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  const int c = threadIdx.x % kRedCols, t = threadIdx.x / kRedCols;
+  const int col = grp * kRedCols + c;
   T s = 0;
   if (col < k) {
-    const int first_chunk = (shape == kLower) ? ((col / bw) * bw / rows_per_chunk) : 0;
+    const int first_chunk = (shape == kLower) ? ((col / CW) * CW / rpc) : 0;
     for (int ch = first_chunk + t; ch < nchunks; ch += 256 / kRedCols) s += part[(size_t)ch * ps + col];
   }
-  // lanes of one column are kRedCols apart inside the wave (threads t*16 + c):
-  // reduce the 4 chunk lanes of this wave, then the 4 waves through LDS
+  // lanes of one column are kRedCols apart inside the wave: reduce the wave's
+  // 4 chunk lanes, then the 4 waves through LDS
 #pragma unroll
   for (int off = 32; off >= kRedCols; off >>= 1) s += __shfl_xor(s, off, kWave);
   __shared__ T sh[4][kRedCols];
@@ -159,12 +134,86 @@ __global__ void __launch_bounds__(256) gemv_cols_reduce_kernel(int k, int ps, in
 }
 
 // ---------------------------------------------------------------------------
+// single-problem kernels.  TAG only separates launch sites in profiles (same
+// code for every value): 0 generic, 1 C^T p, 2 Sigma M u, 3 M^T v (the CG-step
+// operator sweeps), 4 X_P r, 5 X_P^T t (the P_H apply).
+template <typename T, int TAG, int U>
+__global__ void __launch_bounds__(256) gemv_rows_kernel(
+    const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x,
+    T* __restrict__ y, T alpha, T beta, const T* __restrict__ y0, int nsplit, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  rows_body<T, U>(A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, blockIdx.x, gridDim.x,
+                  reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int TAG, int U>
+__global__ void __launch_bounds__(256) gemv_cols_part_kernel(
+    const T* __restrict__ A, int lda, int m, int shape, const T* __restrict__ x, T* __restrict__ part, int rpc,
+    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  cols_part_body<T, U>(A, lda, m, shape, x, part, rpc, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) gemv_cols_reduce_kernel(int k, int ps, int shape, const T* __restrict__ part,
+                                                               int rpc, int nchunks, T* __restrict__ y, T alpha,
+                                                               T beta, const T* __restrict__ y0,
+                                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  cols_reduce_body<T>(k, ps, shape, part, rpc, nchunks, y, alpha, beta, y0, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels (one flattened grid over a descriptor list)
+template <typename T, int TAG, int U>
+__global__ void __launch_bounds__(256) bgemv_rows_kernel(const RowsDesc<T>* __restrict__ descs,
+                                                         const int* __restrict__ prefix, int ndesc) {
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const RowsDesc<T> d = descs[j];
+  if (d.skip && *d.skip) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  rows_body<T, U>(d.A, d.lda, d.m, d.k, d.shape, d.x, d.y, d.alpha, d.beta, d.y0, d.nsplit, blockIdx.x - prefix[j],
+                  d.nblocks, reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int TAG, int U>
+__global__ void __launch_bounds__(256) bgemv_cols_part_kernel(const ColsDesc<T>* __restrict__ descs,
+                                                              const int* __restrict__ prefix, int ndesc) {
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const ColsDesc<T> d = descs[j];
+  if (d.skip && *d.skip) return;
+  const int local = blockIdx.x - prefix[j];
+  cols_part_body<T, U>(d.A, d.lda, d.m, d.shape, d.x, d.part, d.rpc, local % d.tiles, local / d.tiles, d.tiles);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) bgemv_cols_reduce_kernel(const ColsDesc<T>* __restrict__ descs,
+                                                                const int* __restrict__ prefix, int ndesc) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const ColsDesc<T> d = descs[j];
+  if (d.skip && *d.skip) return;
+  cols_reduce_body<T>(d.k, d.tiles * CW, d.shape, d.part, d.rpc, d.nchunks, d.y, d.alpha, d.beta, d.y0,
+                      blockIdx.x - prefix[j]);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 template <typename T>
 int gemv_rows_grid(int m) {
   int blocks = (m + 3) / 4;
   int cap = dev_info().cu_count * tune().rows_bpc;
   return blocks < cap ? blocks : cap;
+}
+
+template <typename T>
+size_t rows_smem_bytes(int m, int k, int shape, int lda) {
+  constexpr int CH = kWave * Vec16<T>::n;
+  int maxlen = (shape == kLower) ? (m < k ? m : k) : k;
+  int lenR = (maxlen + CH - 1) / CH * CH;
+  if (lenR > lda) lenR = lda;
+  return (size_t)lenR * sizeof(T);
 }
 
 template <typename T, int TAG>
@@ -183,11 +232,7 @@ template <typename T>
 hipError_t launch_gemv_rows(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y,
                             T alpha, T beta, const T* y0, int nsplit, const int* skip, int tag, const EventPair* ev) {
   if (m <= 0) return hipSuccess;
-  constexpr int CH = kWave * Vec16<T>::n;
-  int maxlen = (shape == kLower) ? (m < k ? m : k) : k;
-  int lenR = (maxlen + CH - 1) / CH * CH;
-  if (lenR > lda) lenR = lda;
-  size_t smem = (size_t)lenR * sizeof(T);
+  size_t smem = rows_smem_bytes<T>(m, k, shape, lda);
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   if (nsplit < 0) nsplit = m;
   dim3 grid(gemv_rows_grid<T>(m));
@@ -199,14 +244,13 @@ hipError_t launch_gemv_rows(hipStream_t st, const T* A, int lda, int m, int k, i
   return hipGetLastError();
 }
 
-// Column tiling: block width bw (columns), chunks of rows_per_chunk rows.
+// Column tiling: 64-lane tiles of CW columns, chunks of rows_per_chunk rows,
+// about target_blocks workgroups over the whole sweep.
 template <typename T>
-void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& bw) {
+void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& tiles, int target_blocks) {
   constexpr int CW = kWave * Vec16<T>::n;
-  bw = tune().cols_wide ? 4 * CW : CW;
-  int tiles = (k + bw - 1) / bw;
-  int target = dev_info().cu_count * tune().cols_bpc;
-  int nc = target / (tiles > 0 ? tiles : 1);
+  tiles = (k + CW - 1) / CW;
+  int nc = target_blocks / (tiles > 0 ? tiles : 1);
   int maxc = (m + 15) / 16;
   if (nc > maxc) nc = maxc;
   if (nc < 1) nc = 1;
@@ -217,63 +261,182 @@ void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& bw) {
   nchunks = (m + rpc - 1) / rpc;
 }
 
+// Exact partial-buffer sizes (elements) of one column sweep over an m x k
+// operand: in the single-problem launch shape and in the batched shape.
+template <typename T>
+size_t gemv_cols_need(int m, int k) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  if (m <= 0 || k <= 0) return 0;
+  int rpc, nch, tiles;
+  gemv_cols_plan<T>(m, k, rpc, nch, tiles, dev_info().cu_count * tune().cols_bpc);
+  return (size_t)nch * tiles * CW;
+}
+
+template <typename T>
+static int bcols_target(int m, int k) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  // about 64 rows per chunk: enough work per workgroup without a large reduction
+  return ((k + CW - 1) / CW) * ((m + 63) / 64);
+}
+
+template <typename T>
+size_t bgemv_cols_need(int m, int k) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  if (m <= 0 || k <= 0) return 0;
+  int rpc, nch, tiles;
+  gemv_cols_plan<T>(m, k, rpc, nch, tiles, bcols_target<T>(m, k));
+  return (size_t)nch * tiles * CW;
+}
+
 size_t gemv_cols_part_elems(int max_ld) {
-  // chunks <= max(1, target / tiles), so chunks * tiles * bw <= target * bw + tiles * bw
-  return (size_t)dev_info().cu_count * kMaxColsBpc * 1024 + (size_t)max_ld + 4096;
+  // chunks <= max(1, target / tiles), so chunks * tiles * CW <= target * CW + tiles * CW
+  return (size_t)dev_info().cu_count * kMaxColsBpc * 256 + (size_t)max_ld + 4096;
 }
 
 template <typename T, int TAG>
-static void launch_cols_tag(dim3 grid, hipStream_t st, const EventPair* ev, const T* A, int lda, int m, int k,
-                            int shape, const T* x, T* part, int rpc, const int* skip) {
-  if (tune().cols_wide)
-    QPG_LAUNCH((gemv_cols_part_kernel<T, TAG, 1, 8>), grid, dim3(256), 0u, st, ev, A, lda, m, k, shape, x, part, rpc,
-               skip);
-  else if (tune().cols_unroll == 8)
-    QPG_LAUNCH((gemv_cols_part_kernel<T, TAG, 0, 8>), grid, dim3(256), 0u, st, ev, A, lda, m, k, shape, x, part, rpc,
-               skip);
+static void launch_cols_tag(dim3 grid, hipStream_t st, const EventPair* ev, const T* A, int lda, int m, int shape,
+                            const T* x, T* part, int rpc, const int* skip) {
+  if (tune().cols_unroll == 8)
+    QPG_LAUNCH((gemv_cols_part_kernel<T, TAG, 8>), grid, dim3(256), 0u, st, ev, A, lda, m, shape, x, part, rpc, skip);
   else
-    QPG_LAUNCH((gemv_cols_part_kernel<T, TAG, 0, 4>), grid, dim3(256), 0u, st, ev, A, lda, m, k, shape, x, part, rpc,
-               skip);
+    QPG_LAUNCH((gemv_cols_part_kernel<T, TAG, 4>), grid, dim3(256), 0u, st, ev, A, lda, m, shape, x, part, rpc, skip);
 }
 
 template <typename T>
 hipError_t launch_gemv_cols(hipStream_t st, const T* A, int lda, int m, int k, int shape, const T* x, T* y,
                             T alpha, T beta, const T* y0, const GemvWork<T>& w, const int* skip, int tag,
                             const EventPair* ev) {
+  constexpr int CW = kWave * Vec16<T>::n;
   if (k <= 0) return hipSuccess;
   if (m <= 0) return hipErrorInvalidValue;
   if (shape == kLower && k > m) return hipErrorInvalidValue;  // every column tile must meet a row chunk
-  int rpc, nch, bw;
-  gemv_cols_plan<T>(m, k, rpc, nch, bw);
-  const int tiles = (k + bw - 1) / bw;
-  if ((size_t)nch * tiles * bw > w.part_elems) return hipErrorInvalidValue;
-  constexpr int CW = kWave * Vec16<T>::n;
-  if ((k + CW - 1) / CW * CW > lda) return hipErrorInvalidValue;  // every active 64-lane tile reads inside the row
+  int rpc, nch, tiles;
+  gemv_cols_plan<T>(m, k, rpc, nch, tiles, dev_info().cu_count * tune().cols_bpc);
+  if ((size_t)nch * tiles * CW > w.part_elems) return hipErrorInvalidValue;
+  if (tiles * CW > lda) return hipErrorInvalidValue;  // the last tile reads inside the padded row
   dim3 grid(tiles, nch);
   switch (tag) {
-    case 1: launch_cols_tag<T, 1>(grid, st, ev, A, lda, m, k, shape, x, w.part, rpc, skip); break;
-    case 3: launch_cols_tag<T, 3>(grid, st, ev, A, lda, m, k, shape, x, w.part, rpc, skip); break;
-    case 5: launch_cols_tag<T, 5>(grid, st, ev, A, lda, m, k, shape, x, w.part, rpc, skip); break;
-    default: launch_cols_tag<T, 0>(grid, st, ev, A, lda, m, k, shape, x, w.part, rpc, skip);
+    case 1: launch_cols_tag<T, 1>(grid, st, ev, A, lda, m, shape, x, w.part, rpc, skip); break;
+    case 3: launch_cols_tag<T, 3>(grid, st, ev, A, lda, m, shape, x, w.part, rpc, skip); break;
+    case 5: launch_cols_tag<T, 5>(grid, st, ev, A, lda, m, shape, x, w.part, rpc, skip); break;
+    default: launch_cols_tag<T, 0>(grid, st, ev, A, lda, m, shape, x, w.part, rpc, skip);
   }
   hipLaunchKernelGGL(gemv_cols_reduce_kernel<T>, dim3((k + kRedCols - 1) / kRedCols), dim3(256), 0, st, k,
-                     tiles * bw, bw, shape, w.part, rpc, nch, y, alpha, beta, y0, skip);
+                     tiles * CW, shape, w.part, rpc, nch, y, alpha, beta, y0, skip);
   return hipGetLastError();
 }
 
-template int gemv_rows_grid<double>(int);
-template int gemv_rows_grid<float>(int);
-template hipError_t launch_gemv_rows<double>(hipStream_t, const double*, int, int, int, int, const double*, double*,
-                                             double, double, const double*, int, const int*, int, const EventPair*);
-template hipError_t launch_gemv_rows<float>(hipStream_t, const float*, int, int, int, int, const float*, float*,
-                                            float, float, const float*, int, const int*, int, const EventPair*);
-template hipError_t launch_gemv_cols<double>(hipStream_t, const double*, int, int, int, int, const double*, double*,
-                                             double, double, const double*, const GemvWork<double>&, const int*, int,
-                                             const EventPair*);
-template hipError_t launch_gemv_cols<float>(hipStream_t, const float*, int, int, int, int, const float*, float*,
-                                            float, float, const float*, const GemvWork<float>&, const int*, int,
-                                            const EventPair*);
-template void gemv_cols_plan<double>(int, int, int&, int&, int&);
-template void gemv_cols_plan<float>(int, int, int&, int&, int&);
+// ---- batched launchers ----------------------------------------------------
+template <typename T>
+void fill_rows_desc(RowsDesc<T>& d, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha, T beta,
+                    const T* y0, int nsplit, const int* skip) {
+  d.A = A;
+  d.lda = lda;
+  d.m = m;
+  d.k = k;
+  d.shape = shape;
+  d.x = x;
+  d.y = y;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.y0 = y0;
+  d.nsplit = nsplit < 0 ? m : nsplit;
+  d.skip = skip;
+  // a batch has many problems in flight, so each gets about one row per wave
+  int blocks = (m + 15) / 16;
+  d.nblocks = blocks < 1 ? 1 : blocks;
+}
+
+template <typename T>
+bool fill_cols_desc(ColsDesc<T>& d, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha, T beta,
+                    const T* y0, T* part, size_t part_elems, const int* skip) {
+  constexpr int CW = kWave * Vec16<T>::n;
+  d.A = A;
+  d.lda = lda;
+  d.m = m;
+  d.k = k;
+  d.shape = shape;
+  d.x = x;
+  d.y = y;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.y0 = y0;
+  d.part = part;
+  d.skip = skip;
+  gemv_cols_plan<T>(m, k, d.rpc, d.nchunks, d.tiles, bcols_target<T>(m, k));
+  d.nblocks = d.tiles * d.nchunks;
+  d.rblocks = (k + kRedCols - 1) / kRedCols;
+  return (size_t)d.nchunks * d.tiles * CW <= part_elems && d.tiles * CW <= lda && !(shape == kLower && k > m);
+}
+
+template <typename T>
+hipError_t launch_bgemv_rows(hipStream_t st, const RowsDesc<T>* ddesc, const int* dprefix, int ndesc, int total_blocks,
+                             size_t smem, int tag) {
+  if (ndesc <= 0 || total_blocks <= 0) return hipSuccess;
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  dim3 grid(total_blocks);
+  const bool u8 = tune().rows_unroll == 8;
+  switch (tag) {
+    case 2:
+      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 2, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 2, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+      break;
+    case 4:
+      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 4, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 4, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+      break;
+    default:
+      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 0, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 0, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int* dprefix_part, int total_part,
+                             const int* dprefix_red, int total_red, int ndesc, int tag) {
+  if (ndesc <= 0 || total_part <= 0) return hipSuccess;
+  const bool u8 = tune().cols_unroll == 8;
+  dim3 grid(total_part);
+  switch (tag) {
+    case 1:
+      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 1, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 1, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      break;
+    case 3:
+      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 3, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 3, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      break;
+    case 5:
+      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 5, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 5, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      break;
+    default:
+      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 0, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 0, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+  }
+  hipLaunchKernelGGL(bgemv_cols_reduce_kernel<T>, dim3(total_red), dim3(256), 0, st, ddesc, dprefix_red, ndesc);
+  return hipGetLastError();
+}
+
+#define QPG_GEMV_INST(T)                                                                                          \
+  template int gemv_rows_grid<T>(int);                                                                            \
+  template size_t rows_smem_bytes<T>(int, int, int, int);                                                         \
+  template hipError_t launch_gemv_rows<T>(hipStream_t, const T*, int, int, int, int, const T*, T*, T, T,          \
+                                          const T*, int, const int*, int, const EventPair*);                     \
+  template hipError_t launch_gemv_cols<T>(hipStream_t, const T*, int, int, int, int, const T*, T*, T, T,          \
+                                          const T*, const GemvWork<T>&, const int*, int, const EventPair*);      \
+  template void gemv_cols_plan<T>(int, int, int&, int&, int&, int);                                               \
+  template size_t gemv_cols_need<T>(int, int);                                                                    \
+  template size_t bgemv_cols_need<T>(int, int);                                                                   \
+  template void fill_rows_desc<T>(RowsDesc<T>&, const T*, int, int, int, int, const T*, T*, T, T, const T*, int,  \
+                                  const int*);                                                                    \
+  template bool fill_cols_desc<T>(ColsDesc<T>&, const T*, int, int, int, int, const T*, T*, T, T, const T*, T*,  \
+                                  size_t, const int*);                                                            \
+  template hipError_t launch_bgemv_rows<T>(hipStream_t, const RowsDesc<T>*, const int*, int, int, size_t, int);   \
+  template hipError_t launch_bgemv_cols<T>(hipStream_t, const ColsDesc<T>*, const int*, int, const int*, int,     \
+                                           int, int);
+QPG_GEMV_INST(double)
+QPG_GEMV_INST(float)
 
 }  // namespace qpg

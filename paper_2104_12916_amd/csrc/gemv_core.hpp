@@ -131,44 +131,6 @@ __device__ __forceinline__ void cols_block_partial(const T* __restrict__ A, int 
   __syncthreads();
 }
 
-// Per-wave partial of y_j = sum_i A_ij x_i over rows [r0, r1) for the column
-// tile starting at c0 (64 lanes x 16 B), U rows in flight; the result is
-// returned in acc (each lane its 16 bytes of columns).  Shape kLower skips rows
-// above the diagonal of the tile.
-template <typename T, int U>
-__device__ __forceinline__ void cols_wave_partial(const T* __restrict__ A, int lda, int r0, int r1, int c0, int shape,
-                                                  const T* __restrict__ x, T* acc) {
-  using V = typename Vec16<T>::type;
-  constexpr int VE = Vec16<T>::n;
-  const int lane = threadIdx.x % kWave;
-#pragma unroll
-  for (int e = 0; e < VE; ++e) acc[e] = 0;
-  const int j = c0 + lane * VE;
-  int i = r0;
-  if (shape == kLower && i < c0) i = c0;
-  for (; i < r1; i += U) {
-    V a[U];
-    T xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int ii = i + u;
-      if (ii < r1) {
-        a[u] = __builtin_nontemporal_load(reinterpret_cast<const V*>(A + (size_t)ii * lda + j));
-        xv[u] = x[ii];
-      } else {
-        xv[u] = 0;
-#pragma unroll
-        for (int e = 0; e < VE; ++e) a[u][e] = 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int e = 0; e < VE; ++e) acc[e] += a[u][e] * xv[u];
-    }
-  }
-}
-
 // Block-wide sum (and max) helpers for 256-thread blocks.
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* sh /* >= 4 */) {

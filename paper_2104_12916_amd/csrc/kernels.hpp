@@ -1,6 +1,7 @@
 // Internal launcher declarations (not part of the C ABI).
 #pragma once
 #include "common.hpp"
+#include "desc.hpp"
 
 namespace qpg {
 
@@ -14,10 +15,29 @@ hipError_t launch_gemv_cols(hipStream_t st, const T* A, int lda, int m, int k, i
                             T beta, const T* y0, const GemvWork<T>& w, const int* skip, int tag = 0,
                             const EventPair* ev = nullptr);
 template <typename T>
-void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& bw);
+void gemv_cols_plan(int m, int k, int& rows_per_chunk, int& nchunks, int& tiles, int target_blocks);
 template <typename T>
 int gemv_rows_grid(int m);
+template <typename T>
+size_t rows_smem_bytes(int m, int k, int shape, int lda);
 size_t gemv_cols_part_elems(int max_ld);
+template <typename T>
+size_t gemv_cols_need(int m, int k);   // single-problem launch shape
+template <typename T>
+size_t bgemv_cols_need(int m, int k);  // batched launch shape
+// batched sweeps over descriptor lists (desc.hpp)
+template <typename T>
+void fill_rows_desc(RowsDesc<T>& d, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha, T beta,
+                    const T* y0, int nsplit, const int* skip);
+template <typename T>
+bool fill_cols_desc(ColsDesc<T>& d, const T* A, int lda, int m, int k, int shape, const T* x, T* y, T alpha, T beta,
+                    const T* y0, T* part, size_t part_elems, const int* skip);
+template <typename T>
+hipError_t launch_bgemv_rows(hipStream_t st, const RowsDesc<T>* ddesc, const int* dprefix, int ndesc, int total_blocks,
+                             size_t smem, int tag);
+template <typename T>
+hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int* dprefix_part, int total_part,
+                             const int* dprefix_red, int total_red, int ndesc, int tag);
 
 // blas.hip -----------------------------------------------------------------
 // Tile skip rules for GEMM operands with known zero blocks (indices in op()

@@ -17,7 +17,8 @@
 // Scalars live in device memory (PcgScalars); every kernel returns at once
 // when the stop flag is set, so the host only polls every few steps.  The
 // reductions over workgroup partials run in a single workgroup in a fixed
-// order, so a solve is bitwise reproducible.
+// order, so a solve is bitwise reproducible.  Each kernel also has a batched
+// form over PcgDesc lists (one CG solve per QP) that runs the same body.
 #include "kernels.hpp"
 #include "gemv_core.hpp"
 #include "pcg.hpp"
@@ -35,13 +36,14 @@ __device__ __forceinline__ void pcg_check_stop(PcgScalars* sc, double rr, double
 }
 
 // --------------------------------------------------------------------------
+// device bodies
+
 // x = 0, r = b, (z = P^{-1} r, p = z, rho = r^T z for P_L / none), stop tests.
 template <typename T>
-__global__ void __launch_bounds__(kUpd) pcg_init_kernel(int m2, const T* __restrict__ b, const T* __restrict__ dvec,
-                                                        const T* __restrict__ wts, T* __restrict__ x,
-                                                        T* __restrict__ r, T* __restrict__ z, T* __restrict__ p,
-                                                        int prec, double rtol, double wtol, int maxit,
-                                                        PcgScalars* __restrict__ sc) {
+__device__ __forceinline__ void init_body(int m2, const T* __restrict__ b, const T* __restrict__ dvec,
+                                          const T* __restrict__ wts, T* __restrict__ x, T* __restrict__ r,
+                                          T* __restrict__ z, T* __restrict__ p, int prec, double rtol, double wtol,
+                                          int maxit, PcgScalars* __restrict__ sc) {
   __shared__ double sh[16];
   double bb = 0, rz = 0, wm = 0;
   for (int i = threadIdx.x; i < m2; i += blockDim.x) {
@@ -75,23 +77,18 @@ __global__ void __launch_bounds__(kUpd) pcg_init_kernel(int m2, const T* __restr
   }
 }
 
-// --------------------------------------------------------------------------
-// q = C w + D p over rows of C (one wavefront per row, w staged in LDS), and
-// the workgroup's partial of p^T q.
+// Rows of q = C w + D p dealt to workgroup bid of nb (one wavefront per row,
+// w staged in LDS), and the workgroup's partial of p^T q into bpart[bid].
 template <typename T, int U>
-__global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int ldc, int m2, int n,
-                                                    const T* __restrict__ w, const T* __restrict__ dvec,
-                                                    const T* __restrict__ p, T* __restrict__ q,
-                                                    const PcgScalars* __restrict__ sc, double* __restrict__ bpart) {
-  if (sc->done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* ws = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2, int n, const T* __restrict__ w,
+                                       const T* __restrict__ dvec, const T* __restrict__ p, T* __restrict__ q,
+                                       double* __restrict__ bpart, int bid, int nb, T* ws) {
   __shared__ double sh[16];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
   const int lenR = round_chunk<T>(n, ldc);
   stage_x<T>(ws, w, n, lenR);
   double pq = 0;
-  for (int i = blockIdx.x * waves + wave; i < m2; i += gridDim.x * waves) {
+  for (int i = bid * waves + wave; i < m2; i += nb * waves) {
     T v = row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane);
     if (lane == 0) {
       T pi = p[i];
@@ -101,20 +98,16 @@ __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int
     }
   }
   pq = block_sum<double>(pq, sh);
-  if (threadIdx.x == 0) bpart[blockIdx.x] = pq;
+  if (threadIdx.x == 0) bpart[bid] = pq;
 }
 
-// --------------------------------------------------------------------------
 // The vector part of the step: alpha = rho / p^T q, dnu += alpha p,
 // r -= alpha q, stop tests; for P_L / none also z, rho' = r^T z, beta, p.
 template <typename T>
-__global__ void __launch_bounds__(kUpd) pcg_update_kernel(int m2, int nparts, const double* __restrict__ bpart,
-                                                          const T* __restrict__ dvec, T* __restrict__ p,
-                                                          const T* __restrict__ q, T* __restrict__ x,
-                                                          T* __restrict__ r, T* __restrict__ z,
-                                                          const T* __restrict__ wts, int prec,
-                                                          PcgScalars* __restrict__ sc) {
-  if (sc->done) return;
+__device__ __forceinline__ void update_body(int m2, int nparts, const double* __restrict__ bpart,
+                                            const T* __restrict__ dvec, T* __restrict__ p, const T* __restrict__ q,
+                                            T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                            const T* __restrict__ wts, int prec, PcgScalars* __restrict__ sc) {
   __shared__ double sh[16];
   __shared__ double alpha_s, beta_s;
   __shared__ int stop_s;
@@ -167,14 +160,11 @@ __global__ void __launch_bounds__(kUpd) pcg_update_kernel(int m2, int nparts, co
   for (int i = threadIdx.x; i < m2; i += blockDim.x) p[i] = z[i] + bt * p[i];
 }
 
-// --------------------------------------------------------------------------
 // After z = P_H^{-1} r: rho' = r^T z, beta = rho' / rho (0 on the first step),
 // p = z + beta p.
 template <typename T>
-__global__ void __launch_bounds__(kUpd) pcg_ph_update_kernel(int m2, const T* __restrict__ r,
-                                                             const T* __restrict__ z, T* __restrict__ p, int init,
-                                                             PcgScalars* __restrict__ sc) {
-  if (sc->done) return;
+__device__ __forceinline__ void ph_update_body(int m2, const T* __restrict__ r, const T* __restrict__ z,
+                                               T* __restrict__ p, int init, PcgScalars* __restrict__ sc) {
   __shared__ double sh[16];
   __shared__ double beta_s;
   double rz = 0;
@@ -188,6 +178,80 @@ __global__ void __launch_bounds__(kUpd) pcg_ph_update_kernel(int m2, const T* __
   __syncthreads();
   const T bt = (T)beta_s;
   for (int i = threadIdx.x; i < m2; i += blockDim.x) p[i] = init ? z[i] : z[i] + bt * p[i];
+}
+
+// --------------------------------------------------------------------------
+// single-solve kernels
+template <typename T>
+__global__ void __launch_bounds__(kUpd) pcg_init_kernel(int m2, const T* __restrict__ b, const T* __restrict__ dvec,
+                                                        const T* __restrict__ wts, T* __restrict__ x,
+                                                        T* __restrict__ r, T* __restrict__ z, T* __restrict__ p,
+                                                        int prec, double rtol, double wtol, int maxit,
+                                                        PcgScalars* __restrict__ sc) {
+  init_body<T>(m2, b, dvec, wts, x, r, z, p, prec, rtol, wtol, maxit, sc);
+}
+
+template <typename T, int U>
+__global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int ldc, int m2, int n,
+                                                    const T* __restrict__ w, const T* __restrict__ dvec,
+                                                    const T* __restrict__ p, T* __restrict__ q,
+                                                    const PcgScalars* __restrict__ sc, double* __restrict__ bpart) {
+  if (sc->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  q_body<T, U>(C, ldc, m2, n, w, dvec, p, q, bpart, blockIdx.x, gridDim.x, reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kUpd) pcg_update_kernel(int m2, int nparts, const double* __restrict__ bpart,
+                                                          const T* __restrict__ dvec, T* __restrict__ p,
+                                                          const T* __restrict__ q, T* __restrict__ x,
+                                                          T* __restrict__ r, T* __restrict__ z,
+                                                          const T* __restrict__ wts, int prec,
+                                                          PcgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  update_body<T>(m2, nparts, bpart, dvec, p, q, x, r, z, wts, prec, sc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kUpd) pcg_ph_update_kernel(int m2, const T* __restrict__ r,
+                                                             const T* __restrict__ z, T* __restrict__ p, int init,
+                                                             PcgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  ph_update_body<T>(m2, r, z, p, init, sc);
+}
+
+// --------------------------------------------------------------------------
+// batched kernels over PcgDesc lists: one workgroup per solve for the vector
+// kernels, a flattened grid with a prefix table for the q sweep
+template <typename T>
+__global__ void __launch_bounds__(kUpd) bpcg_init_kernel(const PcgDesc<T>* __restrict__ descs) {
+  const PcgDesc<T> d = descs[blockIdx.x];
+  init_body<T>(d.m2, d.b, d.dvec, d.wts, d.x, d.r, d.z, d.p, d.prec, d.rtol, d.wtol, d.maxit, d.sc);
+}
+
+template <typename T, int U>
+__global__ void __launch_bounds__(256) bpcg_q_kernel(const PcgDesc<T>* __restrict__ descs,
+                                                     const int* __restrict__ prefix, int ndesc) {
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const PcgDesc<T> d = descs[j];
+  if (d.sc->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  q_body<T, U>(d.C, d.ldc, d.m2, d.n, d.w, d.dvec, d.p, d.q, d.bpart, blockIdx.x - prefix[j], d.qblocks,
+               reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kUpd) bpcg_update_kernel(const PcgDesc<T>* __restrict__ descs) {
+  const PcgDesc<T> d = descs[blockIdx.x];
+  if (d.sc->done) return;
+  update_body<T>(d.m2, d.qblocks, d.bpart, d.dvec, d.p, d.q, d.x, d.r, d.z, d.wts, d.prec, d.sc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kUpd) bpcg_ph_update_kernel(const PcgDesc<T>* __restrict__ descs, int init) {
+  const PcgDesc<T> d = descs[blockIdx.x];
+  if (d.sc->done) return;
+  ph_update_body<T>(d.m2, d.r, d.z, d.p, init, d.sc);
 }
 
 // --------------------------------------------------------------------------
@@ -237,6 +301,41 @@ hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, i
   return hipGetLastError();
 }
 
+// ---- batched launchers ------------------------------------------------------
+int bpcg_q_blocks(int m2) { return m2 > 16 ? (m2 + 15) / 16 : 1; }
+
+template <typename T>
+hipError_t bpcg_init(hipStream_t st, const PcgDesc<T>* d, int ndesc) {
+  if (ndesc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bpcg_init_kernel<T>, dim3(ndesc), dim3(kUpd), 0, st, d);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem) {
+  if (ndesc <= 0 || total_blocks <= 0) return hipSuccess;
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  if (tune().rows_unroll == 8)
+    hipLaunchKernelGGL((bpcg_q_kernel<T, 8>), dim3(total_blocks), dim3(256), smem, st, d, prefix, ndesc);
+  else
+    hipLaunchKernelGGL((bpcg_q_kernel<T, 4>), dim3(total_blocks), dim3(256), smem, st, d, prefix, ndesc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bpcg_update(hipStream_t st, const PcgDesc<T>* d, int ndesc) {
+  if (ndesc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bpcg_update_kernel<T>, dim3(ndesc), dim3(kUpd), 0, st, d);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bpcg_ph_update(hipStream_t st, const PcgDesc<T>* d, int ndesc, int init) {
+  if (ndesc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bpcg_ph_update_kernel<T>, dim3(ndesc), dim3(kUpd), 0, st, d, init);
+  return hipGetLastError();
+}
+
 #define QPG_PCG_INST(T)                                                                                           \
   template hipError_t pcg_init<T>(hipStream_t, int, const T*, const T*, const T*, T*, T*, T*, T*, int, double,   \
                                   double, int, PcgScalars*);                                                      \
@@ -245,7 +344,11 @@ hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, i
                                const PcgScalars*, double*, int, const EventPair*);                                \
   template hipError_t pcg_update<T>(hipStream_t, int, const double*, const T*, T*, const T*, T*, T*, T*,          \
                                     const T*, int, PcgScalars*);                                                  \
-  template hipError_t pcg_ph_update<T>(hipStream_t, int, const T*, const T*, T*, int, PcgScalars*);
+  template hipError_t pcg_ph_update<T>(hipStream_t, int, const T*, const T*, T*, int, PcgScalars*);               \
+  template hipError_t bpcg_init<T>(hipStream_t, const PcgDesc<T>*, int);                                          \
+  template hipError_t bpcg_q<T>(hipStream_t, const PcgDesc<T>*, const int*, int, int, size_t);                    \
+  template hipError_t bpcg_update<T>(hipStream_t, const PcgDesc<T>*, int);                                        \
+  template hipError_t bpcg_ph_update<T>(hipStream_t, const PcgDesc<T>*, int, int);
 QPG_PCG_INST(double)
 QPG_PCG_INST(float)
 

@@ -2,6 +2,7 @@
 // (ipm.hip).  Internal to the library.
 #pragma once
 #include "common.hpp"
+#include "desc.hpp"
 
 namespace qpg {
 
@@ -20,6 +21,16 @@ hipError_t pcg_update(hipStream_t st, int m2, const double* bpart, const T* dvec
                       const T* wts, int prec, PcgScalars* sc);
 template <typename T>
 hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, int init, PcgScalars* sc);
+// batched forms: descriptor list in device memory, one solve per entry
+int bpcg_q_blocks(int m2);
+template <typename T>
+hipError_t bpcg_init(hipStream_t st, const PcgDesc<T>* d, int ndesc);
+template <typename T>
+hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem);
+template <typename T>
+hipError_t bpcg_update(hipStream_t st, const PcgDesc<T>* d, int ndesc);
+template <typename T>
+hipError_t bpcg_ph_update(hipStream_t st, const PcgDesc<T>* d, int ndesc, int init);
 
 // ---- IPM (ipm.hip) -------------------------------------------------------
 // Scalars of one IPM iteration, resident in device memory.

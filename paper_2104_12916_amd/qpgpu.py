@@ -24,7 +24,8 @@ QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
 EXPORTS = (
     "qp_default_options", "qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply",
     "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
-    "qp_last_error",
+    "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
+    "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy",
 )
 
 
@@ -83,8 +84,22 @@ def lib():
     L.qp_status_str.restype = ct.c_char_p
     L.qp_last_error.argtypes = [P]
     L.qp_last_error.restype = ct.c_char_p
+    LL, SZ = ct.c_longlong, ct.c_size_t
+    L.qp_batch_create.argtypes = [ct.POINTER(P), ct.POINTER(qp_options), SZ, P]
+    L.qp_batch_admit.argtypes = [P, I, I, I, P, P, P, P, P, P, I, ct.POINTER(LL)]
+    L.qp_batch_step.argtypes = [P, I, ct.POINTER(I)]
+    L.qp_batch_finished.argtypes = [P, ct.POINTER(LL), I, ct.POINTER(I)]
+    L.qp_batch_collect.argtypes = [P, LL, P, P, P, P, I, ct.POINTER(qp_ipm_info)]
+    L.qp_batch_query.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(SZ), ct.POINTER(SZ), ct.POINTER(LL)]
+    L.qp_batch_footprint.argtypes = [ct.POINTER(qp_options), I, I, I]
+    L.qp_batch_footprint.restype = SZ
+    L.qp_batch_last_error.argtypes = [P]
+    L.qp_batch_last_error.restype = ct.c_char_p
+    L.qp_batch_destroy.argtypes = [P]
+    L.qp_batch_destroy.restype = None
     for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
-                 "qp_op_time", "qp_profile_get"):
+                 "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
+                 "qp_batch_finished", "qp_batch_collect", "qp_batch_query"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -198,6 +213,126 @@ def qp_ctx_bytes(ctx) -> int:
 
 def qp_destroy(ctx) -> None:
     lib().qp_destroy(ctx)
+
+
+# --- batches ------------------------------------------------------------------
+def qp_batch_create(opt: qp_options | None = None, budget_bytes: int = 0, stream=None):
+    """Returns (status, batch handle)."""
+    b = ct.c_void_p()
+    if opt is None:
+        opt = qp_default_options()
+    st = lib().qp_batch_create(ct.byref(b), ct.byref(opt), int(budget_bytes), ct.c_void_p(stream) if stream else None)
+    return st, b
+
+
+def qp_batch_admit(batch, H, c, A, b, C, d):
+    """Returns (status, ticket)."""
+    n, m1, m2 = H.shape[0], A.shape[0], C.shape[0]
+    where = _where(H, c, A, b, C, d)
+    t = ct.c_longlong(0)
+    st = lib().qp_batch_admit(batch, n, m1, m2, *(_ptr(a)[0] for a in (H, c, A, b, C, d)), where, ct.byref(t))
+    return st, t.value
+
+
+def qp_batch_step(batch, max_rounds: int = 1):
+    """Returns (status, finished-and-uncollected count)."""
+    nd = ct.c_int(0)
+    st = lib().qp_batch_step(batch, int(max_rounds), ct.byref(nd))
+    return st, nd.value
+
+
+def qp_batch_finished(batch, cap: int = 4096):
+    """Returns (status, list of finished tickets)."""
+    arr = (ct.c_longlong * max(cap, 1))()
+    cnt = ct.c_int(0)
+    st = lib().qp_batch_finished(batch, arr, int(cap), ct.byref(cnt))
+    return st, [arr[k] for k in range(cnt.value)]
+
+
+def qp_batch_collect(batch, ticket: int, x, lam, nu, s):
+    """Returns (status of the QP, qp_ipm_info)."""
+    info = qp_ipm_info()
+    st = lib().qp_batch_collect(batch, int(ticket), _ptr(x)[0], _ptr(lam)[0], _ptr(nu)[0], _ptr(s)[0],
+                                _where(x, lam, nu, s), ct.byref(info))
+    return st, info
+
+
+def qp_batch_query(batch):
+    """Returns (status, dict of the batch counters)."""
+    a, f, r = ct.c_int(0), ct.c_int(0), ct.c_longlong(0)
+    u, cap = ct.c_size_t(0), ct.c_size_t(0)
+    st = lib().qp_batch_query(batch, ct.byref(a), ct.byref(f), ct.byref(u), ct.byref(cap), ct.byref(r))
+    return st, {"in_flight": a.value, "finished": f.value, "bytes_used": u.value, "bytes_capacity": cap.value,
+                "rounds": r.value}
+
+
+def qp_batch_footprint(opt: qp_options | None, n: int, m1: int, m2: int) -> int:
+    return int(lib().qp_batch_footprint(ct.byref(opt) if opt is not None else None, int(n), int(m1), int(m2)))
+
+
+def qp_batch_last_error(batch) -> str:
+    return lib().qp_batch_last_error(batch).decode()
+
+
+def qp_batch_destroy(batch) -> None:
+    lib().qp_batch_destroy(batch)
+
+
+class Batch:
+    """Owns one batch; admit/step/collect with NumPy host arrays."""
+
+    def __init__(self, budget_bytes: int = 0, **opts):
+        stream = opts.pop("stream", None)
+        self.opt = qp_default_options(**opts)
+        st, b = qp_batch_create(self.opt, budget_bytes, stream)
+        if st != QP_OK:
+            raise QpError(st, "qp_batch_create failed")
+        self.b = b
+        self.sizes = {}
+
+    def admit(self, H, c, A, b, C, d):
+        """Ticket, or None when the batch has no room now (QP_E_NOMEM)."""
+        st, t = qp_batch_admit(self.b, H, c, A, b, C, d)
+        if st == QP_E_NOMEM:
+            return None
+        if st != QP_OK:
+            raise QpError(st, qp_batch_last_error(self.b))
+        self.sizes[t] = (H.shape[0], A.shape[0], C.shape[0])
+        return t
+
+    def step(self, rounds: int = 1) -> int:
+        st, nd = qp_batch_step(self.b, rounds)
+        if st != QP_OK:
+            raise QpError(st, qp_batch_last_error(self.b))
+        return nd
+
+    def finished(self):
+        st, t = qp_batch_finished(self.b)
+        if st != QP_OK:
+            raise QpError(st, qp_batch_last_error(self.b))
+        return t
+
+    def collect(self, ticket, accept=(QP_OK,)):
+        n, m1, m2 = self.sizes.pop(ticket)
+        x, lam, nu, s = np.zeros(n), np.zeros(m1), np.zeros(m2), np.zeros(m2)
+        st, info = qp_batch_collect(self.b, ticket, x, lam, nu, s)
+        if st not in accept:
+            raise QpError(st, qp_batch_last_error(self.b))
+        return x, lam, nu, s, info
+
+    def query(self):
+        return qp_batch_query(self.b)[1]
+
+    def close(self):
+        if self.b:
+            qp_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --- convenience wrapper used by tests and the benchmark --------------------

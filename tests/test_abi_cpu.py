@@ -89,3 +89,33 @@ def test_binding_marshalling_rejects_wrong_dtypes():
         qpgpu._ptr(np.zeros(3, dtype=np.float32))
     with pytest.raises(TypeError):
         qpgpu._ptr(np.zeros((3, 3))[:, :2])
+
+
+def test_batch_calls_reject_null_handles():
+    L = qpgpu.lib()
+    LL = ct.c_longlong(0)
+    n_done = ct.c_int(0)
+    assert L.qp_batch_create(None, None, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_admit(None, 3, 1, 2, None, None, None, None, None, None, 0, ct.byref(LL)) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_step(None, 1, ct.byref(n_done)) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_finished(None, None, 0, ct.byref(n_done)) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_collect(None, 1, None, None, None, None, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_query(None, None, None, None, None, None) == qpgpu.QP_E_INVALID
+    assert L.qp_batch_last_error(None) == b""
+    L.qp_batch_destroy(None)
+
+
+def test_batch_footprint_is_positive_monotone_and_validates():
+    opt = qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ)
+    f = [qpgpu.qp_batch_footprint(opt, n, n // 4, n // 2) for n in (64, 128, 512, 1024)]
+    assert all(a > 0 for a in f) and f == sorted(f)
+    # the footprint holds at least the matrices H, A, C and the inverse factor of K0
+    n = 512
+    assert f[2] >= 8 * (n * n + (n // 4) * n + (n // 2) * n + (n + n // 4) ** 2)
+    # P_L needs no X_P buffers; the mixed path adds float32 copies
+    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_LOW_DOF), 512, 128, 256) < f[2]
+    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ, precision=qpgpu.QP_MIXED),
+                                    512, 128, 256) > f[2]
+    assert qpgpu.qp_batch_footprint(opt, 0, 1, 1) == 0
+    assert qpgpu.qp_batch_footprint(opt, 5, 6, 1) == 0
+    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(tau=2.0), 5, 2, 1) == 0
