@@ -16,6 +16,13 @@ Prints one JSON line.  Extra objects:
   cpu_baseline  the oracle on this host's cores, a bounded sample of the same
                 instance extrapolated to a whole solve
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload lowdof]
+
+--workload batch: 512 independent QPs (n ~ U{64..1024}, m1 = n/4, m2 = n/2)
+  solved together through qp_batch_*, inputs resident in HBM; a step is the
+  whole batch.  Also times the single-QP float64 path over the same QPs.
+--workload serve: a stream of QPs of log-uniform size arriving from host
+  memory; saturated throughput, then Poisson arrivals at 0.5x and 0.8x of it
+  with p50/p99 latency from arrival to result.
 """
 import argparse
 import hashlib
@@ -30,12 +37,18 @@ sys.path.insert(0, ROOT)
 METRIC = "QP solves/s at rel KKT res 1e-8 (batched FP32 vs plain FP64); HBM GB/s; p99 lat"
 HBM_PEAK_GBS = 8000.0
 
+BATCH_DESC = ("512 independent dense QPs, n ~ U{64..1024}, m1 = n/4, m2 = n/2 (seeds 1000+i), "
+              "preconditioner by the smaller CG bound (P_H here), batched in one qp_batch")
+SERVE_DESC = ("stream of dense QPs, n log-uniform 128..4096, m1 = n U(1/8, 1/2), m2 = n U(1/2, 1) "
+              "(stream seed 5000, request i seed 1e6+i), continuous batching under a memory budget")
 WORKLOADS = {
     "lowdof": dict(desc="one dense QP n=4096, m1=3072 equalities, m2=2048 inequalities, low-dof P_L",
                    prec="PL", seeds=[100, 101, 102]),
     "fewEq": dict(desc="one dense QP n=4096, m1=256, m2=4096, H eigenvalues 1e-4..1e2, few-equalities P_H",
                   prec="PH", seeds=[200, 201, 202]),
     "small": dict(desc="one dense QP n=200, m1=50, m2=100", prec="PH", seeds=list(range(16))),
+    "batch": dict(desc=BATCH_DESC, prec="auto", seeds=[1000]),
+    "serve": dict(desc=SERVE_DESC, prec="auto", seeds=[5000]),
 }
 OP_NAMES = ["gemv_cols_part_kernel<T,1> (C^T p)", "gemv_rows_kernel<T,2> (Sigma M u)",
             "gemv_cols_part_kernel<T,3> (M^T v)", "pcg_q_kernel<T> (C w + D p)",
@@ -109,6 +122,276 @@ def cpu_baseline(workload, seed, sample_iters, gpu_iters):
     }
 
 
+def _oracle_solve_timed(spec):
+    """Worker of the CPU baseline pool: one oracle solve with one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle import ipm
+    seed, n, m1, m2 = spec
+    qp = synth.gaussian_qp(seed, n, m1, m2)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        ipm.solve(qp)
+        return time.perf_counter() - t
+
+
+def cpu_baseline_pool(specs, budget_s=20.0):
+    """Oracle throughput on independent QPs: one process per host core, one BLAS
+    thread each, over a bounded sample of the workload's instances."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    workers = min(16, os.cpu_count() or 1)
+    times = []
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(_oracle_solve_timed, sp) for sp in specs]
+        for f in futs:
+            times.append(f.result())
+            if time.perf_counter() - t0 > budget_s:
+                for g in futs:
+                    g.cancel()
+                break
+    done = len(times)
+    rate = workers * done / max(1e-9, sum(times))
+    return {"value": rate, "unit": "QP solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{done} instances of the workload (n = {min(s[1] for s in specs[:done])}.."
+                       f"{max(s[1] for s in specs[:done])}), full-system oracle IPM, {workers} processes x 1 BLAS thread; "
+                       f"rate = processes x solves / summed solve time (generation excluded)")}
+
+
+def batch_roofline(prof, elem):
+    """Dominant batched sweep: algorithmic bytes per sampled launch over its time."""
+    ms, by, cnt = prof
+    names = ["bgemv_cols_part_kernel<T,1> (C^T p)", "bgemv_rows_kernel<T,2> (Sigma M u)",
+             "bgemv_cols_part_kernel<T,3> (M^T v)", "bpcg_q_kernel<T> (C w + D p)",
+             "bgemv_rows_kernel<T,4> (X_P r)", "bgemv_cols_part_kernel<T,5> (X_P^T t)"]
+    ops = {}
+    for o in range(6):
+        if cnt[o] > 0 and ms[o] > 0:
+            ops[names[o]] = dict(avg_us=round(ms[o] * 1e3, 2), samples=int(cnt[o]), avg_bytes=int(by[o]),
+                                 gbs=round(by[o] / (ms[o] * 1e-3) / 1e9, 1))
+    if not ops:
+        return None, ops
+    dom = max(range(6), key=lambda o: ms[o] if cnt[o] else -1)
+    ach = by[dom] / (ms[dom] * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                traffic=None, kernel=names[dom], bytes_per_launch=int(by[dom]), avg_launch_us=round(ms[dom] * 1e3, 2),
+                traffic_note="no counters taken for the batched sweeps"), ops
+
+
+def run_batch_workload(args):
+    import numpy as np
+    import torch
+    import synth
+    from oracle import ipm, kkt
+    from paper_2104_12916_amd import qpgpu
+    torch.cuda.set_device(0)
+    prec = {"PL": qpgpu.QP_PREC_LOW_DOF, "PH": qpgpu.QP_PREC_FEW_EQ, "none": qpgpu.QP_PREC_NONE,
+            "auto": qpgpu.QP_PREC_AUTO}[args.prec or "auto"]
+    precision = qpgpu.QP_FP64 if args.precision == "fp64" else qpgpu.QP_MIXED
+    sizes = synth.batch_sizes(args.batch_count, 1000)
+    t = time.perf_counter()
+    qps = [synth.gaussian_qp(*sz) for sz in sizes]
+    print(f"generated {len(qps)} QPs in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    dev = [tuple(torch.from_numpy(a).cuda() for a in qp.arrays()) for qp in qps]
+    torch.cuda.synchronize()
+    opt = qpgpu.qp_default_options(prec=prec, precision=precision)
+    budget = int(1.05 * sum(qpgpu.qp_batch_footprint(opt, q.n, q.m1, q.m2) for q in qps)) + (64 << 20)
+
+    def solve_all(k, profile):
+        b = qpgpu.Batch(budget, prec=prec, precision=precision, profile=int(profile))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [b.admit(*dev[i]) for i in range(k)]
+        assert all(tk is not None for tk in tickets), "batch budget too small"
+        rounds = 0
+        while b.query()["in_flight"]:
+            b.step(1)
+            rounds += 1
+        out = [b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV)) for tk in tickets]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = b.profile() if profile else None
+        b.close()
+        return el, out, rounds, prof
+
+    for w in range(args.warmup):
+        solve_all(min(16, len(qps)), False)
+        print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    steps = max(1, args.steps)
+    times, res, prof = [], None, None
+    for st in range(steps):
+        el, out, rounds, p = solve_all(len(qps), st == 0)
+        times.append(el)
+        if st == 0:
+            res, prof = out, p
+        print(f"step {st + 1}/{steps}: {len(qps)} QPs in {el:.2f} s ({rounds} rounds)", file=sys.stderr, flush=True)
+    elapsed = sum(times)
+    # parity: the oracle's KKT score of every result; objective against the oracle on a spread of sizes
+    bad, worst = set(), 0.0
+    ipm_it, cg = [], 0
+    for i, (qp, (x, lam, nu, s, info)) in enumerate(zip(qps, res)):
+        sc, _ = kkt.rel_kkt(qp, x, lam, nu)
+        worst = max(worst, sc)
+        if not (sc <= 1e-8 and info.status == qpgpu.QP_OK):
+            bad.add(i)
+        ipm_it.append(info.ipm_iters)
+        cg += info.pcg_iters_total
+    order = sorted(range(len(qps)), key=lambda i: qps[i].n)
+    sample = sorted(set(order[int(f * (len(order) - 1))] for f in (0.0, 0.5, 1.0)))
+    worst_obj = 0.0
+    for i in sample:
+        ref = ipm.solve(qps[i])
+        f = kkt.objective(qps[i], res[i][0])
+        e = abs(f - ref.obj) / max(1.0, abs(ref.obj))
+        worst_obj = max(worst_obj, e)
+        if e > 1e-7:
+            bad.add(i)
+    ok = len(qps) - len(bad)
+    print(f"parity: {ok}/{len(qps)} pass; worst rel_kkt {worst:.2e}, worst obj err {worst_obj:.2e} "
+          f"(oracle solves of {len(sample)} QPs)", file=sys.stderr, flush=True)
+    # the single-QP float64 path over the same resident QPs
+    single = None
+    if args.single_count > 0:
+        k = min(args.single_count, len(qps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            sv = qpgpu.Solver(*dev[i], prec=prec)
+            sv.factor()
+            x = torch.empty(qps[i].n, dtype=torch.float64, device="cuda")
+            lam = torch.empty(qps[i].m1, dtype=torch.float64, device="cuda")
+            nu = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
+            sl = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
+            st_, info = qpgpu.qp_ipm_solve(sv.ctx, x, lam, nu, sl)
+            sv.close()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        single = dict(value=k / el, unit="QP solves/s", qps=k, seconds=round(el, 3),
+                      path="qp_setup + qp_factor_K0 + qp_ipm_solve per QP, float64, inputs in HBM")
+        print(f"single-QP fp64 loop: {k} QPs in {el:.2f} s", file=sys.stderr, flush=True)
+    elem = 4 if precision == qpgpu.QP_MIXED else 8
+    roof, ops = batch_roofline(prof, elem)
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        pick = sorted(rng.choice(len(sizes), size=min(48, len(sizes)), replace=False))
+        cpu = cpu_baseline_pool([sizes[i] for i in pick])
+    value = ok * steps / elapsed
+    line = {
+        "metric": METRIC, "value": value, "unit": "QP solves/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
+        "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
+        "config": {"workload": f"batch: {BATCH_DESC}", "qps": len(qps), "precond": args.prec or "auto",
+                   "precision": args.precision, "budget_bytes": budget},
+        "roofline": roof, "cpu_baseline": cpu,
+        "parity": dict(passed=ok, solves=len(qps), max_rel_kkt=worst, max_obj_rel_err=worst_obj,
+                       obj_checked=len(sample)),
+        "single_qp_fp64_gpu": single,
+        "speedup_vs_single_qp_fp64": (value / single["value"]) if single else None,
+        "ipm_iters_range": [min(ipm_it), max(ipm_it)], "cg_steps_total": int(cg),
+        "batched_sweeps": ops,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve_workload(args):
+    import collections
+    import numpy as np
+    import torch
+    import synth
+    from oracle import ipm, kkt
+    from paper_2104_12916_amd import qpgpu
+    torch.cuda.set_device(0)
+    prec = {"PL": qpgpu.QP_PREC_LOW_DOF, "PH": qpgpu.QP_PREC_FEW_EQ, "none": qpgpu.QP_PREC_NONE,
+            "auto": qpgpu.QP_PREC_AUTO}[args.prec or "auto"]
+    precision = qpgpu.QP_FP64 if args.precision == "fp64" else qpgpu.QP_MIXED
+    nw, nm = args.serve_warmup, args.serve_requests
+    specs = synth.serving_stream(nw + nm, seed=5000)
+    t = time.perf_counter()
+    reqs = [synth.gaussian_qp(*sp) for sp in specs]
+    print(f"generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def serve(rate):
+        """Run the stream; rate None admits everything at t = 0 (saturation)."""
+        rng = np.random.default_rng(5001)
+        gaps = np.zeros(len(reqs)) if rate is None else rng.exponential(1.0 / rate, size=len(reqs))
+        arrive = np.cumsum(gaps)
+        b = qpgpu.Batch(budget, prec=prec, precision=precision)
+        pending = collections.deque()
+        owner, lat, results = {}, {}, {}
+        t0 = time.perf_counter()
+        i = done = 0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arrive[i] <= now:
+                pending.append(i)
+                i += 1
+            while pending:
+                tk = b.admit(*reqs[pending[0]].arrays())
+                if tk is None:
+                    break
+                owner[tk] = pending.popleft()
+            if b.query()["in_flight"]:
+                b.step(1)
+            elif i < len(reqs):
+                time.sleep(max(0.0, arrive[i] - (time.perf_counter() - t0)))
+            for tk in b.finished():
+                k = owner.pop(tk)
+                results[k] = b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))
+                lat[k] = time.perf_counter() - t0 - arrive[k]
+                done += 1
+        b.close()
+        meas = list(range(nw, len(reqs)))
+        t_first = min(arrive[k] for k in meas)
+        t_last = max(arrive[k] + lat[k] for k in meas)
+        lm = np.array([lat[k] for k in meas]) * 1e3
+        return results, dict(solves_per_s=len(meas) / max(1e-9, t_last - t_first), p50_ms=float(np.percentile(lm, 50)),
+                             p99_ms=float(np.percentile(lm, 99)), mean_ms=float(lm.mean()))
+
+    res_sat, sat = serve(None)
+    x_rate = sat["solves_per_s"]
+    print(f"saturated: {x_rate:.2f} solves/s", file=sys.stderr, flush=True)
+    loads = {}
+    for f in (0.5, 0.8):
+        _, st_ = serve(f * x_rate)
+        loads[f"{f}X"] = {k: round(v, 3) for k, v in st_.items()}
+        print(f"load {f}X: {st_}", file=sys.stderr, flush=True)
+    ok, worst = 0, 0.0
+    for k in range(nw, len(reqs)):
+        x, lam, nu, s, info = res_sat[k]
+        sc, _ = kkt.rel_kkt(reqs[k], x, lam, nu)
+        worst = max(worst, sc)
+        ok += int(sc <= 1e-8 and info.status == qpgpu.QP_OK)
+    # objective against the oracle and alone-versus-mix equality on the smallest requests
+    small = sorted(range(nw, len(reqs)), key=lambda k: reqs[k].n)[:3]
+    worst_obj, same = 0.0, True
+    for k in small:
+        ref = ipm.solve(reqs[k])
+        worst_obj = max(worst_obj, abs(kkt.objective(reqs[k], res_sat[k][0]) - ref.obj) / max(1.0, abs(ref.obj)))
+        b = qpgpu.Batch(budget, prec=prec, precision=precision)
+        tk = b.admit(*reqs[k].arrays())
+        b.step(10 ** 6)
+        xa = b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))[0]
+        b.close()
+        same = same and bool(np.array_equal(xa, res_sat[k][0]))
+    line = {
+        "metric": METRIC, "value": x_rate * ok / nm, "unit": "QP solves/s", "n_gpus": 1, "steps": nm,
+        "warmup": nw, "ms_per_step": 1e3 / max(1e-9, x_rate), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
+        "data": "synthetic (seeded dense Gaussian QPs arriving from host memory; admission includes the upload)",
+        "config": {"workload": f"serve: {SERVE_DESC}", "requests": nm, "warmup_requests": nw,
+                   "budget_gb": args.serve_budget_gb, "precond": args.prec or "auto", "precision": args.precision},
+        "latency": {"saturated": {k: round(v, 3) for k, v in sat.items()}, **loads},
+        "parity": dict(passed=ok, solves=nm, max_rel_kkt=worst, max_obj_rel_err=worst_obj,
+                       alone_equals_mix=same, checked_alone=len(small)),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,11 +402,24 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--single-count", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-warmup", type=int, default=10)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (independent QPs shard "
               "across GPUs with no exchange, and this build measures one GPU's share).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"
+        return run_batch_workload(args)
+    if args.workload == "serve":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"
+        return run_serve_workload(args)
 
     import numpy as np
     import torch

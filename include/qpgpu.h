@@ -247,6 +247,13 @@ size_t qp_batch_footprint(const qp_options* opt, int n, int m1, int m2);
 /* Message of the last batch-level failure ("" if none; never NULL). */
 const char* qp_batch_last_error(const qp_batch* b);
 
+/* Sampled batched CG-step sweeps (options.profile set at creation): the first
+ * step of every poll chunk is timed with HIP events.  Per sweep, in the order
+ * of qp_profile_get: average device time per launch (ms), average algorithmic
+ * matrix bytes per launch over the QPs the launch covered, and the number of
+ * samples.  reset != 0 clears them. */
+qp_status qp_batch_profile_get(qp_batch* b, double avg_ms[6], double avg_bytes[6], long long samples[6], int reset);
+
 /* Free the batch, its arena and every result not collected.  NULL accepted. */
 void qp_batch_destroy(qp_batch* b);
 

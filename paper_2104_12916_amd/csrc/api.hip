@@ -128,17 +128,20 @@ static size_t round_bytes(size_t bytes) { return ((bytes ? bytes : 1) + kGranule
 
 void* dalloc_bytes(qp_ctx* ctx, size_t bytes) {
   bytes = round_bytes(bytes);
-  void* p = nullptr;
-  if (ctx->arena) {
-    p = ctx->arena->alloc(bytes);
-    if (!p) {
-      set_err(ctx, "batch memory budget exhausted (%zu bytes requested, largest free range %zu)", bytes,
-              ctx->arena->largest_free());
-      throw Fail{QP_E_NOMEM};
+  if (ctx->pooled) {
+    // carve from the current region (zeroed as a whole by its owner)
+    qp_ctx::Region* rg = ctx->cur_rg;
+    if (!rg || rg->used + bytes > rg->size) {
+      set_err(ctx, "internal: region exhausted (%zu + %zu > %zu bytes)", rg ? rg->used : 0, bytes, rg ? rg->size : 0);
+      throw Fail{QP_E_DEVICE};
     }
-  } else {
-    HIPCHK(ctx, hipMalloc(&p, bytes));
+    void* p = rg->base + rg->used;
+    rg->used += bytes;
+    ctx->bytes += bytes;
+    return p;
   }
+  void* p = nullptr;
+  HIPCHK(ctx, hipMalloc(&p, bytes));
   HIPCHK(ctx, hipMemsetAsync(p, 0, bytes, ctx->stream));
   ctx->allocs.push_back(p);
   ctx->bytes += bytes;
@@ -146,26 +149,41 @@ void* dalloc_bytes(qp_ctx* ctx, size_t bytes) {
 }
 
 void dfree(qp_ctx* ctx, void* p) {
-  if (!p) return;
+  if (!p || ctx->pooled) return;  // pooled buffers go back with their region
   for (size_t i = 0; i < ctx->allocs.size(); ++i)
     if (ctx->allocs[i] == p) {
       ctx->allocs.erase(ctx->allocs.begin() + i);
       break;
     }
-  if (ctx->arena)
-    ctx->arena->free(p);
-  else
-    (void)hipFree(p);
+  (void)hipFree(p);
+}
+
+static void free_region(qp_ctx* ctx, qp_ctx::Region& rg) {
+  if (rg.base && ctx->arena) ctx->arena->free(rg.base);
+  rg = qp_ctx::Region{};
 }
 
 void free_all(qp_ctx* ctx) {
-  for (void* p : ctx->allocs) {
-    if (ctx->arena)
-      ctx->arena->free(p);
-    else
-      (void)hipFree(p);
+  if (ctx->pooled) {
+    free_region(ctx, ctx->main_rg);
+    free_region(ctx, ctx->scratch_rg);
+    ctx->cur_rg = nullptr;
+    return;
   }
+  for (void* p : ctx->allocs) (void)hipFree(p);
   ctx->allocs.clear();
+}
+
+// Take a region of `bytes` from the batch arena for a pooled context.
+static void take_region(qp_ctx* ctx, qp_ctx::Region& rg, size_t bytes) {
+  rg.base = static_cast<char*>(ctx->arena->alloc(bytes));
+  if (!rg.base) {
+    set_err(ctx, "batch memory budget exhausted (%zu bytes requested, largest free range %zu)", bytes,
+            ctx->arena->largest_free());
+    throw Fail{QP_E_NOMEM};
+  }
+  rg.size = bytes;
+  rg.used = 0;
 }
 
 // Copy a dense rows x cols row-major caller matrix (ld = cols) into a padded
@@ -344,8 +362,34 @@ static void layout_factor_scratch(qp_ctx* ctx, Get&& get) {
   if (resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ) D(ctx->fYt, (size_t)m2 * ctx->ldn);
 }
 
+static size_t layout_bytes(qp_ctx* ctx, bool scratch) {
+  size_t total = 0;
+  static char dummy;
+  auto sum = [&](size_t bytes) -> void* {
+    total += round_bytes(bytes);
+    return &dummy;
+  };
+  qp_ctx tmp;
+  init_dims(&tmp, ctx->n, ctx->m1, ctx->m2, ctx->opt);
+  tmp.pooled = ctx->pooled;
+  if (scratch)
+    layout_factor_scratch(&tmp, sum);
+  else
+    layout_buffers(&tmp, sum);
+  return total;
+}
+
 void alloc_all(qp_ctx* ctx) {
+  if (ctx->pooled) {
+    const size_t bytes = layout_bytes(ctx, false);
+    take_region(ctx, ctx->main_rg, bytes);
+    // one fill for every buffer: padding columns and the zero upper triangles
+    // of the inverse factors are read by the sweeps
+    HIPCHK(ctx, hipMemsetAsync(ctx->main_rg.base, 0, bytes, ctx->stream));
+    ctx->cur_rg = &ctx->main_rg;
+  }
   layout_buffers(ctx, [&](size_t bytes) { return dalloc_bytes(ctx, bytes); });
+  ctx->cur_rg = nullptr;
   if (!ctx->pooled) {
     HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_sc, sizeof(PcgScalars), hipHostMallocDefault));
     HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_isc, sizeof(IpmScalars), hipHostMallocDefault));
@@ -354,11 +398,18 @@ void alloc_all(qp_ctx* ctx) {
   }
 }
 
+// Every scratch buffer is written before it is read, so the region is not zeroed.
 void alloc_factor_scratch(qp_ctx* ctx) {
+  if (ctx->pooled) {
+    take_region(ctx, ctx->scratch_rg, layout_bytes(ctx, true));
+    ctx->cur_rg = &ctx->scratch_rg;
+  }
   layout_factor_scratch(ctx, [&](size_t bytes) { return dalloc_bytes(ctx, bytes); });
+  ctx->cur_rg = nullptr;
 }
 
 void free_factor_scratch(qp_ctx* ctx) {
+  if (ctx->pooled) free_region(ctx, ctx->scratch_rg);
   for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fYt}) {
     dfree(ctx, *p);
     *p = nullptr;
@@ -782,7 +833,7 @@ bool ipm_check(qp_ctx* ctx, IpmRun& R) {
   return true;
 }
 
-void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R) {
+void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R, bool factor_ph) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2;
   // w = [I 0] K0^{-1} [-r_g; r_e];  C w feeds r_nu
@@ -794,7 +845,7 @@ void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R) {
   // predictor right-hand side and D
   HIPCHK(ctx, ipm_rhs(st, m2, 0, ctx->ri, ctx->s, ctx->nu, ctx->Cw, nullptr, nullptr, ctx->isc, ctx->rc, ctx->rhs,
                       ctx->dvec));
-  if (R.prec == kPrecH) ph_factor(ctx, ctx->dvec);
+  if (R.prec == kPrecH && factor_ph) ph_factor(ctx, ctx->dvec);
 }
 
 void ipm_after_predictor(qp_ctx* ctx) {

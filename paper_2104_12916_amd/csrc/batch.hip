@@ -73,8 +73,18 @@ struct qp_batch {
   // descriptor staging (pinned host and device copies)
   char *h_stage = nullptr, *d_stage = nullptr;
   size_t stage_cap = 0;
+  bool stage_busy = false;  // an upload from the pinned staging area may still be in flight
   long long rounds = 0;
   long long cg_launched = 0;  // batched CG steps launched
+  // sampled sweeps (options.profile): the first CG step of every poll chunk is
+  // stamped with HIP events; bytes are the algorithmic matrix bytes of that
+  // launch over the QPs it covered.  Order: C^T p, Sigma M u, M^T v,
+  // q = C w + D p, X_P r, X_P^T t.
+  EventPair prof_ev[kProfOps] = {};
+  bool prof_ready = false;
+  double prof_ms[kProfOps] = {};
+  double prof_bytes[kProfOps] = {};
+  long long prof_n[kProfOps] = {};
 };
 
 namespace {
@@ -93,10 +103,15 @@ struct Packer {
 
 // Copy the packed sections to the device.  Only called right after the stream
 // was synchronized, so the pinned staging area is no longer being read.
+void bsync(qp_batch* B) {
+  HIPCHK(&B->sink, hipStreamSynchronize(B->stream));
+  B->stage_busy = false;
+}
+
 void stage_upload(qp_batch* B, Packer& pk) {
   qp_ctx* sk = &B->sink;
+  if (B->stage_busy) bsync(B);
   if (pk.total > B->stage_cap) {
-    HIPCHK(sk, hipStreamSynchronize(B->stream));
     if (B->h_stage) (void)hipHostFree(B->h_stage);
     if (B->d_stage) (void)hipFree(B->d_stage);
     B->h_stage = B->d_stage = nullptr;
@@ -111,6 +126,16 @@ void stage_upload(qp_batch* B, Packer& pk) {
     off += (pr.second + 255) / 256 * 256;
   }
   HIPCHK(sk, hipMemcpyAsync(B->d_stage, B->h_stage, pk.total, hipMemcpyHostToDevice, B->stream));
+  B->stage_busy = true;
+}
+
+// Upload the descriptor lists of recorded factorization launches and run them.
+void run_ops(qp_batch* B, const BatchedOps& ops) {
+  if (ops.empty()) return;
+  Packer pk;
+  pk.add(ops.bytes().data(), ops.bytes().size());
+  stage_upload(B, pk);
+  HIPCHK(&B->sink, ops.run(B->stream, B->d_stage));
 }
 
 void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
@@ -126,7 +151,7 @@ void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
                                 (size_t)(hi - lo + 1) * kInfoStride * sizeof(int), hipMemcpyDeviceToHost, B->stream));
     }
   }
-  HIPCHK(sk, hipStreamSynchronize(B->stream));
+  bsync(B);
 }
 
 // ---- batched PCG ------------------------------------------------------------------
@@ -265,12 +290,12 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
 
 // P_H apply z = X_P^T (X_P r) and the p update for the P_H solves of the lists.
 template <typename T>
-void launch_ph_apply(qp_batch* B, const StepLists<T>& L, int init) {
+void launch_ph_apply(qp_batch* B, const StepLists<T>& L, int init, const EventPair* ev = nullptr) {
   qp_ctx* sk = &B->sink;
   const int nph = (int)L.ph.size();
   if (!nph) return;
-  HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nph, L.r4t, L.r4smem, 4));
-  HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nph, 5));
+  HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nph, L.r4t, L.r4smem, 4, ev ? &ev[4] : nullptr));
+  HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nph, 5, ev ? &ev[5] : nullptr));
   HIPCHK(sk, bpcg_ph_update<T>(B->stream, L.dph, nph, init));
 }
 
@@ -286,13 +311,19 @@ void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
     maxit_all = std::max(maxit_all, it.maxit);
   }
   StepLists<T> L;
-  // the staging area may still feed an earlier copy: wait before rewriting it
-  HIPCHK(sk, hipStreamSynchronize(B->stream));
   build_lists<T>(B, act, L);
   const int nall = (int)act.size();
   HIPCHK(sk, bpcg_init<T>(B->stream, L.dpd, nall));
   launch_ph_apply<T>(B, L, 1);
   const int poll = B->opt.poll_every > 0 ? B->opt.poll_every : 32;
+  const bool prof = B->opt.profile != 0;
+  if (prof && !B->prof_ready) {
+    for (int o = 0; o < kProfOps; ++o) {
+      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].begin));
+      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].end));
+    }
+    B->prof_ready = true;
+  }
   long long launched = 0;
   for (;;) {
     if (launched > (long long)maxit_all + 2LL * poll) {
@@ -301,12 +332,13 @@ void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
     }
     const int na = (int)act.size();
     for (int k = 0; k < poll; ++k) {
-      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1));
-      HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2));
-      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3));
-      HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem));
+      const EventPair* ev = (prof && k == 0) ? B->prof_ev : nullptr;
+      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1, ev ? &ev[0] : nullptr));
+      HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
+      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3, ev ? &ev[2] : nullptr));
+      HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem, ev ? &ev[3] : nullptr));
       HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
-      launch_ph_apply<T>(B, L, 0);
+      launch_ph_apply<T>(B, L, 0, ev);
     }
     launched += poll;
     B->cg_launched += poll;
@@ -317,6 +349,32 @@ void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
       hi = std::max(hi, pool);
     }
     sync_pools(B, lo, hi, false);
+    if (prof) {
+      // every QP of the chunk was still iterating, so the sampled step covered all of them
+      double bytes[kProfOps] = {0, 0, 0, 0, 0, 0};
+      for (BItem<T>* it : act) {
+        const qp_ctx* c = it->ctx;
+        const double mn = (double)c->n * (c->n + 1) / 2 + (double)c->m1 * c->n;
+        const double cn = (double)c->m2 * c->n, xp = (double)c->m2 * (c->m2 + 1) / 2;
+        bytes[0] += cn * sizeof(T);
+        bytes[1] += mn * sizeof(T);
+        bytes[2] += mn * sizeof(T);
+        bytes[3] += cn * sizeof(T);
+        if (it->prec == kPrecH) {
+          bytes[4] += xp * sizeof(T);
+          bytes[5] += xp * sizeof(T);
+        }
+      }
+      for (int o = 0; o < kProfOps; ++o) {
+        if (bytes[o] == 0) continue;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, B->prof_ev[o].begin, B->prof_ev[o].end) == hipSuccess) {
+          B->prof_ms[o] += ms;
+          B->prof_bytes[o] += bytes[o];
+          B->prof_n[o] += 1;
+        }
+      }
+    }
     std::vector<BItem<T>*> still;
     for (BItem<T>* it : act) {
       const PcgScalars& h = B->h_sc[it->ctx->sc - B->d_sc];
@@ -479,7 +537,7 @@ void finish_slot(qp_batch* B, Slot* s, qp_status st) {
                              B->stream));
     HIPCHK(c, hipMemcpyAsync(s->nu.data(), c->nu, (size_t)c->m2 * sizeof(double), hipMemcpyDeviceToHost, B->stream));
     HIPCHK(c, hipMemcpyAsync(s->s.data(), c->s, (size_t)c->m2 * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-    HIPCHK(c, hipStreamSynchronize(B->stream));
+    bsync(B);
     ipm_fill_info(c, s->R, &s->info);
   }
   s->info.status = st;
@@ -504,18 +562,124 @@ bool per_qp(qp_batch* B, Slot* s, F&& f) {
   }
 }
 
-// One IPM iteration for every QP in flight (and the set-up of new ones).
-void run_round(qp_batch* B) {
-  // factor and start the QPs admitted since the last round
-  for (Slot* s : std::vector<Slot*>(B->live)) {
-    if (s->state != kQueued) continue;
+// K0 = L Sigma L^T of every newly admitted QP at once (the steps of factor()
+// and ph_setup(), each one batched launch per recursion node), then the
+// initial point.  QPs whose H or A H^{-1} A^T has a bad pivot finish here.
+void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
+  auto drop_failed = [&](int code, const char* what) {
+    std::vector<Slot*> ok;
+    for (Slot* s : fresh) {
+      if (B->h_info[(size_t)s->pool * kInfoStride] != 0) {
+        set_err(s->ctx, "%s", what);
+        s->err = s->ctx->err;
+        finish_slot(B, s, (qp_status)code);
+      } else {
+        ok.push_back(s);
+      }
+    }
+    fresh.swap(ok);
+  };
+  auto pool_range = [&](int& lo, int& hi) {
+    lo = kMaxSlots;
+    hi = -1;
+    for (Slot* s : fresh) {
+      lo = std::min(lo, s->pool);
+      hi = std::max(hi, s->pool);
+    }
+  };
+  BatchedOps o1;
+  std::vector<CholJob> cj;
+  std::vector<GemmDesc> gw, gs;
+  for (Slot* s : fresh) {
+    qp_ctx* c = s->ctx;
+    HIPCHK(c, hipMemsetAsync(c->info, 0, sizeof(int), B->stream));
+    HIPCHK(c, hipMemcpyAsync(c->fHw, c->H, (size_t)c->n * c->ldn * sizeof(double), hipMemcpyDeviceToDevice,
+                             B->stream));
+    double* XH = c->Linv;
+    cj.push_back(CholJob{c->fHw, c->ldn, XH, c->ldN, c->n, c->ftmp, c->info, QP_E_NOT_SPD});
+    gw.push_back(GemmDesc{c->A, XH, c->fWt, c->ldn, c->ldN, c->ldn, c->m1, c->n, c->n});       // W^T = A X_H^T
+    gs.push_back(GemmDesc{c->fWt, c->fWt, c->fS, c->ldn, c->ldn, c->ldm1, c->m1, c->m1, c->n});  // S = W^T W
+  }
+  o1.chol_inv(cj);
+  o1.gemm(0, 1, 1.0, 0.0, kBUpper, gw);
+  o1.gemm(0, 1, 1.0, 0.0, kOutLower, gs);
+  run_ops(B, o1);
+  int lo, hi;
+  pool_range(lo, hi);
+  sync_pools(B, lo, hi, true);
+  drop_failed(QP_E_NOT_SPD, "Cholesky factorization of H failed: H is not positive definite");
+  if (fresh.empty()) return;
+  BatchedOps o2;
+  std::vector<CholJob> cs;
+  std::vector<GemmDesc> g1, g2, gy, gt;
+  for (Slot* s : fresh) {
+    qp_ctx* c = s->ctx;
+    const int n = c->n;
+    double* XH = c->Linv;
+    double* G = c->Linv + (size_t)n * c->ldN;
+    double* XS = G + n;
+    cs.push_back(CholJob{c->fS, c->ldm1, XS, c->ldN, c->m1, c->ftmp, c->info, QP_E_RANK});
+    g1.push_back(GemmDesc{c->fWt, XH, c->fG, c->ldn, c->ldN, c->ldn, c->m1, n, n});      // W^T X_H
+    g2.push_back(GemmDesc{XS, c->fG, G, c->ldN, c->ldn, c->ldN, c->m1, n, c->m1});       // G = -X_S W^T X_H
+    if (s->R.prec == kPrecH || prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH) {
+      gy.push_back(GemmDesc{c->C, XH, c->fYt, c->ldn, c->ldN, c->ldn, c->m2, n, n});           // C X_H^T
+      gt.push_back(GemmDesc{c->fYt, c->fYt, c->T, c->ldn, c->ldn, c->ldm2, c->m2, c->m2, n});  // T = C H^{-1} C^T
+    }
+  }
+  o2.chol_inv(cs);
+  o2.gemm(0, 0, 1.0, 0.0, kBLower, g1);
+  o2.gemm(0, 0, -1.0, 0.0, kALower, g2);
+  o2.gemm(0, 1, 1.0, 0.0, kBUpper, gy);
+  o2.gemm(0, 1, 1.0, 0.0, kOutLower, gt);
+  run_ops(B, o2);
+  pool_range(lo, hi);
+  sync_pools(B, lo, hi, true);
+  drop_failed(QP_E_RANK, "Cholesky factorization of A H^{-1} A^T failed: A is rank deficient");
+  for (Slot* s : fresh) {
     per_qp(B, s, [&] {
-      factor(s->ctx);
-      ipm_start(s->ctx, s->R);
-      free_factor_scratch(s->ctx);
+      qp_ctx* c = s->ctx;
+      if (c->opt.precision == QP_MIXED)
+        HIPCHK(c, (convert_2d<double, float>(B->stream, c->Linv, c->ldN, c->Linv32, c->ldN, c->N, c->N)));
+      c->factored = true;
+      c->ph_ready = prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH;
+      ipm_start(c, s->R);
       s->state = kRunning;
     });
   }
+  // the scratch is read by the launches above: free it once they have run
+  bsync(B);
+  for (Slot* s : fresh)
+    if (s->ctx) free_factor_scratch(s->ctx);
+}
+
+// X_P = chol(D + C H^{-1} C^T)^{-1} for the new D of every P_H QP, batched.
+void batched_ph_factor(qp_batch* B, const std::vector<Slot*>& go) {
+  BatchedOps o;
+  std::vector<CholJob> cj;
+  std::vector<Slot*> ph;
+  for (Slot* s : go) {
+    if (s->R.prec != kPrecH) continue;
+    qp_ctx* c = s->ctx;
+    HIPCHK(c, add_diag_copy(B->stream, c->m2, c->T, c->ldm2, c->dvec, c->P, c->ldm2));
+    cj.push_back(CholJob{c->P, c->ldm2, c->XP, c->ldm2, c->m2, c->ptmp, c->info, QP_E_INVALID});
+    ph.push_back(s);
+  }
+  if (ph.empty()) return;
+  o.chol_inv(cj);
+  run_ops(B, o);
+  for (Slot* s : ph) {
+    qp_ctx* c = s->ctx;
+    if (c->opt.precision == QP_MIXED)
+      HIPCHK(c, (convert_2d<double, float>(B->stream, c->XP, c->ldm2, c->XP32, c->ldm2, c->m2, c->m2)));
+  }
+}
+
+// One IPM iteration for every QP in flight (and the set-up of new ones).
+void run_round(qp_batch* B) {
+  std::vector<Slot*> fresh;
+  for (Slot* s : B->live)
+    if (s->state == kQueued) fresh.push_back(s);
+  if (!fresh.empty()) batched_factor(B, fresh);
   auto prune = [&] {
     std::vector<Slot*> keep;
     for (Slot* s : B->live)
@@ -541,10 +705,11 @@ void run_round(qp_batch* B) {
       finish_slot(B, s, st);
       continue;
     }
-    if (per_qp(B, s, [&] { ipm_predictor_setup(s->ctx, s->R); })) go.push_back(s);
+    if (per_qp(B, s, [&] { ipm_predictor_setup(s->ctx, s->R, false); })) go.push_back(s);
   }
   prune();
   if (go.empty()) return;
+  batched_ph_factor(B, go);
   auto solve = [&](bool corrector) {
     std::vector<RsItem> items;
     for (Slot* s : go) {
@@ -599,6 +764,11 @@ extern "C" {
 void qp_batch_destroy(qp_batch* B) {
   if (!B) return;
   if (B->stream) (void)hipStreamSynchronize(B->stream);
+  if (B->prof_ready)
+    for (int o = 0; o < kProfOps; ++o) {
+      (void)hipEventDestroy(B->prof_ev[o].begin);
+      (void)hipEventDestroy(B->prof_ev[o].end);
+    }
   for (Slot* s : B->live) {
     release_slot_memory(B, s);
     delete s;
@@ -797,5 +967,19 @@ size_t qp_batch_footprint(const qp_options* opt, int n, int m1, int m2) {
 }
 
 const char* qp_batch_last_error(const qp_batch* B) { return B ? B->sink.err.c_str() : ""; }
+
+qp_status qp_batch_profile_get(qp_batch* B, double avg_ms[6], double avg_bytes[6], long long samples[6], int reset) {
+  if (!B || !avg_ms || !avg_bytes || !samples) return QP_E_INVALID;
+  for (int o = 0; o < kProfOps; ++o) {
+    samples[o] = B->prof_n[o];
+    avg_ms[o] = B->prof_n[o] ? B->prof_ms[o] / (double)B->prof_n[o] : 0.0;
+    avg_bytes[o] = B->prof_n[o] ? B->prof_bytes[o] / (double)B->prof_n[o] : 0.0;
+    if (reset) {
+      B->prof_ms[o] = B->prof_bytes[o] = 0;
+      B->prof_n[o] = 0;
+    }
+  }
+  return QP_OK;
+}
 
 }  // extern "C"

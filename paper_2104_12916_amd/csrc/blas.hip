@@ -10,6 +10,9 @@
 //                   A22 -= L21 L21^T;            (L22, X22) = chol_inv(A22);
 //                   X21 = -X22 (L21 X11),
 //                 so almost every flop runs in the MFMA GEMM.
+#include <algorithm>
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace qpg {
@@ -19,10 +22,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int GB = 64;   // tile
 constexpr int GK = 16;   // k step
 
-__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                                       int lda, int ta, const double* __restrict__ B, int ldb, int tb,
-                                                       double beta, double* __restrict__ C, int ldc, int flags) {
-  const int i0 = blockIdx.y * GB, j0 = blockIdx.x * GB;
+__device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                                          int ta, const double* __restrict__ B, int ldb, int tb, double beta,
+                                          double* __restrict__ C, int ldc, int flags, int bx, int by) {
+  const int i0 = by * GB, j0 = bx * GB;
   if ((flags & kOutLower) && j0 > i0 + GB - 1) return;
   __shared__ double As[GK][GB + 4];
   __shared__ double Bs[GK][GB + 4];
@@ -136,6 +139,21 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, doub
       }
 }
 
+__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                       int lda, int ta, const double* __restrict__ B, int ldb, int tb,
+                                                       double beta, double* __restrict__ C, int ldc, int flags) {
+  gemm_body(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags, blockIdx.x, blockIdx.y);
+}
+
+// One GEMM per blockIdx.z, same op/scalars for all; tiles outside a problem's
+// M x N exit at once.
+__global__ void __launch_bounds__(256) gemm_f64_batched_kernel(const GemmDesc* __restrict__ descs, int ta, int tb,
+                                                               double alpha, double beta, int flags) {
+  const GemmDesc g = descs[blockIdx.z];
+  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
+  gemm_body(g.M, g.N, g.K, alpha, g.A, g.lda, ta, g.B, g.ldb, tb, beta, g.C, g.ldc, flags, blockIdx.x, blockIdx.y);
+}
+
 hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
                     const double* B, int ldb, double beta, double* C, int ldc, int flags) {
   if (M <= 0 || N <= 0) return hipSuccess;
@@ -154,55 +172,103 @@ constexpr int LEAF = 64;
 // matrix the computed pivot is a rounding residue of order eps * ||A||.
 constexpr double kPivRel = 1e-13;
 
+// Leaf: right-looking LDL^T of a <= 64 x 64 SPD block held in registers, then
+// L = L_1 D^{1/2} and X = L^{-1} = D^{-1/2} L_1^{-1}.  Thread t owns the 4 x 4
+// sub-block (rows 4 (t / 16) .., cols 4 (t % 16) ..) of both A and X.  Step j
+// publishes column j of A and row j of X (both final after step j - 1) in LDS
+// and every thread applies
+//     a_ik -= (a_ij / a_jj) a_kj   (j < k <= i),    x_ik -= (a_ij / a_jj) x_jk   (i > j),
+// which needs a single barrier per step (the broadcast buffers alternate).
+// X starts as I; its rows only mix with earlier rows, so X stays lower triangular.
+__device__ __forceinline__ double pick4(const double (&v)[4], int k) {
+  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
+}
+
+__device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
+                                                   int nb, int* __restrict__ info, int code,
+                                                   const double* __restrict__ dmax) {
+  __shared__ double colA[2][LEAF];
+  __shared__ double rowX[2][LEAF];
+  __shared__ double piv[LEAF];
+  const int t = threadIdx.x, r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
+  const double pmin = kPivRel * (*dmax);
+  double a[4][4], x[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = r0 + r, k = c0 + c;
+      a[r][c] = (i < nb && k <= i) ? A[(size_t)i * lda + k] : 0.0;
+      x[r][c] = (i == k && i < nb) ? 1.0 : 0.0;
+    }
+  bool bad = false;
+  for (int j = 0; j < nb; ++j) {
+    const int buf = j & 1, jj = j & 3;
+    if ((t & 15) == (j >> 2)) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) colA[buf][r0 + r] = pick4(a[r], jj);
+    }
+    if ((t >> 4) == (j >> 2)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double v = jj == 0 ? x[0][c] : (jj == 1 ? x[1][c] : (jj == 2 ? x[2][c] : x[3][c]));
+        rowX[buf][c0 + c] = v;
+      }
+    }
+    __syncthreads();
+    double ajj = colA[buf][j];
+    if (!(ajj > pmin) || !isfinite(ajj)) {  // same decision in every thread
+      bad = true;
+      ajj = 1.0;
+    }
+    if (t == 0) piv[j] = ajj;
+    const double inv = 1.0 / ajj;
+    double ck[4], xk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ck[c] = colA[buf][c0 + c];
+      xk[c] = rowX[buf][c0 + c];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r0 + r;
+      if (i > j && i < nb) {
+        const double coef = colA[buf][i] * inv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int k = c0 + c;
+          if (k > j && k <= i) a[r][c] -= coef * ck[c];
+          x[r][c] -= coef * xk[c];
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = r0 + r;
+    if (i >= nb) continue;
+    const double si = sqrt(piv[i]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = c0 + c;
+      if (k >= nb) continue;
+      if (k <= i) A[(size_t)i * lda + k] = a[r][c] / sqrt(piv[k]);
+      X[(size_t)i * ldx + k] = x[r][c] / si;
+    }
+  }
+  if (t == 0 && bad) *info = code;
+}
+
 __global__ void __launch_bounds__(256) chol_inv_leaf_kernel(double* __restrict__ A, int lda, double* __restrict__ X,
                                                             int ldx, int nb, int* __restrict__ info, int code,
                                                             const double* __restrict__ dmax) {
-  __shared__ double L[LEAF][LEAF + 1];
-  __shared__ double Xs[LEAF][LEAF + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  const double pmin = kPivRel * (*dmax);
-  if (tid == 0) bad = 0;
-  for (int idx = tid; idx < LEAF * LEAF; idx += blockDim.x) {
-    int i = idx / LEAF, k = idx % LEAF;
-    L[i][k] = (i < nb && k <= i) ? A[(size_t)i * lda + k] : 0.0;
-    Xs[i][k] = 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    double piv = L[j][j];
-    __syncthreads();
-    if (!(piv > pmin) || !isfinite(piv)) {
-      if (tid == 0) bad = 1;
-      piv = 1.0;
-    }
-    double dj = sqrt(piv);
-    if (tid == 0) L[j][j] = dj;
-    for (int i = j + 1 + tid; i < nb; i += blockDim.x) L[i][j] = L[i][j] / dj;
-    __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-      int i = idx / nb, k = idx % nb;
-      if (k > j && k <= i) L[i][k] -= L[i][j] * L[k][j];
-    }
-    __syncthreads();
-  }
-  // X = L^{-1}, one column per thread (forward substitution on unit vectors)
-  if (tid < nb) {
-    const int c = tid;
-    Xs[c][c] = 1.0 / L[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += L[i][k] * Xs[k][c];
-      Xs[i][c] = -s / L[i][i];
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    int i = idx / nb, k = idx % nb;
-    if (k <= i) A[(size_t)i * lda + k] = L[i][k];
-    X[(size_t)i * ldx + k] = Xs[i][k];
-  }
-  if (tid == 0 && bad) *info = code;
+  chol_inv_leaf_body(A, lda, X, ldx, nb, info, code, dmax);
+}
+
+__global__ void __launch_bounds__(256) chol_inv_leaf_batched_kernel(const LeafDesc* __restrict__ descs) {
+  const LeafDesc d = descs[blockIdx.x];
+  chol_inv_leaf_body(d.A, d.lda, d.X, d.ldx, d.nb, d.info, d.code, d.dmax);
 }
 
 __global__ void fill2d_kernel(double* __restrict__ X, int ld, int rows, int cols, double v) {
@@ -219,6 +285,16 @@ hipError_t fill2d_f64(hipStream_t st, double* X, int ld, int rows, int cols, dou
   return hipGetLastError();
 }
 
+// Split point of a node of n > LEAF rows: half of the smallest 64 * 2^k >= n.
+// Splits therefore sit at fixed positions (multiples of powers of two), so the
+// recursion of a problem is the same whether it runs alone or inside a batch
+// whose largest problem is bigger (there the extra levels are left-only).
+static int split_of(int n) {
+  int v = LEAF;
+  while (v < n) v *= 2;
+  return v / 2;
+}
+
 // Recursive body.  A: n x n (lower part read, overwritten with scratch), X: n x n
 // output (upper part must be zero on entry), tmp: at least (n/2 + 64) * n doubles.
 static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, int ldx, int n, double* tmp,
@@ -228,9 +304,8 @@ static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, in
     hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(256), 0, st, A, lda, X, ldx, n, info, code, dmax);
     return hipGetLastError();
   }
-  int n1 = ((n / 2) + LEAF - 1) / LEAF * LEAF;
-  if (n1 >= n) n1 = n - LEAF;
-  int n2 = n - n1;
+  const int n1 = split_of(n);
+  const int n2 = n - n1;
   double* A11 = A;
   double* A21 = A + (size_t)n1 * lda;
   double* A22 = A21 + n1;
@@ -250,8 +325,7 @@ static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, in
 }
 
 // Largest diagonal entry of A (n x n) into *out; one workgroup.
-__global__ void __launch_bounds__(256) diag_max_kernel(const double* __restrict__ A, int lda, int n,
-                                                       double* __restrict__ out) {
+__device__ __forceinline__ void diag_max_body(const double* __restrict__ A, int lda, int n, double* __restrict__ out) {
   __shared__ double sh[256];
   double m = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[(size_t)i * lda + i]);
@@ -262,6 +336,16 @@ __global__ void __launch_bounds__(256) diag_max_kernel(const double* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void __launch_bounds__(256) diag_max_kernel(const double* __restrict__ A, int lda, int n,
+                                                       double* __restrict__ out) {
+  diag_max_body(A, lda, n, out);
+}
+
+__global__ void __launch_bounds__(256) diag_max_batched_kernel(const DiagDesc* __restrict__ descs) {
+  const DiagDesc d = descs[blockIdx.x];
+  diag_max_body(d.A, d.lda, d.n, d.out);
 }
 
 // tmp holds chol_inv_tmp_elems(n) doubles; its last element stores max diag(A).
@@ -276,5 +360,127 @@ hipError_t chol_inv_f64(hipStream_t st, double* A, int lda, double* X, int ldx, 
 }
 
 size_t chol_inv_tmp_elems(int n) { return (size_t)(n / 2 + LEAF) * (size_t)(n + LEAF) + 1; }
+
+// ---- batched factorizations ----------------------------------------------------
+template <typename D>
+size_t BatchedOps::push(const std::vector<D>& v) {
+  const size_t off = (bytes_.size() + 255) / 256 * 256;
+  bytes_.resize(off + v.size() * sizeof(D));
+  if (!v.empty()) memcpy(bytes_.data() + off, v.data(), v.size() * sizeof(D));
+  return off;
+}
+
+void BatchedOps::gemm(int ta, int tb, double alpha, double beta, int flags, const std::vector<GemmDesc>& d) {
+  if (d.empty()) return;
+  int mx = 0, nx = 0;
+  for (const GemmDesc& g : d) {
+    mx = std::max(mx, g.M);
+    nx = std::max(nx, g.N);
+  }
+  if (mx <= 0 || nx <= 0) return;
+  Op o{};
+  o.kind = 1;
+  o.count = (int)d.size();
+  o.gx = (nx + GB - 1) / GB;
+  o.gy = (mx + GB - 1) / GB;
+  o.ta = ta;
+  o.tb = tb;
+  o.flags = flags;
+  o.alpha = alpha;
+  o.beta = beta;
+  o.off = push(d);
+  ops_.push_back(o);
+}
+
+// Same recursion as chol_inv_rec over nodes of 64 * 2^k rows starting at 0; at
+// every node a job takes the part of the node inside its own n (possibly none),
+// which is exactly the node chol_inv_rec visits for that job alone.
+void BatchedOps::rec(const std::vector<CholJob>& jobs, int off, int len) {
+  if (len <= LEAF) {
+    std::vector<LeafDesc> d;
+    for (const CholJob& j : jobs) {
+      const int nb = std::min(len, j.n - off);
+      if (nb <= 0) continue;
+      LeafDesc l;
+      l.A = j.A + (size_t)off * j.lda + off;
+      l.X = j.X + (size_t)off * j.ldx + off;
+      l.info = j.info;
+      l.dmax = j.tmp + chol_inv_tmp_elems(j.n) - 1;
+      l.lda = j.lda;
+      l.ldx = j.ldx;
+      l.nb = nb;
+      l.code = j.code;
+      d.push_back(l);
+    }
+    if (d.empty()) return;
+    Op o{};
+    o.kind = 0;
+    o.count = (int)d.size();
+    o.off = push(d);
+    ops_.push_back(o);
+    return;
+  }
+  const int n1 = len / 2;
+  rec(jobs, off, n1);
+  std::vector<GemmDesc> g1, g2, g3, g4;
+  for (const CholJob& j : jobs) {
+    const int n2 = std::min(len, j.n - off) - n1;
+    if (n2 <= 0) continue;
+    double* A21 = j.A + (size_t)(off + n1) * j.lda + off;
+    double* A22 = A21 + n1;
+    double* X11 = j.X + (size_t)off * j.ldx + off;
+    double* X21 = j.X + (size_t)(off + n1) * j.ldx + off;
+    double* X22 = X21 + n1;
+    g1.push_back(GemmDesc{A21, X11, X21, j.lda, j.ldx, j.ldx, n2, n1, n1});    // L21 = A21 X11^T
+    g2.push_back(GemmDesc{X21, X21, A22, j.ldx, j.ldx, j.lda, n2, n2, n1});    // A22 -= L21 L21^T
+    g3.push_back(GemmDesc{X21, X11, j.tmp, j.ldx, j.ldx, n1, n2, n1, n1});     // tmp = L21 X11
+    g4.push_back(GemmDesc{X22, j.tmp, X21, j.ldx, n1, j.ldx, n2, n1, n2});     // X21 = -X22 tmp
+  }
+  gemm(0, 1, 1.0, 0.0, kBUpper, g1);
+  gemm(0, 1, -1.0, 1.0, kOutLower, g2);
+  rec(jobs, off + n1, len - n1);
+  gemm(0, 0, 1.0, 0.0, kBLower, g3);
+  gemm(0, 0, -1.0, 0.0, kALower, g4);
+}
+
+void BatchedOps::chol_inv(const std::vector<CholJob>& jobs) {
+  if (jobs.empty()) return;
+  std::vector<DiagDesc> d;
+  int len = LEAF;
+  for (const CholJob& j : jobs) {
+    d.push_back(DiagDesc{j.A, j.tmp + chol_inv_tmp_elems(j.n) - 1, j.lda, j.n});
+    while (len < j.n) len *= 2;
+  }
+  Op o{};
+  o.kind = 2;
+  o.count = (int)d.size();
+  o.off = push(d);
+  ops_.push_back(o);
+  rec(jobs, 0, len);
+}
+
+hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
+  const char* base = static_cast<const char*>(d_bytes);
+  for (const Op& o : ops_) {
+    if (o.count > 65535) return hipErrorInvalidValue;
+    switch (o.kind) {
+      case 0:
+        hipLaunchKernelGGL(chol_inv_leaf_batched_kernel, dim3(o.count), dim3(256), 0, st,
+                           reinterpret_cast<const LeafDesc*>(base + o.off));
+        break;
+      case 1:
+        if (o.gy > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gemm_f64_batched_kernel, dim3(o.gx, o.gy, o.count), dim3(256), 0, st,
+                           reinterpret_cast<const GemmDesc*>(base + o.off), o.ta, o.tb, o.alpha, o.beta, o.flags);
+        break;
+      default:
+        hipLaunchKernelGGL(diag_max_batched_kernel, dim3(o.count), dim3(256), 0, st,
+                           reinterpret_cast<const DiagDesc*>(base + o.off));
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 }  // namespace qpg

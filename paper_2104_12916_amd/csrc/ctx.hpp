@@ -53,10 +53,18 @@ struct qp_ctx {
   std::string err;
   size_t bytes = 0;
   std::vector<void*> allocs;
-  // batch member: buffers come from the batch arena and the scalar records
-  // (sc, stats, info and their pinned mirrors) live in the batch's pools
+  // batch member: buffers come from two regions of the batch arena (the
+  // persistent buffers, zeroed once, and the factorization scratch), and the
+  // scalar records (sc, stats, info and their pinned mirrors) live in the
+  // batch's pools
   qpg::Arena* arena = nullptr;
   bool pooled = false;
+  struct Region {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+  };
+  Region main_rg, scratch_rg;
+  Region* cur_rg = nullptr;  // region dalloc carves from (pooled contexts)
 
   // problem data (float64)
   double *H = nullptr, *c = nullptr, *A = nullptr, *b = nullptr, *C = nullptr, *d = nullptr;
@@ -197,8 +205,9 @@ void ipm_eval_launch(qp_ctx* ctx, bool copy);
 // After the statistics reached the host: KKT score and stop decision.
 // Returns true when another iteration is due (then R.mu and R.wtol are set).
 bool ipm_check(qp_ctx* ctx, IpmRun& R);
-// r_nu pieces, D and the predictor right-hand side; P_H factor (launches only).
-void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R);
+// r_nu pieces, D and the predictor right-hand side; with factor_ph also the
+// P_H factor for the new D (launches only).
+void ipm_predictor_setup(qp_ctx* ctx, IpmRun& R, bool factor_ph = true);
 // Recovery and step of the predictor, then the corrector right-hand side.
 void ipm_after_predictor(qp_ctx* ctx);
 // Recovery and step of the corrector; closes the iteration.

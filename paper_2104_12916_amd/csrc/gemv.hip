@@ -369,51 +369,48 @@ bool fill_cols_desc(ColsDesc<T>& d, const T* A, int lda, int m, int k, int shape
   return (size_t)d.nchunks * d.tiles * CW <= part_elems && d.tiles * CW <= lda && !(shape == kLower && k > m);
 }
 
+template <typename T, int TAG>
+static void launch_brows_tag(dim3 grid, size_t smem, hipStream_t st, const EventPair* ev, const RowsDesc<T>* ddesc,
+                             const int* dprefix, int ndesc) {
+  if (tune().rows_unroll == 8)
+    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc);
+  else
+    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 4>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc);
+}
+
 template <typename T>
 hipError_t launch_bgemv_rows(hipStream_t st, const RowsDesc<T>* ddesc, const int* dprefix, int ndesc, int total_blocks,
-                             size_t smem, int tag) {
+                             size_t smem, int tag, const EventPair* ev) {
   if (ndesc <= 0 || total_blocks <= 0) return hipSuccess;
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   dim3 grid(total_blocks);
-  const bool u8 = tune().rows_unroll == 8;
   switch (tag) {
-    case 2:
-      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 2, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
-      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 2, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
-      break;
-    case 4:
-      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 4, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
-      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 4, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
-      break;
-    default:
-      if (u8) hipLaunchKernelGGL((bgemv_rows_kernel<T, 0, 8>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
-      else hipLaunchKernelGGL((bgemv_rows_kernel<T, 0, 4>), grid, dim3(256), smem, st, ddesc, dprefix, ndesc);
+    case 2: launch_brows_tag<T, 2>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
+    case 4: launch_brows_tag<T, 4>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
+    default: launch_brows_tag<T, 0>(grid, smem, st, ev, ddesc, dprefix, ndesc);
   }
   return hipGetLastError();
 }
 
+template <typename T, int TAG>
+static void launch_bcols_tag(dim3 grid, hipStream_t st, const EventPair* ev, const ColsDesc<T>* ddesc,
+                             const int* dprefix, int ndesc) {
+  if (tune().cols_unroll == 8)
+    QPG_LAUNCH((bgemv_cols_part_kernel<T, TAG, 8>), grid, dim3(256), 0u, st, ev, ddesc, dprefix, ndesc);
+  else
+    QPG_LAUNCH((bgemv_cols_part_kernel<T, TAG, 4>), grid, dim3(256), 0u, st, ev, ddesc, dprefix, ndesc);
+}
+
 template <typename T>
 hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int* dprefix_part, int total_part,
-                             const int* dprefix_red, int total_red, int ndesc, int tag) {
+                             const int* dprefix_red, int total_red, int ndesc, int tag, const EventPair* ev) {
   if (ndesc <= 0 || total_part <= 0) return hipSuccess;
-  const bool u8 = tune().cols_unroll == 8;
   dim3 grid(total_part);
   switch (tag) {
-    case 1:
-      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 1, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 1, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      break;
-    case 3:
-      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 3, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 3, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      break;
-    case 5:
-      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 5, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 5, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      break;
-    default:
-      if (u8) hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 0, 8>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
-      else hipLaunchKernelGGL((bgemv_cols_part_kernel<T, 0, 4>), grid, dim3(256), 0, st, ddesc, dprefix_part, ndesc);
+    case 1: launch_bcols_tag<T, 1>(grid, st, ev, ddesc, dprefix_part, ndesc); break;
+    case 3: launch_bcols_tag<T, 3>(grid, st, ev, ddesc, dprefix_part, ndesc); break;
+    case 5: launch_bcols_tag<T, 5>(grid, st, ev, ddesc, dprefix_part, ndesc); break;
+    default: launch_bcols_tag<T, 0>(grid, st, ev, ddesc, dprefix_part, ndesc);
   }
   hipLaunchKernelGGL(bgemv_cols_reduce_kernel<T>, dim3(total_red), dim3(256), 0, st, ddesc, dprefix_red, ndesc);
   return hipGetLastError();
@@ -433,9 +430,10 @@ hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int
                                   const int*);                                                                    \
   template bool fill_cols_desc<T>(ColsDesc<T>&, const T*, int, int, int, int, const T*, T*, T, T, const T*, T*,  \
                                   size_t, const int*);                                                            \
-  template hipError_t launch_bgemv_rows<T>(hipStream_t, const RowsDesc<T>*, const int*, int, int, size_t, int);   \
+  template hipError_t launch_bgemv_rows<T>(hipStream_t, const RowsDesc<T>*, const int*, int, int, size_t, int,    \
+                                           const EventPair*);                                                     \
   template hipError_t launch_bgemv_cols<T>(hipStream_t, const ColsDesc<T>*, const int*, int, const int*, int,     \
-                                           int, int);
+                                           int, int, const EventPair*);
 QPG_GEMV_INST(double)
 QPG_GEMV_INST(float)
 

@@ -1,5 +1,7 @@
 // Internal launcher declarations (not part of the C ABI).
 #pragma once
+#include <vector>
+
 #include "common.hpp"
 #include "desc.hpp"
 
@@ -34,10 +36,10 @@ bool fill_cols_desc(ColsDesc<T>& d, const T* A, int lda, int m, int k, int shape
                     const T* y0, T* part, size_t part_elems, const int* skip);
 template <typename T>
 hipError_t launch_bgemv_rows(hipStream_t st, const RowsDesc<T>* ddesc, const int* dprefix, int ndesc, int total_blocks,
-                             size_t smem, int tag);
+                             size_t smem, int tag, const EventPair* ev = nullptr);
 template <typename T>
 hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int* dprefix_part, int total_part,
-                             const int* dprefix_red, int total_red, int ndesc, int tag);
+                             const int* dprefix_red, int total_red, int ndesc, int tag, const EventPair* ev = nullptr);
 
 // blas.hip -----------------------------------------------------------------
 // Tile skip rules for GEMM operands with known zero blocks (indices in op()
@@ -51,5 +53,62 @@ hipError_t fill2d_f64(hipStream_t st, double* X, int ld, int rows, int cols, dou
 hipError_t chol_inv_f64(hipStream_t st, double* A, int lda, double* X, int ldx, int n, double* tmp, int* info,
                         int code);
 size_t chol_inv_tmp_elems(int n);
+
+// Batched forms: one launch covers the same step of many independent problems.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int lda, ldb, ldc;
+  int M, N, K;
+};
+struct LeafDesc {
+  double* A;
+  double* X;
+  int* info;
+  const double* dmax;
+  int lda, ldx, nb, code;
+};
+struct DiagDesc {
+  const double* A;
+  double* out;
+  int lda, n;
+};
+// One chol_inv problem: A (n x n, lower part read and overwritten), X = chol(A)^{-1}
+// (upper part must hold zeros on entry), tmp of chol_inv_tmp_elems(n) doubles.
+struct CholJob {
+  double* A;
+  int lda;
+  double* X;
+  int ldx;
+  int n;
+  double* tmp;
+  int* info;
+  int code;
+};
+
+// A recorded sequence of batched factorization launches.  Descriptor lists are
+// appended to bytes() in 256-byte aligned sections; the caller copies bytes()
+// to device memory and passes its address to run().
+class BatchedOps {
+ public:
+  void gemm(int ta, int tb, double alpha, double beta, int flags, const std::vector<GemmDesc>& d);
+  void chol_inv(const std::vector<CholJob>& jobs);
+  bool empty() const { return ops_.empty(); }
+  const std::vector<unsigned char>& bytes() const { return bytes_; }
+  hipError_t run(hipStream_t st, const void* d_bytes) const;
+
+ private:
+  struct Op {
+    int kind, count, gx, gy, ta, tb, flags;
+    double alpha, beta;
+    size_t off;
+  };
+  template <typename D>
+  size_t push(const std::vector<D>& v);
+  void rec(const std::vector<CholJob>& jobs, int off, int len);
+  std::vector<Op> ops_;
+  std::vector<unsigned char> bytes_;
+};
 
 }  // namespace qpg

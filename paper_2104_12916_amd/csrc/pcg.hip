@@ -312,13 +312,14 @@ hipError_t bpcg_init(hipStream_t st, const PcgDesc<T>* d, int ndesc) {
 }
 
 template <typename T>
-hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem) {
+hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem,
+                  const EventPair* ev) {
   if (ndesc <= 0 || total_blocks <= 0) return hipSuccess;
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   if (tune().rows_unroll == 8)
-    hipLaunchKernelGGL((bpcg_q_kernel<T, 8>), dim3(total_blocks), dim3(256), smem, st, d, prefix, ndesc);
+    QPG_LAUNCH((bpcg_q_kernel<T, 8>), dim3(total_blocks), dim3(256), (uint32_t)smem, st, ev, d, prefix, ndesc);
   else
-    hipLaunchKernelGGL((bpcg_q_kernel<T, 4>), dim3(total_blocks), dim3(256), smem, st, d, prefix, ndesc);
+    QPG_LAUNCH((bpcg_q_kernel<T, 4>), dim3(total_blocks), dim3(256), (uint32_t)smem, st, ev, d, prefix, ndesc);
   return hipGetLastError();
 }
 
@@ -346,7 +347,7 @@ hipError_t bpcg_ph_update(hipStream_t st, const PcgDesc<T>* d, int ndesc, int in
                                     const T*, int, PcgScalars*);                                                  \
   template hipError_t pcg_ph_update<T>(hipStream_t, int, const T*, const T*, T*, int, PcgScalars*);               \
   template hipError_t bpcg_init<T>(hipStream_t, const PcgDesc<T>*, int);                                          \
-  template hipError_t bpcg_q<T>(hipStream_t, const PcgDesc<T>*, const int*, int, int, size_t);                    \
+  template hipError_t bpcg_q<T>(hipStream_t, const PcgDesc<T>*, const int*, int, int, size_t, const EventPair*);  \
   template hipError_t bpcg_update<T>(hipStream_t, const PcgDesc<T>*, int);                                        \
   template hipError_t bpcg_ph_update<T>(hipStream_t, const PcgDesc<T>*, int, int);
 QPG_PCG_INST(double)

@@ -26,7 +26,8 @@ int bpcg_q_blocks(int m2);
 template <typename T>
 hipError_t bpcg_init(hipStream_t st, const PcgDesc<T>* d, int ndesc);
 template <typename T>
-hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem);
+hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int ndesc, int total_blocks, size_t smem,
+                  const EventPair* ev = nullptr);
 template <typename T>
 hipError_t bpcg_update(hipStream_t st, const PcgDesc<T>* d, int ndesc);
 template <typename T>

@@ -25,7 +25,7 @@ EXPORTS = (
     "qp_default_options", "qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply",
     "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
     "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
-    "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy",
+    "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
 )
 
 
@@ -95,11 +95,12 @@ def lib():
     L.qp_batch_footprint.restype = SZ
     L.qp_batch_last_error.argtypes = [P]
     L.qp_batch_last_error.restype = ct.c_char_p
+    L.qp_batch_profile_get.argtypes = [P, ct.POINTER(D), ct.POINTER(D), ct.POINTER(LL), I]
     L.qp_batch_destroy.argtypes = [P]
     L.qp_batch_destroy.restype = None
     for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
-                 "qp_batch_finished", "qp_batch_collect", "qp_batch_query"):
+                 "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -274,6 +275,15 @@ def qp_batch_last_error(batch) -> str:
     return lib().qp_batch_last_error(batch).decode()
 
 
+def qp_batch_profile_get(batch, reset: bool = False):
+    """Returns (status, [avg ms] * 6, [avg bytes] * 6, [samples] * 6)."""
+    ms = (ct.c_double * 6)()
+    by = (ct.c_double * 6)()
+    cnt = (ct.c_longlong * 6)()
+    st = lib().qp_batch_profile_get(batch, ms, by, cnt, int(reset))
+    return st, list(ms), list(by), list(cnt)
+
+
 def qp_batch_destroy(batch) -> None:
     lib().qp_batch_destroy(batch)
 
@@ -322,6 +332,12 @@ class Batch:
 
     def query(self):
         return qp_batch_query(self.b)[1]
+
+    def profile(self, reset=False):
+        st, ms, by, cnt = qp_batch_profile_get(self.b, reset)
+        if st != QP_OK:
+            raise QpError(st, qp_batch_last_error(self.b))
+        return ms, by, cnt
 
     def close(self):
         if self.b:
