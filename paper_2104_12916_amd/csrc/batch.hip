@@ -70,10 +70,19 @@ struct qp_batch {
   std::vector<Slot*> live;                          // queued and running, admission order
   std::unordered_map<long long, Slot*> finished;    // waiting for qp_batch_collect
   long long next_ticket = 1;
-  // descriptor staging (pinned host and device copies)
-  char *h_stage = nullptr, *d_stage = nullptr;
-  size_t stage_cap = 0;
-  bool stage_busy = false;  // an upload from the pinned staging area may still be in flight
+  // descriptor staging: a ring of pinned host areas and their device copies;
+  // an area is rewritten once the event after its last copy has passed
+  struct StageArea {
+    char *h = nullptr, *d = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+  };
+  static constexpr int kStageAreas = 8;
+  StageArea stage[kStageAreas];
+  int stage_next = 0;
+  // per-QP records of the batched IPM kernels, indexed by pool entry
+  IpmDesc* d_ipm = nullptr;
   long long rounds = 0;
   long long cg_launched = 0;  // batched CG steps launched
   // sampled sweeps (options.profile): the first CG step of every poll chunk is
@@ -103,30 +112,37 @@ struct Packer {
 
 // Copy the packed sections to the device.  Only called right after the stream
 // was synchronized, so the pinned staging area is no longer being read.
-void bsync(qp_batch* B) {
-  HIPCHK(&B->sink, hipStreamSynchronize(B->stream));
-  B->stage_busy = false;
-}
+void bsync(qp_batch* B) { HIPCHK(&B->sink, hipStreamSynchronize(B->stream)); }
 
-void stage_upload(qp_batch* B, Packer& pk) {
+// Copy the packed sections to the device through the next staging area and
+// return the device address of the first section.  Launches that read the
+// sections follow on the same stream.
+const char* stage_upload(qp_batch* B, Packer& pk) {
   qp_ctx* sk = &B->sink;
-  if (B->stage_busy) bsync(B);
-  if (pk.total > B->stage_cap) {
-    if (B->h_stage) (void)hipHostFree(B->h_stage);
-    if (B->d_stage) (void)hipFree(B->d_stage);
-    B->h_stage = B->d_stage = nullptr;
-    size_t cap = std::max(pk.total * 2, (size_t)1 << 20);
-    HIPCHK(sk, hipHostMalloc((void**)&B->h_stage, cap, hipHostMallocDefault));
-    HIPCHK(sk, hipMalloc((void**)&B->d_stage, cap));
-    B->stage_cap = cap;
+  qp_batch::StageArea& a = B->stage[B->stage_next];
+  B->stage_next = (B->stage_next + 1) % qp_batch::kStageAreas;
+  if (a.used) HIPCHK(sk, hipEventSynchronize(a.ev));  // the host area's previous copy has been read
+  if (pk.total > a.cap) {
+    bsync(B);  // nothing in flight may still read the old device area
+    if (a.h) (void)hipHostFree(a.h);
+    if (a.d) (void)hipFree(a.d);
+    a.h = a.d = nullptr;
+    a.cap = 0;
+    const size_t cap = std::max(pk.total * 2, (size_t)1 << 20);
+    HIPCHK(sk, hipHostMalloc((void**)&a.h, cap, hipHostMallocDefault));
+    HIPCHK(sk, hipMalloc((void**)&a.d, cap));
+    a.cap = cap;
   }
+  if (!a.ev) HIPCHK(sk, hipEventCreateWithFlags(&a.ev, hipEventDisableTiming));
   size_t off = 0;
   for (auto& pr : pk.parts) {
-    if (pr.second) memcpy(B->h_stage + off, pr.first, pr.second);
+    if (pr.second) memcpy(a.h + off, pr.first, pr.second);
     off += (pr.second + 255) / 256 * 256;
   }
-  HIPCHK(sk, hipMemcpyAsync(B->d_stage, B->h_stage, pk.total, hipMemcpyHostToDevice, B->stream));
-  B->stage_busy = true;
+  HIPCHK(sk, hipMemcpyAsync(a.d, a.h, pk.total, hipMemcpyHostToDevice, B->stream));
+  HIPCHK(sk, hipEventRecord(a.ev, B->stream));
+  a.used = true;
+  return a.d;
 }
 
 // Upload the descriptor lists of recorded factorization launches and run them.
@@ -134,8 +150,8 @@ void run_ops(qp_batch* B, const BatchedOps& ops) {
   if (ops.empty()) return;
   Packer pk;
   pk.add(ops.bytes().data(), ops.bytes().size());
-  stage_upload(B, pk);
-  HIPCHK(&B->sink, ops.run(B->stream, B->d_stage));
+  const char* base = stage_upload(B, pk);
+  HIPCHK(&B->sink, ops.run(B->stream, base));
 }
 
 void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
@@ -268,8 +284,7 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
          o_ph = V(L.ph);
   size_t o_c1p = V(L.c1p), o_c1r = V(L.c1r), o_c3p = V(L.c3p), o_c3r = V(L.c3r), o_c5p = V(L.c5p),
          o_c5r = V(L.c5r), o_r2p = V(L.r2p), o_r4p = V(L.r4p), o_qp = V(L.qp);
-  stage_upload(B, pk);
-  char* base = B->d_stage;
+  const char* base = stage_upload(B, pk);
   L.dc1 = reinterpret_cast<const ColsDesc<T>*>(base + o_c1);
   L.dc3 = reinterpret_cast<const ColsDesc<T>*>(base + o_c3);
   L.dc5 = reinterpret_cast<const ColsDesc<T>*>(base + o_c5);
@@ -393,6 +408,232 @@ void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
   }
 }
 
+// ---- batched IPM phases ---------------------------------------------------------------
+IpmDesc ipm_desc_of(qp_ctx* c) {
+  IpmDesc q{};
+  q.n = c->n;
+  q.m1 = c->m1;
+  q.m2 = c->m2;
+  q.c = c->c;
+  q.b = c->b;
+  q.d = c->d;
+  q.x = c->x;
+  q.lam = c->lam;
+  q.nu = c->nu;
+  q.s = c->s;
+  q.Hx = c->Hx;
+  q.Atl = c->Atl;
+  q.Ctn = c->Ctn;
+  q.Ax = c->Ax;
+  q.Cx = c->Cx;
+  q.rg = c->rg;
+  q.re = c->re;
+  q.ri = c->ri;
+  q.stats = c->stats;
+  q.dvec = c->dvec;
+  q.rc = c->rc;
+  q.rhs = c->rhs;
+  q.Cw = c->Cw;
+  q.vN1 = c->vN1;
+  q.vN2 = c->vN2;
+  q.dx = c->dx;
+  q.dlam = c->dlam;
+  q.dnu = c->dnu;
+  q.ds = c->ds;
+  q.dx_a = c->dx_a;
+  q.dlam_a = c->dlam_a;
+  q.dnu_a = c->dnu_a;
+  q.ds_a = c->ds_a;
+  q.ir_r = c->ir_r;
+  q.ir_x = c->ir_x;
+  q.ir_d = c->ir_d;
+  q.pt = c->pt;
+  q.fd = c->fd;
+  q.fwts = c->fwts;
+  q.fb = c->fb;
+  q.fx = c->fx;
+  q.isc = c->isc;
+  q.sc = c->sc;
+  return q;
+}
+
+// One batched row sweep, one batched column sweep (float64), and the list of
+// pool entries of the batched vector kernels.
+struct RowsL {
+  std::vector<RowsDesc<double>> d;
+  std::vector<int> p;
+  int t = 0;
+  size_t smem = 0, od = 0, op = 0;
+  void add(const double* A, int lda, int m, int k, int shape, const double* x, double* y, double beta,
+           const double* y0, int nsplit) {
+    if (m <= 0) return;
+    RowsDesc<double> r;
+    fill_rows_desc<double>(r, A, lda, m, k, shape, x, y, 1.0, beta, y0, nsplit, nullptr);
+    p.push_back(t);
+    t += r.nblocks;
+    d.push_back(r);
+    smem = std::max(smem, rows_smem_bytes<double>(m, k, shape, lda));
+  }
+  void pack(Packer& pk) {
+    od = pk.add(d.data(), d.size() * sizeof(d[0]));
+    op = pk.add(p.data(), p.size() * sizeof(int));
+  }
+  void launch(qp_batch* B, const char* base, int tag) const {
+    HIPCHK(&B->sink, launch_bgemv_rows<double>(B->stream, reinterpret_cast<const RowsDesc<double>*>(base + od),
+                                               reinterpret_cast<const int*>(base + op), (int)d.size(), t, smem, tag));
+  }
+};
+
+struct ColsL {
+  std::vector<ColsDesc<double>> d;
+  std::vector<int> p, r;
+  int tp = 0, tr = 0;
+  size_t od = 0, op = 0, orr = 0;
+  void add(qp_batch* B, qp_ctx* c, const double* A, int lda, int m, int k, int shape, const double* x, double* y,
+           double beta, const double* y0) {
+    if (k <= 0) return;
+    ColsDesc<double> cd;
+    if (!fill_cols_desc<double>(cd, A, lda, m, k, shape, x, y, 1.0, beta, y0, c->w64.part, c->w64.part_elems,
+                                nullptr)) {
+      set_err(&B->sink, "column sweep (m=%d k=%d) does not fit its workspace", m, k);
+      throw Fail{QP_E_DEVICE};
+    }
+    p.push_back(tp);
+    r.push_back(tr);
+    tp += cd.nblocks;
+    tr += cd.rblocks;
+    d.push_back(cd);
+  }
+  void pack(Packer& pk) {
+    od = pk.add(d.data(), d.size() * sizeof(d[0]));
+    op = pk.add(p.data(), p.size() * sizeof(int));
+    orr = pk.add(r.data(), r.size() * sizeof(int));
+  }
+  void launch(qp_batch* B, const char* base, int tag) const {
+    HIPCHK(&B->sink, launch_bgemv_cols<double>(B->stream, reinterpret_cast<const ColsDesc<double>*>(base + od),
+                                               reinterpret_cast<const int*>(base + op), tp,
+                                               reinterpret_cast<const int*>(base + orr), tr, (int)d.size(), tag));
+  }
+};
+
+struct PoolL {
+  std::vector<int> v;
+  size_t off = 0;
+  explicit PoolL(const std::vector<Slot*>& ss) {
+    for (Slot* s : ss) v.push_back(s->pool);
+  }
+  void pack(Packer& pk) { off = pk.add(v.data(), v.size() * sizeof(int)); }
+  const int* dev(const char* base) const { return reinterpret_cast<const int*>(base + off); }
+  int count() const { return (int)v.size(); }
+};
+
+// vN2 = K0^{-1} vN1 for every QP: the row sweep (with Sigma) and the column sweep over L^{-1}.
+void add_k0_solve(qp_batch* B, RowsL& rl, ColsL& cl, qp_ctx* c) {
+  rl.add(c->Linv, c->ldN, c->N, c->N, kLower, c->vN1, c->vN3, 0.0, nullptr, c->n);
+  cl.add(B, c, c->Linv, c->ldN, c->N, c->N, kLower, c->vN3, c->vN2, 0.0, nullptr);
+}
+
+// Initial point of freshly factored QPs: K0 [x0; -lam0] = [-c; b], s0, nu0, scalars.
+void bphase_start(qp_batch* B, const std::vector<Slot*>& ss) {
+  if (ss.empty()) return;
+  PoolL pl(ss);
+  RowsL k0r, cx;
+  ColsL k0c;
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    add_k0_solve(B, k0r, k0c, c);
+    cx.add(c->C, c->ldn, c->m2, c->n, kDense, c->vN2, c->Cx, 0.0, nullptr, c->m2);
+  }
+  Packer pk;
+  pl.pack(pk);
+  k0r.pack(pk);
+  k0c.pack(pk);
+  cx.pack(pk);
+  const char* base = stage_upload(B, pk);
+  qp_ctx* sk = &B->sink;
+  HIPCHK(sk, bipm_pack(B->stream, B->d_ipm, pl.dev(base), pl.count(), kPackInit));
+  k0r.launch(B, base, 0);
+  k0c.launch(B, base, 0);
+  cx.launch(B, base, 0);
+  HIPCHK(sk, bipm_init(B->stream, B->d_ipm, pl.dev(base), pl.count(), B->opt.tau));
+}
+
+// Residual products and statistics of every iterate (launches only).
+void bphase_eval(qp_batch* B, const std::vector<Slot*>& ss) {
+  PoolL pl(ss);
+  RowsL rows;
+  ColsL ca, cc;
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    rows.add(c->H, c->ldn, c->n, c->n, kDense, c->x, c->Hx, 0.0, nullptr, c->n);
+    rows.add(c->A, c->ldn, c->m1, c->n, kDense, c->x, c->Ax, 0.0, nullptr, c->m1);
+    rows.add(c->C, c->ldn, c->m2, c->n, kDense, c->x, c->Cx, 0.0, nullptr, c->m2);
+    ca.add(B, c, c->A, c->ldn, c->m1, c->n, kDense, c->lam, c->Atl, 0.0, nullptr);
+    cc.add(B, c, c->C, c->ldn, c->m2, c->n, kDense, c->nu, c->Ctn, 0.0, nullptr);
+  }
+  Packer pk;
+  pl.pack(pk);
+  rows.pack(pk);
+  ca.pack(pk);
+  cc.pack(pk);
+  const char* base = stage_upload(B, pk);
+  rows.launch(B, base, 0);
+  ca.launch(B, base, 0);  // both column sweeps use the QP's one workspace: in turn
+  cc.launch(B, base, 0);
+  HIPCHK(&B->sink, bipm_stats(B->stream, B->d_ipm, pl.dev(base), pl.count()));
+}
+
+// r_nu pieces, D and the predictor right-hand side.
+void bphase_predictor(qp_batch* B, const std::vector<Slot*>& ss) {
+  PoolL pl(ss);
+  RowsL k0r, cw;
+  ColsL k0c;
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    add_k0_solve(B, k0r, k0c, c);
+    cw.add(c->C, c->ldn, c->m2, c->n, kDense, c->vN2, c->Cw, 0.0, nullptr, c->m2);
+  }
+  Packer pk;
+  pl.pack(pk);
+  k0r.pack(pk);
+  k0c.pack(pk);
+  cw.pack(pk);
+  const char* base = stage_upload(B, pk);
+  qp_ctx* sk = &B->sink;
+  HIPCHK(sk, bipm_pack(B->stream, B->d_ipm, pl.dev(base), pl.count(), kPackRhs));
+  k0r.launch(B, base, 0);
+  k0c.launch(B, base, 0);
+  cw.launch(B, base, 0);
+  HIPCHK(sk, bipm_rhs(B->stream, B->d_ipm, pl.dev(base), pl.count(), 0));
+}
+
+// Recovery of the directions for dnu (which 0: predictor, 1: corrector), the
+// step, and for the predictor the corrector right-hand side.
+void bphase_recover_step(qp_batch* B, const std::vector<Slot*>& ss, int which) {
+  PoolL pl(ss);
+  RowsL k0r;
+  ColsL ct, k0c;
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    ct.add(B, c, c->C, c->ldn, c->m2, c->n, kDense, which ? c->dnu : c->dnu_a, c->vN1, 1.0, c->rg);
+    add_k0_solve(B, k0r, k0c, c);
+  }
+  Packer pk;
+  pl.pack(pk);
+  ct.pack(pk);
+  k0r.pack(pk);
+  k0c.pack(pk);
+  const char* base = stage_upload(B, pk);
+  qp_ctx* sk = &B->sink;
+  ct.launch(B, base, 0);
+  HIPCHK(sk, bipm_pack(B->stream, B->d_ipm, pl.dev(base), pl.count(), kPackRecover));
+  k0r.launch(B, base, 0);
+  k0c.launch(B, base, 0);
+  HIPCHK(sk, bipm_dirs(B->stream, B->d_ipm, pl.dev(base), pl.count(), which));
+  HIPCHK(sk, bipm_step(B->stream, B->d_ipm, pl.dev(base), pl.count(), which));
+  if (!which) HIPCHK(sk, bipm_rhs(B->stream, B->d_ipm, pl.dev(base), pl.count(), 1));
+}
+
 // ---- batched reduced solve ----------------------------------------------------------
 struct RsItem {
   Slot* slot;
@@ -411,8 +652,55 @@ struct RsItem {
   int last_done = 0;
 };
 
-void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items) {
-  qp_ctx* sk = &B->sink;
+template <typename F>
+void for_slots(std::vector<RsItem*>& v, std::vector<Slot*>& out, F&& pred) {
+  out.clear();
+  for (RsItem* it : v)
+    if (pred(it)) out.push_back(it->slot);
+}
+
+// Float64 residual r = rhs - K_F dnu of the listed QPs (dnu already updated by
+// bir_acc, which also left pt = D dnu): C^T dnu, the M sweeps, C w + pt, then
+// the residual statistics into each QP's PcgScalars.
+void bphase_ir_residual(qp_batch* B, const std::vector<Slot*>& ss, int which) {
+  PoolL pl(ss);
+  ColsL ct, mt;
+  RowsL mr, cr;
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    ct.add(B, c, c->C, c->ldn, c->m2, c->n, kDense, which ? c->dnu : c->dnu_a, c->pu, 0.0, nullptr);
+    mr.add(c->Linv, c->ldN, c->N, c->n, kLower, c->pu, c->pv, 0.0, nullptr, c->n);
+    mt.add(B, c, c->Linv, c->ldN, c->N, c->n, kLower, c->pv, c->pw, 0.0, nullptr);
+    cr.add(c->C, c->ldn, c->m2, c->n, kDense, c->pw, c->ir_x, 1.0, c->pt, c->m2);
+  }
+  Packer pk;
+  pl.pack(pk);
+  ct.pack(pk);
+  mr.pack(pk);
+  mt.pack(pk);
+  cr.pack(pk);
+  const char* base = stage_upload(B, pk);
+  ct.launch(B, base, 0);
+  mr.launch(B, base, 2);
+  mt.launch(B, base, 3);
+  cr.launch(B, base, 0);
+  HIPCHK(&B->sink, bir_residual(B->stream, B->d_ipm, pl.dev(base), pl.count(), which));
+}
+
+// Vector kernel over the listed QPs with a freshly uploaded pool list.
+template <typename F>
+void bvec(qp_batch* B, const std::vector<Slot*>& ss, F&& launch) {
+  if (ss.empty()) return;
+  PoolL pl(ss);
+  Packer pk;
+  pl.pack(pk);
+  const char* base = stage_upload(B, pk);
+  HIPCHK(&B->sink, launch(pl.dev(base), pl.count()));
+}
+
+// The reduced solves of one phase (which 0: predictor, 1: corrector) for all
+// listed QPs; the same refinement as the single-QP solve in mixed precision.
+void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items, int which) {
   if (items.empty()) return;
   if (B->opt.precision != QP_MIXED) {
     std::vector<BItem<double>> bi;
@@ -428,27 +716,26 @@ void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items) {
     }
     return;
   }
-  // Mixed precision: the same refinement as the single-QP solve, with the
-  // float32 sweeps of all QPs batched and the float64 residuals per QP.
+  // Mixed precision: float32 sweeps of all QPs batched, float64 residuals batched.
   const double inner_rtol = 1e-5;
+  std::vector<RsItem*> all;
+  std::vector<Slot*> ss;
   for (auto& it : items) {
-    qp_ctx* c = it.slot->ctx;
-    const int m2 = c->m2;
-    HIPCHK(c, (convert_1d<double, float>(B->stream, it.dvec, c->fd, m2)));
-    if (it.wts) HIPCHK(c, (convert_1d<double, float>(B->stream, it.wts, c->fwts, m2)));
-    HIPCHK(c, fill_vec<double>(B->stream, m2, 0.0, it.dnu));
-    HIPCHK(c, hipMemcpyAsync(c->ir_r, it.rhs, (size_t)m2 * sizeof(double), hipMemcpyDeviceToDevice, B->stream));
     it.done = 2;
+    all.push_back(&it);
   }
+  for_slots(all, ss, [](RsItem*) { return true; });
+  bvec(B, ss, [&](const int* l, int n) { return bir_begin(B->stream, B->d_ipm, l, n, which); });
   for (int sweep = 0; sweep < 30; ++sweep) {
     std::vector<RsItem*> act;
-    for (auto& it : items)
-      if (it.sweeping && it.iters < it.maxit) act.push_back(&it);
+    for (RsItem* it : all)
+      if (it->sweeping && it->iters < it->maxit) act.push_back(it);
     if (act.empty()) break;
+    for_slots(act, ss, [](RsItem*) { return true; });
+    bvec(B, ss, [&](const int* l, int n) { return bir_prep(B->stream, B->d_ipm, l, n); });
     std::vector<BItem<float>> bi;
     for (RsItem* it : act) {
       qp_ctx* c = it->slot->ctx;
-      HIPCHK(c, (convert_1d<double, float>(B->stream, c->ir_r, c->fb, c->m2)));
       PcgBufs<float> bf = bufs32(c);
       bf.wts = it->wts ? c->fwts : nullptr;
       const int cap = mixed_inner_cap(c, it->slot->R.prec);
@@ -457,16 +744,13 @@ void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items) {
     run_bpcg<float>(B, bi);
     int lo = kMaxSlots, hi = -1;
     for (size_t k = 0; k < act.size(); ++k) {
-      RsItem* it = act[k];
-      qp_ctx* c = it->slot->ctx;
-      it->iters += bi[k].iters;
-      it->last_done = bi[k].done;
-      HIPCHK(c, ir_accumulate(B->stream, c->m2, c->fx, it->dnu));
-      kf_apply_dev(c, it->dvec, it->dnu, c->ir_x);
-      HIPCHK(c, ir_residual(B->stream, c->m2, it->rhs, c->ir_x, it->wts, c->ir_r, c->sc));
-      lo = std::min(lo, it->slot->pool);
-      hi = std::max(hi, it->slot->pool);
+      act[k]->iters += bi[k].iters;
+      act[k]->last_done = bi[k].done;
+      lo = std::min(lo, act[k]->slot->pool);
+      hi = std::max(hi, act[k]->slot->pool);
     }
+    bvec(B, ss, [&](const int* l, int n) { return bir_acc(B->stream, B->d_ipm, l, n, which); });
+    bphase_ir_residual(B, ss, which);
     sync_pools(B, lo, hi, false);
     for (RsItem* it : act) {
       const PcgScalars h = B->h_sc[it->slot->pool];
@@ -490,23 +774,22 @@ void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items) {
   // float64 PCG on the remaining correction of the solves whose float32 sweeps stalled
   std::vector<BItem<double>> bi;
   std::vector<RsItem*> fbk;
-  for (auto& it : items) {
-    if (!it.to_fp64) continue;
-    qp_ctx* c = it.slot->ctx;
-    bi.push_back(BItem<double>{c, bufs64(c, it.dvec, it.wts, c->ir_d), c->ir_r, it.slot->R.prec, it.rtol64, it.wtol,
-                               it.maxit - it.iters});
-    fbk.push_back(&it);
+  for (RsItem* it : all) {
+    if (!it->to_fp64) continue;
+    qp_ctx* c = it->slot->ctx;
+    bi.push_back(BItem<double>{c, bufs64(c, it->dvec, it->wts, c->ir_d), c->ir_r, it->slot->R.prec, it->rtol64,
+                               it->wtol, it->maxit - it->iters});
+    fbk.push_back(it);
   }
+  if (fbk.empty()) return;
   run_bpcg<double>(B, bi);
   for (size_t k = 0; k < fbk.size(); ++k) {
-    RsItem* it = fbk[k];
-    qp_ctx* c = it->slot->ctx;
-    it->iters += bi[k].iters;
-    HIPCHK(c, vec_add(B->stream, c->m2, c->ir_d, it->dnu));
-    it->done = bi[k].done;
-    it->fb = 1;
+    fbk[k]->iters += bi[k].iters;
+    fbk[k]->done = bi[k].done;
+    fbk[k]->fb = 1;
   }
-  (void)sk;
+  for_slots(fbk, ss, [](RsItem*) { return true; });
+  bvec(B, ss, [&](const int* l, int n) { return bir_fb_add(B->stream, B->d_ipm, l, n, which); });
 }
 
 // ---- slots ------------------------------------------------------------------------------
@@ -635,18 +918,31 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
   pool_range(lo, hi);
   sync_pools(B, lo, hi, true);
   drop_failed(QP_E_RANK, "Cholesky factorization of A H^{-1} A^T failed: A is rank deficient");
+  std::vector<Mat2dDesc> cv;
+  int max_rows = 0, max_cols = 0;
   for (Slot* s : fresh) {
-    per_qp(B, s, [&] {
-      qp_ctx* c = s->ctx;
-      if (c->opt.precision == QP_MIXED)
-        HIPCHK(c, (convert_2d<double, float>(B->stream, c->Linv, c->ldN, c->Linv32, c->ldN, c->N, c->N)));
-      c->factored = true;
-      c->ph_ready = prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH;
-      ipm_start(c, s->R);
-      s->state = kRunning;
-    });
+    qp_ctx* c = s->ctx;
+    if (c->opt.precision == QP_MIXED) {
+      cv.push_back(Mat2dDesc{c->Linv, c->Linv32, nullptr, c->ldN, c->ldN, c->N, c->N, 1, 1});
+      max_rows = std::max(max_rows, c->N);
+      max_cols = std::max(max_cols, c->N);
+    }
+    c->factored = true;
+    c->ph_ready = prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH;
+    IpmRun& R = s->R;
+    R = IpmRun{};
+    R.prec = prec_mode(resolve_prec(c, c->opt.prec));
+    R.maxit = c->opt.max_pcg > 0 ? c->opt.max_pcg : 20 * c->m2;
+    s->state = kRunning;
   }
-  // the scratch is read by the launches above: free it once they have run
+  if (!cv.empty()) {
+    Packer pk;
+    pk.add(cv.data(), cv.size() * sizeof(Mat2dDesc));
+    const char* base = stage_upload(B, pk);
+    HIPCHK(&B->sink, bmat2d(B->stream, reinterpret_cast<const Mat2dDesc*>(base), (int)cv.size(), max_rows, max_cols));
+  }
+  bphase_start(B, fresh);
+  // the scratch regions were read by the factorization launches: release them once those ran
   bsync(B);
   for (Slot* s : fresh)
     if (s->ctx) free_factor_scratch(s->ctx);
@@ -654,24 +950,28 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
 
 // X_P = chol(D + C H^{-1} C^T)^{-1} for the new D of every P_H QP, batched.
 void batched_ph_factor(qp_batch* B, const std::vector<Slot*>& go) {
-  BatchedOps o;
+  std::vector<Mat2dDesc> add, cv;
   std::vector<CholJob> cj;
-  std::vector<Slot*> ph;
+  int mr = 0;
   for (Slot* s : go) {
     if (s->R.prec != kPrecH) continue;
     qp_ctx* c = s->ctx;
-    HIPCHK(c, add_diag_copy(B->stream, c->m2, c->T, c->ldm2, c->dvec, c->P, c->ldm2));
+    add.push_back(Mat2dDesc{c->T, c->P, c->dvec, c->ldm2, c->ldm2, c->m2, c->m2, 1, 0});
     cj.push_back(CholJob{c->P, c->ldm2, c->XP, c->ldm2, c->m2, c->ptmp, c->info, QP_E_INVALID});
-    ph.push_back(s);
+    if (c->opt.precision == QP_MIXED) cv.push_back(Mat2dDesc{c->XP, c->XP32, nullptr, c->ldm2, c->ldm2, c->m2, c->m2, 1, 1});
+    mr = std::max(mr, c->m2);
   }
-  if (ph.empty()) return;
+  if (cj.empty()) return;
+  Packer pk;
+  const size_t oa = pk.add(add.data(), add.size() * sizeof(Mat2dDesc));
+  const size_t oc = pk.add(cv.data(), cv.size() * sizeof(Mat2dDesc));
+  const char* base = stage_upload(B, pk);
+  HIPCHK(&B->sink, bmat2d(B->stream, reinterpret_cast<const Mat2dDesc*>(base + oa), (int)add.size(), mr, mr));
+  BatchedOps o;
   o.chol_inv(cj);
   run_ops(B, o);
-  for (Slot* s : ph) {
-    qp_ctx* c = s->ctx;
-    if (c->opt.precision == QP_MIXED)
-      HIPCHK(c, (convert_2d<double, float>(B->stream, c->XP, c->ldm2, c->XP32, c->ldm2, c->m2, c->m2)));
-  }
+  if (!cv.empty())
+    HIPCHK(&B->sink, bmat2d(B->stream, reinterpret_cast<const Mat2dDesc*>(base + oc), (int)cv.size(), mr, mr));
 }
 
 // One IPM iteration for every QP in flight (and the set-up of new ones).
@@ -689,9 +989,9 @@ void run_round(qp_batch* B) {
   prune();
   if (B->live.empty()) return;
   // residuals and statistics of every iterate, one copy and one wait for all
+  bphase_eval(B, B->live);
   int lo = kMaxSlots, hi = -1;
   for (Slot* s : B->live) {
-    ipm_eval_launch(s->ctx, false);
     lo = std::min(lo, s->pool);
     hi = std::max(hi, s->pool);
   }
@@ -705,12 +1005,13 @@ void run_round(qp_batch* B) {
       finish_slot(B, s, st);
       continue;
     }
-    if (per_qp(B, s, [&] { ipm_predictor_setup(s->ctx, s->R, false); })) go.push_back(s);
+    go.push_back(s);
   }
   prune();
   if (go.empty()) return;
+  bphase_predictor(B, go);
   batched_ph_factor(B, go);
-  auto solve = [&](bool corrector) {
+  auto solve = [&](int which) {
     std::vector<RsItem> items;
     for (Slot* s : go) {
       qp_ctx* c = s->ctx;
@@ -718,25 +1019,29 @@ void run_round(qp_batch* B) {
       it.slot = s;
       it.dvec = c->dvec;
       it.rhs = c->rhs;
-      it.dnu = corrector ? c->dnu : c->dnu_a;
+      it.dnu = which ? c->dnu : c->dnu_a;
       it.wts = c->nu;
       it.rtol = c->opt.cg_rtol;
       it.wtol = s->R.wtol;
       it.maxit = s->R.maxit;
       items.push_back(it);
     }
-    batched_reduced_solve(B, items);
+    batched_reduced_solve(B, items, which);
     for (auto& it : items) {
       IpmRun& R = it.slot->R;
-      (corrector ? R.k2 : R.k1) = it.iters;
+      (which ? R.k2 : R.k1) = it.iters;
       R.refin_total += it.refin;
       R.fallbacks += it.fb;
     }
   };
-  solve(false);
-  for (Slot* s : go) ipm_after_predictor(s->ctx);
-  solve(true);
-  for (Slot* s : go) ipm_after_corrector(s->ctx, s->R);
+  solve(0);
+  bphase_recover_step(B, go, 0);
+  solve(1);
+  bphase_recover_step(B, go, 1);
+  for (Slot* s : go) {
+    s->R.cg_total += s->R.k1 + s->R.k2;
+    ++s->R.it;
+  }
   B->rounds += 1;
 }
 
@@ -775,10 +1080,15 @@ void qp_batch_destroy(qp_batch* B) {
   }
   for (auto& kv : B->finished) delete kv.second;
   B->arena.release();
-  for (void* p : {(void*)B->d_sc, (void*)B->d_stats, (void*)B->d_info, (void*)B->d_stage})
+  for (void* p : {(void*)B->d_sc, (void*)B->d_stats, (void*)B->d_info, (void*)B->d_ipm})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)B->h_sc, (void*)B->h_stats, (void*)B->h_info, (void*)B->h_isc, (void*)B->h_stage})
+  for (void* p : {(void*)B->h_sc, (void*)B->h_stats, (void*)B->h_info, (void*)B->h_isc})
     if (p) (void)hipHostFree(p);
+  for (auto& a : B->stage) {
+    if (a.h) (void)hipHostFree(a.h);
+    if (a.d) (void)hipFree(a.d);
+    if (a.ev) (void)hipEventDestroy(a.ev);
+  }
   if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
   delete B;
 }
@@ -822,6 +1132,7 @@ qp_status qp_batch_create(qp_batch** out, const qp_options* opt, size_t hbm_budg
     HIPCHK(sk, hipHostMalloc((void**)&B->h_info, (size_t)kMaxSlots * kInfoStride * sizeof(int),
                              hipHostMallocDefault));
     HIPCHK(sk, hipHostMalloc((void**)&B->h_isc, kMaxSlots * sizeof(IpmScalars), hipHostMallocDefault));
+    HIPCHK(sk, hipMalloc((void**)&B->d_ipm, kMaxSlots * sizeof(IpmDesc)));
     for (int k = kMaxSlots - 1; k >= 0; --k) B->free_pools.push_back(k);
     HIPCHK(sk, hipStreamSynchronize(B->stream));
   });
@@ -872,7 +1183,9 @@ qp_status qp_batch_admit(qp_batch* B, int n, int m1, int m2, const double* H, co
     alloc_all(ctx);
     alloc_factor_scratch(ctx);
     upload_problem(ctx, H, c, A, b, C, d, where);
-    // the caller's arrays may be released when this call returns
+    const IpmDesc q = ipm_desc_of(ctx);
+    HIPCHK(ctx, hipMemcpyAsync(B->d_ipm + s->pool, &q, sizeof(IpmDesc), hipMemcpyHostToDevice, B->stream));
+    // the caller's arrays (and q) may be released when this call returns
     sync(ctx);
   });
   if (st != QP_OK) {

@@ -4,6 +4,8 @@
 // (eq. diag-d), the recovered directions (eqs. schur-delta-x, delz), and the
 // Mehrotra predictor-corrector step.  All are small O(n + m) kernels; the
 // reductions use one workgroup so their summation order is fixed.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "gemv_core.hpp"
 #include "pcg.hpp"
@@ -12,7 +14,7 @@ namespace qpg {
 
 constexpr int kRedThreads = 1024;
 
-__global__ void __launch_bounds__(kRedThreads) ipm_stats_kernel(
+__device__ __forceinline__ void ipm_stats_body(
     int n, int m1, int m2, const double* __restrict__ Hx, const double* __restrict__ Atl,
     const double* __restrict__ Ctn, const double* __restrict__ Ax, const double* __restrict__ Cx,
     const double* __restrict__ x, const double* __restrict__ c, const double* __restrict__ lam,
@@ -76,6 +78,16 @@ __global__ void __launch_bounds__(kRedThreads) ipm_stats_kernel(
   vals[kSMin] = -block_max(-s_min, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < kNumStats; ++k) stats[k] = vals[k];
+}
+
+__global__ void __launch_bounds__(kRedThreads) ipm_stats_kernel(
+    int n, int m1, int m2, const double* __restrict__ Hx, const double* __restrict__ Atl,
+    const double* __restrict__ Ctn, const double* __restrict__ Ax, const double* __restrict__ Cx,
+    const double* __restrict__ x, const double* __restrict__ c, const double* __restrict__ lam,
+    const double* __restrict__ b, const double* __restrict__ nu, const double* __restrict__ s,
+    const double* __restrict__ d, double* __restrict__ rg, double* __restrict__ re, double* __restrict__ ri,
+    double* __restrict__ stats) {
+  ipm_stats_body(n, m1, m2, Hx, Atl, Ctn, Ax, Cx, x, c, lam, b, nu, s, d, rg, re, ri, stats);
 }
 
 hipError_t ipm_stats(hipStream_t st, int n, int m1, int m2, const double* Hx, const double* Atl, const double* Ctn,
@@ -149,14 +161,11 @@ __device__ __forceinline__ double ratio(double v, double dv) { return dv < 0.0 ?
 
 // Predictor: alpha_aff, mu_aff, sigma = (mu_aff / mu)^3.
 // Corrector: alpha = min(1, tau alpha_max) and the update of (x, lam, nu, s).
-__global__ void __launch_bounds__(kRedThreads) ipm_step_kernel(int n, int m1, int m2, int corrector,
-                                                               double* __restrict__ x, double* __restrict__ lam,
-                                                               double* __restrict__ nu, double* __restrict__ s,
-                                                               const double* __restrict__ dx,
-                                                               const double* __restrict__ dlam,
-                                                               const double* __restrict__ dnu,
-                                                               const double* __restrict__ ds,
-                                                               IpmScalars* __restrict__ isc) {
+__device__ __forceinline__ void ipm_step_body(int n, int m1, int m2, int corrector, double* __restrict__ x,
+                                              double* __restrict__ lam, double* __restrict__ nu,
+                                              double* __restrict__ s, const double* __restrict__ dx,
+                                              const double* __restrict__ dlam, const double* __restrict__ dnu,
+                                              const double* __restrict__ ds, IpmScalars* __restrict__ isc) {
   __shared__ double sh[16];
   __shared__ double alpha_s;
   double amax = INFINITY, snu = 0;
@@ -196,6 +205,17 @@ __global__ void __launch_bounds__(kRedThreads) ipm_step_kernel(int n, int m1, in
     nu[i] += a * dnu[i];
     s[i] += a * ds[i];
   }
+}
+
+__global__ void __launch_bounds__(kRedThreads) ipm_step_kernel(int n, int m1, int m2, int corrector,
+                                                               double* __restrict__ x, double* __restrict__ lam,
+                                                               double* __restrict__ nu, double* __restrict__ s,
+                                                               const double* __restrict__ dx,
+                                                               const double* __restrict__ dlam,
+                                                               const double* __restrict__ dnu,
+                                                               const double* __restrict__ ds,
+                                                               IpmScalars* __restrict__ isc) {
+  ipm_step_body(n, m1, m2, corrector, x, lam, nu, s, dx, dlam, dnu, ds, isc);
 }
 
 hipError_t ipm_step(hipStream_t st, int n, int m1, int m2, int corrector, double* x, double* lam, double* nu,
@@ -280,11 +300,9 @@ hipError_t ir_accumulate(hipStream_t st, int m, const float* fx, double* x) {
 }
 
 // r = rhs - Kx in float64 with ||r||^2, ||rhs||^2 and max |w_i r_i| into sc.
-__global__ void __launch_bounds__(kRedThreads) ir_residual_kernel(int m, const double* __restrict__ rhs,
-                                                                  const double* __restrict__ Kx,
-                                                                  const double* __restrict__ w,
-                                                                  double* __restrict__ r,
-                                                                  PcgScalars* __restrict__ sc) {
+__device__ __forceinline__ void ir_residual_body(int m, const double* __restrict__ rhs, const double* __restrict__ Kx,
+                                                 const double* __restrict__ w, double* __restrict__ r,
+                                                 PcgScalars* __restrict__ sc) {
   __shared__ double sh[16];
   double rr = 0, bb = 0, wm = 0;
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
@@ -304,9 +322,200 @@ __global__ void __launch_bounds__(kRedThreads) ir_residual_kernel(int m, const d
   }
 }
 
+__global__ void __launch_bounds__(kRedThreads) ir_residual_kernel(int m, const double* __restrict__ rhs,
+                                                                  const double* __restrict__ Kx,
+                                                                  const double* __restrict__ w,
+                                                                  double* __restrict__ r,
+                                                                  PcgScalars* __restrict__ sc) {
+  ir_residual_body(m, rhs, Kx, w, r, sc);
+}
+
 hipError_t ir_residual(hipStream_t st, int m, const double* rhs, const double* Kx, const double* w, double* r,
                        PcgScalars* sc) {
   hipLaunchKernelGGL(ir_residual_kernel, dim3(1), dim3(kRedThreads), 0, st, m, rhs, Kx, w, r, sc);
+  return hipGetLastError();
+}
+
+// ---- batched forms (one workgroup of kRedThreads per QP) ---------------------------
+// The reductions call the bodies above with the same block size, so a QP's
+// statistics, step lengths and refinement residuals are computed in the same
+// order whether it runs alone or in a batch; element-wise steps are exact.
+#define QPG_BENTRY const IpmDesc& q = tab[list[blockIdx.x]]
+
+__global__ void __launch_bounds__(kRedThreads) bipm_stats_kernel(const IpmDesc* __restrict__ tab,
+                                                                 const int* __restrict__ list) {
+  QPG_BENTRY;
+  ipm_stats_body(q.n, q.m1, q.m2, q.Hx, q.Atl, q.Ctn, q.Ax, q.Cx, q.x, q.c, q.lam, q.b, q.nu, q.s, q.d, q.rg, q.re,
+                 q.ri, q.stats);
+}
+
+// vN1 = [-r_g; r_e] (rhs), vN1[n:] = -r_e (recover; top half written by the C^T sweep),
+// vN1 = [-c; b] (initial point).
+__global__ void __launch_bounds__(kRedThreads) bipm_pack_kernel(const IpmDesc* __restrict__ tab,
+                                                                const int* __restrict__ list, int mode) {
+  QPG_BENTRY;
+  if (mode != kPackRecover)
+    for (int i = threadIdx.x; i < q.n; i += blockDim.x) q.vN1[i] = mode == kPackRhs ? -q.rg[i] : -q.c[i];
+  for (int i = threadIdx.x; i < q.m1; i += blockDim.x)
+    q.vN1[q.n + i] = mode == kPackRhs ? q.re[i] : (mode == kPackRecover ? -q.re[i] : q.b[i]);
+}
+
+__global__ void __launch_bounds__(kRedThreads) bipm_rhs_kernel(const IpmDesc* __restrict__ tab,
+                                                               const int* __restrict__ list, int corrector) {
+  QPG_BENTRY;
+  const IpmScalars* isc = q.isc;
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) {
+    double si = q.s[i], ni = q.nu[i];
+    double r = si * ni;
+    if (corrector) r += q.ds_a[i] * q.dnu_a[i] - isc->sigma * isc->mu;
+    q.rc[i] = r;
+    q.rhs[i] = -(q.ri[i] + r / ni) + q.Cw[i];
+    q.dvec[i] = si / ni;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) bipm_dirs_kernel(const IpmDesc* __restrict__ tab,
+                                                                const int* __restrict__ list, int which) {
+  QPG_BENTRY;
+  double* dx = which ? q.dx : q.dx_a;
+  double* dlam = which ? q.dlam : q.dlam_a;
+  double* ds = which ? q.ds : q.ds_a;
+  const double* dnu = which ? q.dnu : q.dnu_a;
+  for (int i = threadIdx.x; i < q.n; i += blockDim.x) dx[i] = q.vN2[i];
+  for (int i = threadIdx.x; i < q.m1; i += blockDim.x) dlam[i] = -q.vN2[q.n + i];
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) ds[i] = -q.rc[i] / q.nu[i] - q.dvec[i] * dnu[i];
+}
+
+__global__ void __launch_bounds__(kRedThreads) bipm_step_kernel(const IpmDesc* __restrict__ tab,
+                                                                const int* __restrict__ list, int corrector) {
+  QPG_BENTRY;
+  if (corrector)
+    ipm_step_body(q.n, q.m1, q.m2, 1, q.x, q.lam, q.nu, q.s, q.dx, q.dlam, q.dnu, q.ds, q.isc);
+  else
+    ipm_step_body(q.n, q.m1, q.m2, 0, q.x, q.lam, q.nu, q.s, q.dx_a, q.dlam_a, q.dnu_a, q.ds_a, q.isc);
+}
+
+// Initial point from vN2 = K0^{-1} [-c; b] and Cx = C x0; IPM scalars reset with tau.
+__global__ void __launch_bounds__(kRedThreads) bipm_init_kernel(const IpmDesc* __restrict__ tab,
+                                                                const int* __restrict__ list, double tau) {
+  QPG_BENTRY;
+  for (int i = threadIdx.x; i < q.n; i += blockDim.x) q.x[i] = q.vN2[i];
+  for (int i = threadIdx.x; i < q.m1; i += blockDim.x) q.lam[i] = -q.vN2[q.n + i];
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) {
+    q.s[i] = fmax(q.Cx[i] - q.d[i], 1.0);
+    q.nu[i] = 1.0;
+  }
+  if (threadIdx.x == 0) {
+    IpmScalars z{};
+    z.tau = tau;
+    *q.isc = z;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) bir_begin_kernel(const IpmDesc* __restrict__ tab,
+                                                                const int* __restrict__ list, int which) {
+  QPG_BENTRY;
+  double* dnu = which ? q.dnu : q.dnu_a;
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) {
+    q.fd[i] = (float)q.dvec[i];
+    q.fwts[i] = (float)q.nu[i];
+    dnu[i] = 0.0;
+    q.ir_r[i] = q.rhs[i];
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) bir_prep_kernel(const IpmDesc* __restrict__ tab,
+                                                               const int* __restrict__ list) {
+  QPG_BENTRY;
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) q.fb[i] = (float)q.ir_r[i];
+}
+
+__global__ void __launch_bounds__(kRedThreads) bir_acc_kernel(const IpmDesc* __restrict__ tab,
+                                                              const int* __restrict__ list, int which) {
+  QPG_BENTRY;
+  double* dnu = which ? q.dnu : q.dnu_a;
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) {
+    const double v = dnu[i] + (double)q.fx[i];
+    dnu[i] = v;
+    q.pt[i] = q.dvec[i] * v;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) bir_residual_kernel(const IpmDesc* __restrict__ tab,
+                                                                   const int* __restrict__ list, int which) {
+  QPG_BENTRY;
+  (void)which;
+  ir_residual_body(q.m2, q.rhs, q.ir_x, q.nu, q.ir_r, q.sc);
+}
+
+__global__ void __launch_bounds__(kRedThreads) bir_fb_add_kernel(const IpmDesc* __restrict__ tab,
+                                                                 const int* __restrict__ list, int which) {
+  QPG_BENTRY;
+  double* dnu = which ? q.dnu : q.dnu_a;
+  for (int i = threadIdx.x; i < q.m2; i += blockDim.x) dnu[i] += q.ir_d[i];
+}
+
+__global__ void bmat2d_kernel(const Mat2dDesc* __restrict__ descs) {
+  const Mat2dDesc m = descs[blockIdx.z];
+  const int i = blockIdx.y;
+  if (i >= m.rows) return;
+  const int jend = m.lower ? min(i + 1, m.cols) : m.cols;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < jend; j += gridDim.x * blockDim.x) {
+    double v = m.src[(size_t)i * m.lds + j];
+    if (m.diag && i == j) v += m.diag[i];
+    if (m.to_float)
+      static_cast<float*>(m.dst)[(size_t)i * m.ldd + j] = (float)v;
+    else
+      static_cast<double*>(m.dst)[(size_t)i * m.ldd + j] = v;
+  }
+}
+
+#define QPG_BLAUNCH(kern, ...)                                                                              \
+  do {                                                                                                      \
+    if (count <= 0) return hipSuccess;                                                                      \
+    hipLaunchKernelGGL(kern, dim3(count), dim3(kRedThreads), 0, st, tab, list, ##__VA_ARGS__);             \
+    return hipGetLastError();                                                                               \
+  } while (0)
+
+hipError_t bipm_stats(hipStream_t st, const IpmDesc* tab, const int* list, int count) {
+  QPG_BLAUNCH(bipm_stats_kernel);
+}
+hipError_t bipm_pack(hipStream_t st, const IpmDesc* tab, const int* list, int count, int mode) {
+  QPG_BLAUNCH(bipm_pack_kernel, mode);
+}
+hipError_t bipm_rhs(hipStream_t st, const IpmDesc* tab, const int* list, int count, int corrector) {
+  QPG_BLAUNCH(bipm_rhs_kernel, corrector);
+}
+hipError_t bipm_dirs(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which) {
+  QPG_BLAUNCH(bipm_dirs_kernel, which);
+}
+hipError_t bipm_step(hipStream_t st, const IpmDesc* tab, const int* list, int count, int corrector) {
+  QPG_BLAUNCH(bipm_step_kernel, corrector);
+}
+hipError_t bipm_init(hipStream_t st, const IpmDesc* tab, const int* list, int count, double tau) {
+  QPG_BLAUNCH(bipm_init_kernel, tau);
+}
+hipError_t bir_begin(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which) {
+  QPG_BLAUNCH(bir_begin_kernel, which);
+}
+hipError_t bir_prep(hipStream_t st, const IpmDesc* tab, const int* list, int count) {
+  QPG_BLAUNCH(bir_prep_kernel);
+}
+hipError_t bir_acc(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which) {
+  QPG_BLAUNCH(bir_acc_kernel, which);
+}
+hipError_t bir_residual(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which) {
+  QPG_BLAUNCH(bir_residual_kernel, which);
+}
+hipError_t bir_fb_add(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which) {
+  QPG_BLAUNCH(bir_fb_add_kernel, which);
+}
+
+hipError_t bmat2d(hipStream_t st, const Mat2dDesc* d, int count, int max_rows, int max_cols) {
+  if (count <= 0 || max_rows <= 0 || max_cols <= 0) return hipSuccess;
+  if (max_rows > 65535 || count > 65535) return hipErrorInvalidValue;
+  const int gx = std::min((max_cols + 255) / 256, 16);
+  hipLaunchKernelGGL(bmat2d_kernel, dim3(gx, max_rows, count), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 

@@ -56,6 +56,30 @@ enum StatIdx : int {
   kNumStats
 };
 
+// Per-QP record of the batched IPM kernels: every vector of one QP's interior
+// point state (fixed for the QP's lifetime).  A batched launch takes the table
+// and a list of entries; workgroup b serves entry list[b].
+struct IpmDesc {
+  int n, m1, m2, pad;
+  const double *c, *b, *d;
+  double *x, *lam, *nu, *s;
+  double *Hx, *Atl, *Ctn, *Ax, *Cx, *rg, *re, *ri, *stats;
+  double *dvec, *rc, *rhs, *Cw, *vN1, *vN2;
+  double *dx, *dlam, *dnu, *ds, *dx_a, *dlam_a, *dnu_a, *ds_a;
+  double *ir_r, *ir_x, *ir_d, *pt;
+  float *fd, *fwts, *fb, *fx;
+  IpmScalars* isc;
+  PcgScalars* sc;
+};
+
+// dst = (D)(src + diag on the diagonal) over rows x cols (lower: j <= i only).
+struct Mat2dDesc {
+  const double* src;
+  void* dst;
+  const double* diag;
+  int lds, ldd, rows, cols, lower, to_float;
+};
+
 hipError_t ipm_stats(hipStream_t st, int n, int m1, int m2, const double* Hx, const double* Atl, const double* Ctn,
                      const double* Ax, const double* Cx, const double* x, const double* c, const double* lam,
                      const double* b, const double* nu, const double* s, const double* d, double* rg, double* re,
@@ -77,6 +101,24 @@ hipError_t vec_add(hipStream_t st, int m, const double* a, double* y);
 hipError_t ir_residual(hipStream_t st, int m, const double* rhs, const double* Kx, const double* w, double* r,
                        PcgScalars* sc);
 hipError_t add_diag_copy(hipStream_t st, int m, const double* T, int ldt, const double* dvec, double* P, int ldp);
+// Batched IPM steps over `count` entries of an IpmDesc table (list: entry
+// indices in device memory).  `which` selects the predictor (0) or corrector
+// (1) vectors where both exist.
+enum PackMode : int { kPackRhs = 0, kPackRecover = 1, kPackInit = 2 };
+hipError_t bipm_stats(hipStream_t st, const IpmDesc* tab, const int* list, int count);
+hipError_t bipm_pack(hipStream_t st, const IpmDesc* tab, const int* list, int count, int mode);
+hipError_t bipm_rhs(hipStream_t st, const IpmDesc* tab, const int* list, int count, int corrector);
+hipError_t bipm_dirs(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which);
+hipError_t bipm_step(hipStream_t st, const IpmDesc* tab, const int* list, int count, int corrector);
+hipError_t bipm_init(hipStream_t st, const IpmDesc* tab, const int* list, int count, double tau);
+// mixed refinement: begin (fd, fwts, dnu = 0, ir_r = rhs), fb = ir_r, dnu += fx
+// with pt = D dnu, residual into sc, dnu += ir_d
+hipError_t bir_begin(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which);
+hipError_t bir_prep(hipStream_t st, const IpmDesc* tab, const int* list, int count);
+hipError_t bir_acc(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which);
+hipError_t bir_residual(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which);
+hipError_t bir_fb_add(hipStream_t st, const IpmDesc* tab, const int* list, int count, int which);
+hipError_t bmat2d(hipStream_t st, const Mat2dDesc* d, int count, int max_rows, int max_cols);
 template <typename T>
 hipError_t fill_vec(hipStream_t st, int n, T v, T* x);
 template <typename S, typename D>
