@@ -25,7 +25,6 @@ Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload lowdof]
   with p50/p99 latency from arrival to result.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -62,14 +61,6 @@ def op_bytes(n, m1, m2, elem):
     return [m2 * n * elem, m_entries * elem, m_entries * elem, m2 * n * elem, xp_entries * elem, xp_entries * elem]
 
 
-def kernel_src_hash():
-    h = hashlib.sha256()
-    for f in ("gemv.hip", "gemv_core.hpp", "pcg.hip", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2104_12916_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload, kernel_tag):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -79,6 +70,7 @@ def load_traffic(workload, kernel_tag):
     rec = t.get(f"{workload}:{kernel_tag}")
     if rec is None:
         return None, "no counters for this kernel/workload"
+    from paper_2104_12916_amd.profile_summary import kernel_src_hash
     if rec.get("src_hash") != kernel_src_hash():
         return None, "kernel source changed since the counters were taken"
     return rec["bytes_per_launch"], rec.get("note", "")
@@ -442,9 +434,14 @@ def main():
         solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=1))
     torch.cuda.synchronize()
 
+    factor_s = []
+
     def step(i):
         s = solvers[i % len(solvers)]
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
         s.factor()
+        factor_s.append(time.perf_counter() - tf)
         x, lam, nu, sl, info = s.ipm(accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))
         return i % len(solvers), x, lam, nu, info
 
@@ -453,6 +450,7 @@ def main():
         print(f"warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     for s in solvers:
         s.profile(reset=True)
+    factor_s.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = []
@@ -508,6 +506,18 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, seeds[0], args.cpu_sample_iters, ipm_iters[0])
 
+    # a0 (and a0' for P_H): algorithmic flops of the once-per-QP factorization over its wall time
+    n, m1, m2 = qp0.n, qp0.m1, qp0.m2
+    fl = n ** 3 / 3 + n * n * m1 + n * m1 * m1 + m1 ** 3 / 3
+    if prec == qpgpu.QP_PREC_FEW_EQ:
+        fl += n * n * m2 + m2 * m2 * n
+    fl *= 2  # multiply-adds
+    f_ms = 1e3 * sum(factor_s) / max(1, len(factor_s))
+    factor = dict(ms=round(f_ms, 3), algorithmic_gflop=round(fl / 1e9, 2),
+                  tflops=round(fl / (f_ms * 1e-3) / 1e12, 2) if f_ms > 0 else None,
+                  mfma_fp64_peak_tflops=78.6,
+                  note="K0 = L Sigma L^T and its inverse factor (+ C H^-1 C^T for P_H); flops counted as the "
+                       "factorization alone (the inverse triangles are extra work not counted)")
     value = ok / elapsed
     line = {
         "metric": METRIC, "value": value, "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
@@ -521,6 +531,8 @@ def main():
         "parity": dict(passed=ok, solves=len(outs), max_rel_kkt=worst_kkt, max_obj_rel_err=worst_obj),
         "ipm_iters": ipm_iters, "cg_iters": cg_iters,
         "us_per_cg_step": round(elapsed / max(1, sum(cg_iters)) * 1e6, 2),
+        "us_per_ipm_iter": round(elapsed / max(1, sum(ipm_iters)) * 1e6, 1),
+        "factor": factor,
         "cg_step_sweeps": ops,
     }
     print(json.dumps(line), flush=True)

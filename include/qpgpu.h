@@ -188,13 +188,15 @@ const char* qp_last_error(const qp_ctx* ctx);
 
 /* ---- Batches of independent QPs ------------------------------------------
  * A batch keeps many QPs of different sizes in flight on one stream and runs
- * the interior point method of qp_ipm_solve for all of them, one iteration of
- * every QP per round.  The CG steps of all reduced solves of a round (eq.
- * ineq-const-reduced, one per QP, predictor and corrector) run together: one
- * launch per operator sweep covers every QP still iterating.  A QP's arithmetic
- * and launch shapes depend only on that QP, so its result does not depend on
- * the other QPs of the batch.  Preconditioner and precision come from the
- * batch options (QP_PREC_AUTO resolves per QP).
+ * the interior point method of qp_ipm_solve for all of them, each QP at its
+ * own pace.  Work proceeds in ticks: one chunk of poll_every CG steps for
+ * every QP inside a reduced solve (eq. ineq-const-reduced), one launch per
+ * operator sweep for all of them, then every QP moves on through the steps
+ * that need no CG (KKT check, right-hand sides, recovery, step, refinement),
+ * batched over the QPs at the same point.  A QP's arithmetic and launch shapes
+ * depend only on that QP, so its result does not depend on the other QPs of
+ * the batch.  Preconditioner and precision come from the batch options
+ * (QP_PREC_AUTO resolves per QP).
  *
  * Memory: the batch takes one device allocation of hbm_budget_bytes at
  * creation (0: 80% of the free device memory) and gives every admitted QP its
@@ -202,10 +204,9 @@ const char* qp_last_error(const qp_ctx* ctx);
  * refused with QP_E_NOMEM while the QP does not fit (qp_batch_footprint tells
  * its size), or when 4096 QPs are in flight.
  *
- * Flow: qp_batch_admit (any time between steps) -> qp_batch_step (factors the
- * new QPs at the start of a round, then advances every QP one iteration per
- * round) -> qp_batch_finished lists finished tickets -> qp_batch_collect copies
- * a result out and forgets the ticket.  Calls on one batch must not overlap. */
+ * Flow: qp_batch_admit (any time between steps) -> qp_batch_step (ticks) ->
+ * qp_batch_finished lists finished tickets -> qp_batch_collect copies a result
+ * out and forgets the ticket.  Calls on one batch must not overlap. */
 typedef struct qp_batch qp_batch;
 
 /* Create a batch.  opt: NULL for defaults; hip_stream: hipStream_t or NULL for
@@ -218,8 +219,9 @@ qp_status qp_batch_create(qp_batch** out, const qp_options* opt, size_t hbm_budg
 qp_status qp_batch_admit(qp_batch* b, int n, int m1, int m2, const double* H, const double* c, const double* A,
                          const double* b_eq, const double* C, const double* d, qp_mem where, long long* ticket);
 
-/* Run up to max_rounds rounds (fewer when nothing is in flight).  n_done (may
- * be NULL) receives the number of finished, uncollected QPs.  A QP that fails
+/* Run up to max_rounds ticks (fewer when nothing is in flight); QPs admitted
+ * since the last call are factored in the first.  n_done (may be NULL)
+ * receives the number of finished, uncollected QPs.  A QP that fails
  * (H not SPD, A rank deficient, no convergence) finishes with that status and
  * does not affect the others; a device error fails the call. */
 qp_status qp_batch_step(qp_batch* b, int max_rounds, int* n_done);
@@ -237,7 +239,7 @@ qp_status qp_batch_collect(qp_batch* b, long long ticket, double* x, double* lam
                            qp_mem where, qp_ipm_info* info);
 
 /* Counters: QPs admitted and not finished, finished and not collected, arena
- * bytes in use and in total, rounds run.  Any pointer may be NULL. */
+ * bytes in use and in total, ticks run.  Any pointer may be NULL. */
 qp_status qp_batch_query(const qp_batch* b, int* in_flight, int* finished, size_t* bytes_used,
                          size_t* bytes_capacity, long long* rounds);
 

@@ -1,22 +1,25 @@
 // Batch driver: many independent QPs of different sizes in flight on one
-// stream, advanced together one interior point iteration per round.
+// stream, each advancing through its own interior point iteration (Sec. 2
+// predictor-corrector on the reduced system of eq. ineq-const-reduced).
 //
-// A round runs, for every QP in flight, the steps of one IPM iteration (Sec. 2
-// predictor-corrector on the reduced system of eq. ineq-const-reduced), with the
-// two reduced solves of all QPs done together: each CG step is one launch per
-// sweep over a descriptor list (desc.hpp) that covers every QP still iterating,
-// so the K0 inverse factors, the C matrices and the P_H factors of all QPs
-// stream through HBM in the same launches.  A QP's stop flag lives in device
-// memory; stopped QPs skip their share of a launch and are dropped from the
-// lists at the next host poll.  Each QP's launch shapes depend only on its own
-// sizes, so its result does not depend on which other QPs share the batch.
+// Scheduling is by ticks.  A tick runs one chunk of CG steps (poll_every of
+// them) for every QP that is inside a reduced solve, as one launch per sweep
+// over a descriptor list (desc.hpp) covering all of those QPs, so the K0
+// inverse factors, the C matrices and the P_H factors of all of them stream
+// through HBM in the same launches.  Then the host waits once, reads every
+// QP's CG scalars and residual statistics, and moves each QP as far as it can
+// go without another host decision: KKT check, right-hand side and P_H factor,
+// start of the next solve, recovery and step, refinement residuals (mixed
+// precision).  Those steps are batched too, over the QPs at the same point.  A
+// QP whose solve ends early moves on at the next tick instead of waiting for
+// the slowest QP, and QPs admitted between ticks start at the next one.  Each
+// QP's arithmetic and launch shapes depend only on that QP, so its result does
+// not depend on which other QPs share the batch or when they arrived.
 //
 // Admission is by memory: every QP's buffers come from one arena of the
 // budget given at creation, so admitting and retiring QPs never calls hipMalloc
-// or hipFree.  New QPs are factored at the start of the next round and join
-// the running set there (continuous batching at iteration granularity).
-// Results are copied to host memory when a QP finishes and its device memory
-// returns to the arena at once.
+// or hipFree.  Results are copied to host memory when a QP finishes and its
+// device memory returns to the arena at once.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -35,12 +38,41 @@ using Clock = std::chrono::steady_clock;
 
 enum SlotState : int { kQueued = 0, kRunning = 1, kFinished = 2 };
 
+template <typename T>
+struct BItem {
+  qp_ctx* ctx = nullptr;
+  PcgBufs<T> bufs{};
+  const T* rhs = nullptr;
+  int prec = 0;
+  double rtol = 0, wtol = -1;
+  int maxit = 0;
+  int iters = 0, done = 0;
+};
+
+// Where a QP is in its interior point iteration (the batch advances each QP
+// on its own; a tick moves every QP as far as it can go without a host decision).
+enum Phase : int {
+  kPhQueued = 0,     // admitted, not factored yet
+  kPhAwaitStats = 1, // residual statistics launched; the KKT check needs them on the host
+  kPhSolve = 2,      // a CG solve of a reduced system is running (in cg64 or cg32)
+  kPhAwaitIR = 3,    // mixed precision: refinement residual launched; the next step needs it
+  kPhDone = 4
+};
+
 struct Slot {
   qp_ctx* ctx = nullptr;
   long long ticket = 0;
   int pool = -1;
   int state = kQueued;
+  int phase = kPhQueued;
   IpmRun R;
+  // the reduced solve in flight: which system, CG steps and refinement state
+  int which = 0;  // 0 predictor, 1 corrector
+  int s_iters = 0, s_refin = 0, s_fb = 0, s_done = 0, last_done = 0;
+  double prev_rr = -1.0, rtol64 = 0.0;
+  long long launched = 0;  // CG steps launched for the current CG run
+  BItem<double> it64{};    // current float64 CG run
+  BItem<float> it32{};     // current float32 CG run (mixed precision)
   qp_status status = QP_OK;
   std::string err;
   int n = 0, m1 = 0, m2 = 0;
@@ -68,6 +100,7 @@ struct qp_batch {
   IpmScalars* h_isc = nullptr;
   std::vector<int> free_pools;
   std::vector<Slot*> live;                          // queued and running, admission order
+  std::vector<Slot*> cg64, cg32;                    // QPs whose current CG run is float64 / float32
   std::unordered_map<long long, Slot*> finished;    // waiting for qp_batch_collect
   long long next_ticket = 1;
   // descriptor staging: a ring of pinned host areas and their device copies;
@@ -78,7 +111,7 @@ struct qp_batch {
     hipEvent_t ev = nullptr;
     bool used = false;
   };
-  static constexpr int kStageAreas = 8;
+  static constexpr int kStageAreas = 32;
   StageArea stage[kStageAreas];
   int stage_next = 0;
   // per-QP records of the batched IPM kernels, indexed by pool entry
@@ -93,6 +126,7 @@ struct qp_batch {
   bool prof_ready = false;
   double prof_ms[kProfOps] = {};
   double prof_bytes[kProfOps] = {};
+  double prof_pending_bytes[kProfOps] = {};
   long long prof_n[kProfOps] = {};
 };
 
@@ -156,6 +190,10 @@ void run_ops(qp_batch* B, const BatchedOps& ops) {
 
 void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
   qp_ctx* sk = &B->sink;
+  if (hi >= lo && (lo < 0 || hi >= kMaxSlots)) {
+    set_err(sk, "internal: pool range [%d, %d] outside the pools", lo, hi);
+    throw Fail{QP_E_DEVICE};
+  }
   if (hi >= lo) {
     HIPCHK(sk, hipMemcpyAsync(B->h_sc + lo, B->d_sc + lo, (size_t)(hi - lo + 1) * sizeof(PcgScalars),
                               hipMemcpyDeviceToHost, B->stream));
@@ -171,17 +209,6 @@ void sync_pools(qp_batch* B, int lo, int hi, bool stats) {
 }
 
 // ---- batched PCG ------------------------------------------------------------------
-template <typename T>
-struct BItem {
-  qp_ctx* ctx;
-  PcgBufs<T> bufs;
-  const T* rhs;
-  int prec;
-  double rtol, wtol;
-  int maxit;
-  int iters = 0, done = 0;
-};
-
 template <typename T>
 struct StepLists {
   std::vector<ColsDesc<T>> c1, c3, c5;  // C^T p, M^T v, X_P^T t
@@ -312,100 +339,6 @@ void launch_ph_apply(qp_batch* B, const StepLists<T>& L, int init, const EventPa
   HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nph, L.r4t, L.r4smem, 4, ev ? &ev[4] : nullptr));
   HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nph, 5, ev ? &ev[5] : nullptr));
   HIPCHK(sk, bpcg_ph_update<T>(B->stream, L.dph, nph, init));
-}
-
-// Run PCG for every item at once; returns when all have stopped.
-template <typename T>
-void run_bpcg(qp_batch* B, std::vector<BItem<T>>& items) {
-  qp_ctx* sk = &B->sink;
-  if (items.empty()) return;
-  std::vector<BItem<T>*> act;
-  int maxit_all = 0;
-  for (auto& it : items) {
-    act.push_back(&it);
-    maxit_all = std::max(maxit_all, it.maxit);
-  }
-  StepLists<T> L;
-  build_lists<T>(B, act, L);
-  const int nall = (int)act.size();
-  HIPCHK(sk, bpcg_init<T>(B->stream, L.dpd, nall));
-  launch_ph_apply<T>(B, L, 1);
-  const int poll = B->opt.poll_every > 0 ? B->opt.poll_every : 32;
-  const bool prof = B->opt.profile != 0;
-  if (prof && !B->prof_ready) {
-    for (int o = 0; o < kProfOps; ++o) {
-      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].begin));
-      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].end));
-    }
-    B->prof_ready = true;
-  }
-  long long launched = 0;
-  for (;;) {
-    if (launched > (long long)maxit_all + 2LL * poll) {
-      set_err(sk, "batched PCG made no progress after %lld launched steps", launched);
-      throw Fail{QP_E_DEVICE};
-    }
-    const int na = (int)act.size();
-    for (int k = 0; k < poll; ++k) {
-      const EventPair* ev = (prof && k == 0) ? B->prof_ev : nullptr;
-      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1, ev ? &ev[0] : nullptr));
-      HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
-      HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3, ev ? &ev[2] : nullptr));
-      HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem, ev ? &ev[3] : nullptr));
-      HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
-      launch_ph_apply<T>(B, L, 0, ev);
-    }
-    launched += poll;
-    B->cg_launched += poll;
-    int lo = kMaxSlots, hi = -1;
-    for (BItem<T>* it : act) {
-      const int pool = (int)(it->ctx->sc - B->d_sc);
-      lo = std::min(lo, pool);
-      hi = std::max(hi, pool);
-    }
-    sync_pools(B, lo, hi, false);
-    if (prof) {
-      // every QP of the chunk was still iterating, so the sampled step covered all of them
-      double bytes[kProfOps] = {0, 0, 0, 0, 0, 0};
-      for (BItem<T>* it : act) {
-        const qp_ctx* c = it->ctx;
-        const double mn = (double)c->n * (c->n + 1) / 2 + (double)c->m1 * c->n;
-        const double cn = (double)c->m2 * c->n, xp = (double)c->m2 * (c->m2 + 1) / 2;
-        bytes[0] += cn * sizeof(T);
-        bytes[1] += mn * sizeof(T);
-        bytes[2] += mn * sizeof(T);
-        bytes[3] += cn * sizeof(T);
-        if (it->prec == kPrecH) {
-          bytes[4] += xp * sizeof(T);
-          bytes[5] += xp * sizeof(T);
-        }
-      }
-      for (int o = 0; o < kProfOps; ++o) {
-        if (bytes[o] == 0) continue;
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, B->prof_ev[o].begin, B->prof_ev[o].end) == hipSuccess) {
-          B->prof_ms[o] += ms;
-          B->prof_bytes[o] += bytes[o];
-          B->prof_n[o] += 1;
-        }
-      }
-    }
-    std::vector<BItem<T>*> still;
-    for (BItem<T>* it : act) {
-      const PcgScalars& h = B->h_sc[it->ctx->sc - B->d_sc];
-      if (h.done) {
-        it->iters = h.iter;
-        it->done = h.done;
-      } else {
-        still.push_back(it);
-      }
-    }
-    if (still.empty()) break;
-    if (still.size() != act.size()) {
-      act.swap(still);
-      build_lists<T>(B, act, L);  // the stream was just synchronized
-    }
-  }
 }
 
 // ---- batched IPM phases ---------------------------------------------------------------
@@ -634,31 +567,7 @@ void bphase_recover_step(qp_batch* B, const std::vector<Slot*>& ss, int which) {
   if (!which) HIPCHK(sk, bipm_rhs(B->stream, B->d_ipm, pl.dev(base), pl.count(), 1));
 }
 
-// ---- batched reduced solve ----------------------------------------------------------
-struct RsItem {
-  Slot* slot;
-  const double* dvec;
-  const double* rhs;
-  double* dnu;
-  const double* wts;
-  double rtol, wtol;
-  int maxit;
-  int iters = 0, done = 0, refin = 0, fb = 0;
-  // mixed-precision sweep state
-  double prev_rr = -1.0;
-  bool sweeping = true;
-  bool to_fp64 = false;
-  double rtol64 = 0;
-  int last_done = 0;
-};
-
-template <typename F>
-void for_slots(std::vector<RsItem*>& v, std::vector<Slot*>& out, F&& pred) {
-  out.clear();
-  for (RsItem* it : v)
-    if (pred(it)) out.push_back(it->slot);
-}
-
+// ---- refinement steps ----------------------------------------------------------------
 // Float64 residual r = rhs - K_F dnu of the listed QPs (dnu already updated by
 // bir_acc, which also left pt = D dnu): C^T dnu, the M sweeps, C w + pt, then
 // the residual statistics into each QP's PcgScalars.
@@ -698,100 +607,6 @@ void bvec(qp_batch* B, const std::vector<Slot*>& ss, F&& launch) {
   HIPCHK(&B->sink, launch(pl.dev(base), pl.count()));
 }
 
-// The reduced solves of one phase (which 0: predictor, 1: corrector) for all
-// listed QPs; the same refinement as the single-QP solve in mixed precision.
-void batched_reduced_solve(qp_batch* B, std::vector<RsItem>& items, int which) {
-  if (items.empty()) return;
-  if (B->opt.precision != QP_MIXED) {
-    std::vector<BItem<double>> bi;
-    for (auto& it : items) {
-      qp_ctx* c = it.slot->ctx;
-      bi.push_back(BItem<double>{c, bufs64(c, it.dvec, it.wts, it.dnu), it.rhs, it.slot->R.prec, it.rtol, it.wtol,
-                                 it.maxit});
-    }
-    run_bpcg<double>(B, bi);
-    for (size_t k = 0; k < items.size(); ++k) {
-      items[k].iters = bi[k].iters;
-      items[k].done = bi[k].done;
-    }
-    return;
-  }
-  // Mixed precision: float32 sweeps of all QPs batched, float64 residuals batched.
-  const double inner_rtol = 1e-5;
-  std::vector<RsItem*> all;
-  std::vector<Slot*> ss;
-  for (auto& it : items) {
-    it.done = 2;
-    all.push_back(&it);
-  }
-  for_slots(all, ss, [](RsItem*) { return true; });
-  bvec(B, ss, [&](const int* l, int n) { return bir_begin(B->stream, B->d_ipm, l, n, which); });
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    std::vector<RsItem*> act;
-    for (RsItem* it : all)
-      if (it->sweeping && it->iters < it->maxit) act.push_back(it);
-    if (act.empty()) break;
-    for_slots(act, ss, [](RsItem*) { return true; });
-    bvec(B, ss, [&](const int* l, int n) { return bir_prep(B->stream, B->d_ipm, l, n); });
-    std::vector<BItem<float>> bi;
-    for (RsItem* it : act) {
-      qp_ctx* c = it->slot->ctx;
-      PcgBufs<float> bf = bufs32(c);
-      bf.wts = it->wts ? c->fwts : nullptr;
-      const int cap = mixed_inner_cap(c, it->slot->R.prec);
-      bi.push_back(BItem<float>{c, bf, c->fb, it->slot->R.prec, inner_rtol, -1.0, std::min(cap, it->maxit - it->iters)});
-    }
-    run_bpcg<float>(B, bi);
-    int lo = kMaxSlots, hi = -1;
-    for (size_t k = 0; k < act.size(); ++k) {
-      act[k]->iters += bi[k].iters;
-      act[k]->last_done = bi[k].done;
-      lo = std::min(lo, act[k]->slot->pool);
-      hi = std::max(hi, act[k]->slot->pool);
-    }
-    bvec(B, ss, [&](const int* l, int n) { return bir_acc(B->stream, B->d_ipm, l, n, which); });
-    bphase_ir_residual(B, ss, which);
-    sync_pools(B, lo, hi, false);
-    for (RsItem* it : act) {
-      const PcgScalars h = B->h_sc[it->slot->pool];
-      it->refin += 1;
-      if (h.bb == 0.0 || h.rr <= it->rtol * it->rtol * h.bb || (it->wtol >= 0.0 && h.wmax <= it->wtol)) {
-        it->done = 1;
-        it->sweeping = false;
-        continue;
-      }
-      const double ref_rr = it->prev_rr >= 0.0 ? it->prev_rr : h.bb;
-      const bool stalled = it->last_done != 1 || h.rr > 1e-2 * ref_rr || !std::isfinite(h.rr);
-      if (stalled && it->iters < it->maxit) {
-        it->to_fp64 = true;
-        it->rtol64 = h.rr > 0.0 ? it->rtol * std::sqrt(h.bb / h.rr) : it->rtol;
-        it->sweeping = false;
-        continue;
-      }
-      it->prev_rr = h.rr;
-    }
-  }
-  // float64 PCG on the remaining correction of the solves whose float32 sweeps stalled
-  std::vector<BItem<double>> bi;
-  std::vector<RsItem*> fbk;
-  for (RsItem* it : all) {
-    if (!it->to_fp64) continue;
-    qp_ctx* c = it->slot->ctx;
-    bi.push_back(BItem<double>{c, bufs64(c, it->dvec, it->wts, c->ir_d), c->ir_r, it->slot->R.prec, it->rtol64,
-                               it->wtol, it->maxit - it->iters});
-    fbk.push_back(it);
-  }
-  if (fbk.empty()) return;
-  run_bpcg<double>(B, bi);
-  for (size_t k = 0; k < fbk.size(); ++k) {
-    fbk[k]->iters += bi[k].iters;
-    fbk[k]->done = bi[k].done;
-    fbk[k]->fb = 1;
-  }
-  for_slots(fbk, ss, [](RsItem*) { return true; });
-  bvec(B, ss, [&](const int* l, int n) { return bir_fb_add(B->stream, B->d_ipm, l, n, which); });
-}
-
 // ---- slots ------------------------------------------------------------------------------
 void release_slot_memory(qp_batch* B, Slot* s) {
   if (s->ctx) {
@@ -827,6 +642,7 @@ void finish_slot(qp_batch* B, Slot* s, qp_status st) {
   s->t_done = Clock::now();
   s->info.t_solve_ms = std::chrono::duration<double, std::milli>(s->t_done - s->t_admit).count();
   s->state = kFinished;
+  s->phase = kPhDone;
   release_slot_memory(B, s);
   B->finished[s->ticket] = s;
 }
@@ -974,75 +790,342 @@ void batched_ph_factor(qp_batch* B, const std::vector<Slot*>& go) {
     HIPCHK(&B->sink, bmat2d(B->stream, reinterpret_cast<const Mat2dDesc*>(base + oc), (int)cv.size(), mr, mr));
 }
 
-// One IPM iteration for every QP in flight (and the set-up of new ones).
-void run_round(qp_batch* B) {
+// ---- the scheduler -----------------------------------------------------------------------
+// Start CG runs (their BItem<T> already filled): initial residual and direction,
+// and for P_H the first preconditioner apply; the QPs join the CG pool.
+template <typename T>
+void start_cg(qp_batch* B, const std::vector<Slot*>& ss, std::vector<Slot*>& pool) {
+  if (ss.empty()) return;
+  std::vector<BItem<T>*> items;
+  for (Slot* s : ss) {
+    BItem<T>* it;
+    if constexpr (sizeof(T) == 8)
+      it = &s->it64;
+    else
+      it = &s->it32;
+    it->iters = it->done = 0;
+    items.push_back(it);
+    s->launched = 0;
+    s->phase = kPhSolve;
+    pool.push_back(s);
+  }
+  StepLists<T> L;
+  build_lists<T>(B, items, L);
+  HIPCHK(&B->sink, bpcg_init<T>(B->stream, L.dpd, (int)items.size()));
+  launch_ph_apply<T>(B, L, 1);
+}
+
+void fill_cg64(Slot* s, double* x, const double* rhs, double rtol, int maxit) {
+  qp_ctx* c = s->ctx;
+  s->it64 = BItem<double>{};
+  s->it64.ctx = c;
+  s->it64.bufs = bufs64(c, c->dvec, c->nu, x);
+  s->it64.rhs = rhs;
+  s->it64.prec = s->R.prec;
+  s->it64.rtol = rtol;
+  s->it64.wtol = s->R.wtol;
+  s->it64.maxit = maxit;
+}
+
+// Next float32 sweep of the mixed refinement: fb = r, CG on K_F delta = r.
+void next_sweep(qp_batch* B, const std::vector<Slot*>& ss) {
+  if (ss.empty()) return;
+  bvec(B, ss, [&](const int* l, int n) { return bir_prep(B->stream, B->d_ipm, l, n); });
+  for (Slot* s : ss) {
+    qp_ctx* c = s->ctx;
+    s->it32 = BItem<float>{};
+    s->it32.ctx = c;
+    s->it32.bufs = bufs32(c);
+    s->it32.rhs = c->fb;
+    s->it32.prec = s->R.prec;
+    s->it32.rtol = 1e-5;
+    s->it32.wtol = -1.0;
+    s->it32.maxit = std::min(mixed_inner_cap(c, s->R.prec), s->R.maxit - s->s_iters);
+  }
+  start_cg<float>(B, ss, B->cg32);
+}
+
+// Begin the reduced solve `which` (0 predictor, 1 corrector) of the listed QPs.
+void start_solve(qp_batch* B, const std::vector<Slot*>& ss, int which) {
+  if (ss.empty()) return;
+  for (Slot* s : ss) {
+    s->which = which;
+    s->s_iters = s->s_refin = s->s_fb = 0;
+    s->s_done = 2;
+    s->last_done = 0;
+    s->prev_rr = -1.0;
+  }
+  if (B->opt.precision != QP_MIXED) {
+    for (Slot* s : ss) fill_cg64(s, which ? s->ctx->dnu : s->ctx->dnu_a, s->ctx->rhs, s->ctx->opt.cg_rtol, s->R.maxit);
+    start_cg<double>(B, ss, B->cg64);
+    return;
+  }
+  bvec(B, ss, [&](const int* l, int n) { return bir_begin(B->stream, B->d_ipm, l, n, which); });
+  next_sweep(B, ss);
+}
+
+// A reduced solve has ended: record it and move the QP on (recovery and step;
+// after the corrector also the next iteration's residual statistics).
+void solves_done(qp_batch* B, std::vector<Slot*>& d0, std::vector<Slot*>& d1) {
+  for (auto* v : {&d0, &d1})
+    for (Slot* s : *v) {
+      IpmRun& R = s->R;
+      (s->which ? R.k2 : R.k1) = s->s_iters;
+      R.refin_total += s->s_refin;
+      R.fallbacks += s->s_fb;
+    }
+  if (!d0.empty()) {
+    bphase_recover_step(B, d0, 0);
+    start_solve(B, d0, 1);
+  }
+  if (!d1.empty()) {
+    bphase_recover_step(B, d1, 1);
+    for (Slot* s : d1) {
+      s->R.cg_total += s->R.k1 + s->R.k2;
+      ++s->R.it;
+      s->phase = kPhAwaitStats;
+    }
+    bphase_eval(B, d1);
+  }
+}
+
+void sync_live_pools(qp_batch* B) {
+  int lo = kMaxSlots, hi = -1;
+  for (Slot* s : B->live) {
+    if (s->pool < 0) continue;  // retired in this tick
+    lo = std::min(lo, s->pool);
+    hi = std::max(hi, s->pool);
+  }
+  sync_pools(B, lo, hi, true);
+}
+
+// CG steps for every QP of a pool: poll_every steps, one launch per sweep.
+template <typename T>
+void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sample) {
+  if (pool.empty()) return;
+  std::vector<BItem<T>*> items;
+  for (Slot* s : pool) {
+    BItem<T>* it;
+    if constexpr (sizeof(T) == 8)
+      it = &s->it64;
+    else
+      it = &s->it32;
+    if (s->launched > (long long)it->maxit + 2LL * poll) {
+      set_err(&B->sink, "batched PCG made no progress after %lld launched steps", s->launched);
+      throw Fail{QP_E_DEVICE};
+    }
+    s->launched += poll;
+    items.push_back(it);
+  }
+  StepLists<T> L;
+  build_lists<T>(B, items, L);
+  qp_ctx* sk = &B->sink;
+  const int na = (int)items.size();
+  for (int k = 0; k < poll; ++k) {
+    const EventPair* ev = (sample && k == 0) ? B->prof_ev : nullptr;
+    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1, ev ? &ev[0] : nullptr));
+    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
+    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3, ev ? &ev[2] : nullptr));
+    HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem, ev ? &ev[3] : nullptr));
+    HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
+    launch_ph_apply<T>(B, L, 0, ev);
+  }
+  if (sample) {
+    // every QP of the chunk was iterating when it started, so the sampled step covered all of them
+    for (int o = 0; o < kProfOps; ++o) B->prof_pending_bytes[o] = 0;
+    for (Slot* s : pool) {
+      const qp_ctx* c = s->ctx;
+      const double mn = (double)c->n * (c->n + 1) / 2 + (double)c->m1 * c->n;
+      const double cn = (double)c->m2 * c->n, xp = (double)c->m2 * (c->m2 + 1) / 2;
+      B->prof_pending_bytes[0] += cn * sizeof(T);
+      B->prof_pending_bytes[1] += mn * sizeof(T);
+      B->prof_pending_bytes[2] += mn * sizeof(T);
+      B->prof_pending_bytes[3] += cn * sizeof(T);
+      if (s->R.prec == kPrecH) {
+        B->prof_pending_bytes[4] += xp * sizeof(T);
+        B->prof_pending_bytes[5] += xp * sizeof(T);
+      }
+    }
+  }
+}
+
+bool advance(qp_batch* B);
+
+// One scheduling tick: admit and factor new QPs, run one poll chunk of CG
+// steps for every QP inside a reduced solve, wait once, then move every QP as
+// far as it can go (KKT checks, refinement decisions, recovery and step, the
+// next solve) before the next chunk.
+void tick(qp_batch* B) {
+  qp_ctx* sk = &B->sink;
+  // (1) QPs admitted since the last tick: factor, initial point, statistics
   std::vector<Slot*> fresh;
   for (Slot* s : B->live)
     if (s->state == kQueued) fresh.push_back(s);
-  if (!fresh.empty()) batched_factor(B, fresh);
   auto prune = [&] {
     std::vector<Slot*> keep;
     for (Slot* s : B->live)
       if (s->state != kFinished) keep.push_back(s);
     B->live.swap(keep);
   };
-  prune();
-  if (B->live.empty()) return;
-  // residuals and statistics of every iterate, one copy and one wait for all
-  bphase_eval(B, B->live);
-  int lo = kMaxSlots, hi = -1;
-  for (Slot* s : B->live) {
-    lo = std::min(lo, s->pool);
-    hi = std::max(hi, s->pool);
+  if (!fresh.empty()) {
+    batched_factor(B, fresh);
+    prune();  // QPs whose factorization failed have left (and given back their pool entry)
+    std::vector<Slot*> ok;
+    for (Slot* s : fresh)
+      if (s->state == kRunning) {
+        s->phase = kPhAwaitStats;
+        ok.push_back(s);
+      }
+    if (!ok.empty()) bphase_eval(B, ok);
   }
-  sync_pools(B, lo, hi, true);
-  std::vector<Slot*> go;
-  for (Slot* s : B->live) {
-    if (!ipm_check(s->ctx, s->R)) {
-      qp_status st = (qp_status)s->R.status;
-      if (st != QP_OK && s->ctx->err.empty())
-        set_err(s->ctx, "IPM stopped at rel_kkt %.3e after %d iterations", s->R.score, s->R.it);
-      finish_slot(B, s, st);
-      continue;
+  // (2) one chunk of CG steps
+  const int poll = B->opt.poll_every > 0 ? B->opt.poll_every : 32;
+  const bool prof = B->opt.profile != 0;
+  if (prof && !B->prof_ready) {
+    for (int o = 0; o < kProfOps; ++o) {
+      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].begin));
+      HIPCHK(sk, hipEventCreate(&B->prof_ev[o].end));
     }
-    go.push_back(s);
+    B->prof_ready = true;
   }
-  prune();
-  if (go.empty()) return;
-  bphase_predictor(B, go);
-  batched_ph_factor(B, go);
-  auto solve = [&](int which) {
-    std::vector<RsItem> items;
-    for (Slot* s : go) {
-      qp_ctx* c = s->ctx;
-      RsItem it{};
-      it.slot = s;
-      it.dvec = c->dvec;
-      it.rhs = c->rhs;
-      it.dnu = which ? c->dnu : c->dnu_a;
-      it.wts = c->nu;
-      it.rtol = c->opt.cg_rtol;
-      it.wtol = s->R.wtol;
-      it.maxit = s->R.maxit;
-      items.push_back(it);
+  const bool s32 = prof && !B->cg32.empty();
+  const bool s64 = prof && !s32 && !B->cg64.empty();
+  launch_chunk<double>(B, B->cg64, poll, s64);
+  launch_chunk<float>(B, B->cg32, poll, s32);
+  if (!B->cg64.empty() || !B->cg32.empty()) B->cg_launched += poll;
+  // (3) wait; every QP's CG scalars, statistics and factorization status on the host
+  sync_live_pools(B);
+  if (s32 || s64) {
+    for (int o = 0; o < kProfOps; ++o) {
+      if (B->prof_pending_bytes[o] == 0) continue;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, B->prof_ev[o].begin, B->prof_ev[o].end) == hipSuccess) {
+        B->prof_ms[o] += ms;
+        B->prof_bytes[o] += B->prof_pending_bytes[o];
+        B->prof_n[o] += 1;
+      }
     }
-    batched_reduced_solve(B, items, which);
-    for (auto& it : items) {
-      IpmRun& R = it.slot->R;
-      (which ? R.k2 : R.k1) = it.iters;
-      R.refin_total += it.refin;
-      R.fallbacks += it.fb;
-    }
-  };
-  solve(0);
-  bphase_recover_step(B, go, 0);
-  solve(1);
-  bphase_recover_step(B, go, 1);
-  for (Slot* s : go) {
-    s->R.cg_total += s->R.k1 + s->R.k2;
-    ++s->R.it;
   }
   B->rounds += 1;
+  // (4) decisions and the launches they lead to; a QP may need a few host
+  // decisions in a row (refinement residual, KKT check) before its next CG run,
+  // so repeat with a short wait for the small kernels in between
+  for (int pass = 0; pass < 4; ++pass) {
+    if (pass > 0) sync_live_pools(B);
+    if (!advance(B)) break;
+  }
+  prune();
+}
+
+// Read the host copies of every QP's scalars and move each QP on; returns true
+// when some QP now waits for a result launched here (one more pass helps it).
+bool advance(qp_batch* B) {
+  {
+    std::vector<Slot*> keep;  // QPs retired by an earlier pass have left
+    for (Slot* s : B->live)
+      if (s->state != kFinished) keep.push_back(s);
+    B->live.swap(keep);
+  }
+  std::vector<Slot*> pred, d0, d1, ir0, ir1, fb, sw;
+  const bool mixed = B->opt.precision == QP_MIXED;
+  auto done_solve = [&](Slot* s) { (s->which ? d1 : d0).push_back(s); };
+  // CG runs that stopped
+  std::vector<Slot*> keep64, keep32;
+  for (Slot* s : B->cg64) {
+    const PcgScalars& h = B->h_sc[s->pool];
+    if (!h.done) {
+      keep64.push_back(s);
+      continue;
+    }
+    s->s_iters += h.iter;
+    if (!mixed) {
+      s->s_done = h.done;
+      done_solve(s);
+    } else {
+      // float64 leg of a mixed solve: add the correction
+      s->s_done = h.done;
+      s->s_fb = 1;
+      fb.push_back(s);
+    }
+  }
+  for (Slot* s : B->cg32) {
+    const PcgScalars& h = B->h_sc[s->pool];
+    if (!h.done) {
+      keep32.push_back(s);
+      continue;
+    }
+    s->s_iters += h.iter;
+    s->last_done = h.done;
+    (s->which ? ir1 : ir0).push_back(s);
+  }
+  B->cg64.swap(keep64);
+  B->cg32.swap(keep32);
+  // refinement residuals that reached the host: converged, stalled, or sweep again
+  std::vector<Slot*> to64;
+  for (Slot* s : B->live) {
+    if (s->phase == kPhAwaitIR) {
+      const PcgScalars h = B->h_sc[s->pool];
+      s->s_refin += 1;
+      const double rt = s->ctx->opt.cg_rtol;
+      if (h.bb == 0.0 || h.rr <= rt * rt * h.bb || (s->R.wtol >= 0.0 && h.wmax <= s->R.wtol)) {
+        s->s_done = 1;
+        done_solve(s);
+        continue;
+      }
+      const double ref_rr = s->prev_rr >= 0.0 ? s->prev_rr : h.bb;
+      const bool stalled = s->last_done != 1 || h.rr > 1e-2 * ref_rr || !std::isfinite(h.rr);
+      if (stalled && s->s_iters < s->R.maxit) {
+        s->rtol64 = h.rr > 0.0 ? rt * std::sqrt(h.bb / h.rr) : rt;
+        to64.push_back(s);
+        continue;
+      }
+      s->prev_rr = h.rr;
+      if (s->s_refin < 30 && s->s_iters < s->R.maxit)
+        sw.push_back(s);
+      else {
+        s->s_done = 2;
+        done_solve(s);
+      }
+    } else if (s->phase == kPhAwaitStats) {
+      if (!ipm_check(s->ctx, s->R)) {
+        qp_status st = (qp_status)s->R.status;
+        if (st != QP_OK && s->ctx->err.empty())
+          set_err(s->ctx, "IPM stopped at rel_kkt %.3e after %d iterations", s->R.score, s->R.it);
+        finish_slot(B, s, st);
+        continue;
+      }
+      pred.push_back(s);
+    }
+  }
+  // (5) launches, grouped by kind over all QPs
+  if (!fb.empty()) {  // float64 corrections of stalled mixed solves are done: dnu += correction
+    std::vector<Slot*> f0, f1;
+    for (Slot* s : fb) (s->which ? f1 : f0).push_back(s);
+    bvec(B, f0, [&](const int* l, int n) { return bir_fb_add(B->stream, B->d_ipm, l, n, 0); });
+    bvec(B, f1, [&](const int* l, int n) { return bir_fb_add(B->stream, B->d_ipm, l, n, 1); });
+    for (Slot* s : fb) done_solve(s);
+  }
+  for (int w = 0; w < 2; ++w) {  // float32 sweeps that stopped: accumulate, float64 residual
+    std::vector<Slot*>& ir = w ? ir1 : ir0;
+    if (ir.empty()) continue;
+    bvec(B, ir, [&](const int* l, int n) { return bir_acc(B->stream, B->d_ipm, l, n, w); });
+    bphase_ir_residual(B, ir, w);
+    for (Slot* s : ir) s->phase = kPhAwaitIR;
+  }
+  if (!to64.empty()) {
+    for (Slot* s : to64) fill_cg64(s, s->ctx->ir_d, s->ctx->ir_r, s->rtol64, s->R.maxit - s->s_iters);
+    start_cg<double>(B, to64, B->cg64);
+  }
+  next_sweep(B, sw);
+  if (!pred.empty()) {
+    bphase_predictor(B, pred);
+    batched_ph_factor(B, pred);
+    start_solve(B, pred, 0);
+  }
+  solves_done(B, d0, d1);
+  for (Slot* s : B->live)
+    if (s->state != kFinished && (s->phase == kPhAwaitStats || s->phase == kPhAwaitIR)) return true;
+  return false;
 }
 
 template <typename F>
@@ -1206,7 +1289,7 @@ qp_status qp_batch_step(qp_batch* B, int max_rounds, int* n_done) {
   if (!B || max_rounds <= 0) return QP_E_INVALID;
   B->sink.err.clear();
   qp_status st = batch_guard(B, [&] {
-    for (int r = 0; r < max_rounds && !B->live.empty(); ++r) run_round(B);
+    for (int r = 0; r < max_rounds && !B->live.empty(); ++r) tick(B);
   });
   if (n_done) *n_done = (int)B->finished.size();
   return st;

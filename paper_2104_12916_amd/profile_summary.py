@@ -1,0 +1,136 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  stats    kernel-stats CSV (rocprofv3 --kernel-trace --stats -f csv) -> markdown
+           table of the top kernels with the command that produced it
+  traffic  FETCH_SIZE and WRITE_SIZE counter CSVs of one profile_ops run
+           (rocprofv3 --pmc, one counter per run) -> per-launch HBM bytes of
+           the CG-step sweeps, scaled by what the same counters read for the
+           run's calibration copy of known size, stored in profiles/traffic.json
+           with the hash of the kernel sources they were taken on
+
+Usage:
+  python -m paper_2104_12916_amd.profile_summary stats CSV OUT.md --title T --cmd C [--note N] [--top 14]
+  python -m paper_2104_12916_amd.profile_summary traffic --fetch F.csv --write W.csv --workload lowdof
+"""
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+COPY_BYTES = 256 << 20  # the calibration copy of profile_ops
+
+# CG-step sweeps of the float64 single-QP path: tag -> kernel name prefix
+SWEEPS = {
+    "C^T": "qpg::gemv_cols_part_kernel<double, 1,",
+    "M": "qpg::gemv_rows_kernel<double, 2,",
+    "M^T": "qpg::gemv_cols_part_kernel<double, 3,",
+    "q": "qpg::pcg_q_kernel<double,",
+}
+
+
+def kernel_src_hash():
+    """Hash of the sources of the sweep kernels (counters go stale when they change)."""
+    h = hashlib.sha256()
+    for f in ("gemv.hip", "gemv_core.hpp", "pcg.hip", "common.hpp"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n, m1, m2, elem=8):
+    """Matrix bytes one launch of each sweep must read: C is m2 x n, M = L^{-1}[:, :n]
+    is the lower trapezoid of n(n+1)/2 + m1 n entries."""
+    mm = n * (n + 1) // 2 + m1 * n
+    return {"C^T": m2 * n * elem, "M": mm * elem, "M^T": mm * elem, "q": m2 * n * elem}
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("qpg::", "").strip()
+
+
+def stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {args.title}", "", "Command (run from the repository root on one MI355X):", "", "```", args.cmd, "```",
+             ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += [f"Total kernel time {total / 1e6:.1f} ms over {sum(int(r['Calls']) for r in rows)} dispatches.", "",
+              "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows[:args.top]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / total:.2f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counters(path):
+    rows = list(csv.DictReader(open(path)))
+    return {int(r["Dispatch_Id"]): r for r in rows}
+
+
+def traffic(args):
+    sys.path.insert(0, ROOT)
+    import synth
+    fetch, write = _counters(args.fetch), _counters(args.write)
+    # calibration: the largest copyBuffer dispatch writes COPY_BYTES
+    copies = [d for d, r in write.items() if "copyBuffer" in r["Kernel_Name"]]
+    cal = max(copies, key=lambda d: float(write[d]["Counter_Value"]))
+    w_scale = COPY_BYTES / (float(write[cal]["Counter_Value"]) * 1024)
+    f_scale = COPY_BYTES / (float(fetch[cal]["Counter_Value"]) * 1024)
+    w = synth.WORKLOADS[args.workload]
+    alg = algorithmic_bytes(w["n"], w["m1"], w["m2"])
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    src = kernel_src_hash()
+    for tag, prefix in SWEEPS.items():
+        ids = [d for d, r in fetch.items() if r["Kernel_Name"].startswith("void " + prefix) or
+               r["Kernel_Name"].startswith(prefix)]
+        if not ids:
+            continue
+        fk = sum(float(fetch[d]["Counter_Value"]) for d in ids) / len(ids)
+        wk = sum(float(write[d]["Counter_Value"]) for d in ids if d in write) / len(ids)
+        out[f"{args.workload}:{tag}"] = {
+            "kernel": _short(fetch[ids[0]]["Kernel_Name"]), "src_hash": src, "dispatches": len(ids),
+            "bytes_per_launch": int(round(fk * 1024 * f_scale + wk * 1024 * w_scale)),
+            "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
+            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+            "algorithmic_bytes": alg[tag],
+            "note": ("rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, over profile_ops; scaled by what the counters "
+                     f"read for the run's {COPY_BYTES >> 20} MiB calibration copy"),
+        }
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("out")
+    a.add_argument("--title", required=True)
+    a.add_argument("--cmd", required=True)
+    a.add_argument("--note", default="")
+    a.add_argument("--top", type=int, default=14)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--workload", default="lowdof")
+    args = ap.parse_args()
+    if args.cmd_name == "stats":
+        stats(args)
+    else:
+        traffic(args)
+
+
+if __name__ == "__main__":
+    main()
