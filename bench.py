@@ -181,17 +181,18 @@ def run_batch_workload(args):
     prec = {"PL": qpgpu.QP_PREC_LOW_DOF, "PH": qpgpu.QP_PREC_FEW_EQ, "none": qpgpu.QP_PREC_NONE,
             "auto": qpgpu.QP_PREC_AUTO}[args.prec or "auto"]
     precision = qpgpu.QP_FP64 if args.precision == "fp64" else qpgpu.QP_MIXED
+    kf = qpgpu.QP_KF_EXPLICIT if args.kf == "explicit" else qpgpu.QP_KF_IMPLICIT
     sizes = synth.batch_sizes(args.batch_count, 1000)
     t = time.perf_counter()
     qps = [synth.gaussian_qp(*sz) for sz in sizes]
     print(f"generated {len(qps)} QPs in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     dev = [tuple(torch.from_numpy(a).cuda() for a in qp.arrays()) for qp in qps]
     torch.cuda.synchronize()
-    opt = qpgpu.qp_default_options(prec=prec, precision=precision)
+    opt = qpgpu.qp_default_options(prec=prec, precision=precision, kf_form=kf)
     budget = int(1.05 * sum(qpgpu.qp_batch_footprint(opt, q.n, q.m1, q.m2) for q in qps)) + (64 << 20)
 
     def solve_all(k, profile):
-        b = qpgpu.Batch(budget, prec=prec, precision=precision, profile=int(profile))
+        b = qpgpu.Batch(budget, prec=prec, precision=precision, profile=int(profile), kf_form=kf)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tickets = [b.admit(*dev[i]) for i in range(k)]
@@ -276,7 +277,7 @@ def run_batch_workload(args):
         "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
         "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
         "config": {"workload": f"batch: {BATCH_DESC}", "qps": len(qps), "precond": args.prec or "auto",
-                   "precision": args.precision, "budget_bytes": budget},
+                   "precision": args.precision, "kf_form": args.kf, "budget_bytes": budget},
         "roofline": roof, "cpu_baseline": cpu,
         "parity": dict(passed=ok, solves=len(qps), max_rel_kkt=worst, max_obj_rel_err=worst_obj,
                        obj_checked=len(sample)),
@@ -299,6 +300,7 @@ def run_serve_workload(args):
     prec = {"PL": qpgpu.QP_PREC_LOW_DOF, "PH": qpgpu.QP_PREC_FEW_EQ, "none": qpgpu.QP_PREC_NONE,
             "auto": qpgpu.QP_PREC_AUTO}[args.prec or "auto"]
     precision = qpgpu.QP_FP64 if args.precision == "fp64" else qpgpu.QP_MIXED
+    kf = qpgpu.QP_KF_EXPLICIT if args.kf == "explicit" else qpgpu.QP_KF_IMPLICIT
     nw, nm = args.serve_warmup, args.serve_requests
     specs = synth.serving_stream(nw + nm, seed=5000)
     t = time.perf_counter()
@@ -311,7 +313,7 @@ def run_serve_workload(args):
         rng = np.random.default_rng(5001)
         gaps = np.zeros(len(reqs)) if rate is None else rng.exponential(1.0 / rate, size=len(reqs))
         arrive = np.cumsum(gaps)
-        b = qpgpu.Batch(budget, prec=prec, precision=precision)
+        b = qpgpu.Batch(budget, prec=prec, precision=precision, kf_form=kf)
         pending = collections.deque()
         owner, lat, results = {}, {}, {}
         t0 = time.perf_counter()
@@ -363,7 +365,7 @@ def run_serve_workload(args):
     for k in small:
         ref = ipm.solve(reqs[k])
         worst_obj = max(worst_obj, abs(kkt.objective(reqs[k], res_sat[k][0]) - ref.obj) / max(1.0, abs(ref.obj)))
-        b = qpgpu.Batch(budget, prec=prec, precision=precision)
+        b = qpgpu.Batch(budget, prec=prec, precision=precision, kf_form=kf)
         tk = b.admit(*reqs[k].arrays())
         b.step(10 ** 6)
         xa = b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))[0]
@@ -375,7 +377,8 @@ def run_serve_workload(args):
         "vs_baseline": None, "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
         "data": "synthetic (seeded dense Gaussian QPs arriving from host memory; admission includes the upload)",
         "config": {"workload": f"serve: {SERVE_DESC}", "requests": nm, "warmup_requests": nw,
-                   "budget_gb": args.serve_budget_gb, "precond": args.prec or "auto", "precision": args.precision},
+                   "budget_gb": args.serve_budget_gb, "precond": args.prec or "auto", "precision": args.precision,
+                   "kf_form": args.kf},
         "latency": {"saturated": {k: round(v, 3) for k, v in sat.items()}, **loads},
         "parity": dict(passed=ok, solves=nm, max_rel_kkt=worst, max_obj_rel_err=worst_obj,
                        alone_equals_mix=same, checked_alone=len(small)),
@@ -392,6 +395,8 @@ def main():
     ap.add_argument("--workload", default="lowdof", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default=None, choices=["PL", "PH", "none", "auto"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--kf", default="implicit", choices=["implicit", "explicit"],
+                    help="how each CG step applies K_F (explicit: operator formed once per QP)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--batch-count", type=int, default=512)
@@ -426,12 +431,13 @@ def main():
     prec = {"PL": qpgpu.QP_PREC_LOW_DOF, "PH": qpgpu.QP_PREC_FEW_EQ, "none": qpgpu.QP_PREC_NONE,
             "auto": qpgpu.QP_PREC_AUTO}[prec_name]
     precision = qpgpu.QP_MIXED if args.precision == "mixed" else qpgpu.QP_FP64
+    kf = qpgpu.QP_KF_EXPLICIT if args.kf == "explicit" else qpgpu.QP_KF_IMPLICIT
     seeds = w["seeds"][:max(1, min(len(w["seeds"]), args.steps))]
     qps, solvers = [], []
     for sd in seeds:
         qp = synth.workload(args.workload, seed=sd)
         qps.append(qp)
-        solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=1))
+        solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=1, kf_form=kf))
     torch.cuda.synchronize()
 
     factor_s = []
@@ -489,6 +495,8 @@ def main():
     qp0 = qps[0]
     elem = 4 if precision == qpgpu.QP_MIXED else 8
     nbytes = op_bytes(qp0.n, qp0.m1, qp0.m2, elem)
+    if kf == qpgpu.QP_KF_EXPLICIT:  # one sweep over E (m2 x m2) replaces the four operator sweeps
+        nbytes = [0, 0, 0, qp0.m2 * qp0.m2 * elem] + nbytes[4:]
     ops = {}
     for o in range(6):
         if cnt[o] > 0:
@@ -511,6 +519,8 @@ def main():
     fl = n ** 3 / 3 + n * n * m1 + n * m1 * m1 + m1 ** 3 / 3
     if prec == qpgpu.QP_PREC_FEW_EQ:
         fl += n * n * m2 + m2 * m2 * n
+    if kf == qpgpu.QP_KF_EXPLICIT:
+        fl += (n * n / 2 + m1 * n) * m2 + m2 * m2 * (n + m1)  # Y = M C^T and E = Y1^T Y1 - Y2^T Y2
     fl *= 2  # multiply-adds
     f_ms = 1e3 * sum(factor_s) / max(1, len(factor_s))
     factor = dict(ms=round(f_ms, 3), algorithmic_gflop=round(fl / 1e9, 2),
@@ -525,7 +535,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
         "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
         "config": {"workload": f"{args.workload}: {w['desc']}", "seeds": seeds, "precond": prec_name,
-                   "precision": args.precision},
+                   "precision": args.precision, "kf_form": args.kf},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": dict(passed=ok, solves=len(outs), max_rel_kkt=worst_kkt, max_obj_rel_err=worst_obj),

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define QPGPU_ABI_VERSION 1
+#define QPGPU_ABI_VERSION 2
 
 typedef struct qp_ctx qp_ctx;
 
@@ -73,6 +73,14 @@ typedef enum {
 
 typedef enum { QP_MEM_HOST = 0, QP_MEM_DEVICE = 1 } qp_mem;
 
+typedef enum {
+  QP_KF_IMPLICIT = 0, /* each CG step applies C^T, the K0 inverse factor twice and C
+                         (Sec. 3.1, implicit form; the default)                     */
+  QP_KF_EXPLICIT = 1  /* K_F - D = C K0^{-1}_{11} C^T (eq. ineq-const-reduced) formed
+                         once per QP after the K0 factorization (m2 x m2, float64,
+                         MFMA GEMMs); each CG step is one m2 x m2 row sweep          */
+} qp_kf_form;
+
 typedef struct {
   double rtol_kkt;  /* IPM stops when the relative KKT score <= rtol_kkt (1e-9)   */
   double cg_theta;  /* IPM's CG stop: max_i |nu_i r_i| <= cg_theta * mu (0.1)     */
@@ -86,6 +94,7 @@ typedef struct {
   int verbose;      /* 1: one line per IPM iteration on stderr                    */
   int profile;      /* 1: time the operator kernels of the first CG step of every
                        poll chunk with HIP events (read with qp_profile_get)     */
+  qp_kf_form kf_form; /* how the CG step applies K_F (QP_KF_IMPLICIT)            */
 } qp_options;
 
 typedef struct {
@@ -128,7 +137,9 @@ qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const d
 /* Factorize K0 = L Sigma L^T once (Sec. 3.1, single factorization), Sigma =
  * diag(I_n, -I_m1), L = [L_H 0; W^T L_S] with L_H L_H^T = H, W = L_H^{-1} A^T,
  * L_S L_S^T = A H^{-1} A^T, and store the inverse factor L^{-1} for the solves.
- * Also forms C H^{-1} C^T when the options' preconditioner resolves to P_H.
+ * Also forms C H^{-1} C^T when the options' preconditioner resolves to P_H, and
+ * with QP_KF_EXPLICIT the reduced operator E = Y_1^T Y_1 - Y_2^T Y_2 from
+ * Y = L^{-1}[:, :n] C^T (top n rows Y_1, bottom m1 rows Y_2), so K_F = D + E.
  * QP_E_NOT_SPD / QP_E_RANK when a Cholesky pivot is not positive. */
 qp_status qp_factor_K0(qp_ctx* ctx);
 

@@ -241,7 +241,8 @@ qp_status check_problem(int n, int m1, int m2, const double* H, const double* c,
 
 qp_status check_options(const qp_options& o) {
   if (!(o.tau > 0 && o.tau < 1) || o.max_ipm < 0 || !(o.rtol_kkt > 0) || o.prec < QP_PREC_NONE ||
-      o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED))
+      o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED) ||
+      (o.kf_form != QP_KF_IMPLICIT && o.kf_form != QP_KF_EXPLICIT))
     return QP_E_INVALID;
   return QP_OK;
 }
@@ -331,6 +332,7 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     D(ctx->stats, kStatsStride);
     ctx->info = static_cast<int*>(get(16 * sizeof(int)));
   }
+  if (kf_explicit(ctx)) D(ctx->E, (size_t)m2 * ctx->ldm2);
   if (need_ph) {
     D(ctx->T, (size_t)m2 * ctx->ldm2);
     D(ctx->P, (size_t)m2 * ctx->ldm2);
@@ -341,6 +343,7 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     F(ctx->Linv32, (size_t)N * ctx->ldN);
     F(ctx->C32, (size_t)m2 * ctx->ldn);
     if (need_ph) F(ctx->XP32, (size_t)m2 * ctx->ldm2);
+    if (kf_explicit(ctx)) F(ctx->E32, (size_t)m2 * ctx->ldm2);
     for (float** v : {&ctx->fr, &ctx->fz, &ctx->fp, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts})
       F(*v, m2);
     for (float** v : {&ctx->fu, &ctx->fw}) F(*v, n);
@@ -360,6 +363,7 @@ static void layout_factor_scratch(qp_ctx* ctx, Get&& get) {
   D(ctx->fG, (size_t)m1 * ctx->ldn);
   D(ctx->ftmp, chol_inv_tmp_elems(n > m1 ? n : m1));
   if (resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ) D(ctx->fYt, (size_t)m2 * ctx->ldn);
+  if (kf_explicit(ctx)) D(ctx->fY, (size_t)ctx->N * ctx->ldm2);
 }
 
 static size_t layout_bytes(qp_ctx* ctx, bool scratch) {
@@ -410,7 +414,7 @@ void alloc_factor_scratch(qp_ctx* ctx) {
 
 void free_factor_scratch(qp_ctx* ctx) {
   if (ctx->pooled) free_region(ctx, ctx->scratch_rg);
-  for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fYt}) {
+  for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fYt, &ctx->fY}) {
     dfree(ctx, *p);
     *p = nullptr;
   }
@@ -464,6 +468,17 @@ static void k0_top_apply(qp_ctx* ctx, const T* Linv, const T* u, T* v, T* w, con
 }
 
 // ---- factorization --------------------------------------------------------
+// E = C K0^{-1}_{11} C^T = Y_1^T Y_1 - Y_2^T Y_2 with Y = M C^T, M = L^{-1}[:, :n]
+// (K0^{-1}_{11} = M^T Sigma M); Y (N x m2, ld ldm2) is scratch.  Full square E.
+static void form_explicit(qp_ctx* ctx, double* Y) {
+  const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2, N = ctx->N, ld = ctx->ldm2;
+  hipStream_t st = ctx->stream;
+  HIPCHK(ctx, gemm_f64(st, 0, 1, N, m2, n, 1.0, ctx->Linv, ctx->ldN, ctx->C, ctx->ldn, 0.0, Y, ld, kALower));
+  HIPCHK(ctx, gemm_f64(st, 1, 0, m2, m2, n, 1.0, Y, ld, Y, ld, 0.0, ctx->E, ld, kNone));
+  const double* Y2 = Y + (size_t)n * ld;
+  HIPCHK(ctx, gemm_f64(st, 1, 0, m2, m2, m1, -1.0, Y2, ld, Y2, ld, 1.0, ctx->E, ld, kNone));
+}
+
 void factor(qp_ctx* ctx) {
   const int n = ctx->n, m1 = ctx->m1, N = ctx->N, ldn = ctx->ldn, ldN = ctx->ldN, ldm1 = ctx->ldm1;
   hipStream_t st = ctx->stream;
@@ -474,11 +489,12 @@ void factor(qp_ctx* ctx) {
     ctx->fS = dalloc<double>(ctx, (size_t)m1 * ldm1);
     ctx->fG = dalloc<double>(ctx, (size_t)m1 * ldn);
     ctx->ftmp = dalloc<double>(ctx, chol_inv_tmp_elems(n > m1 ? n : m1));
+    if (kf_explicit(ctx)) ctx->fY = dalloc<double>(ctx, (size_t)N * ctx->ldm2);
   }
   double *Hw = ctx->fHw, *Wt = ctx->fWt, *S = ctx->fS, *tmpG = ctx->fG, *tmp = ctx->ftmp;
   auto drop = [&] {
     if (!own_scratch) return;
-    for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp}) {
+    for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fY}) {
       dfree(ctx, *p);
       *p = nullptr;
     }
@@ -508,13 +524,20 @@ void factor(qp_ctx* ctx) {
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_info, ctx->info, sizeof(int), hipMemcpyDeviceToHost, st));
   sync(ctx);
   int bad = *ctx->h_info;
-  drop();
   if (bad != 0) {
+    drop();
     set_err(ctx, "Cholesky factorization of A H^{-1} A^T failed: A is rank deficient");
     throw Fail{QP_E_RANK};
   }
+  if (kf_explicit(ctx)) {
+    form_explicit(ctx, ctx->fY);
+    sync(ctx);  // the scratch is about to be released
+  }
+  drop();
   if (ctx->opt.precision == QP_MIXED) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->Linv, ldN, ctx->Linv32, ldN, N, N)));
+    if (kf_explicit(ctx))
+      HIPCHK(ctx, (convert_2d<double, float>(st, ctx->E, ctx->ldm2, ctx->E32, ctx->ldm2, ctx->m2, ctx->m2)));
   }
   ctx->factored = true;
 }
@@ -550,6 +573,7 @@ PcgBufs<double> bufs64(qp_ctx* ctx, const double* dvec, const double* wts, doubl
   B.Linv = ctx->Linv;
   B.C = ctx->C;
   B.XP = ctx->XP;
+  B.E = ctx->E;
   B.dvec = dvec;
   B.wts = wts;
   B.r = ctx->pr;
@@ -570,6 +594,7 @@ PcgBufs<float> bufs32(qp_ctx* ctx) {
   B.Linv = ctx->Linv32;
   B.C = ctx->C32;
   B.XP = ctx->XP32;
+  B.E = ctx->E32;
   B.dvec = ctx->fd;
   B.wts = ctx->fwts;
   B.r = ctx->fr;
@@ -603,6 +628,7 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m2 = ctx->m2;
   const int* skip = &ctx->sc->done;
+  const bool expl = kf_explicit(ctx);
   HIPCHK(ctx, pcg_init<T>(st, m2, rhs, B.dvec, B.wts, B.x, B.r, B.z, B.p, prec, rtol, wtol, maxit, ctx->sc));
   auto ph_apply = [&](int init, const EventPair* ev) {
     HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip, 4,
@@ -633,14 +659,20 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
     launched += poll;
     for (int k = 0; k < poll; ++k) {
       const EventPair* ev = (prof && k == 0) ? ctx->prof_ev : nullptr;
-      HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip, 1,
-                                      ev ? &ev[0] : nullptr));
-      HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n, skip,
-                                      2, ev ? &ev[1] : nullptr));
-      HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr, *B.wk,
-                                      skip, 3, ev ? &ev[2] : nullptr));
-      HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
-                           ev ? &ev[3] : nullptr));
+      if (expl) {
+        // q = E p + D p: one row sweep over the explicit operator
+        HIPCHK(ctx, pcg_q<T>(st, B.E, ctx->ldm2, m2, m2, B.p, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
+                             ev ? &ev[3] : nullptr));
+      } else {
+        HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip,
+                                        1, ev ? &ev[0] : nullptr));
+        HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n,
+                                        skip, 2, ev ? &ev[1] : nullptr));
+        HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr, *B.wk,
+                                        skip, 3, ev ? &ev[2] : nullptr));
+        HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
+                             ev ? &ev[3] : nullptr));
+      }
       HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc));
       if (prec == kPrecH) ph_apply(0, ev);
     }
@@ -649,7 +681,7 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
     if (prof && ctx->h_sc->iter > iter_before) {
       // the sampled step ran (it was the first of the chunk and the solve had not stopped)
       const int nops = (prec == kPrecH) ? 6 : 4;
-      for (int o = 0; o < nops; ++o) {
+      for (int o = expl ? 3 : 0; o < nops; ++o) {
         float ms = 0;
         if (hipEventElapsedTime(&ms, ctx->prof_ev[o].begin, ctx->prof_ev[o].end) == hipSuccess) {
           ctx->prof_ms[o] += ms;
@@ -668,6 +700,12 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
 // q = K_F p in float64 (used by qp_kf_apply and the refinement residual).
 void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
   hipStream_t st = ctx->stream;
+  if (kf_explicit(ctx)) {
+    HIPCHK(ctx, ew_mul(st, ctx->m2, dvec, p, ctx->pt));
+    HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->E, ctx->ldm2, ctx->m2, ctx->m2, kDense, p, q, 1.0, 1.0, ctx->pt,
+                                         ctx->m2, nullptr));
+    return;
+  }
   HIPCHK(ctx, launch_gemv_cols<double>(st, ctx->C, ctx->ldn, ctx->m2, ctx->n, kDense, p, ctx->pu, 1.0, 0.0, nullptr,
                                        ctx->w64, nullptr));
   k0_top_apply<double>(ctx, ctx->Linv, ctx->pu, ctx->pv, ctx->pw, ctx->w64, nullptr);
@@ -936,6 +974,7 @@ void qp_default_options(qp_options* opt) {
   opt->precision = QP_FP64;
   opt->verbose = 0;
   opt->profile = 0;
+  opt->kf_form = QP_KF_IMPLICIT;
 }
 
 const char* qp_status_str(qp_status st) {

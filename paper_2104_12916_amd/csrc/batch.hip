@@ -233,9 +233,11 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     const PcgBufs<T>& b = it->bufs;
     const int* skip = &c->sc->done;
     const int n = c->n, m2 = c->m2, N = c->N;
+    const bool expl = kf_explicit(c);
     ColsDesc<T> cd;
     RowsDesc<T> rd;
     GemvWork<T> wk = *b.wk;
+    if (expl) goto pcg_desc;  // q = E p + D p: only the fused row sweep
     if (!fill_cols_desc<T>(cd, b.C, c->ldn, m2, n, kDense, b.p, b.u, T(1), T(0), nullptr, wk.part, wk.part_elems,
                            skip)) {
       set_err(sk, "column sweep over C does not fit its workspace (m2=%d n=%d)", m2, n);
@@ -261,9 +263,10 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     L.c3pt += cd.nblocks;
     L.c3rt += cd.rblocks;
     L.c3.push_back(cd);
+  pcg_desc:
     PcgDesc<T> pd;
-    pd.C = b.C;
-    pd.w = b.w;
+    pd.C = expl ? b.E : b.C;
+    pd.w = expl ? b.p : b.w;
     pd.dvec = b.dvec;
     pd.wts = b.wts;
     pd.b = it->rhs;
@@ -277,15 +280,15 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     pd.rtol = it->rtol;
     pd.wtol = it->wtol;
     pd.maxit = it->maxit;
-    pd.ldc = c->ldn;
-    pd.n = n;
+    pd.ldc = expl ? c->ldm2 : c->ldn;
+    pd.n = expl ? m2 : n;
     pd.m2 = m2;
     pd.prec = it->prec;
     pd.qblocks = std::min(bpcg_q_blocks(m2), c->bpart_cap);
     L.qp.push_back(L.qt);
     L.qt += pd.qblocks;
     L.pd.push_back(pd);
-    L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, n, kDense, c->ldn));
+    L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, pd.n, kDense, pd.ldc));
     if (it->prec == kPrecH) {
       fill_rows_desc<T>(rd, b.XP, c->ldm2, m2, m2, kLower, b.r, b.t, T(1), T(0), nullptr, m2, skip);
       L.r4p.push_back(L.r4t);
@@ -577,7 +580,12 @@ void bphase_ir_residual(qp_batch* B, const std::vector<Slot*>& ss, int which) {
   RowsL mr, cr;
   for (Slot* s : ss) {
     qp_ctx* c = s->ctx;
-    ct.add(B, c, c->C, c->ldn, c->m2, c->n, kDense, which ? c->dnu : c->dnu_a, c->pu, 0.0, nullptr);
+    double* dnu = which ? c->dnu : c->dnu_a;
+    if (kf_explicit(c)) {  // K_F dnu = E dnu + pt
+      cr.add(c->E, c->ldm2, c->m2, c->m2, kDense, dnu, c->ir_x, 1.0, c->pt, c->m2);
+      continue;
+    }
+    ct.add(B, c, c->C, c->ldn, c->m2, c->n, kDense, dnu, c->pu, 0.0, nullptr);
     mr.add(c->Linv, c->ldN, c->N, c->n, kLower, c->pu, c->pv, 0.0, nullptr, c->n);
     mt.add(B, c, c->Linv, c->ldN, c->N, c->n, kLower, c->pv, c->pw, 0.0, nullptr);
     cr.add(c->C, c->ldn, c->m2, c->n, kDense, c->pw, c->ir_x, 1.0, c->pt, c->m2);
@@ -725,11 +733,25 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
       gt.push_back(GemmDesc{c->fYt, c->fYt, c->T, c->ldn, c->ldn, c->ldm2, c->m2, c->m2, n});  // T = C H^{-1} C^T
     }
   }
+  // explicit operator E = Y_1^T Y_1 - Y_2^T Y_2, Y = L^{-1}[:, :n] C^T (after G is final)
+  std::vector<GemmDesc> ey, ee1, ee2;
+  for (Slot* s : fresh) {
+    qp_ctx* c = s->ctx;
+    if (!kf_explicit(c)) continue;
+    const int ld = c->ldm2;
+    ey.push_back(GemmDesc{c->Linv, c->C, c->fY, c->ldN, c->ldn, ld, c->N, c->m2, c->n});
+    ee1.push_back(GemmDesc{c->fY, c->fY, c->E, ld, ld, ld, c->m2, c->m2, c->n});
+    const double* Y2 = c->fY + (size_t)c->n * ld;
+    ee2.push_back(GemmDesc{Y2, Y2, c->E, ld, ld, ld, c->m2, c->m2, c->m1});
+  }
   o2.chol_inv(cs);
   o2.gemm(0, 0, 1.0, 0.0, kBLower, g1);
   o2.gemm(0, 0, -1.0, 0.0, kALower, g2);
   o2.gemm(0, 1, 1.0, 0.0, kBUpper, gy);
   o2.gemm(0, 1, 1.0, 0.0, kOutLower, gt);
+  o2.gemm(0, 1, 1.0, 0.0, kALower, ey);
+  o2.gemm(1, 0, 1.0, 0.0, kNone, ee1);
+  o2.gemm(1, 0, -1.0, 1.0, kNone, ee2);
   run_ops(B, o2);
   pool_range(lo, hi);
   sync_pools(B, lo, hi, true);
@@ -742,6 +764,7 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
       cv.push_back(Mat2dDesc{c->Linv, c->Linv32, nullptr, c->ldN, c->ldN, c->N, c->N, 1, 1});
       max_rows = std::max(max_rows, c->N);
       max_cols = std::max(max_cols, c->N);
+      if (kf_explicit(c)) cv.push_back(Mat2dDesc{c->E, c->E32, nullptr, c->ldm2, c->ldm2, c->m2, c->m2, 0, 1});
     }
     c->factored = true;
     c->ph_ready = prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH;
@@ -923,9 +946,10 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
   const int na = (int)items.size();
   for (int k = 0; k < poll; ++k) {
     const EventPair* ev = (sample && k == 0) ? B->prof_ev : nullptr;
-    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, na, 1, ev ? &ev[0] : nullptr));
-    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, na, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
-    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, na, 3, ev ? &ev[2] : nullptr));
+    const int n1 = (int)L.c1.size(), n2 = (int)L.r2.size(), n3 = (int)L.c3.size();  // 0 for explicit operators
+    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, n1, 1, ev ? &ev[0] : nullptr));
+    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, n2, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
+    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, n3, 3, ev ? &ev[2] : nullptr));
     HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem, ev ? &ev[3] : nullptr));
     HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
     launch_ph_apply<T>(B, L, 0, ev);
@@ -937,10 +961,14 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
       const qp_ctx* c = s->ctx;
       const double mn = (double)c->n * (c->n + 1) / 2 + (double)c->m1 * c->n;
       const double cn = (double)c->m2 * c->n, xp = (double)c->m2 * (c->m2 + 1) / 2;
-      B->prof_pending_bytes[0] += cn * sizeof(T);
-      B->prof_pending_bytes[1] += mn * sizeof(T);
-      B->prof_pending_bytes[2] += mn * sizeof(T);
-      B->prof_pending_bytes[3] += cn * sizeof(T);
+      if (kf_explicit(c)) {
+        B->prof_pending_bytes[3] += (double)c->m2 * c->m2 * sizeof(T);
+      } else {
+        B->prof_pending_bytes[0] += cn * sizeof(T);
+        B->prof_pending_bytes[1] += mn * sizeof(T);
+        B->prof_pending_bytes[2] += mn * sizeof(T);
+        B->prof_pending_bytes[3] += cn * sizeof(T);
+      }
       if (s->R.prec == kPrecH) {
         B->prof_pending_bytes[4] += xp * sizeof(T);
         B->prof_pending_bytes[5] += xp * sizeof(T);

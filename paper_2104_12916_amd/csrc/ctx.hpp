@@ -76,8 +76,12 @@ struct qp_ctx {
   bool ph_ready = false;
   // float32 copies for the mixed path
   float *Linv32 = nullptr, *C32 = nullptr, *XP32 = nullptr;
+  // explicit reduced operator E = C K0^{-1}_{11} C^T (m2 x m2, full) for QP_KF_EXPLICIT
+  double* E = nullptr;
+  float* E32 = nullptr;
   // factorization scratch allocated ahead of time (batch admission); null: allocated by factor()
   double *fHw = nullptr, *fWt = nullptr, *fS = nullptr, *fG = nullptr, *ftmp = nullptr, *fYt = nullptr;
+  double* fY = nullptr;  // Y = L^{-1}[:, :n] C^T (N x m2), explicit operator only
 
   // vectors (float64)
   double *x = nullptr, *lam = nullptr, *nu = nullptr, *s = nullptr;
@@ -168,6 +172,7 @@ void upload_problem(qp_ctx* ctx, const double* H, const double* c, const double*
 
 // K0 = L Sigma L^T and its inverse factor; throws Fail on a bad pivot.
 void factor(qp_ctx* ctx);
+inline bool kf_explicit(const qp_ctx* ctx) { return ctx->opt.kf_form == QP_KF_EXPLICIT; }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);
 void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN);
@@ -176,7 +181,7 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q);
 // ---- CG buffers -----------------------------------------------------------
 template <typename T>
 struct PcgBufs {
-  const T *Linv, *C, *XP, *dvec, *wts;
+  const T *Linv, *C, *XP, *E, *dvec, *wts;
   T *r, *z, *p, *q, *t, *u, *v, *w, *x;
   const GemvWork<T>* wk;
 };

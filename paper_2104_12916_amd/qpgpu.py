@@ -19,6 +19,7 @@ QP_OK, QP_E_INVALID, QP_E_NOT_SPD, QP_E_RANK, QP_E_NOCONV, QP_E_NOMEM, QP_E_DEVI
 QP_PREC_NONE, QP_PREC_LOW_DOF, QP_PREC_FEW_EQ, QP_PREC_AUTO = range(4)
 QP_FP64, QP_MIXED = 0, 1
 QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
+QP_KF_IMPLICIT, QP_KF_EXPLICIT = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
@@ -34,7 +35,7 @@ class qp_options(ct.Structure):
         ("rtol_kkt", ct.c_double), ("cg_theta", ct.c_double), ("cg_rtol", ct.c_double),
         ("tau", ct.c_double), ("max_ipm", ct.c_int), ("max_pcg", ct.c_int),
         ("poll_every", ct.c_int), ("prec", ct.c_int), ("precision", ct.c_int),
-        ("verbose", ct.c_int), ("profile", ct.c_int),
+        ("verbose", ct.c_int), ("profile", ct.c_int), ("kf_form", ct.c_int),
     ]
 
 

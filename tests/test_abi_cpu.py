@@ -37,6 +37,7 @@ def test_status_strings_and_defaults():
     o = qpgpu.qp_default_options()
     assert o.rtol_kkt == 1e-9 and o.tau == 0.995 and o.max_ipm == 200
     assert o.prec == qpgpu.QP_PREC_AUTO and o.precision == qpgpu.QP_FP64
+    assert o.kf_form == qpgpu.QP_KF_IMPLICIT
     assert qpgpu.lib().qp_last_error(None) == b""
     qpgpu.lib().qp_destroy(None)
 
@@ -116,6 +117,10 @@ def test_batch_footprint_is_positive_monotone_and_validates():
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_LOW_DOF), 512, 128, 256) < f[2]
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ, precision=qpgpu.QP_MIXED),
                                     512, 128, 256) > f[2]
+    # the explicit operator adds E (m2 x m2) and its scratch Y
+    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ,
+                                                             kf_form=qpgpu.QP_KF_EXPLICIT), 512, 128, 256) > f[2]
+    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(kf_form=7), 5, 2, 1) == 0
     assert qpgpu.qp_batch_footprint(opt, 0, 1, 1) == 0
     assert qpgpu.qp_batch_footprint(opt, 5, 6, 1) == 0
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(tau=2.0), 5, 2, 1) == 0
