@@ -294,9 +294,12 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     D(*v, n);
   for (double** v : {&ctx->lam, &ctx->Ax, &ctx->re, &ctx->dlam, &ctx->dlam_a}) D(*v, m1);
   for (double** v : {&ctx->nu, &ctx->s, &ctx->Cx, &ctx->ri, &ctx->dvec, &ctx->rc, &ctx->rhs, &ctx->Cw, &ctx->dnu,
-                     &ctx->ds, &ctx->dnu_a, &ctx->ds_a, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pq, &ctx->pt, &ctx->ir_r,
+                     &ctx->ds, &ctx->dnu_a, &ctx->ds_a, &ctx->pr, &ctx->pz, &ctx->pq, &ctx->pt, &ctx->ir_r,
                      &ctx->ir_x, &ctx->ir_d})
     D(*v, m2);
+  // the CG direction is the input of the explicit operator's row sweep, which may
+  // read it in whole 64-lane chunks: padded to ld_m2, the padding stays zero
+  D(ctx->pp, ctx->ldm2);
   for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) D(*v, N);
   const bool mixed = ctx->opt.precision == QP_MIXED;
   const bool need_ph = !ctx->pooled || resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ;
@@ -344,8 +347,8 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     F(ctx->C32, (size_t)m2 * ctx->ldn);
     if (need_ph) F(ctx->XP32, (size_t)m2 * ctx->ldm2);
     if (kf_explicit(ctx)) F(ctx->E32, (size_t)m2 * ctx->ldm2);
-    for (float** v : {&ctx->fr, &ctx->fz, &ctx->fp, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts})
-      F(*v, m2);
+    for (float** v : {&ctx->fr, &ctx->fz, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts}) F(*v, m2);
+    F(ctx->fp, ctx->ldm2);
     for (float** v : {&ctx->fu, &ctx->fw}) F(*v, n);
     F(ctx->fv, N);
     F(ctx->w32.part, part32);
@@ -662,7 +665,7 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
       if (expl) {
         // q = E p + D p: one row sweep over the explicit operator
         HIPCHK(ctx, pcg_q<T>(st, B.E, ctx->ldm2, m2, m2, B.p, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
-                             ev ? &ev[3] : nullptr));
+                             ev ? &ev[3] : nullptr, tune().qe_stage));
       } else {
         HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip,
                                         1, ev ? &ev[0] : nullptr));

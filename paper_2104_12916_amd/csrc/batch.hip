@@ -285,10 +285,11 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     pd.m2 = m2;
     pd.prec = it->prec;
     pd.qblocks = std::min(bpcg_q_blocks(m2), c->bpart_cap);
+    pd.stage = tune().brows_stage;
     L.qp.push_back(L.qt);
     L.qt += pd.qblocks;
     L.pd.push_back(pd);
-    L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, pd.n, kDense, pd.ldc));
+    if (pd.stage) L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, pd.n, kDense, pd.ldc));
     if (it->prec == kPrecH) {
       fill_rows_desc<T>(rd, b.XP, c->ldm2, m2, m2, kLower, b.r, b.t, T(1), T(0), nullptr, m2, skip);
       L.r4p.push_back(L.r4t);

@@ -43,14 +43,18 @@ DevInfo& dev_info();
 
 // Launch shapes of the streaming sweeps.  Defaults were chosen by timing on
 // gfx950 (qp_op_time); the environment variable QPGPU_TUNE
-// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0") overrides them.
+// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0,qe_stage=0,rows_stage=0") overrides them.
 struct Tune {
-  int rows_bpc = 2;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
-  int rows_unroll = 4;  // 16-byte loads in flight per lane: 4 or 8
+  int rows_bpc = 4;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
+  int rows_unroll = 8;  // 16-byte loads in flight per lane: 4 or 8
   int cols_bpc = 2;     // gemv_cols: target workgroups per CU
   int cols_unroll = 8;  // gemv_cols: rows in flight per wave: 4 or 8
   int ld_pad = 64;      // elements added to every matrix leading dimension (multiple of 64);
                         // breaks the power-of-two row stride of n = 4096 matrices
+  int qe_stage = 0;     // explicit operator sweep: 1 stage p in LDS, 0 read it through the caches
+  int rows_stage = 0;   // other row sweeps (gemv_rows, q = C w + D p): the same choice for their x
+  int brows_stage = 1;  // batched row sweeps (many short rows per QP): stage x in LDS
+  int brows_unroll = 4; // batched row sweeps: 16-byte loads in flight per lane
 };
 Tune& tune();
 constexpr int kMaxRowsBpc = 8;

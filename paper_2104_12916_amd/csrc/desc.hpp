@@ -52,6 +52,7 @@ struct PcgDesc {
   int maxit;
   int ldc, n, m2, prec;
   int qblocks;    // workgroups of the q = C w + D p sweep
+  int stage;      // 1: w staged in LDS; 0: w read from global memory (zero-padded to ldc)
 };
 
 // Map a flattened block index to its descriptor (binary search in prefix).

@@ -47,6 +47,10 @@ Tune& tune() {
       if (!strcmp(tok, "cols_bpc") && val >= 1 && val <= kMaxColsBpc) v.cols_bpc = val;
       if (!strcmp(tok, "cols_unroll") && (val == 4 || val == 8)) v.cols_unroll = val;
       if (!strcmp(tok, "ld_pad") && val >= 0 && val <= 1024 && val % 64 == 0) v.ld_pad = val;
+      if (!strcmp(tok, "qe_stage") && (val == 0 || val == 1)) v.qe_stage = val;
+      if (!strcmp(tok, "rows_stage") && (val == 0 || val == 1)) v.rows_stage = val;
+      if (!strcmp(tok, "brows_stage") && (val == 0 || val == 1)) v.brows_stage = val;
+      if (!strcmp(tok, "brows_unroll") && (val == 4 || val == 8)) v.brows_unroll = val;
     }
     return v;
   }();
@@ -67,11 +71,12 @@ __device__ __forceinline__ void rows_body(const T* __restrict__ A, int lda, int 
   // rows are dealt round-robin over all waves, so every block sees rows up to the last one
   const int maxlen = (shape == kLower) ? min(m, k) : k;
   const int lenR_max = round_chunk<T>(maxlen, lda);
-  stage_x<T>(xs, x, k, lenR_max);
+  if (xs) stage_x<T>(xs, x, k, lenR_max);  // xs null: x is read through the caches
   for (int i = bid * waves + wave; i < m; i += nb * waves) {
     int len = (shape == kLower) ? min(i + 1, k) : k;
     int lenR = round_chunk<T>(len, lda);
-    T v = row_dot<T, U>(A + (size_t)i * lda, xs, lenR, lane);
+    T v = xs ? row_dot<T, U>(A + (size_t)i * lda, xs, lenR, lane)
+             : row_dot_gx<T, U>(A + (size_t)i * lda, x, lenR, k, lane);
     if (lane == 0) {
       v *= alpha;
       if (i >= nsplit) v = -v;
@@ -140,11 +145,12 @@ __device__ __forceinline__ void cols_reduce_body(int k, int ps, int shape, const
 template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) gemv_rows_kernel(
     const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x,
-    T* __restrict__ y, T alpha, T beta, const T* __restrict__ y0, int nsplit, const int* __restrict__ skip) {
+    T* __restrict__ y, T alpha, T beta, const T* __restrict__ y0, int nsplit, const int* __restrict__ skip,
+    int stage) {
   if (skip && *skip) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   rows_body<T, U>(A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, blockIdx.x, gridDim.x,
-                  reinterpret_cast<T*>(smem_raw));
+                  stage ? reinterpret_cast<T*>(smem_raw) : nullptr);
 }
 
 template <typename T, int TAG, int U>
@@ -168,13 +174,13 @@ __global__ void __launch_bounds__(256) gemv_cols_reduce_kernel(int k, int ps, in
 // batched kernels (one flattened grid over a descriptor list)
 template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) bgemv_rows_kernel(const RowsDesc<T>* __restrict__ descs,
-                                                         const int* __restrict__ prefix, int ndesc) {
+                                                         const int* __restrict__ prefix, int ndesc, int stage) {
   const int j = desc_of_block(prefix, ndesc, blockIdx.x);
   const RowsDesc<T> d = descs[j];
   if (d.skip && *d.skip) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   rows_body<T, U>(d.A, d.lda, d.m, d.k, d.shape, d.x, d.y, d.alpha, d.beta, d.y0, d.nsplit, blockIdx.x - prefix[j],
-                  d.nblocks, reinterpret_cast<T*>(smem_raw));
+                  d.nblocks, stage ? reinterpret_cast<T*>(smem_raw) : nullptr);
 }
 
 template <typename T, int TAG, int U>
@@ -220,12 +226,14 @@ template <typename T, int TAG>
 static void launch_rows_tag(dim3 grid, size_t smem, hipStream_t st, const EventPair* ev, const T* A, int lda, int m,
                             int k, int shape, const T* x, T* y, T alpha, T beta, const T* y0, int nsplit,
                             const int* skip) {
+  const int stage = tune().rows_stage;
+  if (!stage) smem = 0;
   if (tune().rows_unroll == 8)
     QPG_LAUNCH((gemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
-               alpha, beta, y0, nsplit, skip);
+               alpha, beta, y0, nsplit, skip, stage);
   else
     QPG_LAUNCH((gemv_rows_kernel<T, TAG, 4>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
-               alpha, beta, y0, nsplit, skip);
+               alpha, beta, y0, nsplit, skip, stage);
 }
 
 template <typename T>
@@ -372,10 +380,12 @@ bool fill_cols_desc(ColsDesc<T>& d, const T* A, int lda, int m, int k, int shape
 template <typename T, int TAG>
 static void launch_brows_tag(dim3 grid, size_t smem, hipStream_t st, const EventPair* ev, const RowsDesc<T>* ddesc,
                              const int* dprefix, int ndesc) {
-  if (tune().rows_unroll == 8)
-    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc);
+  const int stage = tune().brows_stage;
+  if (!stage) smem = 0;
+  if (tune().brows_unroll == 8)
+    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc, stage);
   else
-    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 4>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc);
+    QPG_LAUNCH((bgemv_rows_kernel<T, TAG, 4>), grid, dim3(256), (uint32_t)smem, st, ev, ddesc, dprefix, ndesc, stage);
 }
 
 template <typename T>

@@ -74,6 +74,46 @@ __device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int l
   return wave_sum<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
+// Same dot product with x read from global memory (through the caches) as
+// 16-byte vectors; elements of x at or past xlen read as zero.
+template <typename T, int U = 4>
+__device__ __forceinline__ T row_dot_gx(const T* __restrict__ a, const T* __restrict__ x, int lenR, int xlen,
+                                        int lane) {
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CH = kWave * VE;
+  T acc[4] = {0, 0, 0, 0};
+  int j = lane * VE;
+  const V* av = reinterpret_cast<const V*>(a);
+  auto xload = [&](int jj, T* t) {
+    if (jj + VE <= xlen) {
+      const V w = *reinterpret_cast<const V*>(x + jj);
+      __builtin_memcpy(t, &w, sizeof(V));
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) t[e] = (jj + e < xlen) ? x[jj + e] : T(0);
+    }
+  };
+  for (; j + (U - 1) * CH < lenR; j += U * CH) {
+    V v[U];
+    T t[U][VE];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = __builtin_nontemporal_load(av + (j + u * CH) / VE);
+      xload(j + u * CH, t[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u % 4] += dot16<V, T>(v[u], t[u]);
+  }
+  for (; j < lenR; j += CH) {
+    V v0 = __builtin_nontemporal_load(av + j / VE);
+    T t[VE];
+    xload(j, t);
+    acc[0] += dot16<V, T>(v0, t);
+  }
+  return wave_sum<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+}
+
 template <typename T>
 __device__ __forceinline__ int round_chunk(int len, int ld) {
   constexpr int CH = kWave * Vec16<T>::n;
@@ -144,6 +184,32 @@ __device__ __forceinline__ T block_sum(T v, T* sh /* >= 4 */) {
   for (int w = 0; w < nw; ++w) s += sh[w];
   __syncthreads();
   return s;
+}
+
+// Two sums and a max over the block with one barrier pair; each value follows
+// the same order as block_sum / block_max (wave butterfly, then waves in order).
+__device__ __forceinline__ void block_sum2_max1(double& a, double& b, double& m, double (*sh)[16]) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  a = wave_sum<double>(a);
+  b = wave_sum<double>(b);
+  m = wave_max<double>(m);
+  __syncthreads();
+  if (lane == 0) {
+    sh[0][wave] = a;
+    sh[1][wave] = b;
+    sh[2][wave] = m;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0, sm = sh[2][0];
+  for (int w = 0; w < nw; ++w) {
+    sa += sh[0][w];
+    sb += sh[1][w];
+  }
+  for (int w = 1; w < nw; ++w) sm = fmax(sm, sh[2][w]);
+  a = sa;
+  b = sb;
+  m = sm;
 }
 
 template <typename T>

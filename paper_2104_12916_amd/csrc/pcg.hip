@@ -82,14 +82,15 @@ __device__ __forceinline__ void init_body(int m2, const T* __restrict__ b, const
 template <typename T, int U>
 __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2, int n, const T* __restrict__ w,
                                        const T* __restrict__ dvec, const T* __restrict__ p, T* __restrict__ q,
-                                       double* __restrict__ bpart, int bid, int nb, T* ws) {
+                                       double* __restrict__ bpart, int bid, int nb, T* ws, int stage) {
   __shared__ double sh[16];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
   const int lenR = round_chunk<T>(n, ldc);
-  stage_x<T>(ws, w, n, lenR);
+  if (stage) stage_x<T>(ws, w, n, lenR);  // else w is read through the caches
   double pq = 0;
   for (int i = bid * waves + wave; i < m2; i += nb * waves) {
-    T v = row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane);
+    T v = stage ? row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane)
+                : row_dot_gx<T, U>(C + (size_t)i * ldc, w, lenR, n, lane);
     if (lane == 0) {
       T pi = p[i];
       T qi = v + dvec[i] * pi;
@@ -103,12 +104,36 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
 
 // The vector part of the step: alpha = rho / p^T q, dnu += alpha p,
 // r -= alpha q, stop tests; for P_L / none also z, rho' = r^T z, beta, p.
+// When every thread holds at most kKeep elements, z and p stay in registers
+// between the two passes.  Per-thread partial sums follow the element order
+// i = tid, tid + blockDim, ... in both branches, so the result is the same.
+constexpr int kKeep = 4;
+
+template <typename T>
+__device__ __forceinline__ void update_elem(int i, T a, const T* __restrict__ dvec, const T* __restrict__ p,
+                                            const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r,
+                                            T* __restrict__ z, const T* __restrict__ wts, int prec, double& rr,
+                                            double& wm, double& rz, T& zi, T& pi) {
+  pi = p[i];
+  const T ri = r[i] - a * q[i];
+  x[i] += a * pi;
+  r[i] = ri;
+  rr += (double)ri * ri;
+  if (wts) wm = fmax(wm, fabs((double)wts[i] * ri));
+  if (prec != kPrecH) {
+    zi = (prec == kPrecL) ? ri / dvec[i] : ri;
+    z[i] = zi;
+    rz += (double)ri * zi;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void update_body(int m2, int nparts, const double* __restrict__ bpart,
                                             const T* __restrict__ dvec, T* __restrict__ p, const T* __restrict__ q,
                                             T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
                                             const T* __restrict__ wts, int prec, PcgScalars* __restrict__ sc) {
   __shared__ double sh[16];
+  __shared__ double sh3[3][16];
   __shared__ double alpha_s, beta_s;
   __shared__ int stop_s;
   double s = 0;
@@ -129,22 +154,20 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   if (stop_s) return;
   const T a = (T)alpha_s;
   double rr = 0, rz = 0, wm = 0;
-  for (int i = threadIdx.x; i < m2; i += blockDim.x) {
-    T pi = p[i];
-    T ri = r[i] - a * q[i];
-    x[i] += a * pi;
-    r[i] = ri;
-    rr += (double)ri * ri;
-    if (wts) wm = fmax(wm, fabs((double)wts[i] * ri));
-    if (prec != kPrecH) {
-      T zi = (prec == kPrecL) ? ri / dvec[i] : ri;
-      z[i] = zi;
-      rz += (double)ri * zi;
+  const int bd = blockDim.x;
+  const bool keep = m2 <= kKeep * bd;
+  T zk[kKeep], pk[kKeep];
+  if (keep) {
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+      const int i = threadIdx.x + k * bd;
+      if (i < m2) update_elem<T>(i, a, dvec, p, q, x, r, z, wts, prec, rr, wm, rz, zk[k], pk[k]);
     }
+  } else {
+    T zi, pi;
+    for (int i = threadIdx.x; i < m2; i += bd) update_elem<T>(i, a, dvec, p, q, x, r, z, wts, prec, rr, wm, rz, zi, pi);
   }
-  rr = block_sum<double>(rr, sh);
-  wm = block_max<double>(wm, sh);
-  rz = block_sum<double>(rz, sh);
+  block_sum2_max1(rr, rz, wm, sh3);
   if (threadIdx.x == 0) {
     pcg_check_stop(sc, rr, wm);
     stop_s = sc->done;
@@ -157,7 +180,15 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   __syncthreads();
   if (stop_s || prec == kPrecH) return;
   const T bt = (T)beta_s;
-  for (int i = threadIdx.x; i < m2; i += blockDim.x) p[i] = z[i] + bt * p[i];
+  if (keep) {
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+      const int i = threadIdx.x + k * bd;
+      if (i < m2) p[i] = zk[k] + bt * pk[k];
+    }
+  } else {
+    for (int i = threadIdx.x; i < m2; i += bd) p[i] = z[i] + bt * p[i];
+  }
 }
 
 // After z = P_H^{-1} r: rho' = r^T z, beta = rho' / rho (0 on the first step),
@@ -195,10 +226,11 @@ template <typename T, int U>
 __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int ldc, int m2, int n,
                                                     const T* __restrict__ w, const T* __restrict__ dvec,
                                                     const T* __restrict__ p, T* __restrict__ q,
-                                                    const PcgScalars* __restrict__ sc, double* __restrict__ bpart) {
+                                                    const PcgScalars* __restrict__ sc, double* __restrict__ bpart,
+                                                    int stage) {
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  q_body<T, U>(C, ldc, m2, n, w, dvec, p, q, bpart, blockIdx.x, gridDim.x, reinterpret_cast<T*>(smem_raw));
+  q_body<T, U>(C, ldc, m2, n, w, dvec, p, q, bpart, blockIdx.x, gridDim.x, reinterpret_cast<T*>(smem_raw), stage);
 }
 
 template <typename T>
@@ -237,7 +269,7 @@ __global__ void __launch_bounds__(256) bpcg_q_kernel(const PcgDesc<T>* __restric
   if (d.sc->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   q_body<T, U>(d.C, d.ldc, d.m2, d.n, d.w, d.dvec, d.p, d.q, d.bpart, blockIdx.x - prefix[j], d.qblocks,
-               reinterpret_cast<T*>(smem_raw));
+               reinterpret_cast<T*>(smem_raw), d.stage);
 }
 
 template <typename T>
@@ -270,20 +302,18 @@ int pcg_q_grid(int m2) {
 
 template <typename T>
 hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, const T* p, T* q,
-                 const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev) {
-  constexpr int CH = kWave * Vec16<T>::n;
-  int lenR = (n + CH - 1) / CH * CH;
-  if (lenR > ldc) lenR = ldc;
-  size_t smem = (size_t)lenR * sizeof(T);
+                 const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev, int stage) {
+  if (!tune().rows_stage) stage = 0;
+  size_t smem = stage ? rows_smem_bytes<T>(m2, n, kDense, ldc) : 0;
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   const int grid = pcg_q_grid<T>(m2);
   if (grid > bpart_cap) return hipErrorInvalidValue;
   if (tune().rows_unroll == 8)
     QPG_LAUNCH((pcg_q_kernel<T, 8>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
-               bpart);
+               bpart, stage);
   else
     QPG_LAUNCH((pcg_q_kernel<T, 4>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
-               bpart);
+               bpart, stage);
   return hipGetLastError();
 }
 
@@ -316,7 +346,7 @@ hipError_t bpcg_q(hipStream_t st, const PcgDesc<T>* d, const int* prefix, int nd
                   const EventPair* ev) {
   if (ndesc <= 0 || total_blocks <= 0) return hipSuccess;
   if (smem > 150 * 1024) return hipErrorInvalidValue;
-  if (tune().rows_unroll == 8)
+  if (tune().brows_unroll == 8)
     QPG_LAUNCH((bpcg_q_kernel<T, 8>), dim3(total_blocks), dim3(256), (uint32_t)smem, st, ev, d, prefix, ndesc);
   else
     QPG_LAUNCH((bpcg_q_kernel<T, 4>), dim3(total_blocks), dim3(256), (uint32_t)smem, st, ev, d, prefix, ndesc);
@@ -342,7 +372,7 @@ hipError_t bpcg_ph_update(hipStream_t st, const PcgDesc<T>* d, int ndesc, int in
                                   double, int, PcgScalars*);                                                      \
   template int pcg_q_grid<T>(int);                                                                                \
   template hipError_t pcg_q<T>(hipStream_t, const T*, int, int, int, const T*, const T*, const T*, T*,            \
-                               const PcgScalars*, double*, int, const EventPair*);                                \
+                               const PcgScalars*, double*, int, const EventPair*, int);                           \
   template hipError_t pcg_update<T>(hipStream_t, int, const double*, const T*, T*, const T*, T*, T*, T*,          \
                                     const T*, int, PcgScalars*);                                                  \
   template hipError_t pcg_ph_update<T>(hipStream_t, int, const T*, const T*, T*, int, PcgScalars*);               \

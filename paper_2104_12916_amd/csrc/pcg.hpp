@@ -15,7 +15,7 @@ template <typename T>
 int pcg_q_grid(int m2);
 template <typename T>
 hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, const T* p, T* q,
-                 const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev = nullptr);
+                 const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev = nullptr, int stage = 1);
 template <typename T>
 hipError_t pcg_update(hipStream_t st, int m2, const double* bpart, const T* dvec, T* p, const T* q, T* x, T* r, T* z,
                       const T* wts, int prec, PcgScalars* sc);
