@@ -49,8 +49,8 @@ WORKLOADS = {
     "batch": dict(desc=BATCH_DESC, prec="auto", seeds=[1000]),
     "serve": dict(desc=SERVE_DESC, prec="auto", seeds=[5000]),
 }
-OP_NAMES = ["gemv_cols_part_kernel<T,1> (C^T p)", "gemv_rows_kernel<T,2> (Sigma M u)",
-            "gemv_cols_part_kernel<T,3> (M^T v)", "pcg_q_kernel<T> (C w + D p)",
+OP_NAMES = ["gemv_rows_kernel<T,1> (C^T p over stored C^T)", "gemv_rows_kernel<T,2> (Sigma M u)",
+            "gemv_rows_kernel<T,3> (M^T v over stored M^T)", "pcg_q_kernel<T> (C w + D p)",
             "gemv_rows_kernel<T,4> (X_P r)", "gemv_cols_part_kernel<T,5> (X_P^T t)"]
 
 
@@ -154,8 +154,8 @@ def cpu_baseline_pool(specs, budget_s=20.0):
 def batch_roofline(prof, elem):
     """Dominant batched sweep: algorithmic bytes per sampled launch over its time."""
     ms, by, cnt = prof
-    names = ["bgemv_cols_part_kernel<T,1> (C^T p)", "bgemv_rows_kernel<T,2> (Sigma M u)",
-             "bgemv_cols_part_kernel<T,3> (M^T v)", "bpcg_q_kernel<T> (C w + D p)",
+    names = ["bgemv_rows_kernel<T,1> (C^T p over stored C^T)", "bgemv_rows_kernel<T,2> (Sigma M u)",
+             "bgemv_rows_kernel<T,3> (M^T v over stored M^T)", "bpcg_q_kernel<T> (C w + D p)",
              "bgemv_rows_kernel<T,4> (X_P r)", "bgemv_cols_part_kernel<T,5> (X_P^T t)"]
     ops = {}
     for o in range(6):

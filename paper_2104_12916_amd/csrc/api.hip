@@ -336,6 +336,10 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     ctx->info = static_cast<int*>(get(16 * sizeof(int)));
   }
   if (kf_explicit(ctx)) D(ctx->E, (size_t)m2 * ctx->ldm2);
+  if (op_transposed(ctx)) {
+    D(ctx->CT, (size_t)n * ctx->ldm2);
+    D(ctx->MT, (size_t)n * ctx->ldN);
+  }
   if (need_ph) {
     D(ctx->T, (size_t)m2 * ctx->ldm2);
     D(ctx->P, (size_t)m2 * ctx->ldm2);
@@ -347,6 +351,10 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     F(ctx->C32, (size_t)m2 * ctx->ldn);
     if (need_ph) F(ctx->XP32, (size_t)m2 * ctx->ldm2);
     if (kf_explicit(ctx)) F(ctx->E32, (size_t)m2 * ctx->ldm2);
+    if (op_transposed(ctx)) {
+      F(ctx->CT32, (size_t)n * ctx->ldm2);
+      F(ctx->MT32, (size_t)n * ctx->ldN);
+    }
     for (float** v : {&ctx->fr, &ctx->fz, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts}) F(*v, m2);
     F(ctx->fp, ctx->ldm2);
     for (float** v : {&ctx->fu, &ctx->fw}) F(*v, n);
@@ -537,10 +545,18 @@ void factor(qp_ctx* ctx) {
     sync(ctx);  // the scratch is about to be released
   }
   drop();
+  if (op_transposed(ctx)) {
+    HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT, ctx->ldm2, 0));
+    HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT, ldN, 0));
+  }
   if (ctx->opt.precision == QP_MIXED) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->Linv, ldN, ctx->Linv32, ldN, N, N)));
     if (kf_explicit(ctx))
       HIPCHK(ctx, (convert_2d<double, float>(st, ctx->E, ctx->ldm2, ctx->E32, ctx->ldm2, ctx->m2, ctx->m2)));
+    if (op_transposed(ctx)) {
+      HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT32, ctx->ldm2, 1));
+      HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT32, ldN, 1));
+    }
   }
   ctx->factored = true;
 }
@@ -577,6 +593,8 @@ PcgBufs<double> bufs64(qp_ctx* ctx, const double* dvec, const double* wts, doubl
   B.C = ctx->C;
   B.XP = ctx->XP;
   B.E = ctx->E;
+  B.CT = ctx->CT;
+  B.MT = ctx->MT;
   B.dvec = dvec;
   B.wts = wts;
   B.r = ctx->pr;
@@ -598,6 +616,8 @@ PcgBufs<float> bufs32(qp_ctx* ctx) {
   B.C = ctx->C32;
   B.XP = ctx->XP32;
   B.E = ctx->E32;
+  B.CT = ctx->CT32;
+  B.MT = ctx->MT32;
   B.dvec = ctx->fd;
   B.wts = ctx->fwts;
   B.r = ctx->fr;
@@ -620,6 +640,28 @@ int mixed_inner_cap(const qp_ctx* ctx, int prec) {
 }
 
 // ---- PCG driver (one QP) ------------------------------------------------------
+// u = C^T p, v = Sigma M u, w = M^T v: the first three sweeps of the implicit CG
+// step (row sweeps over the stored transposes, or column sweeps).
+template <typename T>
+static void op_sweeps(qp_ctx* ctx, const PcgBufs<T>& B, const int* skip, const EventPair* ev) {
+  hipStream_t st = ctx->stream;
+  const int n = ctx->n, m2 = ctx->m2, N = ctx->N;
+  if (op_transposed(ctx))
+    HIPCHK(ctx, launch_gemv_rows<T>(st, B.CT, ctx->ldm2, n, m2, kDense, B.p, B.u, T(1), T(0), nullptr, n, skip, 1,
+                                    ev ? &ev[0] : nullptr));
+  else
+    HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip, 1,
+                                    ev ? &ev[0] : nullptr));
+  HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n, skip, 2,
+                                  ev ? &ev[1] : nullptr));
+  if (op_transposed(ctx))
+    HIPCHK(ctx, launch_gemv_rows<T>(st, B.MT, ctx->ldN, n, N, kUpper, B.v, B.w, T(1), T(0), nullptr, n, skip, 3,
+                                    ev ? &ev[2] : nullptr));
+  else
+    HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, N, n, kLower, B.v, B.w, T(1), T(0), nullptr, *B.wk, skip,
+                                    3, ev ? &ev[2] : nullptr));
+}
+
 struct PcgResult {
   int iters = 0;
   int done = 0;
@@ -667,12 +709,7 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
         HIPCHK(ctx, pcg_q<T>(st, B.E, ctx->ldm2, m2, m2, B.p, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
                              ev ? &ev[3] : nullptr, tune().qe_stage));
       } else {
-        HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip,
-                                        1, ev ? &ev[0] : nullptr));
-        HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n,
-                                        skip, 2, ev ? &ev[1] : nullptr));
-        HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr, *B.wk,
-                                        skip, 3, ev ? &ev[2] : nullptr));
+        op_sweeps<T>(ctx, B, skip, ev);
         HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
                              ev ? &ev[3] : nullptr));
       }
@@ -1201,16 +1238,24 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
       auto launch = [&]() {
         switch (op) {
           case 0:
-            HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk,
-                                            nullptr, 1));
+            if (op_transposed(ctx))
+              HIPCHK(ctx, launch_gemv_rows<T>(st, B.CT, ctx->ldm2, n, m2, kDense, B.p, B.u, T(1), T(0), nullptr, n,
+                                              nullptr, 1));
+            else
+              HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk,
+                                              nullptr, 1));
             break;
           case 1:
             HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n,
                                             nullptr, 2));
             break;
           case 2:
-            HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr,
-                                            *B.wk, nullptr, 3));
+            if (op_transposed(ctx))
+              HIPCHK(ctx, launch_gemv_rows<T>(st, B.MT, ctx->ldN, n, ctx->N, kUpper, B.v, B.w, T(1), T(0), nullptr, n,
+                                              nullptr, 3));
+            else
+              HIPCHK(ctx, launch_gemv_cols<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.v, B.w, T(1), T(0), nullptr,
+                                              *B.wk, nullptr, 3));
             break;
           case 3:
             HIPCHK(ctx, launch_gemv_rows<T>(st, B.C, ctx->ldn, m2, n, kDense, B.w, B.q, T(1), T(0), nullptr, m2,
@@ -1218,9 +1263,7 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
             break;
           case 4: {
             const int* skip = &ctx->sc->done;
-            HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk,
-                                            skip, 1));
-            k0_top_apply<T>(ctx, B.Linv, B.u, B.v, B.w, *B.wk, skip);
+            op_sweeps<T>(ctx, B, skip, nullptr);
             HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart,
                                  ctx->bpart_cap));
             HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, nullptr, kPrecL, ctx->sc));

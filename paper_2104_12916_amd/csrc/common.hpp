@@ -32,7 +32,8 @@ struct PcgScalars {
 };
 
 // Triangular shape of a matrix operand.
-enum Shape : int { kDense = 0, kLower = 1 };
+// kUpper: row i holds columns i..cols-1 (zeros before), read from the aligned chunk containing i.
+enum Shape : int { kDense = 0, kLower = 1, kUpper = 2 };
 
 // ---- launch helpers (defined in the .hip files) ---------------------------
 struct DevInfo {
@@ -55,6 +56,8 @@ struct Tune {
   int rows_stage = 0;   // other row sweeps (gemv_rows, q = C w + D p): the same choice for their x
   int brows_stage = 1;  // batched row sweeps (many short rows per QP): stage x in LDS
   int brows_unroll = 4; // batched row sweeps: 16-byte loads in flight per lane
+  int op_t = 1;         // keep transposed copies of C and M so every CG-step sweep is a row sweep
+                        // (0: column sweeps with per-chunk partials, no extra memory)
 };
 Tune& tune();
 constexpr int kMaxRowsBpc = 8;

@@ -79,6 +79,10 @@ struct qp_ctx {
   // explicit reduced operator E = C K0^{-1}_{11} C^T (m2 x m2, full) for QP_KF_EXPLICIT
   double* E = nullptr;
   float* E32 = nullptr;
+  // transposed copies for the implicit CG step (Tune::op_t): C^T (n x ldm2) and
+  // M^T = (L^{-1}[:, :n])^T (n x ldN, upper trapezoid), so C^T p and M^T v are row sweeps
+  double *CT = nullptr, *MT = nullptr;
+  float *CT32 = nullptr, *MT32 = nullptr;
   // factorization scratch allocated ahead of time (batch admission); null: allocated by factor()
   double *fHw = nullptr, *fWt = nullptr, *fS = nullptr, *fG = nullptr, *ftmp = nullptr, *fYt = nullptr;
   double* fY = nullptr;  // Y = L^{-1}[:, :n] C^T (N x m2), explicit operator only
@@ -173,6 +177,8 @@ void upload_problem(qp_ctx* ctx, const double* H, const double* c, const double*
 // K0 = L Sigma L^T and its inverse factor; throws Fail on a bad pivot.
 void factor(qp_ctx* ctx);
 inline bool kf_explicit(const qp_ctx* ctx) { return ctx->opt.kf_form == QP_KF_EXPLICIT; }
+// The implicit CG step reads the stored transposes (C^T, M^T) with row sweeps.
+inline bool op_transposed(const qp_ctx* ctx) { return tune().op_t && !kf_explicit(ctx); }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);
 void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN);
@@ -181,7 +187,7 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q);
 // ---- CG buffers -----------------------------------------------------------
 template <typename T>
 struct PcgBufs {
-  const T *Linv, *C, *XP, *E, *dvec, *wts;
+  const T *Linv, *C, *XP, *E, *CT, *MT, *dvec, *wts;
   T *r, *z, *p, *q, *t, *u, *v, *w, *x;
   const GemvWork<T>* wk;
 };

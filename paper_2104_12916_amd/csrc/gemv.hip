@@ -51,6 +51,7 @@ Tune& tune() {
       if (!strcmp(tok, "rows_stage") && (val == 0 || val == 1)) v.rows_stage = val;
       if (!strcmp(tok, "brows_stage") && (val == 0 || val == 1)) v.brows_stage = val;
       if (!strcmp(tok, "brows_unroll") && (val == 4 || val == 8)) v.brows_unroll = val;
+      if (!strcmp(tok, "op_t") && (val == 0 || val == 1)) v.op_t = val;
     }
     return v;
   }();
@@ -72,11 +73,17 @@ __device__ __forceinline__ void rows_body(const T* __restrict__ A, int lda, int 
   const int maxlen = (shape == kLower) ? min(m, k) : k;
   const int lenR_max = round_chunk<T>(maxlen, lda);
   if (xs) stage_x<T>(xs, x, k, lenR_max);  // xs null: x is read through the caches
+  constexpr int CH = kWave * Vec16<T>::n;
   for (int i = bid * waves + wave; i < m; i += nb * waves) {
-    int len = (shape == kLower) ? min(i + 1, k) : k;
-    int lenR = round_chunk<T>(len, lda);
-    T v = xs ? row_dot<T, U>(A + (size_t)i * lda, xs, lenR, lane)
-             : row_dot_gx<T, U>(A + (size_t)i * lda, x, lenR, k, lane);
+    int s0 = 0, len = k;
+    if (shape == kLower) len = min(i + 1, k);
+    if (shape == kUpper) {
+      s0 = min(i, k) / CH * CH;  // aligned start of the chunk holding the diagonal
+      len = k - s0;
+    }
+    const int lenR = round_chunk<T>(len, lda - s0);
+    const T* arow = A + (size_t)i * lda + s0;
+    T v = xs ? row_dot<T, U>(arow, xs + s0, lenR, lane) : row_dot_gx<T, U>(arow, x + s0, lenR, k - s0, lane);
     if (lane == 0) {
       v *= alpha;
       if (i >= nsplit) v = -v;
@@ -141,7 +148,8 @@ __device__ __forceinline__ void cols_reduce_body(int k, int ps, int shape, const
 // ---------------------------------------------------------------------------
 // single-problem kernels.  TAG only separates launch sites in profiles (same
 // code for every value): 0 generic, 1 C^T p, 2 Sigma M u, 3 M^T v (the CG-step
-// operator sweeps), 4 X_P r, 5 X_P^T t (the P_H apply).
+// operator sweeps; 1 and 3 as row sweeps over the stored transposes, or as
+// column sweeps), 4 X_P r, 5 X_P^T t (the P_H apply).
 template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) gemv_rows_kernel(
     const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x,
@@ -245,7 +253,9 @@ hipError_t launch_gemv_rows(hipStream_t st, const T* A, int lda, int m, int k, i
   if (nsplit < 0) nsplit = m;
   dim3 grid(gemv_rows_grid<T>(m));
   switch (tag) {
+    case 1: launch_rows_tag<T, 1>(grid, smem, st, ev, A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, skip); break;
     case 2: launch_rows_tag<T, 2>(grid, smem, st, ev, A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, skip); break;
+    case 3: launch_rows_tag<T, 3>(grid, smem, st, ev, A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, skip); break;
     case 4: launch_rows_tag<T, 4>(grid, smem, st, ev, A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, skip); break;
     default: launch_rows_tag<T, 0>(grid, smem, st, ev, A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, skip);
   }
@@ -395,7 +405,9 @@ hipError_t launch_bgemv_rows(hipStream_t st, const RowsDesc<T>* ddesc, const int
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   dim3 grid(total_blocks);
   switch (tag) {
+    case 1: launch_brows_tag<T, 1>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
     case 2: launch_brows_tag<T, 2>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
+    case 3: launch_brows_tag<T, 3>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
     case 4: launch_brows_tag<T, 4>(grid, smem, st, ev, ddesc, dprefix, ndesc); break;
     default: launch_brows_tag<T, 0>(grid, smem, st, ev, ddesc, dprefix, ndesc);
   }
@@ -423,6 +435,58 @@ hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int
     default: launch_bcols_tag<T, 0>(grid, st, ev, ddesc, dprefix_part, ndesc);
   }
   hipLaunchKernelGGL(bgemv_cols_reduce_kernel<T>, dim3(total_red), dim3(256), 0, st, ddesc, dprefix_red, ndesc);
+  return hipGetLastError();
+}
+
+// ---- transposes ---------------------------------------------------------------
+// dst = src^T (src rows x cols, row-major), optionally rounded to float32;
+// 32 x 32 tiles through LDS so both sides are coalesced.
+__device__ __forceinline__ void transpose_body(const double* __restrict__ src, int lds, int rows, int cols,
+                                               void* __restrict__ dst, int ldd, int to_float, int bx, int by) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8 threads
+  const int c0 = bx * 32, r0 = by * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = r0 + r, j = c0 + tx;
+    tile[r][tx] = (i < rows && j < cols) ? src[(size_t)i * lds + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = c0 + r, i = r0 + tx;
+    if (j < cols && i < rows) {
+      const double v = tile[tx][r];
+      if (to_float)
+        static_cast<float*>(dst)[(size_t)j * ldd + i] = (float)v;
+      else
+        static_cast<double*>(dst)[(size_t)j * ldd + i] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) transpose_kernel(const double* __restrict__ src, int lds, int rows, int cols,
+                                                        void* __restrict__ dst, int ldd, int to_float) {
+  transpose_body(src, lds, rows, cols, dst, ldd, to_float, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) btranspose_kernel(const TransDesc* __restrict__ descs) {
+  const TransDesc t = descs[blockIdx.z];
+  if ((int)blockIdx.x * 32 >= t.cols || (int)blockIdx.y * 32 >= t.rows) return;
+  transpose_body(t.src, t.lds, t.rows, t.cols, t.dst, t.ldd, t.to_float, blockIdx.x, blockIdx.y);
+}
+
+hipError_t transpose_2d(hipStream_t st, const double* src, int lds, int rows, int cols, void* dst, int ldd,
+                        int to_float) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if ((rows + 31) / 32 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, src, lds, rows,
+                     cols, dst, ldd, to_float);
+  return hipGetLastError();
+}
+
+hipError_t btranspose_2d(hipStream_t st, const TransDesc* d, int count, int max_rows, int max_cols) {
+  if (count <= 0 || max_rows <= 0 || max_cols <= 0) return hipSuccess;
+  if ((max_rows + 31) / 32 > 65535 || count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(btranspose_kernel, dim3((max_cols + 31) / 32, (max_rows + 31) / 32, count), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 

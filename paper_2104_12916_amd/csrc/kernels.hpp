@@ -41,6 +41,16 @@ template <typename T>
 hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int* dprefix_part, int total_part,
                              const int* dprefix_red, int total_red, int ndesc, int tag, const EventPair* ev = nullptr);
 
+// dst = src^T (rows x cols source), float64 or rounded to float32
+struct TransDesc {
+  const double* src;
+  void* dst;
+  int lds, ldd, rows, cols, to_float;
+};
+hipError_t transpose_2d(hipStream_t st, const double* src, int lds, int rows, int cols, void* dst, int ldd,
+                        int to_float);
+hipError_t btranspose_2d(hipStream_t st, const TransDesc* d, int count, int max_rows, int max_cols);
+
 // blas.hip -----------------------------------------------------------------
 // Tile skip rules for GEMM operands with known zero blocks (indices in op()
 // space): kALower: op(A) lower triangular (k <= i); kBLower: op(B) lower (k >= j);

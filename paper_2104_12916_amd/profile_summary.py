@@ -23,12 +23,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 256 << 20  # the calibration copy of profile_ops
 
-# CG-step sweeps of the float64 single-QP path: tag -> kernel name prefix
+# CG-step sweeps of the float64 single-QP path: tag -> kernel name prefixes (C^T p
+# and M^T v are row sweeps over stored transposes, or column sweeps)
 SWEEPS = {
-    "C^T": "qpg::gemv_cols_part_kernel<double, 1,",
-    "M": "qpg::gemv_rows_kernel<double, 2,",
-    "M^T": "qpg::gemv_cols_part_kernel<double, 3,",
-    "q": "qpg::pcg_q_kernel<double,",
+    "C^T": ("qpg::gemv_rows_kernel<double, 1,", "qpg::gemv_cols_part_kernel<double, 1,"),
+    "M": ("qpg::gemv_rows_kernel<double, 2,",),
+    "M^T": ("qpg::gemv_rows_kernel<double, 3,", "qpg::gemv_cols_part_kernel<double, 3,"),
+    "q": ("qpg::pcg_q_kernel<double,",),
 }
 
 
@@ -90,9 +91,10 @@ def traffic(args):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     out = json.load(open(path)) if os.path.exists(path) else {}
     src = kernel_src_hash()
-    for tag, prefix in SWEEPS.items():
-        ids = [d for d, r in fetch.items() if r["Kernel_Name"].startswith("void " + prefix) or
-               r["Kernel_Name"].startswith(prefix)]
+    for tag, prefixes in SWEEPS.items():
+        ids = [d for d, r in fetch.items()
+               if any(r["Kernel_Name"].startswith(pre) or r["Kernel_Name"].startswith("void " + pre)
+                      for pre in prefixes)]
         if not ids:
             continue
         fk = sum(float(fetch[d]["Counter_Value"]) for d in ids) / len(ids)

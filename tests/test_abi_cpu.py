@@ -117,9 +117,10 @@ def test_batch_footprint_is_positive_monotone_and_validates():
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_LOW_DOF), 512, 128, 256) < f[2]
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ, precision=qpgpu.QP_MIXED),
                                     512, 128, 256) > f[2]
-    # the explicit operator adds E (m2 x m2) and its scratch Y
-    assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ,
-                                                             kf_form=qpgpu.QP_KF_EXPLICIT), 512, 128, 256) > f[2]
+    # the explicit operator holds E (m2 x m2) and, during the factorization, Y (N x m2)
+    fe = qpgpu.qp_batch_footprint(qpgpu.qp_default_options(prec=qpgpu.QP_PREC_FEW_EQ,
+                                                           kf_form=qpgpu.QP_KF_EXPLICIT), 512, 128, 256)
+    assert fe >= 8 * (n * n + 128 * n + 256 * n + 640 ** 2 + 256 * 256 + 640 * 256) and fe != f[2]
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(kf_form=7), 5, 2, 1) == 0
     assert qpgpu.qp_batch_footprint(opt, 0, 1, 1) == 0
     assert qpgpu.qp_batch_footprint(opt, 5, 6, 1) == 0
