@@ -52,6 +52,9 @@ WORKLOADS = {
 OP_NAMES = ["gemv_rows_kernel<T,1> (C^T p over stored C^T)", "gemv_rows_kernel<T,2> (Sigma M u)",
             "gemv_rows_kernel<T,3> (M^T v over stored M^T)", "pcg_q_kernel<T> (C w + D p)",
             "gemv_rows_kernel<T,4> (X_P r)", "gemv_cols_part_kernel<T,5> (X_P^T t)"]
+# with the one-pass K0 product, slots 1 and 2 hold its sweep and the sum of its partials
+OP_NAMES_ONE_PASS = OP_NAMES[:1] + ["k0_sym_kernel<T> (M^T Sigma M u, one pass over M)",
+                                    "k0_sym_reduce_kernel<T> (sum of the per-workgroup partials of w)"] + OP_NAMES[3:]
 
 
 def op_bytes(n, m1, m2, elem):
@@ -495,18 +498,23 @@ def main():
     qp0 = qps[0]
     elem = 4 if precision == qpgpu.QP_MIXED else 8
     nbytes = op_bytes(qp0.n, qp0.m1, qp0.m2, elem)
+    one_pass = solvers[0].k0_one_pass()
+    names = OP_NAMES_ONE_PASS if one_pass else OP_NAMES
+    tags = ["C^T", "M1" if one_pass else "M", "M1red" if one_pass else "M^T", "q", "XP", "XP^T"]
+    if one_pass:  # M is read once; the partial sums are workspace, not operator bytes
+        nbytes[2] = 0
     if kf == qpgpu.QP_KF_EXPLICIT:  # one sweep over E (m2 x m2) replaces the four operator sweeps
         nbytes = [0, 0, 0, qp0.m2 * qp0.m2 * elem] + nbytes[4:]
     ops = {}
     for o in range(6):
         if cnt[o] > 0:
-            ops[OP_NAMES[o]] = dict(avg_us=round(avg_ms[o] * 1e3, 2), samples=int(cnt[o]),
-                                    bytes=nbytes[o], gbs=round(nbytes[o] / (avg_ms[o] * 1e-3) / 1e9, 1))
+            ops[names[o]] = dict(avg_us=round(avg_ms[o] * 1e3, 2), samples=int(cnt[o]),
+                                 bytes=nbytes[o], gbs=round(nbytes[o] / (avg_ms[o] * 1e-3) / 1e9, 1))
     dom = int(np.argmax(avg_ms))
     achieved = nbytes[dom] / (avg_ms[dom] * 1e-3) / 1e9
-    traffic, tnote = load_traffic(args.workload, ["C^T", "M", "M^T", "q", "XP", "XP^T"][dom])
+    traffic, tnote = load_traffic(args.workload, tags[dom])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=OP_NAMES[dom],
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=names[dom],
                     bytes_per_launch=nbytes[dom], avg_launch_us=round(avg_ms[dom] * 1e3, 2),
                     traffic_note=tnote)
 

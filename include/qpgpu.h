@@ -13,7 +13,7 @@
  *
  * Method.  Each IPM iteration solves the inequality-constraint reduced system
  * K_F dnu = r_nu (eq. ineq-const-reduced) by preconditioned CG in implicit form,
- * using one factorization of the fixed KKT block done once per QP (Sec. 3.1).
+ * using one factorization of the fixed KKT block done once per QP (Sec. 4.1).
  * This library factorizes K0 = [H A^T; A 0] (the paper's F = [-H A^T; A 0] up to
  * the sign change K0 = -J F J, J = diag(-I_n, I_m1)), so that
  *     K_F = D + [C 0] K0^{-1} [C^T; 0],  D = V^{-1} S (eq. diag-d).
@@ -75,7 +75,7 @@ typedef enum { QP_MEM_HOST = 0, QP_MEM_DEVICE = 1 } qp_mem;
 
 typedef enum {
   QP_KF_IMPLICIT = 0, /* each CG step applies C^T, the K0 inverse factor twice and C
-                         (Sec. 3.1, implicit form; the default)                     */
+                         (Sec. 4.1, implicit form; the default)                     */
   QP_KF_EXPLICIT = 1  /* K_F - D = C K0^{-1}_{11} C^T (eq. ineq-const-reduced) formed
                          once per QP after the K0 factorization (m2 x m2, float64,
                          MFMA GEMMs); each CG step is one m2 x m2 row sweep          */
@@ -134,7 +134,7 @@ qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const d
                    const double* b, const double* C, const double* d, qp_mem where, const qp_options* opt,
                    void* hip_stream);
 
-/* Factorize K0 = L Sigma L^T once (Sec. 3.1, single factorization), Sigma =
+/* Factorize K0 = L Sigma L^T once (Sec. 4.1, single factorization), Sigma =
  * diag(I_n, -I_m1), L = [L_H 0; W^T L_S] with L_H L_H^T = H, W = L_H^{-1} A^T,
  * L_S L_S^T = A H^{-1} A^T, and store the inverse factor L^{-1} for the solves.
  * Also forms C H^{-1} C^T when the options' preconditioner resolves to P_H, and
@@ -170,9 +170,13 @@ qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, doubl
 /* Diagnostic: average device time (ms) of one launch of a CG-step operator
  * kernel, measured with HIP events around `reps` back-to-back launches on the
  * context's stream, in the launch configuration qp_pcg_solve uses:
- *   op 0  u = C^T p            (column sweep over C)
- *   op 1  v = Sigma M u        (row sweep over M = L^{-1}[:, :n])
- *   op 2  w = M^T v            (column sweep over M)
+ *   op 0  u = C^T p            (row sweep over the stored C^T, or column sweep over C)
+ *   op 1  v = Sigma M u        (row sweep over M = L^{-1}[:, :n]); with the
+ *                              one-pass K0 product (qp_k0_one_pass): the
+ *                              single sweep of M that forms M^T Sigma M u as
+ *                              per-workgroup partials
+ *   op 2  w = M^T v            (row sweep over the stored M^T, or column sweep
+ *                              over M); one-pass: the sum of the partials
  *   op 3  q = C w              (row sweep over C)
  *   op 4  one whole P_L CG step (ops 0-2 and the fused q/update kernel)
  * precision QP_MIXED times the float32 copies (context created QP_MIXED).
@@ -180,10 +184,18 @@ qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, doubl
 qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, double* avg_ms);
 
 /* Average device time (ms) per launch and sample counts of the CG-step kernels
- * sampled while options.profile is set, in the order: C^T p column sweep,
- * Sigma M u row sweep, M^T v column sweep, q = C w + D p row sweep, and for
- * P_H the X_P r row sweep and X_P^T t column sweep.  reset != 0 clears them. */
+ * sampled while options.profile is set, in the order of qp_op_time's ops 0-3
+ * (C^T p, Sigma M u or the one-pass sweep of M, M^T v or the sum of its
+ * partials, q = C w + D p), then for P_H the X_P r row sweep and the X_P^T t
+ * column sweep.  reset != 0 clears them. */
 qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset);
+
+/* 1 if the context's implicit CG step forms K0^{-1}_{11} u = M^T Sigma M u
+ * (K0^{-1} = L^{-T} Sigma L^{-1}, M = L^{-1}[:, :n]; Sec. 4.1)
+ * in one pass over M instead of the two triangular sweeps: same product, M read
+ * once.  Chosen at qp_create from n (n <= 4096) and the K_F form; 0 otherwise
+ * or for NULL. */
+int qp_k0_one_pass(const qp_ctx* ctx);
 
 /* Device bytes held by the context (all buffers, factor included). */
 size_t qp_ctx_bytes(const qp_ctx* ctx);

@@ -1,6 +1,6 @@
 """The inequality-constraint reduced system on explicit matrices (oracle only).
 
-Everything here is a plain definition from Sec. 3 of the paper, written with
+Everything here is a plain definition from Sec. 4 of the paper, written with
 dense float64 NumPy/SciPy solves.  It is what the GPU path computes implicitly,
 spelled out so that tests can compare the two element by element.
 
@@ -106,7 +106,7 @@ def P_H(qp, dvec):
 
 
 def preconditioned_eigs(K, P):
-    """Eigenvalues of P^{-1/2} K P^{-1/2} (split preconditioning, Sec. 3.3)."""
+    """Eigenvalues of P^{-1/2} K P^{-1/2} (split preconditioning, Sec. 4.3)."""
     w, V = np.linalg.eigh(P)
     Pmh = (V / np.sqrt(w)) @ V.T
     M = Pmh @ K @ Pmh

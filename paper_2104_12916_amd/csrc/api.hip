@@ -336,9 +336,11 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     ctx->info = static_cast<int*>(get(16 * sizeof(int)));
   }
   if (kf_explicit(ctx)) D(ctx->E, (size_t)m2 * ctx->ldm2);
-  if (op_transposed(ctx)) {
-    D(ctx->CT, (size_t)n * ctx->ldm2);
-    D(ctx->MT, (size_t)n * ctx->ldN);
+  if (op_transposed(ctx)) D(ctx->CT, (size_t)n * ctx->ldm2);
+  if (store_mt(ctx)) D(ctx->MT, (size_t)n * ctx->ldN);
+  if (op_fused(ctx)) {
+    ctx->sympart_bytes = k0_sym_part_elems(n) * sizeof(double);
+    ctx->sympart = get(ctx->sympart_bytes);
   }
   if (need_ph) {
     D(ctx->T, (size_t)m2 * ctx->ldm2);
@@ -351,10 +353,8 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     F(ctx->C32, (size_t)m2 * ctx->ldn);
     if (need_ph) F(ctx->XP32, (size_t)m2 * ctx->ldm2);
     if (kf_explicit(ctx)) F(ctx->E32, (size_t)m2 * ctx->ldm2);
-    if (op_transposed(ctx)) {
-      F(ctx->CT32, (size_t)n * ctx->ldm2);
-      F(ctx->MT32, (size_t)n * ctx->ldN);
-    }
+    if (op_transposed(ctx)) F(ctx->CT32, (size_t)n * ctx->ldm2);
+    if (store_mt(ctx)) F(ctx->MT32, (size_t)n * ctx->ldN);
     for (float** v : {&ctx->fr, &ctx->fz, &ctx->fq, &ctx->ft, &ctx->fx, &ctx->fb, &ctx->fd, &ctx->fwts}) F(*v, m2);
     F(ctx->fp, ctx->ldm2);
     for (float** v : {&ctx->fu, &ctx->fw}) F(*v, n);
@@ -545,18 +545,14 @@ void factor(qp_ctx* ctx) {
     sync(ctx);  // the scratch is about to be released
   }
   drop();
-  if (op_transposed(ctx)) {
-    HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT, ctx->ldm2, 0));
-    HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT, ldN, 0));
-  }
+  if (op_transposed(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT, ctx->ldm2, 0));
+  if (store_mt(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT, ldN, 0));
   if (ctx->opt.precision == QP_MIXED) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->Linv, ldN, ctx->Linv32, ldN, N, N)));
     if (kf_explicit(ctx))
       HIPCHK(ctx, (convert_2d<double, float>(st, ctx->E, ctx->ldm2, ctx->E32, ctx->ldm2, ctx->m2, ctx->m2)));
-    if (op_transposed(ctx)) {
-      HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT32, ctx->ldm2, 1));
-      HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT32, ldN, 1));
-    }
+    if (op_transposed(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT32, ctx->ldm2, 1));
+    if (store_mt(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT32, ldN, 1));
   }
   ctx->factored = true;
 }
@@ -641,7 +637,8 @@ int mixed_inner_cap(const qp_ctx* ctx, int prec) {
 
 // ---- PCG driver (one QP) ------------------------------------------------------
 // u = C^T p, v = Sigma M u, w = M^T v: the first three sweeps of the implicit CG
-// step (row sweeps over the stored transposes, or column sweeps).
+// step (row sweeps over the stored transposes, or column sweeps), or u = C^T p
+// and the one-pass w = M^T Sigma M u (sweep, then the sum of its partials).
 template <typename T>
 static void op_sweeps(qp_ctx* ctx, const PcgBufs<T>& B, const int* skip, const EventPair* ev) {
   hipStream_t st = ctx->stream;
@@ -652,6 +649,13 @@ static void op_sweeps(qp_ctx* ctx, const PcgBufs<T>& B, const int* skip, const E
   else
     HIPCHK(ctx, launch_gemv_cols<T>(st, B.C, ctx->ldn, m2, n, kDense, B.p, B.u, T(1), T(0), nullptr, *B.wk, skip, 1,
                                     ev ? &ev[0] : nullptr));
+  if (op_fused(ctx)) {
+    T* part = static_cast<T*>(ctx->sympart);
+    HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, N, n, B.u, part, ctx->sympart_bytes / sizeof(T), skip,
+                                       ev ? &ev[1] : nullptr));
+    HIPCHK(ctx, launch_k0_sym_reduce<T>(st, N, n, part, B.w, skip, ev ? &ev[2] : nullptr));
+    return;
+  }
   HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n, skip, 2,
                                   ev ? &ev[1] : nullptr));
   if (op_transposed(ctx))
@@ -746,9 +750,16 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
                                          ctx->m2, nullptr));
     return;
   }
-  HIPCHK(ctx, launch_gemv_cols<double>(st, ctx->C, ctx->ldn, ctx->m2, ctx->n, kDense, p, ctx->pu, 1.0, 0.0, nullptr,
-                                       ctx->w64, nullptr));
-  k0_top_apply<double>(ctx, ctx->Linv, ctx->pu, ctx->pv, ctx->pw, ctx->w64, nullptr);
+  if (op_fused(ctx)) {
+    // the CG step's operator sweeps: C^T p, then M^T Sigma M u in one pass
+    PcgBufs<double> B = bufs64(ctx, dvec, nullptr, nullptr);
+    B.p = const_cast<double*>(p);  // read only
+    op_sweeps<double>(ctx, B, nullptr, nullptr);
+  } else {
+    HIPCHK(ctx, launch_gemv_cols<double>(st, ctx->C, ctx->ldn, ctx->m2, ctx->n, kDense, p, ctx->pu, 1.0, 0.0,
+                                         nullptr, ctx->w64, nullptr));
+    k0_top_apply<double>(ctx, ctx->Linv, ctx->pu, ctx->pv, ctx->pw, ctx->w64, nullptr);
+  }
   HIPCHK(ctx, ew_mul(st, ctx->m2, dvec, p, ctx->pt));
   HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->C, ctx->ldn, ctx->m2, ctx->n, kDense, ctx->pw, q, 1.0, 1.0, ctx->pt,
                                        ctx->m2, nullptr));
@@ -1035,6 +1046,8 @@ const char* qp_last_error(const qp_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 
 size_t qp_ctx_bytes(const qp_ctx* ctx) { return ctx ? ctx->bytes : 0; }
 
+int qp_k0_one_pass(const qp_ctx* ctx) { return ctx && op_fused(ctx) ? 1 : 0; }
+
 qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset) {
   if (!ctx || !avg_ms || !samples) return QP_E_INVALID;
   for (int o = 0; o < kProfOps; ++o) {
@@ -1246,11 +1259,17 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
                                               nullptr, 1));
             break;
           case 1:
-            HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n,
-                                            nullptr, 2));
+            if (op_fused(ctx))
+              HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, ctx->N, n, B.u, static_cast<T*>(ctx->sympart),
+                                                 ctx->sympart_bytes / sizeof(T), nullptr));
+            else
+              HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, ctx->N, n, kLower, B.u, B.v, T(1), T(0), nullptr,
+                                              n, nullptr, 2));
             break;
           case 2:
-            if (op_transposed(ctx))
+            if (op_fused(ctx))
+              HIPCHK(ctx, launch_k0_sym_reduce<T>(st, ctx->N, n, static_cast<const T*>(ctx->sympart), B.w, nullptr));
+            else if (op_transposed(ctx))
               HIPCHK(ctx, launch_gemv_rows<T>(st, B.MT, ctx->ldN, n, ctx->N, kUpper, B.v, B.w, T(1), T(0), nullptr, n,
                                               nullptr, 3));
             else
@@ -1271,6 +1290,9 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
           }
         }
       };
+      if (op_fused(ctx))  // partials for the reduce timing
+        HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, ctx->N, n, B.u, static_cast<T*>(ctx->sympart),
+                                           ctx->sympart_bytes / sizeof(T), nullptr));
       launch();  // warm-up
       HIPCHK(ctx, hipEventRecord(e0, st));
       for (int k = 0; k < reps; ++k) launch();

@@ -44,7 +44,8 @@ DevInfo& dev_info();
 
 // Launch shapes of the streaming sweeps.  Defaults were chosen by timing on
 // gfx950 (qp_op_time); the environment variable QPGPU_TUNE
-// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0,qe_stage=0,rows_stage=0") overrides them.
+// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0,qe_stage=0,rows_stage=0,k0_sym=0")
+// overrides them.
 struct Tune {
   int rows_bpc = 4;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
   int rows_unroll = 8;  // 16-byte loads in flight per lane: 4 or 8
@@ -58,10 +59,19 @@ struct Tune {
   int brows_unroll = 4; // batched row sweeps: 16-byte loads in flight per lane
   int op_t = 1;         // keep transposed copies of C and M so every CG-step sweep is a row sweep
                         // (0: column sweeps with per-chunk partials, no extra memory)
+  int k0_sym = 1;       // one pass over M for M^T Sigma M u (n small enough for register rows)
+  int sym_wg = 2;       // one-pass sweep: workgroups per CU (each writes one partial of w)
+  int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
+  int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
+                        // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
+                        // more than the 256 MB last-level cache holds; loading M plainly and C, C^T
+                        // non-temporally keeps part of M cached from step to step (step time 77 -> 70
+                        // us at n = 4096, m1 = 3072, m2 = 2048; the opposite split is equal)
 };
 Tune& tune();
 constexpr int kMaxRowsBpc = 8;
 constexpr int kMaxColsBpc = 8;
+constexpr int kMaxSymWg = 4;
 
 // Optional pair of events recorded around the main kernel of a launch (used to
 // sample kernel durations during a solve).

@@ -104,6 +104,8 @@ struct qp_ctx {
   float *fu = nullptr, *fv = nullptr, *fw = nullptr, *fd = nullptr, *fwts = nullptr;
   // workspaces
   qpg::GemvWork<double> w64{};
+  void* sympart = nullptr;  // per-workgroup partials of the one-pass K0 product
+  size_t sympart_bytes = 0;
   qpg::GemvWork<float> w32{};
   double* bpart = nullptr;  // per-workgroup partials of p^T q
   int bpart_cap = 0;
@@ -179,6 +181,12 @@ void factor(qp_ctx* ctx);
 inline bool kf_explicit(const qp_ctx* ctx) { return ctx->opt.kf_form == QP_KF_EXPLICIT; }
 // The implicit CG step reads the stored transposes (C^T, M^T) with row sweeps.
 inline bool op_transposed(const qp_ctx* ctx) { return tune().op_t && !kf_explicit(ctx); }
+// The implicit CG step forms M^T Sigma M u in one pass over M (stand-alone
+// contexts whose n fits the register rows of the one-pass sweep); M^T is not stored.
+inline bool op_fused(const qp_ctx* ctx) {
+  return tune().k0_sym && !kf_explicit(ctx) && !ctx->pooled && ctx->n <= k0_sym_max_n<double>();
+}
+inline bool store_mt(const qp_ctx* ctx) { return op_transposed(ctx) && !op_fused(ctx); }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);
 void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN);

@@ -20,6 +20,7 @@
 // matrices of many QPs of different sizes.  Both call the same device bodies.
 // Lower-triangular operands (row i holds columns 0..i, zeros above) are read
 // only up to the tile containing the diagonal.  Launch shapes come from tune().
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -52,6 +53,10 @@ Tune& tune() {
       if (!strcmp(tok, "brows_stage") && (val == 0 || val == 1)) v.brows_stage = val;
       if (!strcmp(tok, "brows_unroll") && (val == 4 || val == 8)) v.brows_unroll = val;
       if (!strcmp(tok, "op_t") && (val == 0 || val == 1)) v.op_t = val;
+      if (!strcmp(tok, "k0_sym") && (val == 0 || val == 1)) v.k0_sym = val;
+      if (!strcmp(tok, "sym_wg") && val >= 1 && val <= kMaxSymWg) v.sym_wg = val;
+      if (!strcmp(tok, "sym_rows") && (val == 2 || val == 4)) v.sym_rows = val;
+      if (!strcmp(tok, "ld_nt") && val >= 0 && val <= 3) v.ld_nt = val;
     }
     return v;
   }();
@@ -63,10 +68,15 @@ Tune& tune() {
 
 // Rows bid, bid + nb, ... (in units of 4 waves) of y = alpha A x (+ beta y0),
 // rows >= nsplit negated.  xs: LDS of at least round_chunk(min(m,k) or k) elements.
+// skip (nullable): stop flag of the solve, the same for the whole grid; it is
+// tested after the first row's loads, so its latency overlaps theirs, and a
+// set flag leaves y untouched.
 template <typename T, int U>
 __device__ __forceinline__ void rows_body(const T* __restrict__ A, int lda, int m, int k, int shape,
                                           const T* __restrict__ x, T* __restrict__ y, T alpha, T beta,
-                                          const T* __restrict__ y0, int nsplit, int bid, int nb, T* xs) {
+                                          const T* __restrict__ y0, int nsplit, int bid, int nb, T* xs,
+                                          const int* __restrict__ skip, int nt = 1) {
+  const int sk = skip ? *skip : 0;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int waves = blockDim.x / kWave;
   // rows are dealt round-robin over all waves, so every block sees rows up to the last one
@@ -83,7 +93,13 @@ __device__ __forceinline__ void rows_body(const T* __restrict__ A, int lda, int 
     }
     const int lenR = round_chunk<T>(len, lda - s0);
     const T* arow = A + (size_t)i * lda + s0;
-    T v = xs ? row_dot<T, U>(arow, xs + s0, lenR, lane) : row_dot_gx<T, U>(arow, x + s0, lenR, k - s0, lane);
+    T v;
+    if (nt)
+      v = xs ? row_dot<T, U>(arow, xs + s0, lenR, lane) : row_dot_gx<T, U>(arow, x + s0, lenR, k - s0, lane);
+    else
+      v = xs ? row_dot<T, U, false>(arow, xs + s0, lenR, lane)
+             : row_dot_gx<T, U, false>(arow, x + s0, lenR, k - s0, lane);
+    if (sk) return;
     if (lane == 0) {
       v *= alpha;
       if (i >= nsplit) v = -v;
@@ -154,11 +170,10 @@ template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) gemv_rows_kernel(
     const T* __restrict__ A, int lda, int m, int k, int shape, const T* __restrict__ x,
     T* __restrict__ y, T alpha, T beta, const T* __restrict__ y0, int nsplit, const int* __restrict__ skip,
-    int stage) {
-  if (skip && *skip) return;
+    int stage, int nt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   rows_body<T, U>(A, lda, m, k, shape, x, y, alpha, beta, y0, nsplit, blockIdx.x, gridDim.x,
-                  stage ? reinterpret_cast<T*>(smem_raw) : nullptr);
+                  stage ? reinterpret_cast<T*>(smem_raw) : nullptr, skip, nt);
 }
 
 template <typename T, int TAG, int U>
@@ -185,10 +200,9 @@ __global__ void __launch_bounds__(256) bgemv_rows_kernel(const RowsDesc<T>* __re
                                                          const int* __restrict__ prefix, int ndesc, int stage) {
   const int j = desc_of_block(prefix, ndesc, blockIdx.x);
   const RowsDesc<T> d = descs[j];
-  if (d.skip && *d.skip) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   rows_body<T, U>(d.A, d.lda, d.m, d.k, d.shape, d.x, d.y, d.alpha, d.beta, d.y0, d.nsplit, blockIdx.x - prefix[j],
-                  d.nblocks, stage ? reinterpret_cast<T*>(smem_raw) : nullptr);
+                  d.nblocks, stage ? reinterpret_cast<T*>(smem_raw) : nullptr, d.skip);
 }
 
 template <typename T, int TAG, int U>
@@ -235,13 +249,14 @@ static void launch_rows_tag(dim3 grid, size_t smem, hipStream_t st, const EventP
                             int k, int shape, const T* x, T* y, T alpha, T beta, const T* y0, int nsplit,
                             const int* skip) {
   const int stage = tune().rows_stage;
+  const int nt = tune().ld_nt & 1;
   if (!stage) smem = 0;
   if (tune().rows_unroll == 8)
     QPG_LAUNCH((gemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
-               alpha, beta, y0, nsplit, skip, stage);
+               alpha, beta, y0, nsplit, skip, stage, nt);
   else
     QPG_LAUNCH((gemv_rows_kernel<T, TAG, 4>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
-               alpha, beta, y0, nsplit, skip, stage);
+               alpha, beta, y0, nsplit, skip, stage, nt);
 }
 
 template <typename T>
@@ -438,6 +453,220 @@ hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int
   return hipGetLastError();
 }
 
+// ---- one-pass K0 block product ---------------------------------------------------
+// w = M^T Sigma M u with M = L^{-1}[:, :n] (N x n, lower trapezoid: row i holds
+// columns 0..min(i, n-1)) and Sigma = diag(I_n, -I_{N-n}) -- the K0^{-1}_{11}
+// product of the implicit CG step, K0^{-1} = L^{-T} Sigma L^{-1}.  The step
+// needs M u only to form this product, so every row of M is read once: the
+// workgroup that owns row i forms v_i = sigma_i (M_i . u) and adds v_i M_i^T to
+// its private partial of w.  A second kernel adds the partials in workgroup order.
+//
+// Rows are dealt in units of about n entries: a pair (i, n-1-i) of the
+// triangular part or one row of the rectangular part; workgroup g takes units
+// [g U / G, (g+1) U / G).  The BT threads of a workgroup span the columns
+// (thread t owns columns c*BT*VE + t*VE .. + VE-1 of every row), so u and the
+// partial stay in registers, and R rows share one block reduction.
+
+// Row of local ordinal q in a workgroup's unit range [u0, u1): np pairs first,
+// then the middle row of an odd n and the rectangular rows.
+__device__ __forceinline__ int sym_row(int q, int u0, int np, int us, int n) {
+  if (q < 2 * np) {
+    const int uu = u0 + q / 2;
+    return (q & 1) ? n - 1 - uu : uu;
+  }
+  const int uu = us + (q - 2 * np);
+  const int tri = (n + 1) / 2;
+  return uu < tri ? uu : n + (uu - tri);
+}
+
+template <typename T, int BT, int K, int R, bool NT>
+__global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
+                                                    const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
+                                                    const int* __restrict__ skip) {
+  const int sk = skip ? *skip : 0;  // tested after the first round's loads (uniform over the grid)
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CHB = BT * VE;
+  constexpr int NW = BT / kWave;
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int g = blockIdx.x;
+  const int P = n / 2, U = (n + 1) / 2 + (N - n);
+  const int u0 = (int)((long long)g * U / G), u1 = (int)((long long)(g + 1) * U / G);
+  const int np = max(0, min(u1, P) - u0);
+  const int us = max(u0, P);
+  const int nrows = 2 * np + max(0, u1 - us);
+  T xu[K][VE], acc[K][VE];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int col = c * CHB + tid * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      xu[c][e] = (col + e < n) ? u[col + e] : T(0);
+      acc[c][e] = T(0);
+    }
+  }
+  __shared__ T sh[2][R][NW];
+  int buf = 0;
+  for (int q0 = 0; q0 < nrows; q0 += R) {
+    V a[R][K];
+    int rowi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = q0 + r;
+      int i = -1, len = 0;
+      if (q < nrows) {
+        i = sym_row(q, u0, np, us, n);
+        len = min(i + 1, n);
+      }
+      rowi[r] = i;
+      const T* arow = M + (size_t)(i < 0 ? 0 : i) * ldm;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        const int col = c * CHB + tid * VE;
+        if (col < len) {
+          a[r][c] = ld16<V, NT>(reinterpret_cast<const V*>(arow + col));
+        } else {
+#pragma unroll
+          for (int e = 0; e < VE; ++e) a[r][c][e] = T(0);
+        }
+      }
+    }
+    T d[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      d[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < K; ++c) d[r] += dot16<V, T>(a[r][c], xu[c]);
+    }
+    if (sk) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T s = wave_sum<T>(d[r]);
+      if (lane == 0) sh[buf][r][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T v = sh[buf][r][0];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) v += sh[buf][r][w2];
+      if (rowi[r] >= n) v = -v;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[c][e] += a[r][c][e] * v;
+      }
+    }
+    buf ^= 1;  // the next round writes the other buffer: one barrier per round suffices
+  }
+  T* pg = part + (size_t)g * ldp;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int col = c * CHB + tid * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e)
+      if (col + e < n) pg[col + e] = acc[c][e];
+  }
+}
+
+// w_j = sum over g of part[g][j]: 16 columns per workgroup, 16 lanes per column
+// take g = t, t + 16, ... with four loads in flight, then a fixed butterfly.
+template <typename T>
+__global__ void __launch_bounds__(256) k0_sym_reduce_kernel(const T* __restrict__ part, int ldp, int G, int n,
+                                                            T* __restrict__ w, const int* __restrict__ skip) {
+  const int sk = skip ? *skip : 0;  // tested once the partial loads are in flight
+  const int c = threadIdx.x % kRedCols, t = threadIdx.x / kRedCols;
+  const int col = blockIdx.x * kRedCols + c;
+  constexpr int S = 256 / kRedCols;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  if (col < n) {
+    int g = t;
+    for (; g + 3 * S < G; g += 4 * S) {
+      T v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = part[(size_t)(g + k * S) * ldp + col];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += v[k];
+    }
+    for (; g < G; g += S) acc[0] += part[(size_t)g * ldp + col];
+  }
+  if (sk) return;
+  T s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+  for (int off = 32; off >= kRedCols; off >>= 1) s += __shfl_xor(s, off, kWave);
+  __shared__ T sh[4][kRedCols];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane < kRedCols) sh[wave][lane] = s;
+  __syncthreads();
+  if (threadIdx.x < kRedCols && col < n) w[col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+constexpr int kSymBT = 256;  // threads per workgroup of the one-pass sweep (512 measured slower)
+int k0_sym_ldp(int n) { return (n + 63) / 64 * 64; }
+
+template <typename T>
+int k0_sym_max_n() {
+  return 8 * kSymBT * Vec16<T>::n;
+}
+
+template <typename T>
+int k0_sym_grid(int N, int n) {
+  const int U = (n + 1) / 2 + (N - n);
+  const int cap = dev_info().cu_count * tune().sym_wg;
+  return std::max(1, std::min(U, cap));
+}
+
+size_t k0_sym_part_elems(int n) { return (size_t)dev_info().cu_count * kMaxSymWg * k0_sym_ldp(n); }
+
+template <typename T, int BT, int R, bool NT>
+static void launch_sym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const T* M, int ldm, int N, int n,
+                         const T* u, T* part, int ldp, int G, const int* skip) {
+  const dim3 blk(BT);
+  switch (K) {
+    case 1: QPG_LAUNCH((k0_sym_kernel<T, BT, 1, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 2: QPG_LAUNCH((k0_sym_kernel<T, BT, 2, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 4: QPG_LAUNCH((k0_sym_kernel<T, BT, 4, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    default: QPG_LAUNCH((k0_sym_kernel<T, BT, 8, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+  }
+}
+
+template <typename T>
+hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n, const T* u, T* part,
+                               size_t part_elems, const int* skip, const EventPair* ev) {
+  constexpr int VE = Vec16<T>::n;
+  if (n <= 0) return hipSuccess;
+  if (N < n || n > k0_sym_max_n<T>() || ldm < N || ldm % 64 != 0) return hipErrorInvalidValue;
+  const int G = k0_sym_grid<T>(N, n), ldp = k0_sym_ldp(n);
+  if ((size_t)G * ldp > part_elems) return hipErrorInvalidValue;
+  constexpr int CHB = kSymBT * VE;
+  const int kc = (n + CHB - 1) / CHB;
+  const int K = kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+  const dim3 grid(G);
+  const bool nt = tune().ld_nt & 2;
+  if (tune().sym_rows == 2) {
+    if (nt)
+      launch_sym_r<T, kSymBT, 2, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    else
+      launch_sym_r<T, kSymBT, 2, false>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+  } else {
+    if (nt)
+      launch_sym_r<T, kSymBT, 4, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    else
+      launch_sym_r<T, kSymBT, 4, false>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_k0_sym_reduce(hipStream_t st, int N, int n, const T* part, T* w, const int* skip,
+                                const EventPair* ev) {
+  if (n <= 0) return hipSuccess;
+  const int G = k0_sym_grid<T>(N, n), ldp = k0_sym_ldp(n);
+  QPG_LAUNCH(k0_sym_reduce_kernel<T>, dim3((n + kRedCols - 1) / kRedCols), dim3(256), 0u, st, ev, part, ldp, G, n,
+             w, skip);
+  return hipGetLastError();
+}
+
 // ---- transposes ---------------------------------------------------------------
 // dst = src^T (src rows x cols, row-major), optionally rounded to float32;
 // 32 x 32 tiles through LDS so both sides are coalesced.
@@ -507,7 +736,12 @@ hipError_t btranspose_2d(hipStream_t st, const TransDesc* d, int count, int max_
   template hipError_t launch_bgemv_rows<T>(hipStream_t, const RowsDesc<T>*, const int*, int, int, size_t, int,    \
                                            const EventPair*);                                                     \
   template hipError_t launch_bgemv_cols<T>(hipStream_t, const ColsDesc<T>*, const int*, int, const int*, int,     \
-                                           int, int, const EventPair*);
+                                           int, int, const EventPair*);                                           \
+  template int k0_sym_max_n<T>();                                                                                 \
+  template int k0_sym_grid<T>(int, int);                                                                          \
+  template hipError_t launch_k0_sym_sweep<T>(hipStream_t, const T*, int, int, int, const T*, T*, size_t,          \
+                                             const int*, const EventPair*);                                      \
+  template hipError_t launch_k0_sym_reduce<T>(hipStream_t, int, int, const T*, T*, const int*, const EventPair*);
 QPG_GEMV_INST(double)
 QPG_GEMV_INST(float)
 

@@ -49,10 +49,19 @@ __device__ __forceinline__ float dot16<v4f_t, float>(const v4f_t& a, const float
   return a.x * x[0] + a.y * x[1] + a.z * x[2] + a.w * x[3];
 }
 
+template <typename V, bool NT>
+__device__ __forceinline__ V ld16(const V* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 // Dot product of one matrix row (len elements, already rounded to whole
 // 64-lane x 16-byte chunks, zeros past the true length) with x staged in LDS.
 // Returns the full sum in every lane.
-template <typename T, int U = 4>
+// NT: non-temporal matrix loads (streamed past the caches) or plain loads.
+template <typename T, int U = 4, bool NT = true>
 __device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int lenR, int lane) {
   using V = typename Vec16<T>::type;
   constexpr int VE = Vec16<T>::n;
@@ -63,12 +72,12 @@ __device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int l
   for (; j + (U - 1) * CH < lenR; j += U * CH) {
     V v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(av + (j + u * CH) / VE);
+    for (int u = 0; u < U; ++u) v[u] = ld16<V, NT>(av + (j + u * CH) / VE);
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u % 4] += dot16<V, T>(v[u], xs + j + u * CH);
   }
   for (; j < lenR; j += CH) {
-    V v0 = __builtin_nontemporal_load(av + j / VE);
+    V v0 = ld16<V, NT>(av + j / VE);
     acc[0] += dot16<V, T>(v0, xs + j);
   }
   return wave_sum<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
@@ -76,7 +85,7 @@ __device__ __forceinline__ T row_dot(const T* __restrict__ a, const T* xs, int l
 
 // Same dot product with x read from global memory (through the caches) as
 // 16-byte vectors; elements of x at or past xlen read as zero.
-template <typename T, int U = 4>
+template <typename T, int U = 4, bool NT = true>
 __device__ __forceinline__ T row_dot_gx(const T* __restrict__ a, const T* __restrict__ x, int lenR, int xlen,
                                         int lane) {
   using V = typename Vec16<T>::type;
@@ -99,14 +108,14 @@ __device__ __forceinline__ T row_dot_gx(const T* __restrict__ a, const T* __rest
     T t[U][VE];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = __builtin_nontemporal_load(av + (j + u * CH) / VE);
+      v[u] = ld16<V, NT>(av + (j + u * CH) / VE);
       xload(j + u * CH, t[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u % 4] += dot16<V, T>(v[u], t[u]);
   }
   for (; j < lenR; j += CH) {
-    V v0 = __builtin_nontemporal_load(av + j / VE);
+    V v0 = ld16<V, NT>(av + j / VE);
     T t[VE];
     xload(j, t);
     acc[0] += dot16<V, T>(v0, t);

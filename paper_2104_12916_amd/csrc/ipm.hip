@@ -1,4 +1,4 @@
-// FP64 vector kernels of the outer interior point iteration (Sec. 2 and 3):
+// FP64 vector kernels of the outer interior point iteration (Sec. 2 and 4):
 // residuals of eq. rhs-KKT4 with the statistics of the relative KKT score, the
 // reduced right-hand side r_nu (eq. ineq-const-reduced) and D = V^{-1} S
 // (eq. diag-d), the recovered directions (eqs. schur-delta-x, delz), and the

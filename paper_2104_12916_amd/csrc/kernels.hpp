@@ -23,6 +23,21 @@ int gemv_rows_grid(int m);
 template <typename T>
 size_t rows_smem_bytes(int m, int k, int shape, int lda);
 size_t gemv_cols_part_elems(int max_ld);
+// one-pass w = M^T Sigma M u (M = L^{-1}[:, :n], N x n lower trapezoid, Sigma =
+// diag(I_n, -I_{N-n})): the sweep writes one partial of w per workgroup into
+// part (G x k0_sym_ldp(n)), the reduce adds them in workgroup order into w
+template <typename T>
+int k0_sym_max_n();
+template <typename T>
+int k0_sym_grid(int N, int n);
+int k0_sym_ldp(int n);
+size_t k0_sym_part_elems(int n);  // partial elements for any tune().sym_wg
+template <typename T>
+hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n, const T* u, T* part,
+                               size_t part_elems, const int* skip, const EventPair* ev = nullptr);
+template <typename T>
+hipError_t launch_k0_sym_reduce(hipStream_t st, int N, int n, const T* part, T* w, const int* skip,
+                                const EventPair* ev = nullptr);
 template <typename T>
 size_t gemv_cols_need(int m, int k);   // single-problem launch shape
 template <typename T>

@@ -82,15 +82,25 @@ __device__ __forceinline__ void init_body(int m2, const T* __restrict__ b, const
 template <typename T, int U>
 __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2, int n, const T* __restrict__ w,
                                        const T* __restrict__ dvec, const T* __restrict__ p, T* __restrict__ q,
-                                       double* __restrict__ bpart, int bid, int nb, T* ws, int stage) {
+                                       double* __restrict__ bpart, int bid, int nb, T* ws, int stage,
+                                       const int* __restrict__ done, int nt = 1) {
+  // the stop flag (the same for every workgroup) is tested once the first
+  // row's loads are in flight; a stopped solve leaves q and bpart untouched
+  const int sk = *done;
   __shared__ double sh[16];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
   const int lenR = round_chunk<T>(n, ldc);
   if (stage) stage_x<T>(ws, w, n, lenR);  // else w is read through the caches
   double pq = 0;
   for (int i = bid * waves + wave; i < m2; i += nb * waves) {
-    T v = stage ? row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane)
+    T v;
+    if (nt)
+      v = stage ? row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane)
                 : row_dot_gx<T, U>(C + (size_t)i * ldc, w, lenR, n, lane);
+    else
+      v = stage ? row_dot<T, U, false>(C + (size_t)i * ldc, ws, lenR, lane)
+                : row_dot_gx<T, U, false>(C + (size_t)i * ldc, w, lenR, n, lane);
+    if (sk) return;
     if (lane == 0) {
       T pi = p[i];
       T qi = v + dvec[i] * pi;
@@ -98,6 +108,7 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
       pq += (double)pi * qi;
     }
   }
+  if (sk) return;  // waves without rows
   pq = block_sum<double>(pq, sh);
   if (threadIdx.x == 0) bpart[bid] = pq;
 }
@@ -128,6 +139,23 @@ __device__ __forceinline__ void update_elem(int i, T a, const T* __restrict__ dv
 }
 
 template <typename T>
+__device__ __forceinline__ void update_elem_pre(int i, T a, T di, T pi, T qi, T xi, T ri0, T wi, T* __restrict__ x,
+                                                T* __restrict__ r, T* __restrict__ z, bool has_w, int prec,
+                                                double& rr, double& wm, double& rz, T& zi) {
+  const T ri = ri0 - a * qi;
+  x[i] = xi + a * pi;
+  r[i] = ri;
+  rr += (double)ri * ri;
+  if (has_w) wm = fmax(wm, fabs((double)wi * ri));
+  if (prec != kPrecH) {
+    zi = (prec == kPrecL) ? ri / di : ri;
+    z[i] = zi;
+    rz += (double)ri * zi;
+  }
+}
+
+// Stops at once (before any write) when the solve's stop flag is set.
+template <typename T>
 __device__ __forceinline__ void update_body(int m2, int nparts, const double* __restrict__ bpart,
                                             const T* __restrict__ dvec, T* __restrict__ p, const T* __restrict__ q,
                                             T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
@@ -136,8 +164,28 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   __shared__ double sh3[3][16];
   __shared__ double alpha_s, beta_s;
   __shared__ int stop_s;
+  const int bd = blockDim.x;
+  const bool keep = m2 <= kKeep * bd;
+  // every load of the step is issued before the first wait: the stop flag, the
+  // p^T q partials and (when they fit in registers) this thread's entries
+  const int done0 = sc->done;
   double s = 0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) s += bpart[b];
+  for (int b = threadIdx.x; b < nparts; b += bd) s += bpart[b];
+  T pd[kKeep], pp[kKeep], pq_[kKeep], px[kKeep], pr[kKeep], pw[kKeep];
+  if (keep) {
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+      const int i = threadIdx.x + k * bd;
+      const bool in = i < m2;
+      pp[k] = in ? p[i] : T(0);
+      pq_[k] = in ? q[i] : T(0);
+      px[k] = in ? x[i] : T(0);
+      pr[k] = in ? r[i] : T(0);
+      pd[k] = (in && prec == kPrecL) ? dvec[i] : T(1);
+      pw[k] = (in && wts) ? wts[i] : T(0);
+    }
+  }
+  if (done0) return;
   const double pq = block_sum<double>(s, sh);
   if (threadIdx.x == 0) {
     sc->pq = pq;
@@ -154,14 +202,15 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   if (stop_s) return;
   const T a = (T)alpha_s;
   double rr = 0, rz = 0, wm = 0;
-  const int bd = blockDim.x;
-  const bool keep = m2 <= kKeep * bd;
   T zk[kKeep], pk[kKeep];
   if (keep) {
 #pragma unroll
     for (int k = 0; k < kKeep; ++k) {
       const int i = threadIdx.x + k * bd;
-      if (i < m2) update_elem<T>(i, a, dvec, p, q, x, r, z, wts, prec, rr, wm, rz, zk[k], pk[k]);
+      pk[k] = pp[k];
+      if (i < m2)
+        update_elem_pre<T>(i, a, pd[k], pp[k], pq_[k], px[k], pr[k], pw[k], x, r, z, wts != nullptr, prec, rr, wm, rz,
+                           zk[k]);
     }
   } else {
     T zi, pi;
@@ -227,10 +276,10 @@ __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int
                                                     const T* __restrict__ w, const T* __restrict__ dvec,
                                                     const T* __restrict__ p, T* __restrict__ q,
                                                     const PcgScalars* __restrict__ sc, double* __restrict__ bpart,
-                                                    int stage) {
-  if (sc->done) return;
+                                                    int stage, int nt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  q_body<T, U>(C, ldc, m2, n, w, dvec, p, q, bpart, blockIdx.x, gridDim.x, reinterpret_cast<T*>(smem_raw), stage);
+  q_body<T, U>(C, ldc, m2, n, w, dvec, p, q, bpart, blockIdx.x, gridDim.x, reinterpret_cast<T*>(smem_raw), stage,
+               &sc->done, nt);
 }
 
 template <typename T>
@@ -240,7 +289,6 @@ __global__ void __launch_bounds__(kUpd) pcg_update_kernel(int m2, int nparts, co
                                                           T* __restrict__ r, T* __restrict__ z,
                                                           const T* __restrict__ wts, int prec,
                                                           PcgScalars* __restrict__ sc) {
-  if (sc->done) return;
   update_body<T>(m2, nparts, bpart, dvec, p, q, x, r, z, wts, prec, sc);
 }
 
@@ -266,16 +314,14 @@ __global__ void __launch_bounds__(256) bpcg_q_kernel(const PcgDesc<T>* __restric
                                                      const int* __restrict__ prefix, int ndesc) {
   const int j = desc_of_block(prefix, ndesc, blockIdx.x);
   const PcgDesc<T> d = descs[j];
-  if (d.sc->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   q_body<T, U>(d.C, d.ldc, d.m2, d.n, d.w, d.dvec, d.p, d.q, d.bpart, blockIdx.x - prefix[j], d.qblocks,
-               reinterpret_cast<T*>(smem_raw), d.stage);
+               reinterpret_cast<T*>(smem_raw), d.stage, &d.sc->done);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kUpd) bpcg_update_kernel(const PcgDesc<T>* __restrict__ descs) {
   const PcgDesc<T> d = descs[blockIdx.x];
-  if (d.sc->done) return;
   update_body<T>(d.m2, d.qblocks, d.bpart, d.dvec, d.p, d.q, d.x, d.r, d.z, d.wts, d.prec, d.sc);
 }
 
@@ -308,12 +354,13 @@ hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w,
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   const int grid = pcg_q_grid<T>(m2);
   if (grid > bpart_cap) return hipErrorInvalidValue;
+  const int nt = tune().ld_nt & 1;
   if (tune().rows_unroll == 8)
     QPG_LAUNCH((pcg_q_kernel<T, 8>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
-               bpart, stage);
+               bpart, stage, nt);
   else
     QPG_LAUNCH((pcg_q_kernel<T, 4>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
-               bpart, stage);
+               bpart, stage, nt);
   return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ def main():
     torch.cuda.synchronize()
     print(f"copy kernel: {COPY_BYTES} bytes read, {COPY_BYTES} bytes written", flush=True)
     names = ["C^T p", "Sigma M u", "M^T v", "C w", "CG step"]
+    if s.k0_one_pass():
+        names[1:3] = ["one-pass M^T Sigma M u sweep", "sum of its partials"]
     for op in range(5):
         ms = s.op_time(op, qpgpu.QP_MIXED if mixed else qpgpu.QP_FP64, args.reps)
         print(f"op {op} ({names[op]}): {ms * 1e3:.2f} us per launch", flush=True)

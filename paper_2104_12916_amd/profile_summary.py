@@ -29,6 +29,8 @@ SWEEPS = {
     "C^T": ("qpg::gemv_rows_kernel<double, 1,", "qpg::gemv_cols_part_kernel<double, 1,"),
     "M": ("qpg::gemv_rows_kernel<double, 2,",),
     "M^T": ("qpg::gemv_rows_kernel<double, 3,", "qpg::gemv_cols_part_kernel<double, 3,"),
+    "M1": ("qpg::k0_sym_kernel<double,",),          # one pass over M: M^T Sigma M u
+    "M1red": ("qpg::k0_sym_reduce_kernel<double>",),  # sum of its per-workgroup partials
     "q": ("qpg::pcg_q_kernel<double,",),
 }
 
@@ -46,7 +48,8 @@ def algorithmic_bytes(n, m1, m2, elem=8):
     """Matrix bytes one launch of each sweep must read: C is m2 x n, M = L^{-1}[:, :n]
     is the lower trapezoid of n(n+1)/2 + m1 n entries."""
     mm = n * (n + 1) // 2 + m1 * n
-    return {"C^T": m2 * n * elem, "M": mm * elem, "M^T": mm * elem, "q": m2 * n * elem}
+    return {"C^T": m2 * n * elem, "M": mm * elem, "M^T": mm * elem, "M1": mm * elem, "M1red": 0,
+            "q": m2 * n * elem}
 
 
 def _short(name):

@@ -27,6 +27,7 @@ EXPORTS = (
     "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
     "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
+    "qp_k0_one_pass",
 )
 
 
@@ -77,6 +78,8 @@ def lib():
     L.qp_ipm_solve.argtypes = [P, P, P, P, P, I, ct.POINTER(qp_ipm_info)]
     L.qp_op_time.argtypes = [P, I, I, I, ct.POINTER(D)]
     L.qp_profile_get.argtypes = [P, ct.POINTER(D), ct.POINTER(ct.c_longlong), I]
+    L.qp_k0_one_pass.argtypes = [P]
+    L.qp_k0_one_pass.restype = I
     L.qp_ctx_bytes.argtypes = [P]
     L.qp_ctx_bytes.restype = ct.c_size_t
     L.qp_destroy.argtypes = [P]
@@ -407,6 +410,10 @@ class Solver:
         st, ms, cnt = qp_profile_get(self.ctx, reset)
         self.check(st)
         return ms, cnt
+
+    def k0_one_pass(self):
+        """True if the CG step forms M^T Sigma M u in one pass over M."""
+        return bool(lib().qp_k0_one_pass(self.ctx))
 
     def bytes(self):
         return qp_ctx_bytes(self.ctx)

@@ -2,7 +2,7 @@
 
 Each test ties one oracle function to the mathematics or to the paper:
 brute-force active sets, a closed-form box QP, exact reformulation identities
-(Sec. 3.1), the rank lemmas and spectral theorems (Sec. 3.3), the CG iteration
+(Sec. 4.1), the rank lemmas and spectral theorems (Sec. 4.3), the CG iteration
 corollaries, the inertia of F and generator determinism.  The mutation tests at
 the end plant plausible mistakes in the oracle and check that a pin catches them.
 """
@@ -99,7 +99,7 @@ def test_oracle_reaches_kkt_tolerance_small_workload(seed):
     assert r.obj <= kkt.objective(qp, qp.x0) + 1e-9
 
 
-# --- P4 exact reformulation (Sec. 3.1) ------------------------------------------
+# --- P4 exact reformulation (Sec. 4.1) ------------------------------------------
 def _state(qp, seed):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(qp.n)
