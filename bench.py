@@ -160,6 +160,8 @@ def batch_roofline(prof, elem):
     names = ["bgemv_rows_kernel<T,1> (C^T p over stored C^T)", "bgemv_rows_kernel<T,2> (Sigma M u)",
              "bgemv_rows_kernel<T,3> (M^T v over stored M^T)", "bpcg_q_kernel<T> (C w + D p)",
              "bgemv_rows_kernel<T,4> (X_P r)", "bgemv_cols_part_kernel<T,5> (X_P^T t)"]
+    if cnt[1] > 0 and by[2] == 0:  # one pass over M: slot 1 is that sweep (its partial sums carry no matrix bytes)
+        names[1] = "bk0_sym_kernel<T> (M^T Sigma M u, one pass over M)"
     ops = {}
     for o in range(6):
         if cnt[o] > 0 and ms[o] > 0:

@@ -339,7 +339,9 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
   if (op_transposed(ctx)) D(ctx->CT, (size_t)n * ctx->ldm2);
   if (store_mt(ctx)) D(ctx->MT, (size_t)n * ctx->ldN);
   if (op_fused(ctx)) {
-    ctx->sympart_bytes = k0_sym_part_elems(n) * sizeof(double);
+    // stand-alone: any single-launch grid; batch member: its share of a batched launch
+    const size_t elems = ctx->pooled ? (size_t)bk0_sym_grid<double>(N, n) * k0_sym_ldp(n) : k0_sym_part_elems(n);
+    ctx->sympart_bytes = elems * sizeof(double);
     ctx->sympart = get(ctx->sympart_bytes);
   }
   if (need_ph) {

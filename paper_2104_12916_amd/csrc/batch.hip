@@ -214,14 +214,17 @@ struct StepLists {
   std::vector<ColsDesc<T>> c1, c3, c5;  // C^T p, M^T v, X_P^T t as column sweeps
   std::vector<RowsDesc<T>> r1, r2, r3, r4;  // C^T p and M^T v over stored transposes; Sigma M u, X_P r
   std::vector<PcgDesc<T>> pd, ph;       // all solves; the P_H ones
-  std::vector<int> c1p, c1r, c3p, c3r, c5p, c5r, r1p, r2p, r3p, r4p, qp;
+  std::vector<SymDesc<T>> sy;           // one-pass M^T Sigma M u
+  std::vector<int> c1p, c1r, c3p, c3r, c5p, c5r, r1p, r2p, r3p, r4p, qp, syp, syr;
   int c1pt = 0, c1rt = 0, c3pt = 0, c3rt = 0, c5pt = 0, c5rt = 0, r1t = 0, r2t = 0, r3t = 0, r4t = 0, qt = 0;
+  int sypt = 0, syrt = 0, syK = 1;
   size_t r1smem = 0, r2smem = 0, r3smem = 0, r4smem = 0, qsmem = 0;
   // device addresses after upload
   const ColsDesc<T>*dc1, *dc3, *dc5;
   const RowsDesc<T>*dr1, *dr2, *dr3, *dr4;
   const PcgDesc<T>*dpd, *dph;
-  const int *dc1p, *dc1r, *dc3p, *dc3r, *dc5p, *dc5r, *dr1p, *dr2p, *dr3p, *dr4p, *dqp;
+  const SymDesc<T>* dsy;
+  const int *dc1p, *dc1r, *dc3p, *dc3r, *dc5p, *dc5r, *dr1p, *dr2p, *dr3p, *dr4p, *dqp, *dsyp, *dsyr;
 };
 
 template <typename T>
@@ -238,6 +241,26 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     RowsDesc<T> rd;
     GemvWork<T> wk = *b.wk;
     if (expl) goto pcg_desc;  // q = E p + D p: only the fused row sweep
+    if (op_transposed(c) && op_fused(c)) {  // u = C^T p, then w = M^T Sigma M u in one pass
+      fill_rows_desc<T>(rd, b.CT, c->ldm2, n, m2, kDense, b.p, b.u, T(1), T(0), nullptr, n, skip);
+      L.r1p.push_back(L.r1t);
+      L.r1t += rd.nblocks;
+      L.r1.push_back(rd);
+      L.r1smem = std::max(L.r1smem, rows_smem_bytes<T>(n, m2, kDense, c->ldm2));
+      SymDesc<T> sd;
+      if (!fill_sym_desc<T>(sd, b.Linv, c->ldN, N, n, b.u, b.w, static_cast<T*>(c->sympart),
+                            c->sympart_bytes / sizeof(T), skip)) {
+        set_err(sk, "one-pass K0 product does not fit its workspace (N=%d n=%d)", N, n);
+        throw Fail{QP_E_DEVICE};
+      }
+      L.syp.push_back(L.sypt);
+      L.syr.push_back(L.syrt);
+      L.sypt += sd.G;
+      L.syrt += sd.rblocks;
+      L.syK = std::max(L.syK, k0_sym_width<T>(n));
+      L.sy.push_back(sd);
+      goto pcg_desc;
+    }
     if (op_transposed(c)) {   // u = C^T p, v = Sigma M u, w = M^T v: three row sweeps
       fill_rows_desc<T>(rd, b.CT, c->ldm2, n, m2, kDense, b.p, b.u, T(1), T(0), nullptr, n, skip);
       L.r1p.push_back(L.r1t);
@@ -330,10 +353,14 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
   Packer pk;
   auto V = [&](auto& v) { return pk.add(v.data(), v.size() * sizeof(v[0])); };
   size_t o_c1 = V(L.c1), o_c3 = V(L.c3), o_c5 = V(L.c5), o_r1 = V(L.r1), o_r2 = V(L.r2), o_r3 = V(L.r3),
-         o_r4 = V(L.r4), o_pd = V(L.pd), o_ph = V(L.ph);
+         o_r4 = V(L.r4), o_pd = V(L.pd), o_ph = V(L.ph), o_sy = V(L.sy);
   size_t o_c1p = V(L.c1p), o_c1r = V(L.c1r), o_c3p = V(L.c3p), o_c3r = V(L.c3r), o_c5p = V(L.c5p),
-         o_c5r = V(L.c5r), o_r1p = V(L.r1p), o_r2p = V(L.r2p), o_r3p = V(L.r3p), o_r4p = V(L.r4p), o_qp = V(L.qp);
+         o_c5r = V(L.c5r), o_r1p = V(L.r1p), o_r2p = V(L.r2p), o_r3p = V(L.r3p), o_r4p = V(L.r4p), o_qp = V(L.qp),
+         o_syp = V(L.syp), o_syr = V(L.syr);
   const char* base = stage_upload(B, pk);
+  L.dsy = reinterpret_cast<const SymDesc<T>*>(base + o_sy);
+  L.dsyp = reinterpret_cast<const int*>(base + o_syp);
+  L.dsyr = reinterpret_cast<const int*>(base + o_syr);
   L.dc1 = reinterpret_cast<const ColsDesc<T>*>(base + o_c1);
   L.dc3 = reinterpret_cast<const ColsDesc<T>*>(base + o_c3);
   L.dc5 = reinterpret_cast<const ColsDesc<T>*>(base + o_c5);
@@ -810,10 +837,10 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
     qp_ctx* c = s->ctx;
     if (!op_transposed(c)) continue;
     tr.push_back(TransDesc{c->C, c->CT, c->ldn, c->ldm2, c->m2, c->n, 0});
-    tr.push_back(TransDesc{c->Linv, c->MT, c->ldN, c->ldN, c->N, c->n, 0});
+    if (store_mt(c)) tr.push_back(TransDesc{c->Linv, c->MT, c->ldN, c->ldN, c->N, c->n, 0});
     if (c->opt.precision == QP_MIXED) {
       tr.push_back(TransDesc{c->C, c->CT32, c->ldn, c->ldm2, c->m2, c->n, 1});
-      tr.push_back(TransDesc{c->Linv, c->MT32, c->ldN, c->ldN, c->N, c->n, 1});
+      if (store_mt(c)) tr.push_back(TransDesc{c->Linv, c->MT32, c->ldN, c->ldN, c->N, c->n, 1});
     }
     tr_rows = std::max(tr_rows, c->N);
     tr_cols = std::max(tr_cols, c->n);
@@ -993,12 +1020,18 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
     const EventPair* ev = (sample && k == 0) ? B->prof_ev : nullptr;
     // lists are empty where they do not apply (explicit operators; transposes or not)
     const int n1 = (int)L.c1.size(), n2 = (int)L.r2.size(), n3 = (int)L.c3.size();
-    const int t1 = (int)L.r1.size(), t3 = (int)L.r3.size();
+    const int t1 = (int)L.r1.size(), t3 = (int)L.r3.size(), ns = (int)L.sy.size();
+    // profile slots 1 and 2: the one-pass sweep and its reduce when the list has
+    // one-pass QPs, else the two triangular sweeps
+    const EventPair* e1 = ev && !ns ? &ev[1] : nullptr;
+    const EventPair* e2 = ev && !ns ? &ev[2] : nullptr;
     HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc1, L.dc1p, L.c1pt, L.dc1r, L.c1rt, n1, 1, ev && n1 ? &ev[0] : nullptr));
     HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr1, L.dr1p, t1, L.r1t, L.r1smem, 1, ev && t1 ? &ev[0] : nullptr));
-    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, n2, L.r2t, L.r2smem, 2, ev ? &ev[1] : nullptr));
-    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, n3, 3, ev && n3 ? &ev[2] : nullptr));
-    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr3, L.dr3p, t3, L.r3t, L.r3smem, 3, ev && t3 ? &ev[2] : nullptr));
+    HIPCHK(sk, launch_bk0_sym<T>(B->stream, L.dsy, L.dsyp, L.sypt, L.dsyr, L.syrt, ns, L.syK, ev ? &ev[1] : nullptr,
+                                 ev ? &ev[2] : nullptr));
+    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr2, L.dr2p, n2, L.r2t, L.r2smem, 2, e1));
+    HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc3, L.dc3p, L.c3pt, L.dc3r, L.c3rt, n3, 3, e2 && n3 ? e2 : nullptr));
+    HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr3, L.dr3p, t3, L.r3t, L.r3smem, 3, e2 && t3 ? e2 : nullptr));
     HIPCHK(sk, bpcg_q<T>(B->stream, L.dpd, L.dqp, na, L.qt, L.qsmem, ev ? &ev[3] : nullptr));
     HIPCHK(sk, bpcg_update<T>(B->stream, L.dpd, na));
     launch_ph_apply<T>(B, L, 0, ev);
@@ -1015,7 +1048,7 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
       } else {
         B->prof_pending_bytes[0] += cn * sizeof(T);
         B->prof_pending_bytes[1] += mn * sizeof(T);
-        B->prof_pending_bytes[2] += mn * sizeof(T);
+        if (!op_fused(c)) B->prof_pending_bytes[2] += mn * sizeof(T);  // the one pass reads M once
         B->prof_pending_bytes[3] += cn * sizeof(T);
       }
       if (s->R.prec == kPrecH) {

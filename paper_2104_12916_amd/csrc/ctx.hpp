@@ -181,10 +181,10 @@ void factor(qp_ctx* ctx);
 inline bool kf_explicit(const qp_ctx* ctx) { return ctx->opt.kf_form == QP_KF_EXPLICIT; }
 // The implicit CG step reads the stored transposes (C^T, M^T) with row sweeps.
 inline bool op_transposed(const qp_ctx* ctx) { return tune().op_t && !kf_explicit(ctx); }
-// The implicit CG step forms M^T Sigma M u in one pass over M (stand-alone
-// contexts whose n fits the register rows of the one-pass sweep); M^T is not stored.
+// The implicit CG step forms M^T Sigma M u in one pass over M (n small enough
+// for the register rows of the one-pass sweep); M^T is then not stored.
 inline bool op_fused(const qp_ctx* ctx) {
-  return tune().k0_sym && !kf_explicit(ctx) && !ctx->pooled && ctx->n <= k0_sym_max_n<double>();
+  return tune().k0_sym && !kf_explicit(ctx) && ctx->n <= k0_sym_max_n<double>();
 }
 inline bool store_mt(const qp_ctx* ctx) { return op_transposed(ctx) && !op_fused(ctx); }
 void ph_setup(qp_ctx* ctx);

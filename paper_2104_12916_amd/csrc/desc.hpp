@@ -37,6 +37,19 @@ struct ColsDesc {
   int rblocks;              // second pass: ceil(k / 16)
 };
 
+// One-pass w = M^T Sigma M u of one QP: G workgroups write partials
+// part[g * ldp + j] (j < n), then rblocks workgroups add them into w.
+template <typename T>
+struct SymDesc {
+  const T* M;      // L^{-1} (N x ldm); its first n columns are M
+  const T* u;
+  T* w;
+  T* part;
+  const int* skip;
+  int ldm, N, n, ldp, G;
+  int rblocks;     // ceil(n / 16)
+};
+
 // One CG solve of the reduced system (the vectors of one QP).
 template <typename T>
 struct PcgDesc {

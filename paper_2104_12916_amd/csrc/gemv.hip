@@ -479,17 +479,17 @@ __device__ __forceinline__ int sym_row(int q, int u0, int np, int us, int n) {
   return uu < tri ? uu : n + (uu - tri);
 }
 
+// Workgroup g of G of one product.
 template <typename T, int BT, int K, int R, bool NT>
-__global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
-                                                    const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
-                                                    const int* __restrict__ skip) {
+__device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, int N, int n, const T* __restrict__ u,
+                                            T* __restrict__ part, int ldp, int G, int g,
+                                            const int* __restrict__ skip) {
   const int sk = skip ? *skip : 0;  // tested after the first round's loads (uniform over the grid)
   using V = typename Vec16<T>::type;
   constexpr int VE = Vec16<T>::n;
   constexpr int CHB = BT * VE;
   constexpr int NW = BT / kWave;
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const int g = blockIdx.x;
   const int P = n / 2, U = (n + 1) / 2 + (N - n);
   const int u0 = (int)((long long)g * U / G), u1 = (int)((long long)(g + 1) * U / G);
   const int np = max(0, min(u1, P) - u0);
@@ -571,12 +571,28 @@ __global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int
 
 // w_j = sum over g of part[g][j]: 16 columns per workgroup, 16 lanes per column
 // take g = t, t + 16, ... with four loads in flight, then a fixed butterfly.
+template <typename T, int BT, int K, int R, bool NT>
+__global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
+                                                    const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
+                                                    const int* __restrict__ skip) {
+  k0_sym_body<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
+}
+
+template <typename T, int BT, int K, int R, bool NT>
+__global__ void __launch_bounds__(BT) bk0_sym_kernel(const SymDesc<T>* __restrict__ descs,
+                                                     const int* __restrict__ prefix, int ndesc) {
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const SymDesc<T> d = descs[j];
+  k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j], d.skip);
+}
+
+// Columns grp*16 .. +15 of w = sum over g of part[g].
 template <typename T>
-__global__ void __launch_bounds__(256) k0_sym_reduce_kernel(const T* __restrict__ part, int ldp, int G, int n,
-                                                            T* __restrict__ w, const int* __restrict__ skip) {
+__device__ __forceinline__ void k0_sym_reduce_body(const T* __restrict__ part, int ldp, int G, int n,
+                                                   T* __restrict__ w, const int* __restrict__ skip, int grp) {
   const int sk = skip ? *skip : 0;  // tested once the partial loads are in flight
   const int c = threadIdx.x % kRedCols, t = threadIdx.x / kRedCols;
-  const int col = blockIdx.x * kRedCols + c;
+  const int col = grp * kRedCols + c;
   constexpr int S = 256 / kRedCols;
   T acc[4] = {T(0), T(0), T(0), T(0)};
   if (col < n) {
@@ -599,6 +615,20 @@ __global__ void __launch_bounds__(256) k0_sym_reduce_kernel(const T* __restrict_
   if (lane < kRedCols) sh[wave][lane] = s;
   __syncthreads();
   if (threadIdx.x < kRedCols && col < n) w[col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k0_sym_reduce_kernel(const T* __restrict__ part, int ldp, int G, int n,
+                                                            T* __restrict__ w, const int* __restrict__ skip) {
+  k0_sym_reduce_body<T>(part, ldp, G, n, w, skip, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) bk0_sym_reduce_kernel(const SymDesc<T>* __restrict__ descs,
+                                                             const int* __restrict__ prefix, int ndesc) {
+  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
+  const SymDesc<T> d = descs[j];
+  k0_sym_reduce_body<T>(d.part, d.ldp, d.G, d.n, d.w, d.skip, blockIdx.x - prefix[j]);
 }
 
 constexpr int kSymBT = 256;  // threads per workgroup of the one-pass sweep (512 measured slower)
@@ -638,9 +668,7 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
   if (N < n || n > k0_sym_max_n<T>() || ldm < N || ldm % 64 != 0) return hipErrorInvalidValue;
   const int G = k0_sym_grid<T>(N, n), ldp = k0_sym_ldp(n);
   if ((size_t)G * ldp > part_elems) return hipErrorInvalidValue;
-  constexpr int CHB = kSymBT * VE;
-  const int kc = (n + CHB - 1) / CHB;
-  const int K = kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+  const int K = k0_sym_width<T>(n);
   const dim3 grid(G);
   const bool nt = tune().ld_nt & 2;
   if (tune().sym_rows == 2) {
@@ -654,6 +682,71 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
     else
       launch_sym_r<T, kSymBT, 4, false>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
   }
+  return hipGetLastError();
+}
+
+// Batched forms: each QP gets about one workgroup per kSymUnitsPerWg row units
+// (many QPs share the launch), which keeps its partials near 1/16 of M.
+constexpr int kSymUnitsPerWg = 16;
+
+template <typename T>
+int bk0_sym_grid(int N, int n) {
+  const int U = (n + 1) / 2 + (N - n);
+  return std::max(1, (U + kSymUnitsPerWg - 1) / kSymUnitsPerWg);
+}
+
+template <typename T>
+int k0_sym_width(int n) {
+  constexpr int CHB = kSymBT * Vec16<T>::n;
+  const int kc = (n + CHB - 1) / CHB;
+  return kc <= 1 ? 1 : kc <= 2 ? 2 : kc <= 4 ? 4 : 8;
+}
+
+template <typename T>
+bool fill_sym_desc(SymDesc<T>& d, const T* M, int ldm, int N, int n, const T* u, T* w, T* part, size_t part_elems,
+                   const int* skip) {
+  d.M = M;
+  d.ldm = ldm;
+  d.N = N;
+  d.n = n;
+  d.u = u;
+  d.w = w;
+  d.part = part;
+  d.ldp = k0_sym_ldp(n);
+  d.G = bk0_sym_grid<T>(N, n);
+  d.skip = skip;
+  d.rblocks = (n + kRedCols - 1) / kRedCols;
+  return n > 0 && N >= n && n <= k0_sym_max_n<T>() && ldm >= N && ldm % 64 == 0 &&
+         (size_t)d.G * d.ldp <= part_elems;
+}
+
+template <typename T, int R, bool NT>
+static void launch_bsym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const SymDesc<T>* d,
+                          const int* prefix, int ndesc) {
+  const dim3 blk(kSymBT);
+  switch (K) {
+    case 1: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 1, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    case 2: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 2, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    case 4: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 4, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    default: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 8, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc);
+  }
+}
+
+template <typename T>
+hipError_t launch_bk0_sym(hipStream_t st, const SymDesc<T>* d, const int* prefix_sweep, int total_sweep,
+                          const int* prefix_red, int total_red, int ndesc, int K, const EventPair* ev_sweep,
+                          const EventPair* ev_red) {
+  if (ndesc <= 0 || total_sweep <= 0) return hipSuccess;
+  if (K != 1 && K != 2 && K != 4 && K != 8) return hipErrorInvalidValue;
+  const dim3 grid(total_sweep);
+  if (tune().ld_nt & 2) {
+    if (tune().sym_rows == 2) launch_bsym_r<T, 2, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+    else launch_bsym_r<T, 4, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+  } else {
+    if (tune().sym_rows == 2) launch_bsym_r<T, 2, false>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+    else launch_bsym_r<T, 4, false>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+  }
+  QPG_LAUNCH(bk0_sym_reduce_kernel<T>, dim3(total_red), dim3(256), 0u, st, ev_red, d, prefix_red, ndesc);
   return hipGetLastError();
 }
 
@@ -741,7 +834,12 @@ hipError_t btranspose_2d(hipStream_t st, const TransDesc* d, int count, int max_
   template int k0_sym_grid<T>(int, int);                                                                          \
   template hipError_t launch_k0_sym_sweep<T>(hipStream_t, const T*, int, int, int, const T*, T*, size_t,          \
                                              const int*, const EventPair*);                                      \
-  template hipError_t launch_k0_sym_reduce<T>(hipStream_t, int, int, const T*, T*, const int*, const EventPair*);
+  template hipError_t launch_k0_sym_reduce<T>(hipStream_t, int, int, const T*, T*, const int*, const EventPair*);  \
+  template int bk0_sym_grid<T>(int, int);                                                                         \
+  template int k0_sym_width<T>(int);                                                                              \
+  template bool fill_sym_desc<T>(SymDesc<T>&, const T*, int, int, int, const T*, T*, T*, size_t, const int*);     \
+  template hipError_t launch_bk0_sym<T>(hipStream_t, const SymDesc<T>*, const int*, int, const int*, int, int,    \
+                                        int, const EventPair*, const EventPair*);
 QPG_GEMV_INST(double)
 QPG_GEMV_INST(float)
 

@@ -38,6 +38,19 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
 template <typename T>
 hipError_t launch_k0_sym_reduce(hipStream_t st, int N, int n, const T* part, T* w, const int* skip,
                                 const EventPair* ev = nullptr);
+// batched one-pass product over SymDesc lists: K = register-row width for the
+// widest n of the list (k0_sym_width), workgroups per QP from bk0_sym_grid
+template <typename T>
+int bk0_sym_grid(int N, int n);
+template <typename T>
+int k0_sym_width(int n);
+template <typename T>
+bool fill_sym_desc(SymDesc<T>& d, const T* M, int ldm, int N, int n, const T* u, T* w, T* part, size_t part_elems,
+                   const int* skip);
+template <typename T>
+hipError_t launch_bk0_sym(hipStream_t st, const SymDesc<T>* d, const int* prefix_sweep, int total_sweep,
+                          const int* prefix_red, int total_red, int ndesc, int K, const EventPair* ev_sweep = nullptr,
+                          const EventPair* ev_red = nullptr);
 template <typename T>
 size_t gemv_cols_need(int m, int k);   // single-problem launch shape
 template <typename T>

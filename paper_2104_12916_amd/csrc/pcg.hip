@@ -169,6 +169,8 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   // every load of the step is issued before the first wait: the stop flag, the
   // p^T q partials and (when they fit in registers) this thread's entries
   const int done0 = sc->done;
+  const double rho0 = sc->rho, tol2 = sc->tol2, wtol = sc->wtol;
+  const int iter0 = sc->iter, maxit = sc->maxit;
   double s = 0;
   for (int b = threadIdx.x; b < nparts; b += bd) s += bpart[b];
   T pd[kKeep], pp[kKeep], pq_[kKeep], px[kKeep], pr[kKeep], pw[kKeep];
@@ -194,7 +196,7 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
       stop_s = 1;
     } else {
       stop_s = 0;
-      alpha_s = sc->rho / pq;
+      alpha_s = rho0 / pq;
       sc->alpha = alpha_s;
     }
   }
@@ -218,10 +220,17 @@ __device__ __forceinline__ void update_body(int m2, int nparts, const double* __
   }
   block_sum2_max1(rr, rz, wm, sh3);
   if (threadIdx.x == 0) {
-    pcg_check_stop(sc, rr, wm);
-    stop_s = sc->done;
-    if (!stop_s && prec != kPrecH) {
-      beta_s = rz / sc->rho;
+    // the stop test of pcg_check_stop on the values read at entry
+    int dn = 0;
+    if (rr <= tol2 || (wtol >= 0.0 && wm <= wtol)) dn = 1;
+    else if (iter0 + 1 >= maxit) dn = 2;
+    sc->rr = rr;
+    sc->wmax = wm;
+    sc->iter = iter0 + 1;
+    if (dn) sc->done = dn;
+    stop_s = dn;
+    if (!dn && prec != kPrecH) {
+      beta_s = rz / rho0;
       sc->beta = beta_s;
       sc->rho = rz;
     }
