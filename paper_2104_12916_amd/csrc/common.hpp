@@ -62,6 +62,8 @@ struct Tune {
   int k0_sym = 1;       // one pass over M for M^T Sigma M u (n small enough for register rows)
   int sym_wg = 2;       // one-pass sweep: workgroups per CU (each writes one partial of w)
   int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
+  int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
+                          // 1 us faster per CG step than 1024 at m2 = 2048)
   int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
                         // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
                         // more than the 256 MB last-level cache holds; loading M plainly and C, C^T

@@ -118,7 +118,7 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
 // When every thread holds at most kKeep elements, z and p stay in registers
 // between the two passes.  Per-thread partial sums follow the element order
 // i = tid, tid + blockDim, ... in both branches, so the result is the same.
-constexpr int kKeep = 4;
+// kKeep: entries per thread held in registers (a template parameter of the body).
 
 template <typename T>
 __device__ __forceinline__ void update_elem(int i, T a, const T* __restrict__ dvec, const T* __restrict__ p,
@@ -155,7 +155,7 @@ __device__ __forceinline__ void update_elem_pre(int i, T a, T di, T pi, T qi, T 
 }
 
 // Stops at once (before any write) when the solve's stop flag is set.
-template <typename T>
+template <typename T, int kKeep = 4>
 __device__ __forceinline__ void update_body(int m2, int nparts, const double* __restrict__ bpart,
                                             const T* __restrict__ dvec, T* __restrict__ p, const T* __restrict__ q,
                                             T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
@@ -291,14 +291,14 @@ __global__ void __launch_bounds__(256) pcg_q_kernel(const T* __restrict__ C, int
                &sc->done, nt);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kUpd) pcg_update_kernel(int m2, int nparts, const double* __restrict__ bpart,
-                                                          const T* __restrict__ dvec, T* __restrict__ p,
-                                                          const T* __restrict__ q, T* __restrict__ x,
-                                                          T* __restrict__ r, T* __restrict__ z,
-                                                          const T* __restrict__ wts, int prec,
-                                                          PcgScalars* __restrict__ sc) {
-  update_body<T>(m2, nparts, bpart, dvec, p, q, x, r, z, wts, prec, sc);
+template <typename T, int BD>
+__global__ void __launch_bounds__(BD) pcg_update_kernel(int m2, int nparts, const double* __restrict__ bpart,
+                                                        const T* __restrict__ dvec, T* __restrict__ p,
+                                                        const T* __restrict__ q, T* __restrict__ x,
+                                                        T* __restrict__ r, T* __restrict__ z,
+                                                        const T* __restrict__ wts, int prec,
+                                                        PcgScalars* __restrict__ sc) {
+  update_body<T, (4096 / BD > 4 ? 4096 / BD : 4)>(m2, nparts, bpart, dvec, p, q, x, r, z, wts, prec, sc);
 }
 
 template <typename T>
@@ -376,8 +376,19 @@ hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w,
 template <typename T>
 hipError_t pcg_update(hipStream_t st, int m2, const double* bpart, const T* dvec, T* p, const T* q, T* x, T* r, T* z,
                       const T* wts, int prec, PcgScalars* sc) {
-  hipLaunchKernelGGL(pcg_update_kernel<T>, dim3(1), dim3(kUpd), 0, st, m2, pcg_q_grid<T>(m2), bpart, dvec, p, q, x,
-                     r, z, wts, prec, sc);
+  switch (tune().upd_threads) {
+    case 256:
+      hipLaunchKernelGGL((pcg_update_kernel<T, 256>), dim3(1), dim3(256), 0, st, m2, pcg_q_grid<T>(m2), bpart, dvec,
+                         p, q, x, r, z, wts, prec, sc);
+      break;
+    case 512:
+      hipLaunchKernelGGL((pcg_update_kernel<T, 512>), dim3(1), dim3(512), 0, st, m2, pcg_q_grid<T>(m2), bpart, dvec,
+                         p, q, x, r, z, wts, prec, sc);
+      break;
+    default:
+      hipLaunchKernelGGL((pcg_update_kernel<T, kUpd>), dim3(1), dim3(kUpd), 0, st, m2, pcg_q_grid<T>(m2), bpart,
+                         dvec, p, q, x, r, z, wts, prec, sc);
+  }
   return hipGetLastError();
 }
 
