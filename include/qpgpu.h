@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define QPGPU_ABI_VERSION 2
+#define QPGPU_ABI_VERSION 3
 
 typedef struct qp_ctx qp_ctx;
 
@@ -74,6 +74,13 @@ typedef enum {
 typedef enum { QP_MEM_HOST = 0, QP_MEM_DEVICE = 1 } qp_mem;
 
 typedef enum {
+  QP_PH_EXACT = 0, /* P_H = D + C H^{-1} C^T (eq. preconditioner-2; the default)     */
+  QP_PH_DIAG = 1   /* P_H = D + C diag(H)^{-1} C^T: the form of the PH-KF variant of
+                      the cost models and experiments (Sec. 5.2, Sec. 6); equal to
+                      the exact form when H is diagonal                            */
+} qp_ph_form;
+
+typedef enum {
   QP_KF_IMPLICIT = 0, /* each CG step applies C^T, the K0 inverse factor twice and C
                          (Sec. 4.1, implicit form; the default)                     */
   QP_KF_EXPLICIT = 1  /* K_F - D = C K0^{-1}_{11} C^T (eq. ineq-const-reduced) formed
@@ -95,6 +102,7 @@ typedef struct {
   int profile;      /* 1: time the operator kernels of the first CG step of every
                        poll chunk with HIP events (read with qp_profile_get)     */
   qp_kf_form kf_form; /* how the CG step applies K_F (QP_KF_IMPLICIT)            */
+  qp_ph_form ph_form; /* which H the few-equalities preconditioner uses (EXACT)   */
 } qp_options;
 
 typedef struct {
@@ -196,6 +204,11 @@ qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], in
  * once.  Chosen at qp_create from n (n <= 4096) and the K_F form; 0 otherwise
  * or for NULL. */
 int qp_k0_one_pass(const qp_ctx* ctx);
+
+/* 1 if qp_factor_K0 found C = I (m2 = n; simple bounds x >= d, Sec. 4.2): the CG
+ * step then takes u = p and q = K0^{-1}_{11} p + D p, with no product by C, and
+ * P_H = D + H^{-1}.  0 before qp_factor_K0, otherwise, or for NULL. */
+int qp_c_identity(const qp_ctx* ctx);
 
 /* Device bytes held by the context (all buffers, factor included). */
 size_t qp_ctx_bytes(const qp_ctx* ctx);

@@ -105,6 +105,17 @@ def P_H(qp, dvec):
     return np.diag(dvec) + 0.5 * (T + T.T)
 
 
+def ph_T_diag(qp):
+    """T = C diag(H)^{-1} C^T: the P_H of the PH-KF cost model and experiments (Sec. 5.2)."""
+    return (qp.C / np.diag(qp.H)) @ qp.C.T
+
+
+def P_H_diag(qp, dvec):
+    """P_H with H replaced by its diagonal: D + C diag(H)^{-1} C^T (Sec. 5.2)."""
+    T = ph_T_diag(qp)
+    return np.diag(dvec) + 0.5 * (T + T.T)
+
+
 def preconditioned_eigs(K, P):
     """Eigenvalues of P^{-1/2} K P^{-1/2} (split preconditioning, Sec. 4.3)."""
     w, V = np.linalg.eigh(P)

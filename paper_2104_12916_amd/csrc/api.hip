@@ -242,7 +242,8 @@ qp_status check_problem(int n, int m1, int m2, const double* H, const double* c,
 qp_status check_options(const qp_options& o) {
   if (!(o.tau > 0 && o.tau < 1) || o.max_ipm < 0 || !(o.rtol_kkt > 0) || o.prec < QP_PREC_NONE ||
       o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED) ||
-      (o.kf_form != QP_KF_IMPLICIT && o.kf_form != QP_KF_EXPLICIT))
+      (o.kf_form != QP_KF_IMPLICIT && o.kf_form != QP_KF_EXPLICIT) ||
+      (o.ph_form != QP_PH_EXACT && o.ph_form != QP_PH_DIAG))
     return QP_E_INVALID;
   return QP_OK;
 }
@@ -512,7 +513,10 @@ void factor(qp_ctx* ctx) {
       *p = nullptr;
     }
   };
-  HIPCHK(ctx, hipMemsetAsync(ctx->info, 0, sizeof(int), st));
+  HIPCHK(ctx, hipMemsetAsync(ctx->info, 0, 2 * sizeof(int), st));
+  // info[1]: set when C is not the identity (simple bounds get the C-free CG step)
+  if (ctx->m2 == n)
+    HIPCHK(ctx, matop(st, MatOpDesc{ctx->C, nullptr, nullptr, ctx->info + 1, ldn, 0, 0, ctx->m2, n, kMatIdentity}));
   HIPCHK(ctx, hipMemcpyAsync(Hw, ctx->H, (size_t)n * ldn * sizeof(double), hipMemcpyDeviceToDevice, st));
   double* XH = ctx->Linv;                        // rows 0..n-1, cols 0..n-1
   double* G = ctx->Linv + (size_t)n * ldN;       // rows n..N-1, cols 0..n-1
@@ -522,13 +526,14 @@ void factor(qp_ctx* ctx) {
   // W^T = A X_H^T (m1 x n);  S = W^T W = A H^{-1} A^T (lower)
   HIPCHK(ctx, gemm_f64(st, 0, 1, m1, n, n, 1.0, ctx->A, ldn, XH, ldN, 0.0, Wt, ldn, kBUpper));
   HIPCHK(ctx, gemm_f64(st, 0, 1, m1, m1, n, 1.0, Wt, ldn, Wt, ldn, 0.0, S, ldm1, kOutLower));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->h_info, ctx->info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_info, ctx->info, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   sync(ctx);
   if (*ctx->h_info != 0) {
     set_err(ctx, "Cholesky factorization of H failed: H is not positive definite");
     drop();
     throw Fail{QP_E_NOT_SPD};
   }
+  ctx->c_identity = ctx->m2 == n && ctx->h_info[1] == 0;
   // X_S = L_S^{-1}
   HIPCHK(ctx, chol_inv_f64(st, S, ldm1, XS, ldN, m1, tmp, ctx->info, QP_E_RANK));
   // G = -X_S W^T X_H  (bottom-left block of L^{-1})
@@ -547,13 +552,15 @@ void factor(qp_ctx* ctx) {
     sync(ctx);  // the scratch is about to be released
   }
   drop();
-  if (op_transposed(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT, ctx->ldm2, 0));
+  if (op_transposed(ctx) && !ctx->c_identity)
+    HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT, ctx->ldm2, 0));
   if (store_mt(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT, ldN, 0));
   if (ctx->opt.precision == QP_MIXED) {
     HIPCHK(ctx, (convert_2d<double, float>(st, ctx->Linv, ldN, ctx->Linv32, ldN, N, N)));
     if (kf_explicit(ctx))
       HIPCHK(ctx, (convert_2d<double, float>(st, ctx->E, ctx->ldm2, ctx->E32, ctx->ldm2, ctx->m2, ctx->m2)));
-    if (op_transposed(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT32, ctx->ldm2, 1));
+    if (op_transposed(ctx) && !ctx->c_identity)
+      HIPCHK(ctx, transpose_2d(st, ctx->C, ldn, ctx->m2, n, ctx->CT32, ctx->ldm2, 1));
     if (store_mt(ctx)) HIPCHK(ctx, transpose_2d(st, ctx->Linv, ldN, N, n, ctx->MT32, ldN, 1));
   }
   ctx->factored = true;
@@ -566,7 +573,10 @@ void ph_setup(qp_ctx* ctx) {
   hipStream_t st = ctx->stream;
   const bool own = ctx->fYt == nullptr;
   double* Yt = own ? dalloc<double>(ctx, (size_t)m2 * ctx->ldn) : ctx->fYt;
-  HIPCHK(ctx, gemm_f64(st, 0, 1, m2, n, n, 1.0, ctx->C, ctx->ldn, ctx->Linv, ctx->ldN, 0.0, Yt, ctx->ldn, kBUpper));
+  if (ctx->opt.ph_form == QP_PH_DIAG)  // Y = C diag(H)^{-1/2}
+    HIPCHK(ctx, matop(st, MatOpDesc{ctx->C, ctx->H, Yt, nullptr, ctx->ldn, ctx->ldn, ctx->ldn, m2, n, kMatColScale}));
+  else  // Y = C X_H^T = C L_H^{-T}
+    HIPCHK(ctx, gemm_f64(st, 0, 1, m2, n, n, 1.0, ctx->C, ctx->ldn, ctx->Linv, ctx->ldN, 0.0, Yt, ctx->ldn, kBUpper));
   HIPCHK(ctx, gemm_f64(st, 0, 1, m2, m2, n, 1.0, Yt, ctx->ldn, Yt, ctx->ldn, 0.0, ctx->T, ctx->ldm2, kOutLower));
   sync(ctx);
   if (own) dfree(ctx, Yt);
@@ -645,7 +655,10 @@ template <typename T>
 static void op_sweeps(qp_ctx* ctx, const PcgBufs<T>& B, const int* skip, const EventPair* ev) {
   hipStream_t st = ctx->stream;
   const int n = ctx->n, m2 = ctx->m2, N = ctx->N;
-  if (op_transposed(ctx))
+  const T* u = B.u;
+  if (ctx->c_identity)  // C = I: u = p
+    u = B.p;
+  else if (op_transposed(ctx))
     HIPCHK(ctx, launch_gemv_rows<T>(st, B.CT, ctx->ldm2, n, m2, kDense, B.p, B.u, T(1), T(0), nullptr, n, skip, 1,
                                     ev ? &ev[0] : nullptr));
   else
@@ -653,12 +666,12 @@ static void op_sweeps(qp_ctx* ctx, const PcgBufs<T>& B, const int* skip, const E
                                     ev ? &ev[0] : nullptr));
   if (op_fused(ctx)) {
     T* part = static_cast<T*>(ctx->sympart);
-    HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, N, n, B.u, part, ctx->sympart_bytes / sizeof(T), skip,
+    HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, N, n, u, part, ctx->sympart_bytes / sizeof(T), skip,
                                        ev ? &ev[1] : nullptr));
     HIPCHK(ctx, launch_k0_sym_reduce<T>(st, N, n, part, B.w, skip, ev ? &ev[2] : nullptr));
     return;
   }
-  HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, N, n, kLower, B.u, B.v, T(1), T(0), nullptr, n, skip, 2,
+  HIPCHK(ctx, launch_gemv_rows<T>(st, B.Linv, ctx->ldN, N, n, kLower, u, B.v, T(1), T(0), nullptr, n, skip, 2,
                                   ev ? &ev[1] : nullptr));
   if (op_transposed(ctx))
     HIPCHK(ctx, launch_gemv_rows<T>(st, B.MT, ctx->ldN, n, N, kUpper, B.v, B.w, T(1), T(0), nullptr, n, skip, 3,
@@ -716,8 +729,9 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
                              ev ? &ev[3] : nullptr, tune().qe_stage));
       } else {
         op_sweeps<T>(ctx, B, skip, ev);
-        HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
-                             ev ? &ev[3] : nullptr));
+        // C = I: q = w + D p with no sweep (pcg_q with a null C)
+        HIPCHK(ctx, pcg_q<T>(st, ctx->c_identity ? nullptr : B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc,
+                             ctx->bpart, ctx->bpart_cap, ev ? &ev[3] : nullptr));
       }
       HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc));
       if (prec == kPrecH) ph_apply(0, ev);
@@ -763,6 +777,11 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
     k0_top_apply<double>(ctx, ctx->Linv, ctx->pu, ctx->pv, ctx->pw, ctx->w64, nullptr);
   }
   HIPCHK(ctx, ew_mul(st, ctx->m2, dvec, p, ctx->pt));
+  if (ctx->c_identity && op_fused(ctx)) {  // C = I: q = w + D p
+    HIPCHK(ctx, vec_add(st, ctx->m2, ctx->pw, ctx->pt));
+    HIPCHK(ctx, hipMemcpyAsync(q, ctx->pt, ctx->m2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return;
+  }
   HIPCHK(ctx, launch_gemv_rows<double>(st, ctx->C, ctx->ldn, ctx->m2, ctx->n, kDense, ctx->pw, q, 1.0, 1.0, ctx->pt,
                                        ctx->m2, nullptr));
 }
@@ -1028,6 +1047,7 @@ void qp_default_options(qp_options* opt) {
   opt->verbose = 0;
   opt->profile = 0;
   opt->kf_form = QP_KF_IMPLICIT;
+  opt->ph_form = QP_PH_EXACT;
 }
 
 const char* qp_status_str(qp_status st) {
@@ -1049,6 +1069,8 @@ const char* qp_last_error(const qp_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 size_t qp_ctx_bytes(const qp_ctx* ctx) { return ctx ? ctx->bytes : 0; }
 
 int qp_k0_one_pass(const qp_ctx* ctx) { return ctx && op_fused(ctx) ? 1 : 0; }
+
+int qp_c_identity(const qp_ctx* ctx) { return ctx && ctx->factored && ctx->c_identity ? 1 : 0; }
 
 qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset) {
   if (!ctx || !avg_ms || !samples) return QP_E_INVALID;

@@ -241,72 +241,72 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     RowsDesc<T> rd;
     GemvWork<T> wk = *b.wk;
     if (expl) goto pcg_desc;  // q = E p + D p: only the fused row sweep
-    if (op_transposed(c) && op_fused(c)) {  // u = C^T p, then w = M^T Sigma M u in one pass
-      fill_rows_desc<T>(rd, b.CT, c->ldm2, n, m2, kDense, b.p, b.u, T(1), T(0), nullptr, n, skip);
-      L.r1p.push_back(L.r1t);
-      L.r1t += rd.nblocks;
-      L.r1.push_back(rd);
-      L.r1smem = std::max(L.r1smem, rows_smem_bytes<T>(n, m2, kDense, c->ldm2));
-      SymDesc<T> sd;
-      if (!fill_sym_desc<T>(sd, b.Linv, c->ldN, N, n, b.u, b.w, static_cast<T*>(c->sympart),
-                            c->sympart_bytes / sizeof(T), skip)) {
-        set_err(sk, "one-pass K0 product does not fit its workspace (N=%d n=%d)", N, n);
-        throw Fail{QP_E_DEVICE};
+    {
+      // u = C^T p: a row sweep over the stored C^T, a column sweep over C, or u = p when C = I
+      const T* u = b.u;
+      if (c->c_identity) {
+        u = b.p;
+      } else if (op_transposed(c)) {
+        fill_rows_desc<T>(rd, b.CT, c->ldm2, n, m2, kDense, b.p, b.u, T(1), T(0), nullptr, n, skip);
+        L.r1p.push_back(L.r1t);
+        L.r1t += rd.nblocks;
+        L.r1.push_back(rd);
+        L.r1smem = std::max(L.r1smem, rows_smem_bytes<T>(n, m2, kDense, c->ldm2));
+      } else {
+        if (!fill_cols_desc<T>(cd, b.C, c->ldn, m2, n, kDense, b.p, b.u, T(1), T(0), nullptr, wk.part,
+                               wk.part_elems, skip)) {
+          set_err(sk, "column sweep over C does not fit its workspace (m2=%d n=%d)", m2, n);
+          throw Fail{QP_E_DEVICE};
+        }
+        L.c1p.push_back(L.c1pt);
+        L.c1r.push_back(L.c1rt);
+        L.c1pt += cd.nblocks;
+        L.c1rt += cd.rblocks;
+        L.c1.push_back(cd);
       }
-      L.syp.push_back(L.sypt);
-      L.syr.push_back(L.syrt);
-      L.sypt += sd.G;
-      L.syrt += sd.rblocks;
-      L.syK = std::max(L.syK, k0_sym_width<T>(n));
-      L.sy.push_back(sd);
-      goto pcg_desc;
-    }
-    if (op_transposed(c)) {   // u = C^T p, v = Sigma M u, w = M^T v: three row sweeps
-      fill_rows_desc<T>(rd, b.CT, c->ldm2, n, m2, kDense, b.p, b.u, T(1), T(0), nullptr, n, skip);
-      L.r1p.push_back(L.r1t);
-      L.r1t += rd.nblocks;
-      L.r1.push_back(rd);
-      L.r1smem = std::max(L.r1smem, rows_smem_bytes<T>(n, m2, kDense, c->ldm2));
-      fill_rows_desc<T>(rd, b.Linv, c->ldN, N, n, kLower, b.u, b.v, T(1), T(0), nullptr, n, skip);
+      if (op_fused(c)) {  // w = M^T Sigma M u in one pass
+        SymDesc<T> sd;
+        if (!fill_sym_desc<T>(sd, b.Linv, c->ldN, N, n, u, b.w, static_cast<T*>(c->sympart),
+                              c->sympart_bytes / sizeof(T), skip)) {
+          set_err(sk, "one-pass K0 product does not fit its workspace (N=%d n=%d)", N, n);
+          throw Fail{QP_E_DEVICE};
+        }
+        L.syp.push_back(L.sypt);
+        L.syr.push_back(L.syrt);
+        L.sypt += sd.G;
+        L.syrt += sd.rblocks;
+        L.syK = std::max(L.syK, k0_sym_width<T>(n));
+        L.sy.push_back(sd);
+        goto pcg_desc;
+      }
+      // v = Sigma M u, then w = M^T v over the stored M^T or as a column sweep over M
+      fill_rows_desc<T>(rd, b.Linv, c->ldN, N, n, kLower, u, b.v, T(1), T(0), nullptr, n, skip);
       L.r2p.push_back(L.r2t);
       L.r2t += rd.nblocks;
       L.r2.push_back(rd);
       L.r2smem = std::max(L.r2smem, rows_smem_bytes<T>(N, n, kLower, c->ldN));
-      fill_rows_desc<T>(rd, b.MT, c->ldN, n, N, kUpper, b.v, b.w, T(1), T(0), nullptr, n, skip);
-      L.r3p.push_back(L.r3t);
-      L.r3t += rd.nblocks;
-      L.r3.push_back(rd);
-      L.r3smem = std::max(L.r3smem, rows_smem_bytes<T>(n, N, kUpper, c->ldN));
-      goto pcg_desc;
+      if (op_transposed(c)) {
+        fill_rows_desc<T>(rd, b.MT, c->ldN, n, N, kUpper, b.v, b.w, T(1), T(0), nullptr, n, skip);
+        L.r3p.push_back(L.r3t);
+        L.r3t += rd.nblocks;
+        L.r3.push_back(rd);
+        L.r3smem = std::max(L.r3smem, rows_smem_bytes<T>(n, N, kUpper, c->ldN));
+      } else {
+        if (!fill_cols_desc<T>(cd, b.Linv, c->ldN, N, n, kLower, b.v, b.w, T(1), T(0), nullptr, wk.part,
+                               wk.part_elems, skip)) {
+          set_err(sk, "column sweep over the inverse factor does not fit its workspace (N=%d n=%d)", N, n);
+          throw Fail{QP_E_DEVICE};
+        }
+        L.c3p.push_back(L.c3pt);
+        L.c3r.push_back(L.c3rt);
+        L.c3pt += cd.nblocks;
+        L.c3rt += cd.rblocks;
+        L.c3.push_back(cd);
+      }
     }
-    if (!fill_cols_desc<T>(cd, b.C, c->ldn, m2, n, kDense, b.p, b.u, T(1), T(0), nullptr, wk.part, wk.part_elems,
-                           skip)) {
-      set_err(sk, "column sweep over C does not fit its workspace (m2=%d n=%d)", m2, n);
-      throw Fail{QP_E_DEVICE};
-    }
-    L.c1p.push_back(L.c1pt);
-    L.c1r.push_back(L.c1rt);
-    L.c1pt += cd.nblocks;
-    L.c1rt += cd.rblocks;
-    L.c1.push_back(cd);
-    fill_rows_desc<T>(rd, b.Linv, c->ldN, N, n, kLower, b.u, b.v, T(1), T(0), nullptr, n, skip);
-    L.r2p.push_back(L.r2t);
-    L.r2t += rd.nblocks;
-    L.r2.push_back(rd);
-    L.r2smem = std::max(L.r2smem, rows_smem_bytes<T>(N, n, kLower, c->ldN));
-    if (!fill_cols_desc<T>(cd, b.Linv, c->ldN, N, n, kLower, b.v, b.w, T(1), T(0), nullptr, wk.part, wk.part_elems,
-                           skip)) {
-      set_err(sk, "column sweep over the inverse factor does not fit its workspace (N=%d n=%d)", N, n);
-      throw Fail{QP_E_DEVICE};
-    }
-    L.c3p.push_back(L.c3pt);
-    L.c3r.push_back(L.c3rt);
-    L.c3pt += cd.nblocks;
-    L.c3rt += cd.rblocks;
-    L.c3.push_back(cd);
   pcg_desc:
     PcgDesc<T> pd;
-    pd.C = expl ? b.E : b.C;
+    pd.C = expl ? b.E : (c->c_identity ? nullptr : b.C);  // null: q = w + D p
     pd.w = expl ? b.p : b.w;
     pd.dvec = b.dvec;
     pd.wts = b.wts;
@@ -326,7 +326,7 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     pd.m2 = m2;
     pd.prec = it->prec;
     pd.qblocks = std::min(bpcg_q_blocks(m2), c->bpart_cap);
-    pd.stage = tune().brows_stage;
+    pd.stage = pd.C ? tune().brows_stage : 0;
     L.qp.push_back(L.qt);
     L.qt += pd.qblocks;
     L.pd.push_back(pd);
@@ -747,9 +747,25 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
   BatchedOps o1;
   std::vector<CholJob> cj;
   std::vector<GemmDesc> gw, gs;
+  // C = I test (info[1] is set when C differs from the identity)
+  std::vector<MatOpDesc> idc;
+  int id_rows = 0, id_cols = 0;
   for (Slot* s : fresh) {
     qp_ctx* c = s->ctx;
-    HIPCHK(c, hipMemsetAsync(c->info, 0, sizeof(int), B->stream));
+    HIPCHK(c, hipMemsetAsync(c->info, 0, 2 * sizeof(int), B->stream));
+    if (c->m2 != c->n) continue;
+    idc.push_back(MatOpDesc{c->C, nullptr, nullptr, c->info + 1, c->ldn, 0, 0, c->m2, c->n, kMatIdentity});
+    id_rows = std::max(id_rows, c->m2);
+    id_cols = std::max(id_cols, c->n);
+  }
+  if (!idc.empty()) {
+    Packer pk;
+    pk.add(idc.data(), idc.size() * sizeof(MatOpDesc));
+    const char* base = stage_upload(B, pk);
+    HIPCHK(&B->sink, bmatop(B->stream, reinterpret_cast<const MatOpDesc*>(base), (int)idc.size(), id_rows, id_cols));
+  }
+  for (Slot* s : fresh) {
+    qp_ctx* c = s->ctx;
     HIPCHK(c, hipMemcpyAsync(c->fHw, c->H, (size_t)c->n * c->ldn * sizeof(double), hipMemcpyDeviceToDevice,
                              B->stream));
     double* XH = c->Linv;
@@ -766,9 +782,12 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
   sync_pools(B, lo, hi, true);
   drop_failed(QP_E_NOT_SPD, "Cholesky factorization of H failed: H is not positive definite");
   if (fresh.empty()) return;
+  for (Slot* s : fresh) s->ctx->c_identity = s->ctx->m2 == s->ctx->n && s->ctx->h_info[1] == 0;
   BatchedOps o2;
   std::vector<CholJob> cs;
   std::vector<GemmDesc> g1, g2, gy, gt;
+  std::vector<MatOpDesc> ph_scale;  // diagonal form of P_H
+  int ps_rows = 0, ps_cols = 0;
   for (Slot* s : fresh) {
     qp_ctx* c = s->ctx;
     const int n = c->n;
@@ -779,8 +798,14 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
     g1.push_back(GemmDesc{c->fWt, XH, c->fG, c->ldn, c->ldN, c->ldn, c->m1, n, n});      // W^T X_H
     g2.push_back(GemmDesc{XS, c->fG, G, c->ldN, c->ldn, c->ldN, c->m1, n, c->m1});       // G = -X_S W^T X_H
     if (s->R.prec == kPrecH || prec_mode(resolve_prec(c, c->opt.prec)) == kPrecH) {
-      gy.push_back(GemmDesc{c->C, XH, c->fYt, c->ldn, c->ldN, c->ldn, c->m2, n, n});           // C X_H^T
-      gt.push_back(GemmDesc{c->fYt, c->fYt, c->T, c->ldn, c->ldn, c->ldm2, c->m2, c->m2, n});  // T = C H^{-1} C^T
+      if (c->opt.ph_form == QP_PH_DIAG) {  // C diag(H)^{-1/2}
+        ph_scale.push_back(MatOpDesc{c->C, c->H, c->fYt, nullptr, c->ldn, c->ldn, c->ldn, c->m2, n, kMatColScale});
+        ps_rows = std::max(ps_rows, c->m2);
+        ps_cols = std::max(ps_cols, n);
+      } else {
+        gy.push_back(GemmDesc{c->C, XH, c->fYt, c->ldn, c->ldN, c->ldn, c->m2, n, n});  // C X_H^T
+      }
+      gt.push_back(GemmDesc{c->fYt, c->fYt, c->T, c->ldn, c->ldn, c->ldm2, c->m2, c->m2, n});  // T = Y Y^T
     }
   }
   // explicit operator E = Y_1^T Y_1 - Y_2^T Y_2, Y = L^{-1}[:, :n] C^T (after G is final)
@@ -802,6 +827,13 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
   o2.gemm(0, 1, 1.0, 0.0, kALower, ey);
   o2.gemm(1, 0, 1.0, 0.0, kNone, ee1);
   o2.gemm(1, 0, -1.0, 1.0, kNone, ee2);
+  if (!ph_scale.empty()) {  // before T = Y Y^T, which o2 runs
+    Packer pk;
+    pk.add(ph_scale.data(), ph_scale.size() * sizeof(MatOpDesc));
+    const char* base = stage_upload(B, pk);
+    HIPCHK(&B->sink, bmatop(B->stream, reinterpret_cast<const MatOpDesc*>(base), (int)ph_scale.size(), ps_rows,
+                            ps_cols));
+  }
   run_ops(B, o2);
   pool_range(lo, hi);
   sync_pools(B, lo, hi, true);
@@ -836,10 +868,11 @@ void batched_factor(qp_batch* B, std::vector<Slot*> fresh) {
   for (Slot* s : fresh) {
     qp_ctx* c = s->ctx;
     if (!op_transposed(c)) continue;
-    tr.push_back(TransDesc{c->C, c->CT, c->ldn, c->ldm2, c->m2, c->n, 0});
+    const bool ct = !c->c_identity;  // C = I needs no C^T
+    if (ct) tr.push_back(TransDesc{c->C, c->CT, c->ldn, c->ldm2, c->m2, c->n, 0});
     if (store_mt(c)) tr.push_back(TransDesc{c->Linv, c->MT, c->ldN, c->ldN, c->N, c->n, 0});
     if (c->opt.precision == QP_MIXED) {
-      tr.push_back(TransDesc{c->C, c->CT32, c->ldn, c->ldm2, c->m2, c->n, 1});
+      if (ct) tr.push_back(TransDesc{c->C, c->CT32, c->ldn, c->ldm2, c->m2, c->n, 1});
       if (store_mt(c)) tr.push_back(TransDesc{c->Linv, c->MT32, c->ldN, c->ldN, c->N, c->n, 1});
     }
     tr_rows = std::max(tr_rows, c->N);

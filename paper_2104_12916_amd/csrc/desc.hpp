@@ -53,7 +53,7 @@ struct SymDesc {
 // One CG solve of the reduced system (the vectors of one QP).
 template <typename T>
 struct PcgDesc {
-  const T* C;     // m2 x n, leading dimension ldc
+  const T* C;     // m2 x n, leading dimension ldc; null: C = I (m2 = n)
   const T* w;     // input of the q sweep: w = [I 0] K0^{-1} [C^T p; 0]
   const T* dvec;  // diag(D)
   const T* wts;   // weights of the stop test (nu) or null

@@ -519,6 +519,51 @@ hipError_t bmat2d(hipStream_t st, const Mat2dDesc* d, int count, int max_rows, i
   return hipGetLastError();
 }
 
+// Once-per-QP matrix passes over C: kMatIdentity sets *flag to 1 when C != I
+// (an entry differs from the identity's; the flag starts at 0), kMatColScale
+// writes dst = C diag(H)^{-1/2} for the diagonal form of P_H.
+__device__ __forceinline__ void matop_body(const MatOpDesc& d, int i0, int di, int j0, int dj) {
+  bool bad = false;
+  for (int i = i0; i < d.rows; i += di) {
+    const double* row = d.src + (size_t)i * d.lds;
+    for (int j = j0; j < d.cols; j += dj) {
+      const double v = row[j];
+      if (d.op == kMatIdentity) {
+        bad |= v != (i == j ? 1.0 : 0.0);
+      } else {
+        d.dst[(size_t)i * d.ldd + j] = v / sqrt(d.h[(size_t)j * d.ldh + j]);
+      }
+    }
+  }
+  if (bad) *d.flag = 1;  // every writer stores the same value
+}
+
+__global__ void __launch_bounds__(256) matop_kernel(MatOpDesc d) {
+  matop_body(d, blockIdx.y, gridDim.y, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void __launch_bounds__(256) bmatop_kernel(const MatOpDesc* __restrict__ descs) {
+  const MatOpDesc d = descs[blockIdx.z];
+  matop_body(d, blockIdx.y, gridDim.y, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+static dim3 matop_grid(int rows, int cols, int count) {
+  return dim3(std::min((cols + 255) / 256, 16), std::min(rows, 4096), count);
+}
+
+hipError_t matop(hipStream_t st, const MatOpDesc& d) {
+  if (d.rows <= 0 || d.cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(matop_kernel, matop_grid(d.rows, d.cols, 1), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t bmatop(hipStream_t st, const MatOpDesc* d, int count, int max_rows, int max_cols) {
+  if (count <= 0 || max_rows <= 0 || max_cols <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bmatop_kernel, matop_grid(max_rows, max_cols, count), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
 template <typename S, typename D>
 __global__ void convert_2d_kernel(const S* __restrict__ src, int lds, D* __restrict__ dst, int ldd, int rows,
                                   int cols) {

@@ -94,7 +94,9 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
   double pq = 0;
   for (int i = bid * waves + wave; i < m2; i += nb * waves) {
     T v;
-    if (nt)
+    if (!C)  // C = I: q = w + D p
+      v = w[i];
+    else if (nt)
       v = stage ? row_dot<T, U>(C + (size_t)i * ldc, ws, lenR, lane)
                 : row_dot_gx<T, U>(C + (size_t)i * ldc, w, lenR, n, lane);
     else
@@ -358,7 +360,7 @@ int pcg_q_grid(int m2) {
 template <typename T>
 hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, const T* p, T* q,
                  const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev, int stage) {
-  if (!tune().rows_stage) stage = 0;
+  if (!tune().rows_stage || !C) stage = 0;  // a null C stands for the identity (m2 = n)
   size_t smem = stage ? rows_smem_bytes<T>(m2, n, kDense, ldc) : 0;
   if (smem > 150 * 1024) return hipErrorInvalidValue;
   const int grid = pcg_q_grid<T>(m2);

@@ -13,6 +13,7 @@ hipError_t pcg_init(hipStream_t st, int m2, const T* b, const T* dvec, const T* 
                     double rtol, double wtol, int maxit, PcgScalars* sc);
 template <typename T>
 int pcg_q_grid(int m2);
+// q = C w + D p and the per-workgroup partials of p^T q; C null means C = I (m2 = n).
 template <typename T>
 hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, const T* p, T* q,
                  const PcgScalars* sc, double* bpart, int bpart_cap, const EventPair* ev = nullptr, int stage = 1);
@@ -79,6 +80,18 @@ struct Mat2dDesc {
   const double* diag;
   int lds, ldd, rows, cols, lower, to_float;
 };
+
+// Once-per-QP passes over C (ipm.hip): identity test and diag(H)^{-1/2} column scaling.
+enum MatOp : int { kMatIdentity = 0, kMatColScale = 1 };
+struct MatOpDesc {
+  const double* src;  // C (rows x cols, leading dimension lds)
+  const double* h;    // H (kMatColScale)
+  double* dst;        // C diag(H)^{-1/2} (kMatColScale)
+  int* flag;          // set to 1 when C != I (kMatIdentity)
+  int lds, ldh, ldd, rows, cols, op;
+};
+hipError_t matop(hipStream_t st, const MatOpDesc& d);
+hipError_t bmatop(hipStream_t st, const MatOpDesc* d, int count, int max_rows, int max_cols);
 
 hipError_t ipm_stats(hipStream_t st, int n, int m1, int m2, const double* Hx, const double* Atl, const double* Ctn,
                      const double* Ax, const double* Cx, const double* x, const double* c, const double* lam,

@@ -20,6 +20,7 @@ QP_PREC_NONE, QP_PREC_LOW_DOF, QP_PREC_FEW_EQ, QP_PREC_AUTO = range(4)
 QP_FP64, QP_MIXED = 0, 1
 QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
 QP_KF_IMPLICIT, QP_KF_EXPLICIT = 0, 1
+QP_PH_EXACT, QP_PH_DIAG = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
@@ -27,7 +28,7 @@ EXPORTS = (
     "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
     "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
-    "qp_k0_one_pass",
+    "qp_k0_one_pass", "qp_c_identity",
 )
 
 
@@ -36,7 +37,7 @@ class qp_options(ct.Structure):
         ("rtol_kkt", ct.c_double), ("cg_theta", ct.c_double), ("cg_rtol", ct.c_double),
         ("tau", ct.c_double), ("max_ipm", ct.c_int), ("max_pcg", ct.c_int),
         ("poll_every", ct.c_int), ("prec", ct.c_int), ("precision", ct.c_int),
-        ("verbose", ct.c_int), ("profile", ct.c_int), ("kf_form", ct.c_int),
+        ("verbose", ct.c_int), ("profile", ct.c_int), ("kf_form", ct.c_int), ("ph_form", ct.c_int),
     ]
 
 
@@ -80,6 +81,8 @@ def lib():
     L.qp_profile_get.argtypes = [P, ct.POINTER(D), ct.POINTER(ct.c_longlong), I]
     L.qp_k0_one_pass.argtypes = [P]
     L.qp_k0_one_pass.restype = I
+    L.qp_c_identity.argtypes = [P]
+    L.qp_c_identity.restype = I
     L.qp_ctx_bytes.argtypes = [P]
     L.qp_ctx_bytes.restype = ct.c_size_t
     L.qp_destroy.argtypes = [P]
@@ -414,6 +417,10 @@ class Solver:
     def k0_one_pass(self):
         """True if the CG step forms M^T Sigma M u in one pass over M."""
         return bool(lib().qp_k0_one_pass(self.ctx))
+
+    def c_identity(self):
+        """True once qp_factor_K0 has found C = I (the CG step then has no product by C)."""
+        return bool(lib().qp_c_identity(self.ctx))
 
     def bytes(self):
         return qp_ctx_bytes(self.ctx)

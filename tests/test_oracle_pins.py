@@ -169,6 +169,24 @@ def test_simple_bounds_ph_is_D_plus_Hinv():
     assert np.allclose(reduced.P_H(qp, dvec), np.diag(dvec) + np.linalg.inv(qp.H), rtol=1e-9, atol=1e-9)
 
 
+def test_diag_ph_equals_exact_ph_for_diagonal_H():
+    """With diagonal H the PH-KF preconditioner of Sec. 5.2 is eq. preconditioner-2 itself."""
+    qp = synth.gaussian_qp(5, 14, 4, 9)
+    qp.H = np.diag(np.linspace(0.5, 3.0, 14))
+    dvec = synth.log_uniform(4, 9, 1e-2, 1e2)
+    assert np.allclose(reduced.P_H_diag(qp, dvec), reduced.P_H(qp, dvec), rtol=1e-12, atol=1e-12)
+
+
+def test_diag_ph_entries_by_definition():
+    """Entry (i, j) of C diag(H)^{-1} C^T is sum_k C_ik C_jk / H_kk (loops on a tiny case)."""
+    qp = synth.gaussian_qp(6, 5, 2, 4)
+    T = reduced.ph_T_diag(qp)
+    for i in range(4):
+        for j in range(4):
+            ref = sum(qp.C[i, k] * qp.C[j, k] / qp.H[k, k] for k in range(5))
+            assert abs(T[i, j] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
 # --- P6 spectral theorems -------------------------------------------------------
 @pytest.mark.parametrize("n,m1,m2", [(20, 15, 30), (24, 6, 30), (30, 10, 12), (16, 1, 40), (20, 19, 25)])
 def test_preconditioned_spectra(n, m1, m2):
