@@ -210,6 +210,14 @@ int qp_k0_one_pass(const qp_ctx* ctx);
  * P_H = D + H^{-1}.  0 before qp_factor_K0, otherwise, or for NULL. */
 int qp_c_identity(const qp_ctx* ctx);
 
+/* CG steps of the predictor and of the corrector reduced solve of every IPM
+ * iteration of the last qp_ipm_solve on this context (the counts of the paper's
+ * CG-iteration experiment, Sec. 6.2; bounded by Theorems thm1 and thm2 in exact
+ * arithmetic).  Writes the first min(iterations, cap) counts into each array
+ * that is not NULL and the number of iterations into *count.  QP_E_INVALID for
+ * NULL ctx or count, or cap < 0. */
+qp_status qp_ipm_cg_steps(const qp_ctx* ctx, int* predictor, int* corrector, int cap, int* count);
+
 /* Device bytes held by the context (all buffers, factor included). */
 size_t qp_ctx_bytes(const qp_ctx* ctx);
 

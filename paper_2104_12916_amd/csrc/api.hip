@@ -977,6 +977,8 @@ void ipm_after_corrector(qp_ctx* ctx, IpmRun& R) {
                        ctx->isc));
   R.cg_total += R.k1 + R.k2;
   ++R.it;
+  ctx->cg_trace.push_back(R.k1);
+  ctx->cg_trace.push_back(R.k2);
   if (ctx->opt.verbose) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_isc, ctx->isc, sizeof(IpmScalars), hipMemcpyDeviceToHost, st));
     sync(ctx);
@@ -1000,6 +1002,7 @@ void ipm_fill_info(const qp_ctx* ctx, const IpmRun& R, qp_ipm_info* info) {
 
 static void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
   IpmRun R;
+  ctx->cg_trace.clear();
   ipm_start(ctx, R);
   for (;;) {
     ipm_eval_launch(ctx, true);
@@ -1071,6 +1074,17 @@ size_t qp_ctx_bytes(const qp_ctx* ctx) { return ctx ? ctx->bytes : 0; }
 int qp_k0_one_pass(const qp_ctx* ctx) { return ctx && op_fused(ctx) ? 1 : 0; }
 
 int qp_c_identity(const qp_ctx* ctx) { return ctx && ctx->factored && ctx->c_identity ? 1 : 0; }
+
+qp_status qp_ipm_cg_steps(const qp_ctx* ctx, int* predictor, int* corrector, int cap, int* count) {
+  if (!ctx || !count || cap < 0) return QP_E_INVALID;
+  const int its = (int)(ctx->cg_trace.size() / 2);
+  for (int k = 0; k < its && k < cap; ++k) {
+    if (predictor) predictor[k] = ctx->cg_trace[2 * k];
+    if (corrector) corrector[k] = ctx->cg_trace[2 * k + 1];
+  }
+  *count = its;
+  return QP_OK;
+}
 
 qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset) {
   if (!ctx || !avg_ms || !samples) return QP_E_INVALID;

@@ -71,7 +71,8 @@ struct qp_ctx {
   // inverse factor L^{-1} of K0 = L Sigma L^T (N x ldN, lower, explicit zeros above)
   double* Linv = nullptr;
   bool factored = false;
-  bool c_identity = false;  // C = I found at factorization (m2 = n): the CG step skips both C products
+  bool c_identity = false;
+  std::vector<int> cg_trace;  // CG steps (predictor, corrector) of each IPM iteration of the last solve  // C = I found at factorization (m2 = n): the CG step skips both C products
   // P_H data: T = C H^{-1} C^T (fixed), P = D + T and X_P = chol(P)^{-1} (per D)
   double *T = nullptr, *P = nullptr, *XP = nullptr, *ptmp = nullptr;
   bool ph_ready = false;

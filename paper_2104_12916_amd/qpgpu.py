@@ -28,7 +28,7 @@ EXPORTS = (
     "qp_pcg_solve", "qp_ipm_solve", "qp_op_time", "qp_profile_get", "qp_ctx_bytes", "qp_destroy", "qp_status_str",
     "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
-    "qp_k0_one_pass", "qp_c_identity",
+    "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
 )
 
 
@@ -83,6 +83,8 @@ def lib():
     L.qp_k0_one_pass.restype = I
     L.qp_c_identity.argtypes = [P]
     L.qp_c_identity.restype = I
+    L.qp_ipm_cg_steps.argtypes = [P, ct.POINTER(I), ct.POINTER(I), I, ct.POINTER(I)]
+    L.qp_ipm_cg_steps.restype = I
     L.qp_ctx_bytes.argtypes = [P]
     L.qp_ctx_bytes.restype = ct.c_size_t
     L.qp_destroy.argtypes = [P]
@@ -417,6 +419,16 @@ class Solver:
     def k0_one_pass(self):
         """True if the CG step forms M^T Sigma M u in one pass over M."""
         return bool(lib().qp_k0_one_pass(self.ctx))
+
+    def cg_steps(self):
+        """(predictor, corrector) CG steps of every IPM iteration of the last ipm()."""
+        cnt = ct.c_int(0)
+        st = lib().qp_ipm_cg_steps(self.ctx, None, None, 0, ct.byref(cnt))
+        self.check(st)
+        k = cnt.value
+        a, b = (ct.c_int * max(k, 1))(), (ct.c_int * max(k, 1))()
+        self.check(lib().qp_ipm_cg_steps(self.ctx, a, b, k, ct.byref(cnt)))
+        return list(a[:k]), list(b[:k])
 
     def c_identity(self):
         """True once qp_factor_K0 has found C = I (the CG step then has no product by C)."""
