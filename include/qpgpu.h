@@ -303,6 +303,43 @@ qp_status qp_batch_profile_get(qp_batch* b, double avg_ms[6], double avg_bytes[6
 /* Free the batch, its arena and every result not collected.  NULL accepted. */
 void qp_batch_destroy(qp_batch* b);
 
+/* ---- QPs sharing H, A and C ---------------------------------------------
+ * Many QPs that differ only in c, b and d share K0 and its factorization
+ * (Sec. 4.1) and the operator C K0^{-1}_{11} C^T of eq. ineq-const-reduced;
+ * only D differs.  A qp_shared factorizes K0 once; its solves run the reduced
+ * systems of k such QPs as a block PCG: every CG step applies the shared
+ * operator to the k direction vectors at once, streaming C^T, M, M^T and C once
+ * for all k, while the scalars, the stop test and the preconditioner stay per
+ * QP (P_L or none: P_H would need one factorization of D + C H^{-1} C^T per QP).
+ * The k interior point iterations advance in lockstep.  FP64, implicit K_F.
+ * Arrays of the k QPs are stacked row by row (QP j at offset j * length).
+ */
+typedef struct qp_shared qp_shared;
+
+/* Upload H (n x n), A (m1 x n), C (m2 x n) and factorize K0.  opt: precision
+ * QP_FP64, kf_form QP_KF_IMPLICIT and prec P_L, none or AUTO (= P_L), else
+ * QP_E_INVALID.  Failures of the factorization as qp_factor_K0. */
+qp_status qp_shared_setup(qp_shared** out, int n, int m1, int m2, const double* H, const double* A, const double* C,
+                          qp_mem where, const qp_options* opt, void* hip_stream);
+
+/* k reduced solves K_F(d_j) dnu_j = rhs_j (dvec, rhs, dnu: k x m2) by block PCG
+ * from zero, each to ||r_j||_2 <= rtol ||rhs_j||_2 or maxit steps; info (k
+ * entries, may be NULL) as qp_pcg_solve.  prec: P_L, none or AUTO (= P_L). */
+qp_status qp_shared_pcg_solve(qp_shared* sh, int k, const double* dvec, const double* rhs, double* dnu, qp_mem where,
+                              qp_precond prec, double rtol, int maxit, qp_pcg_info* info);
+
+/* Solve k QPs min 1/2 x^T H x + c_j^T x, A x = b_j, C x >= d_j (c: k x n, b:
+ * k x m1, d: k x m2; outputs x, lambda, nu, s stacked the same way; info: k
+ * entries or NULL).  Returns the first failure of any QP (all are still solved). */
+qp_status qp_shared_ipm_solve(qp_shared* sh, int k, const double* c, const double* b, const double* d, double* x,
+                              double* lambda, double* nu, double* s, qp_mem where, qp_ipm_info* info);
+
+/* Message of the last failure ("" if none; never NULL). */
+const char* qp_shared_last_error(const qp_shared* sh);
+
+/* Free everything of the shared set.  NULL accepted. */
+void qp_shared_destroy(qp_shared* sh);
+
 #ifdef __cplusplus
 }
 #endif

@@ -284,13 +284,18 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
   const int n = ctx->n, m1 = ctx->m1, m2 = ctx->m2, N = ctx->N;
   auto D = [&](double*& p, size_t elems) { p = static_cast<double*>(get(elems * sizeof(double))); };
   auto F = [&](float*& p, size_t elems) { p = static_cast<float*>(get(elems * sizeof(float))); };
-  D(ctx->H, (size_t)n * ctx->ldn);
+  // a shared-matrix member takes H, A, C and the factors from its master
+  const bool own = ctx->master == nullptr;
+  auto DM = [&](double*& p, size_t elems) {
+    if (own) D(p, elems);
+  };
+  DM(ctx->H, (size_t)n * ctx->ldn);
   D(ctx->c, n);
-  D(ctx->A, (size_t)m1 * ctx->ldn);
+  DM(ctx->A, (size_t)m1 * ctx->ldn);
   D(ctx->b, m1);
-  D(ctx->C, (size_t)m2 * ctx->ldn);
+  DM(ctx->C, (size_t)m2 * ctx->ldn);
   D(ctx->d, m2);
-  D(ctx->Linv, (size_t)N * ctx->ldN);
+  DM(ctx->Linv, (size_t)N * ctx->ldN);
   for (double** v : {&ctx->x, &ctx->Hx, &ctx->Atl, &ctx->Ctn, &ctx->rg, &ctx->dx, &ctx->dx_a, &ctx->pu, &ctx->pw})
     D(*v, n);
   for (double** v : {&ctx->lam, &ctx->Ax, &ctx->re, &ctx->dlam, &ctx->dlam_a}) D(*v, m1);
@@ -303,7 +308,7 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
   D(ctx->pp, ctx->ldm2);
   for (double** v : {&ctx->vN1, &ctx->vN2, &ctx->vN3, &ctx->pv}) D(*v, N);
   const bool mixed = ctx->opt.precision == QP_MIXED;
-  const bool need_ph = !ctx->pooled || resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ;
+  const bool need_ph = own && (!ctx->pooled || resolve_prec(ctx, ctx->opt.prec) == QP_PREC_FEW_EQ);
   size_t part64, part32;
   if (!ctx->pooled) {
     int maxld = std::max(std::max(ctx->ldn, ctx->ldN), ctx->ldm2);
@@ -336,9 +341,9 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     D(ctx->stats, kStatsStride);
     ctx->info = static_cast<int*>(get(16 * sizeof(int)));
   }
-  if (kf_explicit(ctx)) D(ctx->E, (size_t)m2 * ctx->ldm2);
-  if (op_transposed(ctx)) D(ctx->CT, (size_t)n * ctx->ldm2);
-  if (store_mt(ctx)) D(ctx->MT, (size_t)n * ctx->ldN);
+  if (kf_explicit(ctx)) DM(ctx->E, (size_t)m2 * ctx->ldm2);
+  if (op_transposed(ctx)) DM(ctx->CT, (size_t)n * ctx->ldm2);
+  if (store_mt(ctx)) DM(ctx->MT, (size_t)n * ctx->ldN);
   if (op_fused(ctx)) {
     // stand-alone: any single-launch grid; batch member: its share of a batched launch
     const size_t elems = ctx->pooled ? (size_t)bk0_sym_grid<double>(N, n) * k0_sym_ldp(n) : k0_sym_part_elems(n);

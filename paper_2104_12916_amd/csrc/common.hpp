@@ -64,6 +64,7 @@ struct Tune {
   int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
   int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
                           // 1 us faster per CG step than 1024 at m2 = 2048)
+  int mv_rt = 1;         // multi-vector sweeps of the block PCG: rows per thread (1 or 2)
   int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
                         // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
                         // more than the 256 MB last-level cache holds; loading M plainly and C, C^T

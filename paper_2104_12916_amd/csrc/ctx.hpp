@@ -72,6 +72,10 @@ struct qp_ctx {
   double* Linv = nullptr;
   bool factored = false;
   bool c_identity = false;
+  // shared-matrix member (qp_shared): H, A, C and every factor belong to the
+  // master context; the member owns only its problem vectors and work vectors
+  const qp_ctx* master = nullptr;
+  bool keep_mt = false;  // store M^T even when the one-pass product applies (block PCG reads it)
   std::vector<int> cg_trace;  // CG steps (predictor, corrector) of each IPM iteration of the last solve  // C = I found at factorization (m2 = n): the CG step skips both C products
   // P_H data: T = C H^{-1} C^T (fixed), P = D + T and X_P = chol(P)^{-1} (per D)
   double *T = nullptr, *P = nullptr, *XP = nullptr, *ptmp = nullptr;
@@ -186,9 +190,9 @@ inline bool op_transposed(const qp_ctx* ctx) { return tune().op_t && !kf_explici
 // The implicit CG step forms M^T Sigma M u in one pass over M (n small enough
 // for the register rows of the one-pass sweep); M^T is then not stored.
 inline bool op_fused(const qp_ctx* ctx) {
-  return tune().k0_sym && !kf_explicit(ctx) && ctx->n <= k0_sym_max_n<double>();
+  return tune().k0_sym && !kf_explicit(ctx) && !ctx->master && ctx->n <= k0_sym_max_n<double>();
 }
-inline bool store_mt(const qp_ctx* ctx) { return op_transposed(ctx) && !op_fused(ctx); }
+inline bool store_mt(const qp_ctx* ctx) { return (op_transposed(ctx) && !op_fused(ctx)) || ctx->keep_mt; }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);
 void k0_solve_dev(qp_ctx* ctx, const double* in, double* out, double* tmpN);

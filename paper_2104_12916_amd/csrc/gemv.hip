@@ -58,6 +58,7 @@ Tune& tune() {
       if (!strcmp(tok, "sym_rows") && (val == 2 || val == 4)) v.sym_rows = val;
       if (!strcmp(tok, "ld_nt") && val >= 0 && val <= 3) v.ld_nt = val;
       if (!strcmp(tok, "upd_threads") && (val == 256 || val == 512 || val == 1024)) v.upd_threads = val;
+      if (!strcmp(tok, "mv_rt") && (val == 1 || val == 2)) v.mv_rt = val;
     }
     return v;
   }();

@@ -29,6 +29,7 @@ EXPORTS = (
     "qp_last_error", "qp_batch_create", "qp_batch_admit", "qp_batch_step", "qp_batch_finished", "qp_batch_collect",
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
     "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
+    "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_shared_last_error", "qp_shared_destroy",
 )
 
 
@@ -107,9 +108,17 @@ def lib():
     L.qp_batch_profile_get.argtypes = [P, ct.POINTER(D), ct.POINTER(D), ct.POINTER(LL), I]
     L.qp_batch_destroy.argtypes = [P]
     L.qp_batch_destroy.restype = None
+    L.qp_shared_setup.argtypes = [ct.POINTER(P), I, I, I, P, P, P, I, ct.POINTER(qp_options), P]
+    L.qp_shared_pcg_solve.argtypes = [P, I, P, P, P, I, I, D, I, ct.POINTER(qp_pcg_info)]
+    L.qp_shared_ipm_solve.argtypes = [P, I, P, P, P, P, P, P, P, I, ct.POINTER(qp_ipm_info)]
+    L.qp_shared_last_error.argtypes = [P]
+    L.qp_shared_last_error.restype = ct.c_char_p
+    L.qp_shared_destroy.argtypes = [P]
+    L.qp_shared_destroy.restype = None
     for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
-                 "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get"):
+                 "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get",
+                 "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -352,6 +361,64 @@ class Batch:
         if self.b:
             qp_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Shared:
+    """QPs sharing H, A and C (qp_shared_*): one K0 factorization, block PCG over k QPs."""
+
+    def __init__(self, H, A, C, **opts):
+        stream = opts.pop("stream", None)
+        self.opt = qp_default_options(**opts)
+        self.n, self.m1, self.m2 = H.shape[0], A.shape[0], C.shape[0]
+        (ph, where), (pa, _), (pc, _) = _ptr(H), _ptr(A), _ptr(C)
+        _where(H, A, C)
+        out = ct.c_void_p()
+        st = lib().qp_shared_setup(ct.byref(out), self.n, self.m1, self.m2, ph, pa, pc, where, ct.byref(self.opt),
+                                   stream)
+        if st != QP_OK:
+            raise QpError(st, "qp_shared_setup failed")
+        self.sh = out
+
+    def check(self, st, accept=(QP_OK,)):
+        if st not in accept:
+            raise QpError(st, (lib().qp_shared_last_error(self.sh) or b"").decode())
+
+    def pcg(self, dvecs, rhss, prec=QP_PREC_LOW_DOF, rtol=1e-10, maxit=0, accept=(QP_OK,)):
+        """dvecs, rhss: k x m2.  Returns (dnu k x m2, [qp_pcg_info] * k)."""
+        dv = np.ascontiguousarray(dvecs, dtype=np.float64)
+        rh = np.ascontiguousarray(rhss, dtype=np.float64)
+        k = dv.shape[0]
+        out = np.zeros_like(rh)
+        infos = (qp_pcg_info * k)()
+        st = lib().qp_shared_pcg_solve(self.sh, k, _ptr(dv)[0], _ptr(rh)[0], _ptr(out)[0], QP_MEM_HOST, int(prec),
+                                       float(rtol), int(maxit), infos)
+        self.check(st, accept)
+        return out, list(infos)
+
+    def ipm(self, cs, bs, ds, accept=(QP_OK,)):
+        """cs: k x n, bs: k x m1, ds: k x m2.  Returns (x, lam, nu, s, [qp_ipm_info] * k)."""
+        c = np.ascontiguousarray(cs, dtype=np.float64)
+        b = np.ascontiguousarray(bs, dtype=np.float64)
+        d = np.ascontiguousarray(ds, dtype=np.float64)
+        k = c.shape[0]
+        x, lam = np.zeros((k, self.n)), np.zeros((k, self.m1))
+        nu, s = np.zeros((k, self.m2)), np.zeros((k, self.m2))
+        infos = (qp_ipm_info * k)()
+        st = lib().qp_shared_ipm_solve(self.sh, k, _ptr(c)[0], _ptr(b)[0], _ptr(d)[0], _ptr(x)[0], _ptr(lam)[0],
+                                       _ptr(nu)[0], _ptr(s)[0], QP_MEM_HOST, infos)
+        self.check(st, accept)
+        return x, lam, nu, s, list(infos)
+
+    def close(self):
+        if getattr(self, "sh", None):
+            lib().qp_shared_destroy(self.sh)
+            self.sh = None
 
     def __del__(self):
         try:

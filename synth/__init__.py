@@ -22,6 +22,8 @@ box_qp(seed, n, m1)
     (C = [0 I; 0 -I]).  Its minimizer has a closed form, used as a test pin.
 batch_sizes / serving_stream
     Size mixes of the batched and streamed workloads.
+shared_family(seed, n, m1, m2, k)
+    k QPs with one H, A, C and their own c, b, d (QPs that share the K0 factor).
 syqp(seed, n, m1)
     The paper's synthetic family SyQP^n_{m1} (Sec. 6.1): block-diagonal H made of
     4 x 4 blocks M^T M with M ~ U[0, 1], banded A with U[0, 1) entries, C = I, d = 0.
@@ -35,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "QP", "gaussian_qp", "illcond_qp", "box_qp", "syqp", "tiny_qp",
-    "batch_sizes", "serving_stream", "log_uniform", "workload",
+    "batch_sizes", "serving_stream", "log_uniform", "workload", "shared_family",
 ]
 
 
@@ -169,6 +171,25 @@ def syqp(seed: int, n: int, m1: int, band: int = 3, H_seed: int | None = None) -
     H = 0.5 * (H + H.T)
     return QP(_c(H), _c(c), _c(A), _c(A @ x0), _c(C), _c(d), _c(x0),
               dict(kind="syqp", seed=seed, n=n, m1=m1, m2=n))
+
+
+def shared_family(seed: int, n: int, m1: int, m2: int, k: int, base=None) -> list:
+    """k QPs sharing H, A and C (those of ``base``, default gaussian_qp(seed, n, m1, m2)).
+
+    QP j draws, from ``default_rng(seed + 1 + j)`` in this order, c_j ~ N(0, 1),
+    x0_j ~ N(0, 1) and s_j ~ U(0.1, 1); b_j = A x0_j and d_j = C x0_j - s_j, so
+    x0_j is strictly feasible for QP j.
+    """
+    base = gaussian_qp(seed, n, m1, m2) if base is None else base
+    out = []
+    for j in range(k):
+        rng = np.random.default_rng(seed + 1 + j)
+        c = rng.standard_normal(base.n)
+        x0 = rng.standard_normal(base.n)
+        s = rng.uniform(0.1, 1.0, base.m2)
+        out.append(QP(base.H, _c(c), base.A, _c(base.A @ x0), base.C, _c(base.C @ x0 - s), _c(x0),
+                      dict(kind="shared", seed=seed, j=j, n=base.n, m1=base.m1, m2=base.m2)))
+    return out
 
 
 def log_uniform(seed: int, size: int, lo: float, hi: float) -> np.ndarray:
