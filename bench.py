@@ -48,6 +48,9 @@ WORKLOADS = {
     "small": dict(desc="one dense QP n=200, m1=50, m2=100", prec="PH", seeds=list(range(16))),
     "batch": dict(desc=BATCH_DESC, prec="auto", seeds=[1000]),
     "serve": dict(desc=SERVE_DESC, prec="auto", seeds=[5000]),
+    "shared": dict(desc="k dense QPs sharing H, A, C of the low-dof instance (n=4096, m1=3072, m2=2048, seed 100) "
+                        "with their own c, b, d (synth.shared_family), P_L, one K0 factorization, block PCG",
+                   prec="PL", seeds=[100]),
 }
 OP_NAMES = ["gemv_rows_kernel<T,1> (C^T p over stored C^T)", "gemv_rows_kernel<T,2> (Sigma M u)",
             "gemv_rows_kernel<T,3> (M^T v over stored M^T)", "pcg_q_kernel<T> (C w + D p)",
@@ -294,6 +297,74 @@ def run_batch_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def run_shared_workload(args):
+    """k QPs that share H, A, C: one factorization, block PCG, lockstep IPMs (qp_shared_*)."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import kkt
+    from paper_2104_12916_amd import qpgpu
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    k = args.shared_k
+    base = synth.workload("lowdof", seed=100)
+    fam = synth.shared_family(100, base.n, base.m1, base.m2, k, base=base)
+    cs, bs, ds = (np.stack([getattr(q, f) for q in fam]) for f in ("c", "b", "d"))
+    print(f"shared: {k} QPs n={base.n} m1={base.m1} m2={base.m2}", file=sys.stderr, flush=True)
+
+    def solve():
+        t0 = time.perf_counter()
+        sh = qpgpu.Shared(base.H, base.A, base.C, prec=qpgpu.QP_PREC_LOW_DOF)  # factorization inside the clock
+        out = sh.ipm(cs, bs, ds)
+        torch.cuda.synchronize()
+        sh.close()
+        return time.perf_counter() - t0, out
+
+    for _ in range(args.warmup):
+        solve()
+    times, out = [], None
+    for i in range(args.steps):
+        dt, out = solve()
+        times.append(dt)
+        print(f"step {i + 1}/{args.steps}: {k} QPs in {dt:.2f} s", file=sys.stderr, flush=True)
+    x, lam, nu, s, infos = out
+    worst, ok = 0.0, 0
+    for j, q in enumerate(fam):
+        sc, _ = kkt.rel_kkt(q, x[j], lam[j], nu[j])
+        worst = max(worst, sc)
+        ok += sc <= 1e-8
+    # the same QPs one at a time through the single-QP path (factorization each time), for comparison
+    single = None
+    if args.single_count > 0:
+        m = min(args.single_count, k)
+        t0 = time.perf_counter()
+        for q in fam[:m]:
+            sv = qpgpu.Solver(*q.arrays(), prec=qpgpu.QP_PREC_LOW_DOF)
+            sv.factor()
+            sv.ipm()
+            sv.close()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        single = dict(value=m / el, unit="QP solves/s", qps=m, seconds=round(el, 2))
+    elapsed = sum(times)
+    value = k * args.steps / elapsed
+    line = {
+        "metric": METRIC, "value": value, "unit": "QP solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
+        "config": {"workload": "shared: " + WORKLOADS["shared"]["desc"], "qps": k, "precond": "PL",
+                   "precision": "fp64", "kf_form": "implicit"},
+        "roofline": None, "cpu_baseline": None,
+        "parity": dict(passed=ok, solves=k, max_rel_kkt=worst),
+        "ipm_iters": [i.ipm_iters for i in infos], "cg_steps": [int(i.pcg_iters_total) for i in infos],
+        "single_qp_fp64_gpu": single,
+        "speedup_vs_single_qp_fp64": (value / single["value"]) if single else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_serve_workload(args):
     import collections
     import numpy as np
@@ -409,6 +480,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--shared-k", type=int, default=16, help="QPs of the shared workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (independent QPs shard "
@@ -422,6 +494,8 @@ def main():
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"
         return run_serve_workload(args)
+    if args.workload == "shared":
+        return run_shared_workload(args)
 
     import numpy as np
     import torch
