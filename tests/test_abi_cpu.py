@@ -125,3 +125,52 @@ def test_batch_footprint_is_positive_monotone_and_validates():
     assert qpgpu.qp_batch_footprint(opt, 0, 1, 1) == 0
     assert qpgpu.qp_batch_footprint(opt, 5, 6, 1) == 0
     assert qpgpu.qp_batch_footprint(qpgpu.qp_default_options(tau=2.0), 5, 2, 1) == 0
+
+
+def test_query_calls_accept_null():
+    L = qpgpu.lib()
+    cnt = ct.c_int(7)
+    assert L.qp_k0_one_pass(None) == 0
+    assert L.qp_c_identity(None) == 0
+    assert L.qp_ipm_cg_steps(None, None, None, 0, ct.byref(cnt)) == qpgpu.QP_E_INVALID
+
+
+def test_ph_form_default_and_validation():
+    o = qpgpu.qp_default_options()
+    assert o.ph_form == qpgpu.QP_PH_EXACT
+    L = qpgpu.lib()
+    n, m1, m2 = 4, 2, 3
+    arrs = [np.eye(n), np.zeros(n), np.ones((m1, n)), np.zeros(m1), np.ones((m2, n)), np.zeros(m2)]
+    ptrs = [a.ctypes.data_as(ct.c_void_p) for a in arrs]
+    bad = qpgpu.qp_default_options(ph_form=5)
+    ctx = ct.c_void_p()
+    assert L.qp_setup(ct.byref(ctx), n, m1, m2, *ptrs, qpgpu.QP_MEM_HOST, ct.byref(bad), None) == qpgpu.QP_E_INVALID
+    assert not ctx.value
+
+
+def test_shared_calls_reject_null_handles_and_unsupported_options():
+    L = qpgpu.lib()
+    P = ct.c_void_p
+    n, m1, m2 = 4, 2, 3
+    H, A, C = np.eye(n), np.ones((m1, n)), np.ones((m2, n))
+    hp, ap, cp = (a.ctypes.data_as(P) for a in (H, A, C))
+    out = P()
+    opt = qpgpu.qp_default_options()
+    assert L.qp_shared_setup(None, n, m1, m2, hp, ap, cp, qpgpu.QP_MEM_HOST, ct.byref(opt), None) == qpgpu.QP_E_INVALID
+    assert L.qp_shared_setup(ct.byref(out), 0, m1, m2, hp, ap, cp, qpgpu.QP_MEM_HOST, ct.byref(opt),
+                             None) == qpgpu.QP_E_INVALID
+    # options the shared solver does not take, and a non-symmetric H, fail before any device work
+    for bad in (dict(precision=qpgpu.QP_MIXED), dict(kf_form=qpgpu.QP_KF_EXPLICIT),
+                dict(prec=qpgpu.QP_PREC_FEW_EQ)):
+        o = qpgpu.qp_default_options(**bad)
+        assert L.qp_shared_setup(ct.byref(out), n, m1, m2, hp, ap, cp, qpgpu.QP_MEM_HOST, ct.byref(o),
+                                 None) == qpgpu.QP_E_INVALID
+        assert not out.value
+    Hn = np.eye(n)
+    Hn[0, 1] = 1.0
+    assert L.qp_shared_setup(ct.byref(out), n, m1, m2, Hn.ctypes.data_as(P), ap, cp, qpgpu.QP_MEM_HOST,
+                             ct.byref(opt), None) == qpgpu.QP_E_INVALID
+    assert L.qp_shared_pcg_solve(None, 1, None, None, None, 0, 1, 1e-8, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_shared_ipm_solve(None, 1, None, None, None, None, None, None, None, 0, None) == qpgpu.QP_E_INVALID
+    assert L.qp_shared_last_error(None) == b""
+    L.qp_shared_destroy(None)
