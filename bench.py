@@ -380,7 +380,11 @@ def run_serve_workload(args):
     nw, nm = args.serve_warmup, args.serve_requests
     specs = synth.serving_stream(nw + nm, seed=5000)
     t = time.perf_counter()
-    reqs = [synth.gaussian_qp(*sp) for sp in specs]
+    reqs = []
+    for sp in specs:
+        reqs.append(synth.gaussian_qp(*sp))
+        if len(reqs) % 250 == 0:
+            print(f"  generated {len(reqs)}/{len(specs)}", file=sys.stderr, flush=True)
     print(f"generated {len(reqs)} requests in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     budget = int(args.serve_budget_gb * (1 << 30))
 
@@ -413,6 +417,8 @@ def run_serve_workload(args):
                 results[k] = b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))
                 lat[k] = time.perf_counter() - t0 - arrive[k]
                 done += 1
+                if done % 250 == 0:
+                    print(f"  {done}/{len(reqs)} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         b.close()
         meas = list(range(nw, len(reqs)))
         t_first = min(arrive[k] for k in meas)

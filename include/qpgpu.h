@@ -191,6 +191,19 @@ qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, doubl
  * Overwrites the context's CG work vectors.  Requires qp_factor_K0. */
 qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, double* avg_ms);
 
+/* Launch-shape table (workgroups per CU, loads in flight, one-pass sweep shape,
+ * update width, cache policy of the matrix loads) of the streaming kernels, per
+ * size bucket: calls on one QP use the bucket of its n, batches the base entry.
+ * qp_tune_set replaces the table with `spec`, in the text format of the cache
+ * that paper_2104_12916_amd/autotune.py writes: lines "default k=v,...",
+ * "n<=N k=v,..." (kernel shapes only), "arch NAME", "# ...".  The layout keys
+ * (ld_pad, op_t, k0_sym) must keep their values: QP_E_INVALID otherwise, or for
+ * an unknown key or value.  Not to be called while other threads launch.
+ * qp_tune_get writes the current table (needed = bytes including the NUL;
+ * buf NULL: only needed). */
+qp_status qp_tune_set(const char* spec);
+qp_status qp_tune_get(char* buf, size_t len, size_t* needed);
+
 /* Average device time (ms) per launch and sample counts of the CG-step kernels
  * sampled while options.profile is set, in the order of qp_op_time's ops 0-3
  * (C^T p, Sigma M u or the one-pass sweep of M, M^T v or the sum of its

@@ -1172,6 +1172,7 @@ qp_status qp_k0_solve(qp_ctx* ctx, const double* rhs, double* out, qp_mem where)
     set_err(ctx, "qp_k0_solve before qp_factor_K0");
     return QP_E_STATE;
   }
+  TuneScope tune_scope(ctx->n);
   return guarded(ctx, [&] {
     upload_vec(ctx, ctx->vN1, rhs, ctx->N, where);
     k0_solve_dev(ctx, ctx->vN1, ctx->vN2, ctx->vN3);
@@ -1186,6 +1187,7 @@ qp_status qp_kf_apply(qp_ctx* ctx, const double* dvec, const double* p, double* 
     set_err(ctx, "qp_kf_apply before qp_factor_K0");
     return QP_E_STATE;
   }
+  TuneScope tune_scope(ctx->n);
   return guarded(ctx, [&] {
     upload_vec(ctx, ctx->dvec, dvec, ctx->m2, where);
     upload_vec(ctx, ctx->ir_r, p, ctx->m2, where);
@@ -1203,6 +1205,7 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
     set_err(ctx, "qp_pcg_solve before qp_factor_K0");
     return QP_E_STATE;
   }
+  TuneScope tune_scope(ctx->n);
   ctx->err.clear();
   qp_status st = guarded(ctx, [&] {
     const int m2 = ctx->m2;
@@ -1263,6 +1266,7 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
     set_err(ctx, "float32 operator copies exist only in a QP_MIXED context");
     return QP_E_STATE;
   }
+  TuneScope tune_scope(ctx->n);
   if (!ctx->factored) {
     set_err(ctx, "qp_op_time before qp_factor_K0");
     return QP_E_STATE;
@@ -1368,6 +1372,7 @@ qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, doubl
     set_err(ctx, "qp_ipm_solve before qp_factor_K0");
     return QP_E_STATE;
   }
+  TuneScope tune_scope(ctx->n);
   ctx->err.clear();
   auto t0 = std::chrono::steady_clock::now();
   qp_status st = guarded(ctx, [&] { ipm_run(ctx, info); });

@@ -43,9 +43,9 @@ struct DevInfo {
 DevInfo& dev_info();
 
 // Launch shapes of the streaming sweeps.  Defaults were chosen by timing on
-// gfx950 (qp_op_time); the environment variable QPGPU_TUNE
-// ("rows_bpc=4,rows_unroll=8,cols_bpc=4,cols_unroll=4,ld_pad=0,qe_stage=0,rows_stage=0,k0_sym=0")
-// overrides them.
+// gfx950 (qp_op_time); per size bucket they come from the autotuner's cache, and
+// the environment variable QPGPU_TUNE ("rows_bpc=4,rows_unroll=8,ld_pad=0,...")
+// overrides the base entry (tune.hip).
 struct Tune {
   int rows_bpc = 4;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
   int rows_unroll = 8;  // 16-byte loads in flight per lane: 4 or 8
@@ -72,6 +72,18 @@ struct Tune {
                         // us at n = 4096, m1 = 3072, m2 = 2048; the opposite split is equal)
 };
 Tune& tune();
+// Selects the launch shapes of the size bucket of n (n <= 0: the base entry) for
+// the enclosing scope on this thread.
+class TuneScope {
+ public:
+  explicit TuneScope(int n);
+  ~TuneScope();
+  TuneScope(const TuneScope&) = delete;
+  TuneScope& operator=(const TuneScope&) = delete;
+
+ private:
+  const Tune* prev_;
+};
 constexpr int kMaxRowsBpc = 8;
 constexpr int kMaxColsBpc = 8;
 constexpr int kMaxSymWg = 4;

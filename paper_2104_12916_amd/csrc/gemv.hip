@@ -30,41 +30,6 @@
 
 namespace qpg {
 
-Tune& tune() {
-  static Tune t = [] {
-    Tune v;
-    const char* e = getenv("QPGPU_TUNE");
-    if (!e) return v;
-    char buf[256];
-    strncpy(buf, e, sizeof(buf) - 1);
-    buf[sizeof(buf) - 1] = 0;
-    for (char* tok = strtok(buf, ","); tok; tok = strtok(nullptr, ",")) {
-      char* eq = strchr(tok, '=');
-      if (!eq) continue;
-      *eq = 0;
-      int val = atoi(eq + 1);
-      if (!strcmp(tok, "rows_bpc") && val >= 1 && val <= kMaxRowsBpc) v.rows_bpc = val;
-      if (!strcmp(tok, "rows_unroll") && (val == 4 || val == 8)) v.rows_unroll = val;
-      if (!strcmp(tok, "cols_bpc") && val >= 1 && val <= kMaxColsBpc) v.cols_bpc = val;
-      if (!strcmp(tok, "cols_unroll") && (val == 4 || val == 8)) v.cols_unroll = val;
-      if (!strcmp(tok, "ld_pad") && val >= 0 && val <= 1024 && val % 64 == 0) v.ld_pad = val;
-      if (!strcmp(tok, "qe_stage") && (val == 0 || val == 1)) v.qe_stage = val;
-      if (!strcmp(tok, "rows_stage") && (val == 0 || val == 1)) v.rows_stage = val;
-      if (!strcmp(tok, "brows_stage") && (val == 0 || val == 1)) v.brows_stage = val;
-      if (!strcmp(tok, "brows_unroll") && (val == 4 || val == 8)) v.brows_unroll = val;
-      if (!strcmp(tok, "op_t") && (val == 0 || val == 1)) v.op_t = val;
-      if (!strcmp(tok, "k0_sym") && (val == 0 || val == 1)) v.k0_sym = val;
-      if (!strcmp(tok, "sym_wg") && val >= 1 && val <= kMaxSymWg) v.sym_wg = val;
-      if (!strcmp(tok, "sym_rows") && (val == 2 || val == 4)) v.sym_rows = val;
-      if (!strcmp(tok, "ld_nt") && val >= 0 && val <= 3) v.ld_nt = val;
-      if (!strcmp(tok, "upd_threads") && (val == 256 || val == 512 || val == 1024)) v.upd_threads = val;
-      if (!strcmp(tok, "mv_rt") && (val == 1 || val == 2)) v.mv_rt = val;
-    }
-    return v;
-  }();
-  return t;
-}
-
 // ---------------------------------------------------------------------------
 // device bodies
 

@@ -249,6 +249,7 @@ qp_status qp_shared_pcg_solve(qp_shared* sh, int k, const double* dvec, const do
   if (prec < QP_PREC_NONE || prec > QP_PREC_AUTO) return QP_E_INVALID;
   qp_ctx* m = sh->master;
   m->err.clear();
+  TuneScope tune_scope(m->n);
   qp_status st = guarded(m, [&] {
     const int m2 = m->m2;
     const int mode = block_prec(sh, prec);
@@ -298,6 +299,7 @@ qp_status qp_shared_ipm_solve(qp_shared* sh, int k, const double* c, const doubl
   if (!sh || k <= 0 || !c || !b || !d || !x || !lambda || !nu || !s) return QP_E_INVALID;
   qp_ctx* m = sh->master;
   m->err.clear();
+  TuneScope tune_scope(m->n);
   const int n = m->n, m1 = m->m1, m2 = m->m2;
   std::vector<IpmRun> R(k);
   qp_status st = guarded(m, [&] {

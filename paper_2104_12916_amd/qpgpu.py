@@ -30,6 +30,7 @@ EXPORTS = (
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
     "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
     "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_shared_last_error", "qp_shared_destroy",
+    "qp_tune_set", "qp_tune_get",
 )
 
 
@@ -115,10 +116,12 @@ def lib():
     L.qp_shared_last_error.restype = ct.c_char_p
     L.qp_shared_destroy.argtypes = [P]
     L.qp_shared_destroy.restype = None
+    L.qp_tune_set.argtypes = [ct.c_char_p]
+    L.qp_tune_get.argtypes = [ct.c_char_p, ct.c_size_t, ct.POINTER(ct.c_size_t)]
     for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
                  "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get",
-                 "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve"):
+                 "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_tune_set", "qp_tune_get"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -149,6 +152,23 @@ def _where(*arrs):
     if len(ws) != 1:
         raise TypeError("mix of host and device arrays in one call")
     return ws.pop()
+
+
+def tune_get() -> str:
+    """Current launch-shape table (the cache format of autotune.py)."""
+    need = ct.c_size_t(0)
+    lib().qp_tune_get(None, 0, ct.byref(need))
+    buf = ct.create_string_buffer(need.value)
+    st = lib().qp_tune_get(buf, need.value, ct.byref(need))
+    if st != QP_OK:
+        raise QpError(st, "qp_tune_get failed")
+    return buf.value.decode()
+
+
+def tune_set(spec: str) -> None:
+    st = lib().qp_tune_set(spec.encode())
+    if st != QP_OK:
+        raise QpError(st, f"qp_tune_set rejected {spec!r}")
 
 
 class QpError(RuntimeError):

@@ -174,3 +174,36 @@ def test_shared_calls_reject_null_handles_and_unsupported_options():
     assert L.qp_shared_ipm_solve(None, 1, None, None, None, None, None, None, None, 0, None) == qpgpu.QP_E_INVALID
     assert L.qp_shared_last_error(None) == b""
     L.qp_shared_destroy(None)
+
+
+def test_tune_table_set_get_and_validation():
+    before = qpgpu.tune_get()
+    assert before.startswith("default ")
+    try:
+        qpgpu.tune_set("# comment\narch gfx950\ndefault rows_bpc=2\nn<=512 sym_wg=1,upd_threads=256\nn<=256 sym_rows=2")
+        t = qpgpu.tune_get().splitlines()
+        assert t[0].startswith("default ") and "rows_bpc=2" in t[0]
+        assert t[1].startswith("n<=256 ") and "sym_rows=2" in t[1] and "rows_bpc=2" in t[1]  # buckets sorted
+        assert t[2].startswith("n<=512 ") and "sym_wg=1" in t[2] and "upd_threads=256" in t[2]
+        for bad in ("default ld_pad=0", "n<=100 ld_pad=128", "default rows_bpc=99", "default nosuchkey=1",
+                    "n<=0 rows_bpc=2"):
+            with pytest.raises(qpgpu.QpError):
+                qpgpu.tune_set(bad)
+    finally:
+        qpgpu.tune_set(before)
+    assert qpgpu.tune_get() == before
+
+
+def test_committed_autotune_cache_parses():
+    path = os.path.join(os.path.dirname(os.path.abspath(qpgpu.LIB_PATH)), "autotune_gfx950.txt")
+    if not os.path.exists(path):
+        pytest.skip("no autotune cache")
+    before = qpgpu.tune_get()
+    try:
+        with open(path) as f:
+            text = f.read()
+        qpgpu.tune_set(text)  # accepted: layout keys equal to the built-in ones
+        want = [ln.split()[0] for ln in text.splitlines() if ln.startswith("n<=")]
+        assert [ln.split()[0] for ln in qpgpu.tune_get().splitlines()[1:]] == want
+    finally:
+        qpgpu.tune_set(before)
