@@ -36,11 +36,15 @@ SWEEPS = {
 
 
 def kernel_src_hash():
-    """Hash of the sources of the sweep kernels (counters go stale when they change)."""
+    """Hash of the sources of the sweep kernels and of their launch-shape table
+    (counters go stale when either changes)."""
     h = hashlib.sha256()
-    for f in ("gemv.hip", "gemv_core.hpp", "pcg.hip", "common.hpp"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("csrc/gemv.hip", "csrc/gemv_core.hpp", "csrc/pcg.hip", "csrc/common.hpp", "csrc/tune.hip",
+              "autotune_gfx950.txt"):
+        path = os.path.join(HERE, f)
+        if os.path.exists(path):
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
