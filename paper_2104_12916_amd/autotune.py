@@ -25,6 +25,7 @@ SPACE = [
     ("rows_unroll", [4, 8]),
     ("sym_wg", [1, 2, 3, 4]),
     ("sym_rows", [2, 4]),
+    ("sym_pipe", [0, 1]),
     ("ld_nt", [0, 1, 2, 3]),
     ("upd_threads", [256, 512, 1024]),
 ]

@@ -62,6 +62,8 @@ struct Tune {
   int k0_sym = 1;       // one pass over M for M^T Sigma M u (n small enough for register rows)
   int sym_wg = 2;       // one-pass sweep: workgroups per CU (each writes one partial of w)
   int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
+  int sym_pipe = 0;     // one-pass sweep: 1 issues the next 2 rows' loads before the current rows'
+                        // reduction (rounds of 2 rows; sym_rows is then ignored)
   int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
                           // 1 us faster per CG step than 1024 at m2 = 2048)
   int mv_rt = 1;         // multi-vector sweeps of the block PCG: rows per thread (1 or 2)

@@ -536,21 +536,142 @@ __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, in
   }
 }
 
+// Pipelined form of the same sweep: the loads of the next R rows are issued
+// before the current rows' dot, block reduction and accumulation, so the
+// workgroup keeps HBM requests in flight across its barriers (two register
+// buffers of R rows; R = 2 keeps them within 256 VGPRs at n = 4096).  Same
+// rows, same order, same arithmetic as k0_sym_body.
+template <typename T, int BT, int K, int R, bool NT>
+__device__ __forceinline__ void k0_sym_body_pipe(const T* __restrict__ M, int ldm, int N, int n,
+                                                 const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
+                                                 int g, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // before any matrix load is in flight
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CHB = BT * VE;
+  constexpr int NW = BT / kWave;
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int P = n / 2, U = (n + 1) / 2 + (N - n);
+  const int u0 = (int)((long long)g * U / G), u1 = (int)((long long)(g + 1) * U / G);
+  const int np = max(0, min(u1, P) - u0);
+  const int us = max(u0, P);
+  const int nrows = 2 * np + max(0, u1 - us);
+  T xu[K][VE], acc[K][VE];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int col = c * CHB + tid * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      xu[c][e] = (col + e < n) ? u[col + e] : T(0);
+      acc[c][e] = T(0);
+    }
+  }
+  __shared__ T sh[2][R][NW];
+  int buf = 0;
+  // Issue the loads of rows q0 .. q0 + R - 1 into a; lens[r] = entries of row r
+  // (0 past the workgroup's range).  Every lane issues every load (a lane past
+  // its row's length loads column 0 of a valid row; consume() masks it), so
+  // the loads form one unconditional group and the wait before a round's use
+  // leaves the next round's group in flight.
+  auto issue = [&](int q0, V (&a)[R][K], int (&rowi)[R], int (&lens)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = q0 + r;
+      int i = -1, len = 0;
+      if (q < nrows) {
+        i = sym_row(q, u0, np, us, n);
+        len = min(i + 1, n);
+      }
+      rowi[r] = i;
+      lens[r] = len;
+      const T* arow = M + (size_t)(i < 0 ? 0 : i) * ldm;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        const int col = c * CHB + tid * VE;
+        a[r][c] = ld16<V, NT>(reinterpret_cast<const V*>(arow + (col < len ? col : 0)));
+      }
+    }
+  };
+  // consume rows held in a (one block reduction for the R dots, then the rank-one updates)
+  auto consume = [&](V (&a)[R][K], const int (&rowi)[R], const int (&lens)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        const bool in = c * CHB + tid * VE < lens[r];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) a[r][c][e] = in ? a[r][c][e] : T(0);
+      }
+    }
+    T d[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      d[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < K; ++c) d[r] += dot16<V, T>(a[r][c], xu[c]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T s = wave_sum<T>(d[r]);
+      if (lane == 0) sh[buf][r][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T v = sh[buf][r][0];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) v += sh[buf][r][w2];
+      if (rowi[r] >= n) v = -v;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[c][e] += a[r][c][e] * v;
+      }
+    }
+    buf ^= 1;
+  };
+  V a0[R][K], a1[R][K];
+  int r0[R], r1[R], l0[R], l1[R];
+  issue(0, a0, r0, l0);
+  for (int q0 = 0; q0 < nrows; q0 += 2 * R) {
+    issue(q0 + R, a1, r1, l1);  // past the end: masked (one cached line per wave)
+    consume(a0, r0, l0);
+    if (q0 + R >= nrows) break;
+    issue(q0 + 2 * R, a0, r0, l0);
+    consume(a1, r1, l1);
+  }
+  T* pg = part + (size_t)g * ldp;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const int col = c * CHB + tid * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e)
+      if (col + e < n) pg[col + e] = acc[c][e];
+  }
+}
+
 // w_j = sum over g of part[g][j]: 16 columns per workgroup, 16 lanes per column
 // take g = t, t + 16, ... with four loads in flight, then a fixed butterfly.
-template <typename T, int BT, int K, int R, bool NT>
+template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
 __global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
                                                     const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
                                                     const int* __restrict__ skip) {
-  k0_sym_body<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
+  if constexpr (PIPE)
+    k0_sym_body_pipe<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
+  else
+    k0_sym_body<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
 }
 
-template <typename T, int BT, int K, int R, bool NT>
+template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
 __global__ void __launch_bounds__(BT) bk0_sym_kernel(const SymDesc<T>* __restrict__ descs,
                                                      const int* __restrict__ prefix, int ndesc) {
   const int j = desc_of_block(prefix, ndesc, blockIdx.x);
   const SymDesc<T> d = descs[j];
-  k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j], d.skip);
+  if constexpr (PIPE)
+    k0_sym_body_pipe<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j],
+                                      d.skip);
+  else
+    k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j], d.skip);
 }
 
 // Columns grp*16 .. +15 of w = sum over g of part[g].
@@ -615,15 +736,15 @@ int k0_sym_grid(int N, int n) {
 
 size_t k0_sym_part_elems(int n) { return (size_t)dev_info().cu_count * kMaxSymWg * k0_sym_ldp(n); }
 
-template <typename T, int BT, int R, bool NT>
+template <typename T, int BT, int R, bool NT, bool PIPE = false>
 static void launch_sym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const T* M, int ldm, int N, int n,
                          const T* u, T* part, int ldp, int G, const int* skip) {
   const dim3 blk(BT);
   switch (K) {
-    case 1: QPG_LAUNCH((k0_sym_kernel<T, BT, 1, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    case 2: QPG_LAUNCH((k0_sym_kernel<T, BT, 2, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    case 4: QPG_LAUNCH((k0_sym_kernel<T, BT, 4, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    default: QPG_LAUNCH((k0_sym_kernel<T, BT, 8, R, NT>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    case 1: QPG_LAUNCH((k0_sym_kernel<T, BT, 1, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 2: QPG_LAUNCH((k0_sym_kernel<T, BT, 2, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 4: QPG_LAUNCH((k0_sym_kernel<T, BT, 4, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    default: QPG_LAUNCH((k0_sym_kernel<T, BT, 8, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
   }
 }
 
@@ -638,7 +759,12 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
   const int K = k0_sym_width<T>(n);
   const dim3 grid(G);
   const bool nt = tune().ld_nt & 2;
-  if (tune().sym_rows == 2) {
+  if (tune().sym_pipe) {  // pipelined rounds of 2 rows
+    if (nt)
+      launch_sym_r<T, kSymBT, 2, true, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    else
+      launch_sym_r<T, kSymBT, 2, false, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+  } else if (tune().sym_rows == 2) {
     if (nt)
       launch_sym_r<T, kSymBT, 2, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
     else
@@ -687,15 +813,15 @@ bool fill_sym_desc(SymDesc<T>& d, const T* M, int ldm, int N, int n, const T* u,
          (size_t)d.G * d.ldp <= part_elems;
 }
 
-template <typename T, int R, bool NT>
+template <typename T, int R, bool NT, bool PIPE = false>
 static void launch_bsym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const SymDesc<T>* d,
                           const int* prefix, int ndesc) {
   const dim3 blk(kSymBT);
   switch (K) {
-    case 1: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 1, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    case 2: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 2, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    case 4: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 4, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    default: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 8, R, NT>), grid, blk, 0u, st, ev, d, prefix, ndesc);
+    case 1: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 1, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    case 2: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 2, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    case 4: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 4, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
+    default: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 8, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc);
   }
 }
 
@@ -706,7 +832,10 @@ hipError_t launch_bk0_sym(hipStream_t st, const SymDesc<T>* d, const int* prefix
   if (ndesc <= 0 || total_sweep <= 0) return hipSuccess;
   if (K != 1 && K != 2 && K != 4 && K != 8) return hipErrorInvalidValue;
   const dim3 grid(total_sweep);
-  if (tune().ld_nt & 2) {
+  if (tune().sym_pipe) {
+    if (tune().ld_nt & 2) launch_bsym_r<T, 2, true, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+    else launch_bsym_r<T, 2, false, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
+  } else if (tune().ld_nt & 2) {
     if (tune().sym_rows == 2) launch_bsym_r<T, 2, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
     else launch_bsym_r<T, 4, true>(K, grid, st, ev_sweep, d, prefix_sweep, ndesc);
   } else {

@@ -95,3 +95,50 @@ def test_autotune_cache_is_loaded(gpu, table):
         for x in want.split()[1].split(","):
             k, v = x.split("=")
             assert kv[k] == v, (got, want)
+
+
+ONE_PASS_SIZES = [(1, 1, 1), (3, 2, 5), (129, 65, 40), (513, 300, 64), (1025, 512, 100), (2049, 2049, 31),
+                  (4095, 9, 64), (4096, 3072, 257)]
+
+
+@pytest.mark.parametrize("sym_wg", [1, 2])
+@pytest.mark.parametrize("n,m1,m2", ONE_PASS_SIZES)
+def test_pipelined_one_pass_is_bitwise_the_two_row_sweep(gpu, table, sym_wg, n, m1, m2):
+    """The pipelined one-pass sweep reads the same rows in the same order with the
+    same arithmetic as the two-rows-per-round sweep: K_F p is bitwise equal."""
+    base = table.splitlines()[0]
+    qp = synth.gaussian_qp(5500 + n + m1, n, m1, m2)
+    s = qpgpu.Solver(*qp.arrays())
+    assert s.k0_one_pass()
+    s.factor()
+    dvec = synth.log_uniform(13, m2, 1e-3, 1e3)
+    p = np.random.default_rng(n + 7).standard_normal(m2)
+    out = {}
+    for pipe in (0, 1):
+        for nt in (1, 3):
+            qpgpu.tune_set(f"{base}\ndefault sym_rows=2,sym_pipe={pipe},sym_wg={sym_wg},ld_nt={nt}")
+            out[pipe, nt] = s.kf_apply(dvec, p)
+    s.close()
+    assert relerr(out[1, 1], reduced.kf_apply(qp, dvec, p)) <= k0_tol(qp)
+    for key in out:
+        assert np.array_equal(out[key], out[0, 1]), key
+
+
+def test_pipelined_one_pass_in_batches(gpu, table):
+    """Batched one-pass sweep (every QP of the batch in one launch) with and
+    without pipelining: bitwise the same IPM results."""
+    base = table.splitlines()[0]
+    rng = np.random.default_rng(77)
+    qps = [synth.gaussian_qp(5600 + i, int(nn), int(nn) // 4, int(nn) // 2)
+           for i, nn in enumerate(rng.integers(40, 700, size=6))]
+    res = {}
+    for pipe in (0, 1):
+        qpgpu.tune_set(f"{base}\ndefault sym_rows=2,sym_pipe={pipe}")
+        b = qpgpu.Batch(0, prec=qpgpu.QP_PREC_FEW_EQ)
+        tickets = [b.admit(*qp.arrays()) for qp in qps]
+        b.step(1000)
+        assert set(b.finished()) == set(tickets)
+        res[pipe] = [b.collect(t)[0] for t in tickets]
+        b.close()
+    for x0, x1, qp in zip(res[0], res[1], qps):
+        assert np.array_equal(x0, x1)
