@@ -599,6 +599,14 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=names[dom],
                     bytes_per_launch=nbytes[dom], avg_launch_us=round(avg_ms[dom] * 1e3, 2),
                     traffic_note=tnote)
+    # practical ceiling: the read rate of a plain streaming kernel over 2 GiB (8x the last-level cache)
+    probe = {}
+    for wg in (4, 8, 16):
+        probe[wg] = (2 << 30) / (min(qpgpu.hbm_read_time(2 << 30, wg, 10) for _ in range(3)) * 1e-3) / 1e9
+    best = max(probe, key=probe.get)
+    roofline["measured_read_peak"] = dict(
+        value=round(probe[best], 1), unit="GB/s", frac=round(achieved / probe[best], 4),
+        probe=f"qp_hbm_read_time: 2 GiB, 16-byte non-temporal loads, {best} workgroups per CU (best of 4, 8, 16)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -191,6 +191,16 @@ qp_status qp_ipm_solve(qp_ctx* ctx, double* x, double* lambda, double* nu, doubl
  * Overwrites the context's CG work vectors.  Requires qp_factor_K0. */
 qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, double* avg_ms);
 
+/* Diagnostic: the HBM read rate of a plain streaming kernel on the current
+ * device, the practical ceiling of the CG-step sweeps (all of which stream a
+ * matrix, Sec. 4.1).  Allocates a device buffer of `bytes` (a multiple of 16;
+ * pick several times the 256 MB last-level cache), reads it with 16-byte
+ * non-temporal loads from cu_count * wg_per_cu workgroups (1..32), and writes
+ * the average time (ms) of `reps` back-to-back passes to *avg_ms; frees the
+ * buffer before returning.  QP_E_INVALID for bad arguments (no device work),
+ * QP_E_NOMEM if the buffer does not fit, QP_E_DEVICE on a HIP error. */
+qp_status qp_hbm_read_time(size_t bytes, int wg_per_cu, int reps, double* avg_ms);
+
 /* Launch-shape table (workgroups per CU, loads in flight, one-pass sweep shape,
  * update width, cache policy of the matrix loads) of the streaming kernels, per
  * size bucket: calls on one QP use the bucket of its n, batches the base entry.

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqpgpu.so")
-SOURCES = ["api.hip", "batch.hip", "shared.hip", "gemv.hip", "blas.hip", "pcg.hip", "ipm.hip", "block.hip",
+SOURCES = ["api.hip", "batch.hip", "shared.hip", "gemv.hip", "blas.hip", "pcg.hip", "ipm.hip", "block.hip", "stream.hip",
            "tune.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

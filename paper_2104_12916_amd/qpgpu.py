@@ -30,7 +30,7 @@ EXPORTS = (
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
     "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
     "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_shared_last_error", "qp_shared_destroy",
-    "qp_tune_set", "qp_tune_get",
+    "qp_tune_set", "qp_tune_get", "qp_hbm_read_time",
 )
 
 
@@ -118,10 +118,12 @@ def lib():
     L.qp_shared_destroy.restype = None
     L.qp_tune_set.argtypes = [ct.c_char_p]
     L.qp_tune_get.argtypes = [ct.c_char_p, ct.c_size_t, ct.POINTER(ct.c_size_t)]
+    L.qp_hbm_read_time.argtypes = [ct.c_size_t, I, I, ct.POINTER(D)]
     for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
                  "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get",
-                 "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_tune_set", "qp_tune_get"):
+                 "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_tune_set", "qp_tune_get",
+                 "qp_hbm_read_time"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -163,6 +165,15 @@ def tune_get() -> str:
     if st != QP_OK:
         raise QpError(st, "qp_tune_get failed")
     return buf.value.decode()
+
+
+def hbm_read_time(nbytes: int, wg_per_cu: int = 8, reps: int = 20) -> float:
+    """Average ms of one streaming read of an nbytes device buffer (qp_hbm_read_time)."""
+    ms = ct.c_double(0.0)
+    st = lib().qp_hbm_read_time(nbytes, wg_per_cu, reps, ct.byref(ms))
+    if st != QP_OK:
+        raise QpError(st, "qp_hbm_read_time failed")
+    return ms.value
 
 
 def tune_set(spec: str) -> None:

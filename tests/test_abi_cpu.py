@@ -207,3 +207,11 @@ def test_committed_autotune_cache_parses():
         assert [ln.split()[0] for ln in qpgpu.tune_get().splitlines()[1:]] == want
     finally:
         qpgpu.tune_set(before)
+
+
+def test_hbm_read_probe_rejects_bad_arguments():
+    ms = ct.c_double(0.0)
+    L = qpgpu.lib()
+    for nbytes, wg, reps in ((0, 8, 1), (17, 8, 1), (1 << 20, 0, 1), (1 << 20, 33, 1), (1 << 20, 8, 0)):
+        assert L.qp_hbm_read_time(nbytes, wg, reps, ct.byref(ms)) == qpgpu.QP_E_INVALID
+    assert L.qp_hbm_read_time(1 << 20, 8, 1, None) == qpgpu.QP_E_INVALID

@@ -142,3 +142,11 @@ def test_pipelined_one_pass_in_batches(gpu, table):
         b.close()
     for x0, x1, qp in zip(res[0], res[1], qps):
         assert np.array_equal(x0, x1)
+
+
+def test_hbm_read_probe_rate_is_plausible(gpu):
+    """The read-rate probe streams its buffer: a rate between 1 TB/s and the 8 TB/s
+    interface peak (a 1 GiB buffer, 4x the last-level cache)."""
+    nbytes = 1 << 30
+    gbs = nbytes / (qpgpu.hbm_read_time(nbytes, 8, 5) * 1e-3) / 1e9
+    assert 1000.0 < gbs < 8000.0, gbs
