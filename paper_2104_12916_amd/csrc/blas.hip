@@ -174,23 +174,23 @@ constexpr double kPivRel = 1e-13;
 
 // Leaf: right-looking LDL^T of a <= 64 x 64 SPD block held in registers, then
 // L = L_1 D^{1/2} and X = L^{-1} = D^{-1/2} L_1^{-1}.  Thread t owns the 4 x 4
-// sub-block (rows 4 (t / 16) .., cols 4 (t % 16) ..) of both A and X.  Step j
-// publishes column j of A and row j of X (both final after step j - 1) in LDS
-// and every thread applies
+// sub-block (rows 4 (t / 16) .., cols 4 (t % 16) ..) of both A and X.  Column j
+// of the elimination applies
 //     a_ik -= (a_ij / a_jj) a_kj   (j < k <= i),    x_ik -= (a_ij / a_jj) x_jk   (i > j),
-// which needs a single barrier per step (the broadcast buffers alternate).
-// X starts as I; its rows only mix with earlier rows, so X stays lower triangular.
-__device__ __forceinline__ double pick4(const double (&v)[4], int k) {
-  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
-}
-
+// with X starting as I (its rows only mix with earlier rows, so it stays lower
+// triangular).  The columns are taken four at a time: the owners of column
+// block J publish it (and the owners of rows 4J..4J+3 those rows of X) in LDS,
+// one barrier, and then every thread eliminates the 4 x 4 diagonal block and
+// the block's part of the rows it needs, and applies the four column steps to
+// its sub-blocks.  Each entry sees the same updates in the same order as with
+// one column per step, with one barrier per four columns.
 __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
                                                    int nb, int* __restrict__ info, int code,
                                                    const double* __restrict__ dmax) {
-  __shared__ double colA[2][LEAF];
-  __shared__ double rowX[2][LEAF];
+  __shared__ double pan[2][LEAF][4];  // column block J of A (rows >= 4J), double-buffered
+  __shared__ double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J
   __shared__ double piv[LEAF];
-  const int t = threadIdx.x, r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15, r0 = tr * 4, c0 = tc * 4;
   const double pmin = kPivRel * (*dmax);
   double a[4][4], x[4][4];
 #pragma unroll
@@ -202,43 +202,132 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
       x[r][c] = (i == k && i < nb) ? 1.0 : 0.0;
     }
   bool bad = false;
-  for (int j = 0; j < nb; ++j) {
-    const int buf = j & 1, jj = j & 3;
-    if ((t & 15) == (j >> 2)) {
+  const int nblk = (nb + 3) / 4;
+  for (int J = 0; J < nblk; ++J) {
+    const int buf = J & 1, j0 = 4 * J;
+    if (tc == J && tr >= J) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) colA[buf][r0 + r] = pick4(a[r], jj);
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pan[buf][r0 + r][q] = a[r][q];
     }
-    if ((t >> 4) == (j >> 2)) {
+    if (tr == J) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double v = jj == 0 ? x[0][c] : (jj == 1 ? x[1][c] : (jj == 2 ? x[2][c] : x[3][c]));
-        rowX[buf][c0 + c] = v;
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xrow[buf][r][c0 + c] = x[r][c];
     }
     __syncthreads();
-    double ajj = colA[buf][j];
-    if (!(ajj > pmin) || !isfinite(ajj)) {  // same decision in every thread
-      bad = true;
-      ajj = 1.0;
-    }
-    if (t == 0) piv[j] = ajj;
-    const double inv = 1.0 / ajj;
-    double ck[4], xk[4];
+    // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
+    // at its own column step (E[p][p] is the pivot d_p).
+    double E[4][4], dinv[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      ck[c] = colA[buf][c0 + c];
-      xk[c] = rowX[buf][c0 + c];
-    }
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = r0 + r;
-      if (i > j && i < nb) {
-        const double coef = colA[buf][i] * inv;
+      for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? pan[buf][j0 + i][q] : 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      double d = E[p][p];
+      if (j0 + p < nb) {
+        if (!(d > pmin) || !isfinite(d)) {  // same decision in every thread
+          bad = true;
+          d = 1.0;
+        }
+      } else {
+        d = 1.0;  // past the block's end: the row and column are zero
+      }
+      E[p][p] = d;
+      dinv[p] = 1.0 / d;
+#pragma unroll
+      for (int i = p + 1; i < 4; ++i) {
+        const double coef = E[i][p] * dinv[p];
+#pragma unroll
+        for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
+      }
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) piv[j0 + p] = E[p][p];
+    }
+    // Row i >= j0 + 4 through the block's four steps: ev[p] = eliminated a_{i, j0+p},
+    // cf[p] = ev[p] / d_p (the multiplier of step j0 + p).
+    auto row_steps = [&](int i, double (&ev)[4], double (&cf)[4]) {
+      double g[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[q] = pan[buf][i][q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+#pragma unroll
+        for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
+        ev[p] = g[p];
+        cf[p] = g[p] * dinv[p];
+      }
+    };
+    double cfr[4][4], evr[4][4];  // this thread's rows r0 + r
+    if (tr > J) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) row_steps(min(r0 + r, LEAF - 1), evr[r], cfr[r]);
+    }
+    // A: the owners of the column block keep its eliminated values; sub-blocks right of
+    // it and on or below the diagonal take the four rank-one updates.
+    if (tc == J && tr == J) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q <= r; ++q) a[r][q] = E[r][q];
+    } else if (tc == J && tr > J) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r0 + r < nb) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[r][q] = evr[r][q];
+        }
+    } else if (tc > J && tr >= tc) {
+      double evc[4][4], cfc[4][4];  // the rows k = c0 + c (columns of this sub-block)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) row_steps(c0 + c, evc[c], cfc[c]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + r;
+        if (i >= nb) continue;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const int k = c0 + c;
-          if (k > j && k <= i) a[r][c] -= coef * ck[c];
-          x[r][c] -= coef * xk[c];
+          if (c0 + c > i) continue;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) a[r][c] -= cfr[r][p] * evc[c][p];
+        }
+      }
+    }
+    // X: rows j0..j0+3 first eliminate among themselves, then rows below take them.
+    if (tr >= J) {
+      double xf[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xf[p][c] = xrow[buf][p][c0 + c];
+#pragma unroll
+      for (int p = 1; p < 4; ++p)
+#pragma unroll
+        for (int pp = 0; pp < p; ++pp) {
+          const double l = E[p][pp] * dinv[pp];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) xf[p][c] -= l * xf[pp][c];
+        }
+      if (tr == J) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r0 + r < nb) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[r][c] = xf[r][c];
+          }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r0 + r >= nb) continue;
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[r][c] -= cfr[r][p] * xf[p][c];
         }
       }
     }
