@@ -7,8 +7,8 @@
 //                 the Cholesky factor (LL^T = A, X = L^{-1}).
 //   chol_inv      recursive blocked driver: with A = [A11 .; A21 A22],
 //                   (L11, X11) = chol_inv(A11);  L21 = A21 X11^T;
-//                   A22 -= L21 L21^T;            (L22, X22) = chol_inv(A22);
-//                   X21 = -X22 (L21 X11),
+//                   A22 -= L21 L21^T and T = L21 X11 (one launch);
+//                   (L22, X22) = chol_inv(A22);  X21 = -X22 T,
 //                 so almost every flop runs in the MFMA GEMM.
 #include <algorithm>
 #include <cstring>
@@ -162,6 +162,46 @@ hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double 
   hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc,
                      flags);
   return hipGetLastError();
+}
+
+// Two independent GEMMs in one launch (blockIdx.z selects the problem).
+struct GemmArgs {
+  int ta, tb, M, N, K;
+  double alpha;
+  const double* A;
+  int lda;
+  const double* B;
+  int ldb;
+  double beta;
+  double* C;
+  int ldc, flags;
+};
+
+__global__ void __launch_bounds__(256) gemm_f64_pair_kernel(GemmArgs g0, GemmArgs g1) {
+  const GemmArgs g = blockIdx.z == 0 ? g0 : g1;
+  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
+  gemm_body(g.M, g.N, g.K, g.alpha, g.A, g.lda, g.ta, g.B, g.ldb, g.tb, g.beta, g.C, g.ldc, g.flags, blockIdx.x,
+            blockIdx.y);
+}
+
+static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmArgs& g1) {
+  const int gx = (std::max(g0.N, g1.N) + GB - 1) / GB, gy = (std::max(g0.M, g1.M) + GB - 1) / GB;
+  if (gx <= 0 || gy <= 0) return hipSuccess;
+  if (gy > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gemm_f64_pair_kernel, dim3(gx, gy, 2), dim3(256), 0, st, g0, g1);
+  return hipGetLastError();
+}
+
+// Batched form: blockIdx.z < count0 takes d0[z] with o0, the rest d1[z - count0] with o1.
+__global__ void __launch_bounds__(256) gemm_f64_batched_pair_kernel(const GemmDesc* __restrict__ d0, int count0,
+                                                                    GemmOp o0, const GemmDesc* __restrict__ d1,
+                                                                    GemmOp o1) {
+  const int z = blockIdx.z;
+  const GemmDesc g = z < count0 ? d0[z] : d1[z - count0];
+  const GemmOp o = z < count0 ? o0 : o1;
+  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
+  gemm_body(g.M, g.N, g.K, o.alpha, g.A, g.lda, o.ta, g.B, g.ldb, o.tb, o.beta, g.C, g.ldc, o.flags, blockIdx.x,
+            blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,7 +425,9 @@ static int split_of(int n) {
 }
 
 // Recursive body.  A: n x n (lower part read, overwritten with scratch), X: n x n
-// output (upper part must be zero on entry), tmp: at least (n/2 + 64) * n doubles.
+// output (upper part must be zero on entry), tmp: chol_inv_tmp_elems(n) - 1
+// doubles (a node keeps its n2 x n1 block of L21 X11 while its right child
+// works past it; the deepest chain of such blocks stays below that size).
 static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, int ldx, int n, double* tmp,
                                int* info, int code, const double* dmax) {
   hipError_t e;
@@ -404,11 +446,14 @@ static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, in
   if ((e = chol_inv_rec(st, A11, lda, X11, ldx, n1, tmp, info, code, dmax)) != hipSuccess) return e;
   // L21 = A21 X11^T  (op(B) = X11^T is upper triangular) -> stored in X21
   if ((e = gemm_f64(st, 0, 1, n2, n1, n1, 1.0, A21, lda, X11, ldx, 0.0, X21, ldx, kBUpper)) != hipSuccess) return e;
-  // A22 -= L21 L21^T (lower part only)
-  if ((e = gemm_f64(st, 0, 1, n2, n2, n1, -1.0, X21, ldx, X21, ldx, 1.0, A22, lda, kOutLower)) != hipSuccess) return e;
-  if ((e = chol_inv_rec(st, A22, lda, X22, ldx, n2, tmp, info, code, dmax)) != hipSuccess) return e;
-  // tmp = L21 X11 (X11 lower), then X21 = -X22 tmp (X22 lower)
-  if ((e = gemm_f64(st, 0, 0, n2, n1, n1, 1.0, X21, ldx, X11, ldx, 0.0, tmp, n1, kBLower)) != hipSuccess) return e;
+  // one launch, both reading only L21 and X11: A22 -= L21 L21^T (lower part) and
+  // tmp = L21 X11 (X11 lower)
+  const GemmArgs s22{0, 1, n2, n2, n1, -1.0, X21, ldx, X21, ldx, 1.0, A22, lda, kOutLower};
+  const GemmArgs t21{0, 0, n2, n1, n1, 1.0, X21, ldx, X11, ldx, 0.0, tmp, n1, kBLower};
+  if ((e = gemm_f64_pair(st, s22, t21)) != hipSuccess) return e;
+  double* tmp_right = tmp + (size_t)n2 * n1;  // past this node's block
+  if ((e = chol_inv_rec(st, A22, lda, X22, ldx, n2, tmp_right, info, code, dmax)) != hipSuccess) return e;
+  // X21 = -X22 tmp (X22 lower)
   if ((e = gemm_f64(st, 0, 0, n2, n1, n2, -1.0, X22, ldx, tmp, n1, 0.0, X21, ldx, kALower)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -472,12 +517,35 @@ void BatchedOps::gemm(int ta, int tb, double alpha, double beta, int flags, cons
   o.count = (int)d.size();
   o.gx = (nx + GB - 1) / GB;
   o.gy = (mx + GB - 1) / GB;
-  o.ta = ta;
-  o.tb = tb;
-  o.flags = flags;
-  o.alpha = alpha;
-  o.beta = beta;
+  o.g0 = GemmOp{ta, tb, flags, alpha, beta};
   o.off = push(d);
+  ops_.push_back(o);
+}
+
+void BatchedOps::gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, const GemmOp& o1,
+                           const std::vector<GemmDesc>& d1) {
+  if (d0.empty() || d1.empty()) {
+    if (!d0.empty()) gemm(o0.ta, o0.tb, o0.alpha, o0.beta, o0.flags, d0);
+    if (!d1.empty()) gemm(o1.ta, o1.tb, o1.alpha, o1.beta, o1.flags, d1);
+    return;
+  }
+  int mx = 0, nx = 0;
+  for (const auto* d : {&d0, &d1})
+    for (const GemmDesc& g : *d) {
+      mx = std::max(mx, g.M);
+      nx = std::max(nx, g.N);
+    }
+  if (mx <= 0 || nx <= 0) return;
+  Op o{};
+  o.kind = 3;
+  o.count = (int)d0.size();
+  o.count2 = (int)d1.size();
+  o.gx = (nx + GB - 1) / GB;
+  o.gy = (mx + GB - 1) / GB;
+  o.g0 = o0;
+  o.g1 = o1;
+  o.off = push(d0);
+  o.off2 = push(d1);
   ops_.push_back(o);
 }
 
@@ -512,6 +580,7 @@ void BatchedOps::rec(const std::vector<CholJob>& jobs, int off, int len) {
   const int n1 = len / 2;
   rec(jobs, off, n1);
   std::vector<GemmDesc> g1, g2, g3, g4;
+  std::vector<CholJob> right;  // jobs reaching the right child, scratch past this node's block
   for (const CholJob& j : jobs) {
     const int n2 = std::min(len, j.n - off) - n1;
     if (n2 <= 0) continue;
@@ -522,13 +591,15 @@ void BatchedOps::rec(const std::vector<CholJob>& jobs, int off, int len) {
     double* X22 = X21 + n1;
     g1.push_back(GemmDesc{A21, X11, X21, j.lda, j.ldx, j.ldx, n2, n1, n1});    // L21 = A21 X11^T
     g2.push_back(GemmDesc{X21, X21, A22, j.ldx, j.ldx, j.lda, n2, n2, n1});    // A22 -= L21 L21^T
-    g3.push_back(GemmDesc{X21, X11, j.tmp, j.ldx, j.ldx, n1, n2, n1, n1});     // tmp = L21 X11
-    g4.push_back(GemmDesc{X22, j.tmp, X21, j.ldx, n1, j.ldx, n2, n1, n2});     // X21 = -X22 tmp
+    g3.push_back(GemmDesc{X21, X11, j.work, j.ldx, j.ldx, n1, n2, n1, n1});    // tmp = L21 X11
+    g4.push_back(GemmDesc{X22, j.work, X21, j.ldx, n1, j.ldx, n2, n1, n2});    // X21 = -X22 tmp
+    CholJob r = j;
+    r.work = j.work + (size_t)n2 * n1;
+    right.push_back(r);
   }
   gemm(0, 1, 1.0, 0.0, kBUpper, g1);
-  gemm(0, 1, -1.0, 1.0, kOutLower, g2);
-  rec(jobs, off + n1, len - n1);
-  gemm(0, 0, 1.0, 0.0, kBLower, g3);
+  gemm_pair(GemmOp{0, 1, kOutLower, -1.0, 1.0}, g2, GemmOp{0, 0, kBLower, 1.0, 0.0}, g3);
+  rec(right, off + n1, len - n1);
   gemm(0, 0, -1.0, 0.0, kALower, g4);
 }
 
@@ -545,7 +616,9 @@ void BatchedOps::chol_inv(const std::vector<CholJob>& jobs) {
   o.count = (int)d.size();
   o.off = push(d);
   ops_.push_back(o);
-  rec(jobs, 0, len);
+  std::vector<CholJob> js = jobs;
+  for (CholJob& j : js) j.work = j.tmp;
+  rec(js, 0, len);
 }
 
 hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
@@ -560,7 +633,14 @@ hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
       case 1:
         if (o.gy > 65535) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gemm_f64_batched_kernel, dim3(o.gx, o.gy, o.count), dim3(256), 0, st,
-                           reinterpret_cast<const GemmDesc*>(base + o.off), o.ta, o.tb, o.alpha, o.beta, o.flags);
+                           reinterpret_cast<const GemmDesc*>(base + o.off), o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
+                           o.g0.flags);
+        break;
+      case 3:
+        if (o.gy > 65535 || o.count + o.count2 > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gemm_f64_batched_pair_kernel, dim3(o.gx, o.gy, o.count + o.count2), dim3(256), 0, st,
+                           reinterpret_cast<const GemmDesc*>(base + o.off), o.count, o.g0,
+                           reinterpret_cast<const GemmDesc*>(base + o.off2), o.g1);
         break;
       default:
         hipLaunchKernelGGL(diag_max_batched_kernel, dim3(o.count), dim3(256), 0, st,

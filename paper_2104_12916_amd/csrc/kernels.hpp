@@ -123,6 +123,12 @@ struct CholJob {
   double* tmp;
   int* info;
   int code;
+  double* work = nullptr;  // scratch of the node being recorded (BatchedOps sets it inside tmp)
+};
+// Operation of one list of a batched GEMM launch: C = alpha op(A) op(B) + beta C.
+struct GemmOp {
+  int ta, tb, flags;
+  double alpha, beta;
 };
 
 // A recorded sequence of batched factorization launches.  Descriptor lists are
@@ -131,6 +137,9 @@ struct CholJob {
 class BatchedOps {
  public:
   void gemm(int ta, int tb, double alpha, double beta, int flags, const std::vector<GemmDesc>& d);
+  // Two independent lists with their own operations in one launch.
+  void gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, const GemmOp& o1,
+                 const std::vector<GemmDesc>& d1);
   void chol_inv(const std::vector<CholJob>& jobs);
   bool empty() const { return ops_.empty(); }
   const std::vector<unsigned char>& bytes() const { return bytes_; }
@@ -138,9 +147,9 @@ class BatchedOps {
 
  private:
   struct Op {
-    int kind, count, gx, gy, ta, tb, flags;
-    double alpha, beta;
-    size_t off;
+    int kind, count, count2, gx, gy;
+    GemmOp g0, g1;
+    size_t off, off2;
   };
   template <typename D>
   size_t push(const std::vector<D>& v);
