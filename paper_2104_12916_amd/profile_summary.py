@@ -57,6 +57,7 @@ def algorithmic_bytes(n, m1, m2, elem=8):
 
 
 def _short(name):
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "").replace("qpg::", "").strip()
 
 
