@@ -466,7 +466,7 @@ __device__ __forceinline__ void diag_max_body(const double* __restrict__ A, int 
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sh[0];

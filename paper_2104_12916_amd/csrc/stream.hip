@@ -59,19 +59,19 @@ extern "C" qp_status qp_hbm_read_time(size_t bytes, int wg_per_cu, int reps, dou
     const auto* p = static_cast<const qpg::v2d_probe_t*>(buf);
     const size_t n2 = bytes / 16;
     hipLaunchKernelGGL(qpg::hbm_read_kernel, dim3(grid), dim3(qpg::kProbeBT), 0, nullptr, p, n2, out);  // warm-up
-    hipEventRecord(e0, nullptr);
+    bool ok = hipEventRecord(e0, nullptr) == hipSuccess;
     for (int r = 0; r < reps; ++r)
       hipLaunchKernelGGL(qpg::hbm_read_kernel, dim3(grid), dim3(qpg::kProbeBT), 0, nullptr, p, n2, out);
-    hipEventRecord(e1, nullptr);
-    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-      st = QP_E_DEVICE;
-    else
+    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, nullptr) == hipSuccess &&
+         hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok)
       *avg_ms = (double)ms / reps;
+    else
+      st = QP_E_DEVICE;
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (out) hipFree(out);
-  if (buf) hipFree(buf);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (out) (void)hipFree(out);
+  if (buf) (void)hipFree(buf);
   return st;
 }
