@@ -46,6 +46,15 @@ def run_batch(qps, budget=0, rounds=1000, **opts):
     return out
 
 
+def _check_reported(qp, x, lam, nu, info):
+    """The KKT score and objective the library reports for its returned iterate
+    (computed in float64 on the GPU) agree with the oracle's on the same iterate."""
+    sc, _ = kkt.rel_kkt(qp, x, lam, nu)
+    assert abs(info.rel_kkt - sc) <= 1e-12 + 1e-6 * sc, (info.rel_kkt, sc)
+    f = kkt.objective(qp, x)
+    assert abs(info.obj - f) <= 1e-10 * max(1.0, abs(f)), (info.obj, f)
+
+
 def check_against_oracle(qp, x, lam, nu, f_ref):
     score, parts = kkt.rel_kkt(qp, x, lam, nu)
     assert score <= 1e-8, parts
@@ -62,6 +71,7 @@ def test_batch_matches_oracle(gpu, prec, precision):
         ref = ipm.solve(qp)
         assert ref.converged
         check_against_oracle(qp, x, lam, nu, ref.obj)
+        _check_reported(qp, x, lam, nu, info)
         assert np.all(nu > 0) and np.all(s > 0)
         assert info.status == qpgpu.QP_OK and info.ipm_iters <= ref.iters + 10
         assert info.t_solve_ms > 0

@@ -64,6 +64,15 @@ def test_fullsize_pcg_true_residual(gpu, lowdof):
     assert info.iters <= 10 * qp.m2
 
 
+def _check_reported(qp, x, lam, nu, info):
+    """The KKT score and objective the library reports for its returned iterate
+    (computed in float64 on the GPU) agree with the oracle's on the same iterate."""
+    sc, _ = kkt.rel_kkt(qp, x, lam, nu)
+    assert abs(info.rel_kkt - sc) <= 1e-12 + 1e-6 * sc, (info.rel_kkt, sc)
+    f = kkt.objective(qp, x)
+    assert abs(info.obj - f) <= 1e-10 * max(1.0, abs(f)), (info.obj, f)
+
+
 def test_fullsize_lowdof_ipm_matches_oracle(gpu, lowdof):
     qp, s = lowdof
     g = golden("lowdof", 100)
@@ -73,6 +82,7 @@ def test_fullsize_lowdof_ipm_matches_oracle(gpu, lowdof):
     f = kkt.objective(qp, x)
     assert abs(f - g["obj"]) <= 1e-7 * max(1.0, abs(g["obj"]))
     assert info.ipm_iters <= g["iters"] + 10
+    _check_reported(qp, x, lam, nu, info)  # the score bench.py counts solves by
 
 
 def test_fullsize_fewEq_ipm_matches_oracle(gpu):

@@ -106,6 +106,15 @@ def test_pcg_iteration_count_follows_the_corollaries(gpu, n, m1, m2, prec, bound
     s.close()
 
 
+def _check_reported(qp, x, lam, nu, info):
+    """The KKT score and objective the library reports for its returned iterate
+    (computed in float64 on the GPU) agree with the oracle's on the same iterate."""
+    sc, _ = kkt.rel_kkt(qp, x, lam, nu)
+    assert abs(info.rel_kkt - sc) <= 1e-12 + 1e-6 * sc, (info.rel_kkt, sc)
+    f = kkt.objective(qp, x)
+    assert abs(info.obj - f) <= 1e-10 * max(1.0, abs(f)), (info.obj, f)
+
+
 def _check_ipm(qp, x, lam, nu, f_ref):
     sc, parts = kkt.rel_kkt(qp, x, lam, nu)
     assert sc <= 1e-8, parts
@@ -123,6 +132,7 @@ def test_ipm_small_workload_matches_oracle(gpu, seed, prec):
     s.factor()
     x, lam, nu, sl, info = s.ipm()
     _check_ipm(qp, x, lam, nu, ref.obj)
+    _check_reported(qp, x, lam, nu, info)
     assert np.all(nu > 0) and np.all(sl > 0)
     assert info.ipm_iters <= ref.iters + 5
     s.close()

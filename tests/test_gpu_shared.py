@@ -69,6 +69,15 @@ def test_block_pcg_with_identity_C(gpu):
         assert relerr(dnu[j], ref) <= 1e-8, j
 
 
+def _check_reported(qp, x, lam, nu, info):
+    """The KKT score and objective the library reports for its returned iterate
+    (computed in float64 on the GPU) agree with the oracle's on the same iterate."""
+    sc, _ = kkt.rel_kkt(qp, x, lam, nu)
+    assert abs(info.rel_kkt - sc) <= 1e-12 + 1e-6 * sc, (info.rel_kkt, sc)
+    f = kkt.objective(qp, x)
+    assert abs(info.obj - f) <= 1e-10 * max(1.0, abs(f)), (info.obj, f)
+
+
 @pytest.mark.parametrize("n,m1,m2,k", [(60, 20, 30, 4), (200, 50, 100, 12), (140, 100, 90, 20)])
 @pytest.mark.parametrize("prec", [PL, PN, qpgpu.QP_PREC_AUTO])
 def test_shared_ipm_matches_oracle(gpu, n, m1, m2, k, prec):
@@ -85,6 +94,7 @@ def test_shared_ipm_matches_oracle(gpu, n, m1, m2, k, prec):
         f_ref = ipm.solve(q).obj
         assert abs(kkt.objective(q, x[j]) - f_ref) <= 1e-7 * max(1.0, abs(f_ref)), j
         assert infos[j].status == qpgpu.QP_OK
+        _check_reported(q, x[j], lam[j], nu[j], infos[j])
 
 
 def test_shared_ipm_on_syqp_family(gpu):
