@@ -474,7 +474,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (independent QPs shard "
-              "across GPUs with no exchange, and this build measures one GPU's share).", file=sys.stderr)
+              "across GPUs with no exchange; bench.py measures one GPU).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         if args.precision == "fp64" and "--precision" not in sys.argv:
