@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .kkt import rel_kkt, objective
+from .kkt import rel_kkt, objective, newton_residuals
 
 
 class OracleInputError(ValueError):
@@ -91,6 +91,19 @@ def max_step(v, dv) -> float:
     return float(np.min(-v[neg] / dv[neg]))
 
 
+def centering(mu, mu_aff) -> float:
+    """Mehrotra's centering parameter sigma = (mu_aff / mu)^3 (sigma of eq. nonlinear)."""
+    return (mu_aff / mu) ** 3
+
+
+def corrector_rc(s, nu, ds_aff, dnu_aff, sigma, mu):
+    """Last block of the corrector right-hand side: S V e + dS_aff dV_aff e - sigma mu e.
+
+    The complementarity row of eq. nonsym-indef-KKT with Mehrotra's second-order term.
+    """
+    return s * nu + ds_aff * dnu_aff - sigma * mu
+
+
 def newton_matrix(qp, nu, s):
     """Coefficient matrix of eq. nonsym-indef-KKT at (nu, s)."""
     n, m1, m2 = qp.n, qp.m1, qp.m2
@@ -125,12 +138,11 @@ def solve(qp, tol: float = 1e-10, max_iter: int = 200, tau: float = 0.995,
     converged = sc <= tol
     limit = max_iter if max_iters_cap is None else min(max_iter, max_iters_cap)
     while not converged and it < limit:
-        r_d = qp.H @ x + qp.c - qp.A.T @ lam - qp.C.T @ nu
-        r_e = qp.A @ x - qp.b
-        r_i = qp.C @ x - qp.d - s
+        # residuals of eq. rhs-KKT4; the first row of eq. nonsym-indef-KKT carries -r_g
+        r_g, r_e, r_i = newton_residuals(qp, x, lam, nu, s)
         mu = float(s @ nu) / m2
         lu = sla.lu_factor(newton_matrix(qp, nu, s))
-        base = np.concatenate([r_d, r_e, r_i])
+        base = np.concatenate([-r_g, r_e, r_i])
 
         def split(sol):
             return (sol[:n], sol[n:n + m1], sol[n + m1:n + m1 + m2], sol[n + m1 + m2:])
@@ -140,9 +152,9 @@ def solve(qp, tol: float = 1e-10, max_iter: int = 200, tau: float = 0.995,
         dx_a, dl_a, dn_a, ds_a = aff
         a_aff = min(1.0, max_step(s, ds_a), max_step(nu, dn_a))
         mu_aff = float((s + a_aff * ds_a) @ (nu + a_aff * dn_a)) / m2
-        sigma = (mu_aff / mu) ** 3
+        sigma = centering(mu, mu_aff)
         # corrector
-        rc = s * nu + ds_a * dn_a - sigma * mu
+        rc = corrector_rc(s, nu, ds_a, dn_a, sigma, mu)
         dx, dl, dn, ds = split(sla.lu_solve(lu, -np.concatenate([base, rc])))
         a_max = min(max_step(s, ds), max_step(nu, dn))
         alpha = min(1.0, tau * a_max)

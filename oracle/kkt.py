@@ -47,8 +47,8 @@ def rel_kkt(qp, x, lam, nu):
     rho_d = inf(rd) / (1.0 + max(inf(Hx), inf(qp.c), inf(ATl), inf(CTn)))
     rho_e = inf(Ax - qp.b) / (1.0 + max(inf(Ax), inf(qp.b)))
     rho_p = (float(np.max(np.maximum(qp.d - Cx, 0.0))) if Cx.size else 0.0) / (1.0 + inf(qp.d))
-    pobj = float(0.5 * x @ Hx + qp.c @ x)
-    dobj = float(-0.5 * x @ Hx + qp.b @ lam + qp.d @ nu)
+    pobj = objective(qp, x)
+    dobj = dual_objective(qp, x, lam, nu)
     rho_gap = abs(pobj - dobj) / (1.0 + abs(pobj))
     rho_nu = max(0.0, float(np.max(-nu)) if nu.size else 0.0) / (1.0 + inf(nu))
     parts = dict(rho_d=rho_d, rho_e=rho_e, rho_p=rho_p, rho_gap=rho_gap, rho_nu=rho_nu)
