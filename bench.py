@@ -15,8 +15,15 @@ Prints one JSON line.  Extra objects:
                 library's stream during the timed solves (qp_profile_get);
                 traffic from the committed rocprofv3 counter summary when it was
                 taken on the current kernel source, else null
-  cpu_baseline  the oracle on this host's cores, a bounded sample of the same
-                instance extrapolated to a whole solve
+  cpu_baseline  the oracle on this host's cores: one whole timed solve of the
+                same instance (the full-system IPM to its own tolerance)
+  batch         the 512-QP batched workload beside the headline: batched mixed
+                precision, batched float64 and the single-QP float64 path over
+                the same QPs resident in HBM (solves/s each), the share of CG
+                steps run in float64, and the objectives of a fixed 24-QP sample
+                against the oracle's stored values (tests/golden)
+  cg_per_ipm_iter  CG steps of every predictor and corrector solve of one
+                headline solve beside the Theorem thm1 / thm2 bound
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload lowdof]
 
 --workload batch: 512 independent QPs (n ~ U{64..1024}, m1 = n/4, m2 = n/2)
@@ -90,6 +97,33 @@ def golden(workload, seed):
         with open(path) as f:
             return json.load(f)
     return None
+
+
+def golden_set(name):
+    """Stored oracle results of a named instance set ({seed: record}; {} if absent)."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_set_{name}.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return {r["seed"]: r for r in json.load(f)["records"]}
+
+
+def cpu_baseline_full(workload, seed):
+    """One whole oracle solve of the same instance, timed on this host's cores."""
+    import synth
+    from oracle import ipm
+    from threadpoolctl import threadpool_info
+    qp = synth.workload(workload, seed=seed)
+    t0 = time.perf_counter()
+    r = ipm.solve(qp)
+    el = time.perf_counter() - t0
+    threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
+    return {
+        "value": 1.0 / el, "unit": "QP solves/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"one whole solve of seed {seed}: validation, initial point and {r.iters} full-system IPM "
+                   f"iterations (dense LU of the {qp.n + qp.m1 + 2 * qp.m2}-square Newton matrix) to rel KKT "
+                   f"{r.rel_kkt:.1e} in {el:.1f} s; {os.cpu_count()} host CPUs"),
+    }
 
 
 def cpu_baseline(workload, seed, sample_iters, gpu_iters):
@@ -181,6 +215,122 @@ def batch_roofline(prof, elem):
                 traffic_note="no counters taken for the batched sweeps"), ops
 
 
+def batch_instances(count):
+    """The batched workload's QPs, generated on the host and copied to HBM once."""
+    import torch
+    import synth
+    sizes = synth.batch_sizes(count, 1000)
+    t = time.perf_counter()
+    qps = [synth.gaussian_qp(*sz) for sz in sizes]
+    print(f"generated {len(qps)} QPs in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    dev = [tuple(torch.from_numpy(a).cuda() for a in qp.arrays()) for qp in qps]
+    torch.cuda.synchronize()
+    return sizes, qps, dev
+
+
+def solve_batch(dev, k, budget, profile=False, **opts):
+    """Admit the first k resident QPs into one batch and run it to the end.
+    Returns (seconds, [(x, lam, nu, s, info)], ticks, sampled profile)."""
+    import torch
+    from paper_2104_12916_amd import qpgpu
+    b = qpgpu.Batch(budget, profile=int(profile), **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [b.admit(*dev[i]) for i in range(k)]
+    assert all(tk is not None for tk in tickets), "batch budget too small"
+    rounds = 0
+    while b.query()["in_flight"]:
+        b.step(1)
+        rounds += 1
+    out = [b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV)) for tk in tickets]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = b.profile() if profile else None
+    b.close()
+    return el, out, rounds, prof
+
+
+def batch_quality(sizes, res, gold):
+    """Parity and work counts of one batched run: every QP's reported KKT score,
+    the objectives of the stored oracle sample, CG steps and their float64 share."""
+    from paper_2104_12916_amd import qpgpu
+    bad, worst, worst_obj, sampled = set(), 0.0, 0.0, 0
+    ipm_it, cg, cg64, fb = [], 0, 0, 0
+    for i, (x, lam, nu, s, info) in enumerate(res):
+        worst = max(worst, info.rel_kkt)
+        ok = info.rel_kkt <= 1e-8 and info.status == qpgpu.QP_OK
+        g = gold.get(sizes[i][0])
+        if g is not None:
+            e = abs(info.obj - g["obj"]) / max(1.0, abs(g["obj"]))
+            worst_obj = max(worst_obj, e)
+            sampled += 1
+            ok = ok and e <= 1e-7
+        if not ok:
+            bad.add(i)
+        ipm_it.append(info.ipm_iters)
+        cg += info.pcg_iters_total
+        cg64 += info.pcg_iters_fp64
+        fb += info.fp64_fallbacks
+    return dict(passed=len(res) - len(bad), solves=len(res), max_rel_kkt=worst,
+                sample_max_obj_rel_err=worst_obj, sample_checked=sampled,
+                ipm_iters_range=[min(ipm_it), max(ipm_it)], reduced_solves=2 * sum(ipm_it),
+                fp64_fallback_solves=fb, cg_steps=int(cg), cg_steps_fp64=int(cg64),
+                fp64_cg_share=round(cg64 / max(1, cg), 4))
+
+
+def single_qp_loop(dev, qps, k, prec):
+    """The plain single-QP float64 path over the first k resident QPs, one after another."""
+    import torch
+    from paper_2104_12916_amd import qpgpu
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(k):
+        sv = qpgpu.Solver(*dev[i], prec=prec)
+        sv.factor()
+        x = torch.empty(qps[i].n, dtype=torch.float64, device="cuda")
+        lam = torch.empty(qps[i].m1, dtype=torch.float64, device="cuda")
+        nu = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
+        sl = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
+        st_, info = qpgpu.qp_ipm_solve(sv.ctx, x, lam, nu, sl)
+        infos.append(info)
+        sv.close()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, infos
+
+
+def config4_legs(count=512, single=True):
+    """The 512-QP batched workload: batched mixed, batched float64 and the single-QP
+    float64 loop over the same QPs in HBM (factorization and every IPM iteration inside
+    the clock; one 16-QP warm-up batch per precision first)."""
+    from paper_2104_12916_amd import qpgpu
+    sizes, qps, dev = batch_instances(count)
+    gold = golden_set("batch24")
+    out = {"workload": BATCH_DESC, "qps": count}
+    for name, precision in (("batched_mixed", qpgpu.QP_MIXED), ("batched_fp64", qpgpu.QP_FP64)):
+        opt = qpgpu.qp_default_options(prec=qpgpu.QP_PREC_AUTO, precision=precision)
+        budget = int(1.05 * sum(qpgpu.qp_batch_footprint(opt, q.n, q.m1, q.m2) for q in qps)) + (64 << 20)
+        solve_batch(dev, min(16, count), budget, prec=qpgpu.QP_PREC_AUTO, precision=precision)
+        el, res, rounds, _ = solve_batch(dev, count, budget, prec=qpgpu.QP_PREC_AUTO, precision=precision)
+        q = batch_quality(sizes, res, gold)
+        out[name] = dict(value=round(q["passed"] / el, 2), unit="QP solves/s", seconds=round(el, 3), ticks=rounds,
+                         dtype="f32+f64" if precision == qpgpu.QP_MIXED else "f64", **q)
+        print(f"config-4 {name}: {count} QPs in {el:.2f} s, {q['passed']} pass, fp64 CG share "
+              f"{q['fp64_cg_share']}", file=sys.stderr, flush=True)
+    if single:
+        el, infos = single_qp_loop(dev, qps, count, qpgpu.QP_PREC_AUTO)
+        res = [(None, None, None, None, i) for i in infos]
+        q = batch_quality(sizes, res, gold)
+        out["single_qp_fp64"] = dict(value=round(q["passed"] / el, 2), unit="QP solves/s", seconds=round(el, 3),
+                                     path="qp_setup + qp_factor_K0 + qp_ipm_solve per QP, float64", **q)
+        print(f"config-4 single-QP fp64 loop: {count} QPs in {el:.2f} s", file=sys.stderr, flush=True)
+        base = out["single_qp_fp64"]["value"]
+        out["speedup_batched_mixed_vs_single_fp64"] = round(out["batched_mixed"]["value"] / base, 2)
+        out["speedup_batched_fp64_vs_single_fp64"] = round(out["batched_fp64"]["value"] / base, 2)
+    out["speedup_mixed_vs_fp64_batched"] = round(out["batched_mixed"]["value"] / out["batched_fp64"]["value"], 3)
+    return out
+
+
 def run_batch_workload(args):
     import numpy as np
     import torch
@@ -191,31 +341,12 @@ def run_batch_workload(args):
             "auto": qpgpu.QP_PREC_AUTO}[args.prec or "auto"]
     precision = qpgpu.QP_FP64 if args.precision == "fp64" else qpgpu.QP_MIXED
     kf = qpgpu.QP_KF_EXPLICIT if args.kf == "explicit" else qpgpu.QP_KF_IMPLICIT
-    sizes = synth.batch_sizes(args.batch_count, 1000)
-    t = time.perf_counter()
-    qps = [synth.gaussian_qp(*sz) for sz in sizes]
-    print(f"generated {len(qps)} QPs in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
-    dev = [tuple(torch.from_numpy(a).cuda() for a in qp.arrays()) for qp in qps]
-    torch.cuda.synchronize()
+    sizes, qps, dev = batch_instances(args.batch_count)
     opt = qpgpu.qp_default_options(prec=prec, precision=precision, kf_form=kf)
     budget = int(1.05 * sum(qpgpu.qp_batch_footprint(opt, q.n, q.m1, q.m2) for q in qps)) + (64 << 20)
 
     def solve_all(k, profile):
-        b = qpgpu.Batch(budget, prec=prec, precision=precision, profile=int(profile), kf_form=kf)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tickets = [b.admit(*dev[i]) for i in range(k)]
-        assert all(tk is not None for tk in tickets), "batch budget too small"
-        rounds = 0
-        while b.query()["in_flight"]:
-            b.step(1)
-            rounds += 1
-        out = [b.collect(tk, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV)) for tk in tickets]
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        prof = b.profile() if profile else None
-        b.close()
-        return el, out, rounds, prof
+        return solve_batch(dev, k, budget, profile, prec=prec, precision=precision, kf_form=kf)
 
     for w in range(args.warmup):
         solve_all(min(16, len(qps)), False)
@@ -229,34 +360,15 @@ def run_batch_workload(args):
             res, prof = out, p
         print(f"step {st + 1}/{steps}: {len(qps)} QPs in {el:.2f} s ({rounds} rounds)", file=sys.stderr, flush=True)
     elapsed = sum(times)
-    # every result's reported KKT score (objectives against the oracle: tests/test_gpu_batch.py)
-    bad, worst = set(), 0.0
-    ipm_it, cg = [], 0
-    for i, (x, lam, nu, s, info) in enumerate(res):
-        worst = max(worst, info.rel_kkt)
-        if not (info.rel_kkt <= 1e-8 and info.status == qpgpu.QP_OK):
-            bad.add(i)
-        ipm_it.append(info.ipm_iters)
-        cg += info.pcg_iters_total
-    ok = len(qps) - len(bad)
+    # every result's reported KKT score, and the stored oracle objectives of the 24-QP sample
+    quality = batch_quality(sizes, res, golden_set("batch24"))
+    ok, worst = quality["passed"], quality["max_rel_kkt"]
     print(f"parity: {ok}/{len(qps)} pass; worst rel_kkt {worst:.2e}", file=sys.stderr, flush=True)
     # the single-QP float64 path over the same resident QPs
     single = None
     if args.single_count > 0:
         k = min(args.single_count, len(qps))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(k):
-            sv = qpgpu.Solver(*dev[i], prec=prec)
-            sv.factor()
-            x = torch.empty(qps[i].n, dtype=torch.float64, device="cuda")
-            lam = torch.empty(qps[i].m1, dtype=torch.float64, device="cuda")
-            nu = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
-            sl = torch.empty(qps[i].m2, dtype=torch.float64, device="cuda")
-            st_, info = qpgpu.qp_ipm_solve(sv.ctx, x, lam, nu, sl)
-            sv.close()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        el, _ = single_qp_loop(dev, qps, k, prec)
         single = dict(value=k / el, unit="QP solves/s", qps=k, seconds=round(el, 3),
                       path="qp_setup + qp_factor_K0 + qp_ipm_solve per QP, float64, inputs in HBM")
         print(f"single-QP fp64 loop: {k} QPs in {el:.2f} s", file=sys.stderr, flush=True)
@@ -276,12 +388,10 @@ def run_batch_workload(args):
         "config": {"workload": f"batch: {BATCH_DESC}", "qps": len(qps), "precond": args.prec or "auto",
                    "precision": args.precision, "kf_form": args.kf, "budget_bytes": budget},
         "roofline": roof, "cpu_baseline": cpu,
-        "parity": dict(passed=ok, solves=len(qps), max_rel_kkt=worst,
-                       note="rel KKT score the library reports per QP; objectives against the oracle in "
-                            "tests/test_gpu_batch.py"),
+        "parity": dict(note="rel KKT score the library reports per QP; objectives of the 24-QP sample against "
+                            "the oracle's stored values", **quality),
         "single_qp_fp64_gpu": single,
         "speedup_vs_single_qp_fp64": (value / single["value"]) if single else None,
-        "ipm_iters_range": [min(ipm_it), max(ipm_it)], "cg_steps_total": int(cg),
         "batched_sweeps": ops,
     }
     print(json.dumps(line), flush=True)
@@ -464,7 +574,10 @@ def main():
     ap.add_argument("--kf", default="implicit", choices=["implicit", "explicit"],
                     help="how each CG step applies K_F (explicit: operator formed once per QP)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--cpu-sample-iters", type=int, default=0,
+                    help="0: time one whole oracle solve; k > 0: k IPM iterations extrapolated")
+    ap.add_argument("--no-batch-legs", action="store_true",
+                    help="skip the 512-QP batched legs that the default workload reports beside its headline")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--single-count", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -591,9 +704,29 @@ def main():
         value=round(probe[best], 1), unit="GB/s", frac=round(achieved / probe[best], 4),
         probe=f"qp_hbm_read_time: 2 GiB, 16-byte non-temporal loads, {best} workgroups per CU (best of 4, 8, 16)")
 
+    # CG steps of every reduced solve of one headline solve beside the theorem bound
+    pred, corr = solvers[0].cg_steps()
+    if prec == qpgpu.QP_PREC_LOW_DOF:
+        bound, thm = min(qp0.m2, qp0.n - qp0.m1) + 1, "thm1 / cor:cg1 (P_L): min(m2, n - m1) + 1"
+    elif prec == qpgpu.QP_PREC_FEW_EQ:
+        bound, thm = min(qp0.m2, qp0.m1) + 1, "thm2 / cor:cg2 (P_H): min(m2, m1) + 1"
+    else:
+        bound, thm = qp0.m2, "no preconditioner: m2"
+    cg_per_iter = dict(seed=seeds[0], predictor=pred, corrector=corr, bound=bound, theorem=thm,
+                       over_bound=sum(int(k > bound) for k in pred + corr), solves=len(pred) + len(corr),
+                       note="exact-arithmetic bound; the late IPM iterations' ill-conditioned systems need more "
+                            "steps in float64")
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, seeds[0], args.cpu_sample_iters, ipm_iters[0])
+        if args.cpu_sample_iters > 0:
+            cpu = cpu_baseline(args.workload, seeds[0], args.cpu_sample_iters, ipm_iters[0])
+        else:
+            cpu = cpu_baseline_full(args.workload, seeds[0])
+
+    batch = None
+    if args.workload == "lowdof" and not args.no_batch_legs:
+        batch = config4_legs(args.batch_count, single=args.single_count > 0)
 
     # a0 (and a0' for P_H): algorithmic flops of the once-per-QP factorization over its wall time
     n, m1, m2 = qp0.n, qp0.m1, qp0.m2
@@ -620,11 +753,12 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": dict(passed=ok, solves=len(outs), max_rel_kkt=worst_kkt, max_obj_rel_err=worst_obj),
-        "ipm_iters": ipm_iters, "cg_iters": cg_iters,
+        "ipm_iters": ipm_iters, "cg_iters": cg_iters, "cg_per_ipm_iter": cg_per_iter,
         "us_per_cg_step": round(elapsed / max(1, sum(cg_iters)) * 1e6, 2),
         "us_per_ipm_iter": round(elapsed / max(1, sum(ipm_iters)) * 1e6, 1),
         "factor": factor,
         "cg_step_sweeps": ops,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

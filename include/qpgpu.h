@@ -27,7 +27,10 @@
  *              read during the call; outputs are written to caller buffers.
  *   Streams    all device work runs on the stream given to qp_setup (a
  *              hipStream_t, or NULL for a stream owned by the context); calls
- *              return after their results are complete.
+ *              return after their results are complete.  Device inputs are
+ *              read on that stream, and a context-owned stream does not wait
+ *              for any other: the caller orders the work that wrote them
+ *              before the call (by passing its stream, or by synchronizing it).
  *   Errors     status codes only; no C++ exception crosses the ABI.  The text
  *              of the last error of a context is available from qp_last_error.
  *   Threads    a context is not thread-safe; distinct contexts are independent.
@@ -41,7 +44,7 @@
 extern "C" {
 #endif
 
-#define QPGPU_ABI_VERSION 3
+#define QPGPU_ABI_VERSION 4
 
 typedef struct qp_ctx qp_ctx;
 
@@ -124,6 +127,8 @@ typedef struct {
   int refinements_total;   /* float64 refinement sweeps over all reduced solves   */
   int fp64_fallbacks;      /* mixed reduced solves finished by float64 CG          */
   double t_solve_ms;       /* wall time of qp_ipm_solve (host clock)              */
+  long long pcg_iters_fp64; /* CG steps run in float64: all of pcg_iters_total with
+                              QP_FP64, the float64 fallback's share with QP_MIXED */
 } qp_ipm_info;
 
 /* Defaults listed in the field comments above. */
@@ -270,6 +275,9 @@ const char* qp_last_error(const qp_ctx* ctx);
  * buffers from it; a QP's memory returns as soon as it finishes.  Admission is
  * refused with QP_E_NOMEM while the QP does not fit (qp_batch_footprint tells
  * its size), or when 4096 QPs are in flight.
+ *
+ * Device inputs of qp_batch_admit are read on the batch's stream, which waits
+ * for no other stream: the caller finishes the work that wrote them first.
  *
  * Flow: qp_batch_admit (any time between steps) -> qp_batch_step (ticks) ->
  * qp_batch_finished lists finished tickets -> qp_batch_collect copies a result

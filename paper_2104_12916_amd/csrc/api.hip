@@ -795,13 +795,15 @@ void kf_apply_dev(qp_ctx* ctx, const double* dvec, const double* p, double* q) {
 // device float64 vectors.  Returns CG steps; sets *done to the PCG stop code.
 static int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double* rhs, double* dnu,
                          const double* wts, double rtol, double wtol, int maxit, int* done, int* refinements,
-                         int* fallback) {
+                         int* fallback, int* iters64) {
   *refinements = 0;
   *fallback = 0;
+  *iters64 = 0;
   if (ctx->opt.precision != QP_MIXED) {
     PcgBufs<double> B = bufs64(ctx, dvec, wts, dnu);
     PcgResult r = run_pcg<double>(ctx, B, rhs, prec, rtol, wtol, maxit);
     *done = r.done;
+    *iters64 = r.iters;
     return r.iters;
   }
   // Mixed: float32 PCG sweeps on the residual equation K_F delta = r inside a
@@ -848,6 +850,7 @@ static int reduced_solve(qp_ctx* ctx, int prec, const double* dvec, const double
       const double rtol64 = h.rr > 0.0 ? rtol * std::sqrt(h.bb / h.rr) : rtol;
       PcgResult r64 = run_pcg<double>(ctx, B64, ctx->ir_r, prec, rtol64, wtol, maxit - total);
       total += r64.iters;
+      *iters64 = r64.iters;
       HIPCHK(ctx, vec_add(st, m2, ctx->ir_d, dnu));
       *done = r64.done;
       *fallback = 1;
@@ -1003,6 +1006,7 @@ void ipm_fill_info(const qp_ctx* ctx, const IpmRun& R, qp_ipm_info* info) {
   info->status = R.status;
   info->refinements_total = R.refin_total;
   info->fp64_fallbacks = R.fallbacks;
+  info->pcg_iters_fp64 = ctx->opt.precision == QP_MIXED ? R.cg64 : R.cg_total;
 }
 
 static void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
@@ -1014,16 +1018,18 @@ static void ipm_run(qp_ctx* ctx, qp_ipm_info* info) {
     sync(ctx);
     if (!ipm_check(ctx, R)) break;
     ipm_predictor_setup(ctx, R);
-    int done = 0, refin = 0, fb = 0;
+    int done = 0, refin = 0, fb = 0, it64 = 0;
     R.k1 = reduced_solve(ctx, R.prec, ctx->dvec, ctx->rhs, ctx->dnu_a, ctx->nu, ctx->opt.cg_rtol, R.wtol, R.maxit,
-                         &done, &refin, &fb);
+                         &done, &refin, &fb, &it64);
     R.refin_total += refin;
     R.fallbacks += fb;
+    R.cg64 += it64;
     ipm_after_predictor(ctx);
     R.k2 = reduced_solve(ctx, R.prec, ctx->dvec, ctx->rhs, ctx->dnu, ctx->nu, ctx->opt.cg_rtol, R.wtol, R.maxit,
-                         &done, &refin, &fb);
+                         &done, &refin, &fb, &it64);
     R.refin_total += refin;
     R.fallbacks += fb;
+    R.cg64 += it64;
     ipm_after_corrector(ctx, R);
   }
   ipm_fill_info(ctx, R, info);
@@ -1231,8 +1237,9 @@ qp_status qp_pcg_solve(qp_ctx* ctx, const double* dvec, const double* rhs, doubl
       }
     }
     int mi = maxit > 0 ? maxit : 10 * m2;
-    int done = 0, refin = 0, fb = 0;
-    int iters = reduced_solve(ctx, mode, ctx->dvec, ctx->rhs, ctx->dnu, nullptr, rtol, -1.0, mi, &done, &refin, &fb);
+    int done = 0, refin = 0, fb = 0, it64 = 0;
+    int iters = reduced_solve(ctx, mode, ctx->dvec, ctx->rhs, ctx->dnu, nullptr, rtol, -1.0, mi, &done, &refin, &fb,
+                              &it64);
     // true residual in float64
     kf_apply_dev(ctx, ctx->dvec, ctx->dnu, ctx->ir_x);
     HIPCHK(ctx, ir_residual(ctx->stream, m2, ctx->rhs, ctx->ir_x, nullptr, ctx->ir_r, ctx->sc));

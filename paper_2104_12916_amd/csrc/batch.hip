@@ -69,6 +69,7 @@ struct Slot {
   // the reduced solve in flight: which system, CG steps and refinement state
   int which = 0;  // 0 predictor, 1 corrector
   int s_iters = 0, s_refin = 0, s_fb = 0, s_done = 0, last_done = 0;
+  int s_iters64 = 0;  // mixed precision: CG steps of the float64 fallback run
   double prev_rr = -1.0, rtol64 = 0.0;
   long long launched = 0;  // CG steps launched for the current CG run
   BItem<double> it64{};    // current float64 CG run
@@ -978,7 +979,7 @@ void start_solve(qp_batch* B, const std::vector<Slot*>& ss, int which) {
   if (ss.empty()) return;
   for (Slot* s : ss) {
     s->which = which;
-    s->s_iters = s->s_refin = s->s_fb = 0;
+    s->s_iters = s->s_refin = s->s_fb = s->s_iters64 = 0;
     s->s_done = 2;
     s->last_done = 0;
     s->prev_rr = -1.0;
@@ -1001,6 +1002,7 @@ void solves_done(qp_batch* B, std::vector<Slot*>& d0, std::vector<Slot*>& d1) {
       (s->which ? R.k2 : R.k1) = s->s_iters;
       R.refin_total += s->s_refin;
       R.fallbacks += s->s_fb;
+      R.cg64 += s->s_iters64;
     }
   if (!d0.empty()) {
     bphase_recover_step(B, d0, 0);
@@ -1186,6 +1188,7 @@ bool advance(qp_batch* B) {
       done_solve(s);
     } else {
       // float64 leg of a mixed solve: add the correction
+      s->s_iters64 += h.iter;
       s->s_done = h.done;
       s->s_fb = 1;
       fb.push_back(s);

@@ -216,6 +216,7 @@ int mixed_inner_cap(const qp_ctx* ctx, int prec);
 struct IpmRun {
   int prec = 0, maxit = 0, it = 0;
   long long cg_total = 0;
+  long long cg64 = 0;  // mixed precision: CG steps of the float64 fallback runs
   int refin_total = 0, fallbacks = 0;
   int k1 = 0, k2 = 0;
   double score = 0, parts[5] = {0, 0, 0, 0, 0};

@@ -55,7 +55,7 @@ class qp_ipm_info(ct.Structure):
         ("ipm_iters", ct.c_int), ("pcg_iters_total", ct.c_longlong), ("rel_kkt", ct.c_double),
         ("rel_kkt_parts", ct.c_double * 5), ("obj", ct.c_double), ("mu", ct.c_double),
         ("status", ct.c_int), ("refinements_total", ct.c_int), ("fp64_fallbacks", ct.c_int),
-        ("t_solve_ms", ct.c_double),
+        ("t_solve_ms", ct.c_double), ("pcg_iters_fp64", ct.c_longlong),
     ]
 
 
@@ -149,6 +149,30 @@ def _ptr(a):
     raise TypeError(f"unsupported array type {type(a)}")
 
 
+def _has_tensor(*arrs) -> bool:
+    return any(not isinstance(a, np.ndarray) for a in arrs)
+
+
+def _torch_stream(*arrs):
+    """torch's current stream (as an int) when any argument is a torch tensor and
+    that stream is not the null stream, else None."""
+    if not _has_tensor(*arrs):
+        return None
+    import torch
+    return torch.cuda.current_stream().cuda_stream or None
+
+
+def _wait_torch(*arrs) -> None:
+    """Wait for torch's current stream when any argument is a torch tensor.
+
+    The library reads device inputs (and writes device outputs) on its own stream,
+    which waits for no other stream; this orders the call after the torch work that
+    wrote the inputs or still reads the outputs."""
+    if _has_tensor(*arrs):
+        import torch
+        torch.cuda.current_stream().synchronize()
+
+
 def _where(*arrs):
     ws = {_ptr(a)[1] for a in arrs}
     if len(ws) != 1:
@@ -205,9 +229,13 @@ def qp_last_error(ctx) -> str:
 
 
 def qp_setup(H, c, A, b, C, d, opt: qp_options | None = None, stream=None):
-    """Returns (status, ctx).  stream: hipStream_t as int, or None."""
+    """Returns (status, ctx).  stream: hipStream_t as int, or None (torch's current
+    stream for torch tensors, else a stream owned by the context)."""
     n, m1, m2 = H.shape[0], A.shape[0], C.shape[0]
     where = _where(H, c, A, b, C, d)
+    _wait_torch(H, c, A, b, C, d)
+    if stream is None:
+        stream = _torch_stream(H, c, A, b, C, d)
     ctx = ct.c_void_p()
     if opt is None:
         opt = qp_default_options()
@@ -221,15 +249,18 @@ def qp_factor_K0(ctx) -> int:
 
 
 def qp_k0_solve(ctx, rhs, out) -> int:
+    _wait_torch(rhs, out)
     return lib().qp_k0_solve(ctx, _ptr(rhs)[0], _ptr(out)[0], _where(rhs, out))
 
 
 def qp_kf_apply(ctx, dvec, p, q) -> int:
+    _wait_torch(dvec, p, q)
     return lib().qp_kf_apply(ctx, _ptr(dvec)[0], _ptr(p)[0], _ptr(q)[0], _where(dvec, p, q))
 
 
 def qp_pcg_solve(ctx, dvec, rhs, dnu, prec: int, rtol: float, maxit: int = 0):
     info = qp_pcg_info()
+    _wait_torch(dvec, rhs, dnu)
     st = lib().qp_pcg_solve(ctx, _ptr(dvec)[0], _ptr(rhs)[0], _ptr(dnu)[0], _where(dvec, rhs, dnu), int(prec),
                             float(rtol), int(maxit), ct.byref(info))
     return st, info
@@ -237,6 +268,7 @@ def qp_pcg_solve(ctx, dvec, rhs, dnu, prec: int, rtol: float, maxit: int = 0):
 
 def qp_ipm_solve(ctx, x, lam, nu, s):
     info = qp_ipm_info()
+    _wait_torch(x, lam, nu, s)
     st = lib().qp_ipm_solve(ctx, _ptr(x)[0], _ptr(lam)[0], _ptr(nu)[0], _ptr(s)[0], _where(x, lam, nu, s),
                             ct.byref(info))
     return st, info
@@ -276,9 +308,11 @@ def qp_batch_create(opt: qp_options | None = None, budget_bytes: int = 0, stream
 
 
 def qp_batch_admit(batch, H, c, A, b, C, d):
-    """Returns (status, ticket)."""
+    """Returns (status, ticket).  Torch tensors: waits for torch's current stream
+    first, since the batch reads them on its own stream."""
     n, m1, m2 = H.shape[0], A.shape[0], C.shape[0]
     where = _where(H, c, A, b, C, d)
+    _wait_torch(H, c, A, b, C, d)
     t = ct.c_longlong(0)
     st = lib().qp_batch_admit(batch, n, m1, m2, *(_ptr(a)[0] for a in (H, c, A, b, C, d)), where, ct.byref(t))
     return st, t.value
@@ -302,6 +336,7 @@ def qp_batch_finished(batch, cap: int = 4096):
 def qp_batch_collect(batch, ticket: int, x, lam, nu, s):
     """Returns (status of the QP, qp_ipm_info)."""
     info = qp_ipm_info()
+    _wait_torch(x, lam, nu, s)
     st = lib().qp_batch_collect(batch, int(ticket), _ptr(x)[0], _ptr(lam)[0], _ptr(nu)[0], _ptr(s)[0],
                                 _where(x, lam, nu, s), ct.byref(info))
     return st, info
@@ -359,6 +394,10 @@ class Batch:
         self.sizes[t] = (H.shape[0], A.shape[0], C.shape[0])
         return t
 
+    def footprint(self, n: int, m1: int, m2: int) -> int:
+        """Arena bytes a QP of these sizes takes under this batch's options."""
+        return qp_batch_footprint(self.opt, n, m1, m2)
+
     def step(self, rounds: int = 1) -> int:
         st, nd = qp_batch_step(self.b, rounds)
         if st != QP_OK:
@@ -409,6 +448,9 @@ class Shared:
         self.n, self.m1, self.m2 = H.shape[0], A.shape[0], C.shape[0]
         (ph, where), (pa, _), (pc, _) = _ptr(H), _ptr(A), _ptr(C)
         _where(H, A, C)
+        _wait_torch(H, A, C)
+        if stream is None:
+            stream = _torch_stream(H, A, C)
         out = ct.c_void_p()
         st = lib().qp_shared_setup(ct.byref(out), self.n, self.m1, self.m2, ph, pa, pc, where, ct.byref(self.opt),
                                    stream)

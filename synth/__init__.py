@@ -37,7 +37,8 @@ import numpy as np
 
 __all__ = [
     "QP", "gaussian_qp", "illcond_qp", "box_qp", "syqp", "tiny_qp",
-    "batch_sizes", "serving_stream", "log_uniform", "workload", "shared_family",
+    "batch_sizes", "batch_sample", "large_batch_sizes", "serving_stream", "log_uniform", "workload",
+    "shared_family",
 ]
 
 
@@ -208,6 +209,27 @@ def batch_sizes(count: int = 512, seed: int = 1000):
     rng = np.random.default_rng(seed)
     ns = rng.integers(64, 1025, size=count)
     return [(seed + i, int(n), int(n) // 4, int(n) // 2) for i, n in enumerate(ns)]
+
+
+def batch_sample(count: int = 24, top: int = 8, total: int = 512, seed: int = 1000):
+    """A fixed sample of the batched workload's draw batch_sizes(total, seed).
+
+    The ``top`` largest QPs of the draw (its n >= 1008 end) and ``count - top``
+    others evenly spaced in the order of n, so the sample spans the whole size
+    range.  Returns (seed_i, n, m1, m2) tuples in draw order.
+    """
+    sizes = batch_sizes(total, seed)
+    ns = np.array([sz[1] for sz in sizes])
+    order = np.argsort(ns, kind="stable")
+    rest = order[:-top]
+    pick = rest[np.linspace(0, len(rest) - 1, count - top).round().astype(int)]
+    return [sizes[i] for i in sorted(set(order[-top:].tolist()) | set(pick.tolist()))]
+
+
+def large_batch_sizes():
+    """QPs of the batched workload's shape (m1 = n/4, m2 = n/2) above its n <= 1024
+    range, at n = 1500, 2500 and 4000 (the largest sizes of the streamed mix)."""
+    return [(7001, 1500, 375, 750), (7002, 2500, 625, 1250), (7003, 4000, 1000, 2000)]
 
 
 def serving_stream(count: int, seed: int = 5000, base: int = 10 ** 6,

@@ -80,6 +80,32 @@ def test_diag_ph_ipm_matches_oracle(gpu, kind, seed):
     s.close()
 
 
+@pytest.mark.parametrize("kind,n,m1,m2", [("gaussian", 60, 4, 80), ("gaussian", 90, 10, 70), ("illcond", 64, 8, 64)])
+def test_diag_ph_step_count_follows_the_oracle(gpu, kind, n, m1, m2):
+    """On a general H the diagonal form is a different preconditioner from the exact
+    P_H: the GPU takes the oracle's step count under P_H_diag (the same recurrence in
+    the same precision), and that count differs from the exact form's,
+    so the test tells the two forms apart."""
+    gen = synth.gaussian_qp if kind == "gaussian" else synth.illcond_qp
+    qp = gen(5150 + n + m1, n, m1, m2)
+    dvec = synth.log_uniform(25, m2, 1e-2, 1e2)
+    rhs = np.random.default_rng(m2).standard_normal(m2)
+    K = reduced.kf_explicit(qp, dvec)
+    counts = {}
+    for name, P in (("diag", reduced.P_H_diag(qp, dvec)), ("exact", reduced.P_H(qp, dvec))):
+        cf = sla.cho_factor(P)
+        _, counts[name], _ = reduced.pcg(lambda v: K @ v, rhs, lambda r: sla.cho_solve(cf, r), 1e-6, 10 * m2)
+    assert abs(counts["diag"] - counts["exact"]) >= 3, counts
+    s = qpgpu.Solver(*qp.arrays(), ph_form=DIAG)
+    s.factor()
+    dnu, info = s.pcg(dvec, rhs, prec=PH, rtol=1e-6)
+    s.close()
+    # long float64 CG runs may drift by a few steps between two summation orders
+    assert abs(info.iters - counts["diag"]) <= max(1, 0.05 * counts["diag"]), (info.iters, counts)
+    ref = sla.cho_solve(sla.cho_factor(K), rhs)
+    assert relerr(dnu, ref) <= 1e-4
+
+
 def test_diag_ph_is_the_exact_ph_for_diagonal_H(gpu):
     qp = synth.gaussian_qp(5200, 150, 40, 120)
     qp.H = np.ascontiguousarray(np.diag(np.linspace(0.2, 5.0, 150)))
