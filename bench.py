@@ -64,9 +64,12 @@ WORKLOADS = {
 OP_NAMES = ["gemv_rows_kernel<T,1> (C^T p over stored C^T)", "gemv_rows_kernel<T,2> (Sigma M u)",
             "gemv_rows_kernel<T,3> (M^T v over stored M^T)", "pcg_q_kernel<T> (C w + D p)",
             "gemv_rows_kernel<T,4> (X_P r)", "gemv_cols_part_kernel<T,5> (X_P^T t)"]
-# with the one-pass K0 product, slots 1 and 2 hold its sweep and the sum of its partials
+# with the one-pass K0 product, slots 1 and 2 hold its sweep and the sum of its partials, and
+# slots 4 and 5 the one-pass P_H apply X_P^T X_P r (m2 <= 4096) and the sum of its partials
 OP_NAMES_ONE_PASS = OP_NAMES[:1] + ["k0_sym_kernel<T> (M^T Sigma M u, one pass over M)",
-                                    "k0_sym_reduce_kernel<T> (sum of the per-workgroup partials of w)"] + OP_NAMES[3:]
+                                    "k0_sym_reduce_kernel<T> (sum of the per-workgroup partials of w)"] + OP_NAMES[3:4] + [
+    "k0_sym_kernel<T> over X_P (X_P^T X_P r, one pass)", "k0_sym_reduce_kernel<T> (sum of the partials of z)"]
+ONE_PASS_MAX = 4096  # widest operand of the float64 one-pass sweep
 
 
 def op_bytes(n, m1, m2, elem):
@@ -201,6 +204,10 @@ def batch_roofline(prof, elem):
              "bgemv_rows_kernel<T,4> (X_P r)", "bgemv_cols_part_kernel<T,5> (X_P^T t)"]
     if cnt[1] > 0 and by[2] == 0:  # one pass over M: slot 1 is that sweep (its partial sums carry no matrix bytes)
         names[1] = "bk0_sym_kernel<T> (M^T Sigma M u, one pass over M)"
+        names[2] = "bk0_sym_reduce_kernel<T> (sum of the partials of w)"
+    if cnt[4] > 0 and by[5] == 0:  # one pass over X_P in the P_H apply, then the sum of its partials
+        names[4] = "bk0_sym_kernel<T> over X_P (X_P^T X_P r, one pass)"
+        names[5] = "bk0_sym_reduce_kernel<T> (sum of the partials of z)"
     ops = {}
     for o in range(6):
         if cnt[o] > 0 and ms[o] > 0:
@@ -573,6 +580,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kf", default="implicit", choices=["implicit", "explicit"],
                     help="how each CG step applies K_F (explicit: operator formed once per QP)")
+    ap.add_argument("--cg-graph", type=int, default=0, choices=[0, 1],
+                    help="1: replay each poll chunk of CG steps as a captured hipGraph (single-QP workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
                     help="0: time one whole oracle solve; k > 0: k IPM iterations extrapolated")
@@ -618,7 +627,8 @@ def main():
     for sd in seeds:
         qp = synth.workload(args.workload, seed=sd)
         qps.append(qp)
-        solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=1, kf_form=kf))
+        solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=0 if args.cg_graph else 1,
+                                    kf_form=kf, cg_graph=args.cg_graph))
     torch.cuda.synchronize()
 
     factor_s = []
@@ -681,6 +691,10 @@ def main():
     tags = ["C^T", "M1" if one_pass else "M", "M1red" if one_pass else "M^T", "q", "XP", "XP^T"]
     if one_pass:  # M is read once; the partial sums are workspace, not operator bytes
         nbytes[2] = 0
+        if qp0.m2 <= ONE_PASS_MAX:  # so is X_P in the P_H apply
+            nbytes[5] = 0
+        else:
+            names = names[:4] + OP_NAMES[4:]
     if kf == qpgpu.QP_KF_EXPLICIT:  # one sweep over E (m2 x m2) replaces the four operator sweeps
         nbytes = [0, 0, 0, qp0.m2 * qp0.m2 * elem] + nbytes[4:]
     ops = {}
@@ -689,6 +703,8 @@ def main():
             ops[names[o]] = dict(avg_us=round(avg_ms[o] * 1e3, 2), samples=int(cnt[o]),
                                  bytes=nbytes[o], gbs=round(nbytes[o] / (avg_ms[o] * 1e-3) / 1e9, 1))
     dom = int(np.argmax(avg_ms))
+    if avg_ms[dom] <= 0:  # no samples (graph replay takes none)
+        avg_ms[dom] = float("nan")
     achieved = nbytes[dom] / (avg_ms[dom] * 1e-3) / 1e9
     traffic, tnote = load_traffic(args.workload, tags[dom])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -749,7 +765,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
         "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
         "config": {"workload": f"{args.workload}: {w['desc']}", "seeds": seeds, "precond": prec_name,
-                   "precision": args.precision, "kf_form": args.kf},
+                   "precision": args.precision, "kf_form": args.kf, "cg_graph": args.cg_graph},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": dict(passed=ok, solves=len(outs), max_rel_kkt=worst_kkt, max_obj_rel_err=worst_obj),

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define QPGPU_ABI_VERSION 4
+#define QPGPU_ABI_VERSION 5
 
 typedef struct qp_ctx qp_ctx;
 
@@ -106,6 +106,10 @@ typedef struct {
                        poll chunk with HIP events (read with qp_profile_get)     */
   qp_kf_form kf_form; /* how the CG step applies K_F (QP_KF_IMPLICIT)            */
   qp_ph_form ph_form; /* which H the few-equalities preconditioner uses (EXACT)   */
+  int cg_graph;     /* 1: a single-QP solve captures its chunk of poll_every CG
+                       steps once as a hipGraph and replays it for every chunk
+                       (same kernels and arguments; no profile samples); 0: the
+                       steps are launched one by one (0)                        */
 } qp_options;
 
 typedef struct {
@@ -222,8 +226,10 @@ qp_status qp_tune_get(char* buf, size_t len, size_t* needed);
 /* Average device time (ms) per launch and sample counts of the CG-step kernels
  * sampled while options.profile is set, in the order of qp_op_time's ops 0-3
  * (C^T p, Sigma M u or the one-pass sweep of M, M^T v or the sum of its
- * partials, q = C w + D p), then for P_H the X_P r row sweep and the X_P^T t
- * column sweep.  reset != 0 clears them. */
+ * partials, q = C w + D p), then for P_H the apply z = X_P^T X_P r: its one pass
+ * over X_P and the sum of its partials when m2 <= 4096 and the one-pass K0
+ * product is on, else the X_P r row sweep and the X_P^T t column sweep.
+ * reset != 0 clears them. */
 qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], int reset);
 
 /* 1 if the context's implicit CG step forms K0^{-1}_{11} u = M^T Sigma M u

@@ -209,6 +209,11 @@ void download_vec(qp_ctx* ctx, double* dst, const double* src, int n, qp_mem whe
 
 void sync(qp_ctx* ctx) { HIPCHK(ctx, hipStreamSynchronize(ctx->stream)); }
 
+void release_cg_graphs(qp_ctx* ctx) {
+  for (auto& e : ctx->cg_graphs) (void)hipGraphExecDestroy(e.second);
+  ctx->cg_graphs.clear();
+}
+
 bool finite_all(const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -243,7 +248,7 @@ qp_status check_options(const qp_options& o) {
   if (!(o.tau > 0 && o.tau < 1) || o.max_ipm < 0 || !(o.rtol_kkt > 0) || o.prec < QP_PREC_NONE ||
       o.prec > QP_PREC_AUTO || (o.precision != QP_FP64 && o.precision != QP_MIXED) ||
       (o.kf_form != QP_KF_IMPLICIT && o.kf_form != QP_KF_EXPLICIT) ||
-      (o.ph_form != QP_PH_EXACT && o.ph_form != QP_PH_DIAG))
+      (o.ph_form != QP_PH_EXACT && o.ph_form != QP_PH_DIAG) || (o.cg_graph != 0 && o.cg_graph != 1))
     return QP_E_INVALID;
   return QP_OK;
 }
@@ -349,6 +354,12 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
     const size_t elems = ctx->pooled ? (size_t)bk0_sym_grid<double>(N, n) * k0_sym_ldp(n) : k0_sym_part_elems(n);
     ctx->sympart_bytes = elems * sizeof(double);
     ctx->sympart = get(ctx->sympart_bytes);
+  }
+  if (need_ph && ph_fused(ctx)) {
+    const size_t elems =
+        ctx->pooled ? (size_t)bk0_sym_grid<double>(m2, m2) * k0_sym_ldp(m2) : k0_sym_part_elems(m2);
+    ctx->phpart_bytes = elems * sizeof(double);
+    ctx->phpart = get(ctx->phpart_bytes);
   }
   if (need_ph) {
     D(ctx->T, (size_t)m2 * ctx->ldm2);
@@ -691,6 +702,32 @@ struct PcgResult {
   int done = 0;
 };
 
+// Executable graph of one poll chunk for these buffers: captured from `record`
+// (which only launches kernels) on the context's stream the first time.
+template <typename F>
+static hipGraphExec_t cg_graph_for(qp_ctx* ctx, const CgGraphKey& key, F&& record) {
+  for (const auto& e : ctx->cg_graphs)
+    if (e.first == key) return e.second;
+  if (ctx->cg_graphs.size() >= 8) release_cg_graphs(ctx);  // buffers changed many times: start over
+  HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    record();
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(ctx->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(ctx, hipStreamEndCapture(ctx->stream, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(ctx, e);
+  ctx->cg_graphs.emplace_back(key, ex);
+  return ex;
+}
+
 template <typename T>
 static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int prec, double rtol, double wtol,
                          int maxit) {
@@ -700,10 +737,17 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
   const bool expl = kf_explicit(ctx);
   HIPCHK(ctx, pcg_init<T>(st, m2, rhs, B.dvec, B.wts, B.x, B.r, B.z, B.p, prec, rtol, wtol, maxit, ctx->sc));
   auto ph_apply = [&](int init, const EventPair* ev) {
-    HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip, 4,
-                                    ev ? &ev[4] : nullptr));
-    HIPCHK(ctx, launch_gemv_cols<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.t, B.z, T(1), T(0), nullptr, *B.wk, skip,
-                                    5, ev ? &ev[5] : nullptr));
+    if (ph_fused(ctx)) {  // z = X_P^T X_P r in one pass over X_P, then the sum of its partials
+      T* part = static_cast<T*>(ctx->phpart);
+      HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.XP, ctx->ldm2, m2, m2, B.r, part, ctx->phpart_bytes / sizeof(T), skip,
+                                         ev ? &ev[4] : nullptr));
+      HIPCHK(ctx, launch_k0_sym_reduce<T>(st, m2, m2, part, B.z, skip, ev ? &ev[5] : nullptr));
+    } else {
+      HIPCHK(ctx, launch_gemv_rows<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.r, B.t, T(1), T(0), nullptr, m2, skip,
+                                      4, ev ? &ev[4] : nullptr));
+      HIPCHK(ctx, launch_gemv_cols<T>(st, B.XP, ctx->ldm2, m2, m2, kLower, B.t, B.z, T(1), T(0), nullptr, *B.wk,
+                                      skip, 5, ev ? &ev[5] : nullptr));
+    }
     HIPCHK(ctx, pcg_ph_update<T>(st, m2, B.r, B.z, B.p, init, ctx->sc));
   };
   if (prec == kPrecH) ph_apply(1, nullptr);
@@ -726,20 +770,30 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
       throw Fail{QP_E_DEVICE};
     }
     launched += poll;
-    for (int k = 0; k < poll; ++k) {
-      const EventPair* ev = (prof && k == 0) ? ctx->prof_ev : nullptr;
-      if (expl) {
-        // q = E p + D p: one row sweep over the explicit operator
-        HIPCHK(ctx, pcg_q<T>(st, B.E, ctx->ldm2, m2, m2, B.p, B.dvec, B.p, B.q, ctx->sc, ctx->bpart, ctx->bpart_cap,
-                             ev ? &ev[3] : nullptr, tune().qe_stage));
-      } else {
-        op_sweeps<T>(ctx, B, skip, ev);
-        // C = I: q = w + D p with no sweep (pcg_q with a null C)
-        HIPCHK(ctx, pcg_q<T>(st, ctx->c_identity ? nullptr : B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc,
-                             ctx->bpart, ctx->bpart_cap, ev ? &ev[3] : nullptr));
+    auto chunk = [&](bool sampled) {
+      for (int k = 0; k < poll; ++k) {
+        const EventPair* ev = (sampled && k == 0) ? ctx->prof_ev : nullptr;
+        if (expl) {
+          // q = E p + D p: one row sweep over the explicit operator
+          HIPCHK(ctx, pcg_q<T>(st, B.E, ctx->ldm2, m2, m2, B.p, B.dvec, B.p, B.q, ctx->sc, ctx->bpart,
+                               ctx->bpart_cap, ev ? &ev[3] : nullptr, tune().qe_stage));
+        } else {
+          op_sweeps<T>(ctx, B, skip, ev);
+          // C = I: q = w + D p with no sweep (pcg_q with a null C)
+          HIPCHK(ctx, pcg_q<T>(st, ctx->c_identity ? nullptr : B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc,
+                               ctx->bpart, ctx->bpart_cap, ev ? &ev[3] : nullptr));
+        }
+        HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc));
+        if (prec == kPrecH) ph_apply(0, ev);
       }
-      HIPCHK(ctx, pcg_update<T>(st, m2, ctx->bpart, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc));
-      if (prec == kPrecH) ph_apply(0, ev);
+    };
+    if (ctx->opt.cg_graph) {
+      // the chunk's launches take the same arguments every time (the scalars live in
+      // device memory), so one captured graph per set of buffers serves every chunk
+      const CgGraphKey key{sizeof(T), prec, (const void*)B.dvec, (const void*)B.wts, (const void*)B.x, poll};
+      HIPCHK(ctx, hipGraphLaunch(cg_graph_for(ctx, key, [&] { chunk(false); }), st));
+    } else {
+      chunk(prof);
     }
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_sc, ctx->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
     sync(ctx);
@@ -1062,6 +1116,7 @@ void qp_default_options(qp_options* opt) {
   opt->profile = 0;
   opt->kf_form = QP_KF_IMPLICIT;
   opt->ph_form = QP_PH_EXACT;
+  opt->cg_graph = 0;
 }
 
 const char* qp_status_str(qp_status st) {
@@ -1113,6 +1168,7 @@ qp_status qp_profile_get(qp_ctx* ctx, double avg_ms[6], long long samples[6], in
 void qp_destroy(qp_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  release_cg_graphs(ctx);
   if (ctx->prof_ready)
     for (int o = 0; o < kProfOps; ++o) {
       (void)hipEventDestroy(ctx->prof_ev[o].begin);

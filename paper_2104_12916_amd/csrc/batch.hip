@@ -216,15 +216,17 @@ struct StepLists {
   std::vector<RowsDesc<T>> r1, r2, r3, r4;  // C^T p and M^T v over stored transposes; Sigma M u, X_P r
   std::vector<PcgDesc<T>> pd, ph;       // all solves; the P_H ones
   std::vector<SymDesc<T>> sy;           // one-pass M^T Sigma M u
-  std::vector<int> c1p, c1r, c3p, c3r, c5p, c5r, r1p, r2p, r3p, r4p, qp, syp, syr;
+  std::vector<SymDesc<T>> sph;          // one-pass X_P^T X_P r (P_H solves)
+  std::vector<int> c1p, c1r, c3p, c3r, c5p, c5r, r1p, r2p, r3p, r4p, qp, syp, syr, sphp, sphr;
   int c1pt = 0, c1rt = 0, c3pt = 0, c3rt = 0, c5pt = 0, c5rt = 0, r1t = 0, r2t = 0, r3t = 0, r4t = 0, qt = 0;
-  int sypt = 0, syrt = 0, syK = 1;
+  int sypt = 0, syrt = 0, syK = 1, sphpt = 0, sphrt = 0, sphK = 1;
   size_t r1smem = 0, r2smem = 0, r3smem = 0, r4smem = 0, qsmem = 0;
   // device addresses after upload
   const ColsDesc<T>*dc1, *dc3, *dc5;
   const RowsDesc<T>*dr1, *dr2, *dr3, *dr4;
   const PcgDesc<T>*dpd, *dph;
-  const SymDesc<T>* dsy;
+  const SymDesc<T>*dsy, *dsph;
+  const int *dsphp, *dsphr;
   const int *dc1p, *dc1r, *dc3p, *dc3r, *dc5p, *dc5r, *dr1p, *dr2p, *dr3p, *dr4p, *dqp, *dsyp, *dsyr;
 };
 
@@ -332,7 +334,21 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
     L.qt += pd.qblocks;
     L.pd.push_back(pd);
     if (pd.stage) L.qsmem = std::max(L.qsmem, rows_smem_bytes<T>(m2, pd.n, kDense, pd.ldc));
-    if (it->prec == kPrecH) {
+    if (it->prec == kPrecH && ph_fused(c)) {  // z = X_P^T X_P r in one pass over X_P
+      SymDesc<T> sd;
+      if (!fill_sym_desc<T>(sd, b.XP, c->ldm2, m2, m2, b.r, b.z, static_cast<T*>(c->phpart),
+                            c->phpart_bytes / sizeof(T), skip)) {
+        set_err(sk, "one-pass P_H apply does not fit its workspace (m2=%d)", m2);
+        throw Fail{QP_E_DEVICE};
+      }
+      L.sphp.push_back(L.sphpt);
+      L.sphr.push_back(L.sphrt);
+      L.sphpt += sd.G;
+      L.sphrt += sd.rblocks;
+      L.sphK = std::max(L.sphK, k0_sym_width<T>(m2));
+      L.sph.push_back(sd);
+      L.ph.push_back(pd);
+    } else if (it->prec == kPrecH) {
       fill_rows_desc<T>(rd, b.XP, c->ldm2, m2, m2, kLower, b.r, b.t, T(1), T(0), nullptr, m2, skip);
       L.r4p.push_back(L.r4t);
       L.r4t += rd.nblocks;
@@ -354,14 +370,17 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
   Packer pk;
   auto V = [&](auto& v) { return pk.add(v.data(), v.size() * sizeof(v[0])); };
   size_t o_c1 = V(L.c1), o_c3 = V(L.c3), o_c5 = V(L.c5), o_r1 = V(L.r1), o_r2 = V(L.r2), o_r3 = V(L.r3),
-         o_r4 = V(L.r4), o_pd = V(L.pd), o_ph = V(L.ph), o_sy = V(L.sy);
+         o_r4 = V(L.r4), o_pd = V(L.pd), o_ph = V(L.ph), o_sy = V(L.sy), o_sph = V(L.sph);
   size_t o_c1p = V(L.c1p), o_c1r = V(L.c1r), o_c3p = V(L.c3p), o_c3r = V(L.c3r), o_c5p = V(L.c5p),
          o_c5r = V(L.c5r), o_r1p = V(L.r1p), o_r2p = V(L.r2p), o_r3p = V(L.r3p), o_r4p = V(L.r4p), o_qp = V(L.qp),
-         o_syp = V(L.syp), o_syr = V(L.syr);
+         o_syp = V(L.syp), o_syr = V(L.syr), o_sphp = V(L.sphp), o_sphr = V(L.sphr);
   const char* base = stage_upload(B, pk);
   L.dsy = reinterpret_cast<const SymDesc<T>*>(base + o_sy);
   L.dsyp = reinterpret_cast<const int*>(base + o_syp);
   L.dsyr = reinterpret_cast<const int*>(base + o_syr);
+  L.dsph = reinterpret_cast<const SymDesc<T>*>(base + o_sph);
+  L.dsphp = reinterpret_cast<const int*>(base + o_sphp);
+  L.dsphr = reinterpret_cast<const int*>(base + o_sphr);
   L.dc1 = reinterpret_cast<const ColsDesc<T>*>(base + o_c1);
   L.dc3 = reinterpret_cast<const ColsDesc<T>*>(base + o_c3);
   L.dc5 = reinterpret_cast<const ColsDesc<T>*>(base + o_c5);
@@ -390,8 +409,13 @@ void launch_ph_apply(qp_batch* B, const StepLists<T>& L, int init, const EventPa
   qp_ctx* sk = &B->sink;
   const int nph = (int)L.ph.size();
   if (!nph) return;
-  HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nph, L.r4t, L.r4smem, 4, ev ? &ev[4] : nullptr));
-  HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nph, 5, ev ? &ev[5] : nullptr));
+  // one-pass QPs (profile slots 4 and 5: the sweep and its reduce), then any with X_P too wide for it
+  const int ns = (int)L.sph.size(), nr = (int)L.r4.size(), nc = (int)L.c5.size();
+  HIPCHK(sk, launch_bk0_sym<T>(B->stream, L.dsph, L.dsphp, L.sphpt, L.dsphr, L.sphrt, ns, L.sphK,
+                               ev ? &ev[4] : nullptr, ev ? &ev[5] : nullptr));
+  HIPCHK(sk, launch_bgemv_rows<T>(B->stream, L.dr4, L.dr4p, nr, L.r4t, L.r4smem, 4, ev && !ns ? &ev[4] : nullptr));
+  HIPCHK(sk, launch_bgemv_cols<T>(B->stream, L.dc5, L.dc5p, L.c5pt, L.dc5r, L.c5rt, nc, 5,
+                                  ev && !ns ? &ev[5] : nullptr));
   HIPCHK(sk, bpcg_ph_update<T>(B->stream, L.dph, nph, init));
 }
 
@@ -1088,7 +1112,7 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
       }
       if (s->R.prec == kPrecH) {
         B->prof_pending_bytes[4] += xp * sizeof(T);
-        B->prof_pending_bytes[5] += xp * sizeof(T);
+        if (!ph_fused(c)) B->prof_pending_bytes[5] += xp * sizeof(T);  // the one pass reads X_P once
       }
     }
   }

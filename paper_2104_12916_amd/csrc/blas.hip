@@ -18,119 +18,161 @@
 namespace qpg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
-constexpr int GB = 64;   // tile
-constexpr int GK = 16;   // k step
+// ---- tiled FP64 GEMM ----------------------------------------------------------
+// A workgroup of 256 threads (2 x 2 wavefronts) owns a BM x BN tile of C; each
+// wavefront a (BM/2) x (BN/2) block of 16 x 16 v_mfma_f64_16x16x4f64 accumulators.
+// The k loop runs over BK-deep slabs of op(A) and op(B) staged in LDS, two
+// buffers: the global loads of slab t+1 (16-byte vectors where the operand is
+// aligned) are in flight while the matrix cores work on slab t, and one barrier
+// per slab separates the buffers.  Each element of C is summed in the same order
+// (k = klo, klo + 4, ... through the same instruction) whatever the tile shape,
+// so the shape can be chosen per launch without changing results.
+constexpr int GK = 16;    // k slab
+constexpr int GPAD = 4;   // LDS row padding (doubles)
 
+template <int BM, int BN>
+struct GemmTile {
+  static constexpr int WM = BM / 2, WN = BN / 2;    // per-wavefront block
+  static constexpr int FM = WM / 16, FN = WN / 16;  // MFMA blocks per wavefront
+  static constexpr int LA = BM * GK / 2 / 256;      // 16-byte loads per thread, A slab
+  static constexpr int LB = BN * GK / 2 / 256;      // and B slab
+  static constexpr int AS = BM + GPAD, BS = BN + GPAD;
+  static constexpr size_t kLdsBytes = 2 * GK * (AS + BS) * sizeof(double);
+};
+constexpr size_t kLdsBig = GemmTile<128, 128>::kLdsBytes, kLdsSmall = GemmTile<64, 64>::kLdsBytes;
+
+// Elements idx, idx+1 of row p (zero at or past lim); one 16-byte load when allowed.
+__device__ __forceinline__ v2d ld_pair(const double* __restrict__ p, int idx, int lim, bool vec) {
+  if (vec && idx + 1 < lim) return *reinterpret_cast<const v2d*>(p + idx);
+  v2d r;
+  r.x = idx < lim ? p[idx] : 0.0;
+  r.y = idx + 1 < lim ? p[idx + 1] : 0.0;
+  return r;
+}
+
+template <int BM, int BN>
 __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
                                           int ta, const double* __restrict__ B, int ldb, int tb, double beta,
                                           double* __restrict__ C, int ldc, int flags, int bx, int by) {
-  const int i0 = by * GB, j0 = bx * GB;
-  if ((flags & kOutLower) && j0 > i0 + GB - 1) return;
-  __shared__ double As[GK][GB + 4];
-  __shared__ double Bs[GK][GB + 4];
+  using G = GemmTile<BM, BN>;
+  const int i0 = by * BM, j0 = bx * BN;
+  if ((flags & kOutLower) && j0 > i0 + BM - 1) return;
+  extern __shared__ double lds[];
+  double* As = lds;                    // [2][GK][AS]
+  double* Bs = lds + 2 * GK * G::AS;   // [2][GK][BS]
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
+  const int wr = (wave / 2) * G::WM, wc = (wave % 2) * G::WN;
   // k range that can be nonzero for this tile
   int klo = 0, khi = K;
-  if (flags & kALower) khi = min(khi, i0 + GB);       // op(A)[i][k] = 0 for k > i
-  if (flags & kBUpper) khi = min(khi, j0 + GB);       // op(B)[k][j] = 0 for k > j
-  if (flags & kBLower) klo = max(klo, j0);            // op(B)[k][j] = 0 for k < j
-  if (flags & kAUpper) klo = max(klo, i0);            // op(A)[i][k] = 0 for k < i
+  if (flags & kALower) khi = min(khi, i0 + BM);  // op(A)[i][k] = 0 for k > i
+  if (flags & kBUpper) khi = min(khi, j0 + BN);  // op(B)[k][j] = 0 for k > j
+  if (flags & kBLower) klo = max(klo, j0);       // op(B)[k][j] = 0 for k < j
+  if (flags & kAUpper) klo = max(klo, i0);       // op(A)[i][k] = 0 for k < i
   klo = klo / GK * GK;
-  v4d acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  // 16-byte loads need 16-byte aligned rows (every slab starts at an even index)
+  const bool va = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 2 == 0);
+  const bool vb = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && (ldb % 2 == 0);
 
-  double ra[4], rb[4];
-  auto load_tiles = [&](int k0) {
-    if (!ta) {  // op(A)[i][k] = A[i*lda + k]
-      int r = tid / 4, kq = (tid % 4) * 4;
-      int gi = i0 + r;
+  v4d acc[G::FM][G::FN];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int gk = k0 + kq + e;
-        ra[e] = (gi < M && gk < K) ? A[(size_t)gi * lda + gk] : 0.0;
-      }
-    } else {    // op(A)[i][k] = A[k*lda + i]
-      int kr = tid / 16, iq = (tid % 16) * 4;
-      int gk = k0 + kr;
+  for (int a = 0; a < G::FM; ++a)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int gi = i0 + iq + e;
-        ra[e] = (gi < M && gk < K) ? A[(size_t)gk * lda + gi] : 0.0;
+    for (int b = 0; b < G::FN; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+
+  v2d ra[G::LA], rb[G::LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < G::LA; ++e) {
+      const int v = tid + 256 * e;
+      if (!ta) {  // op(A)[i][k] = A[i lda + k]: pairs along k
+        const int row = v / (GK / 2), kv = v % (GK / 2), gi = i0 + row;
+        ra[e] = gi < M ? ld_pair(A + (size_t)gi * lda, k0 + 2 * kv, K, va) : v2d{0, 0};
+      } else {    // op(A)[i][k] = A[k lda + i]: pairs along i
+        const int kr = v / (BM / 2), iv = v % (BM / 2), gk = k0 + kr;
+        ra[e] = gk < K ? ld_pair(A + (size_t)gk * lda, i0 + 2 * iv, M, va) : v2d{0, 0};
       }
     }
-    if (!tb) {  // op(B)[k][j] = B[k*ldb + j]
-      int kr = tid / 16, jq = (tid % 16) * 4;
-      int gk = k0 + kr;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int gj = j0 + jq + e;
-        rb[e] = (gj < N && gk < K) ? B[(size_t)gk * ldb + gj] : 0.0;
-      }
-    } else {    // op(B)[k][j] = B[j*ldb + k]
-      int r = tid / 4, kq = (tid % 4) * 4;
-      int gj = j0 + r;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int gk = k0 + kq + e;
-        rb[e] = (gj < N && gk < K) ? B[(size_t)gj * ldb + gk] : 0.0;
+    for (int e = 0; e < G::LB; ++e) {
+      const int v = tid + 256 * e;
+      if (!tb) {  // op(B)[k][j] = B[k ldb + j]: pairs along j
+        const int kr = v / (BN / 2), jv = v % (BN / 2), gk = k0 + kr;
+        rb[e] = gk < K ? ld_pair(B + (size_t)gk * ldb, j0 + 2 * jv, N, vb) : v2d{0, 0};
+      } else {    // op(B)[k][j] = B[j ldb + k]: pairs along k
+        const int col = v / (GK / 2), kv = v % (GK / 2), gj = j0 + col;
+        rb[e] = gj < N ? ld_pair(B + (size_t)gj * ldb, k0 + 2 * kv, K, vb) : v2d{0, 0};
       }
     }
   };
-  auto store_tiles = [&]() {
-    if (!ta) {
-      int r = tid / 4, kq = (tid % 4) * 4;
+  auto store = [&](int buf) {
+    double* as = As + buf * GK * G::AS;
+    double* bs = Bs + buf * GK * G::BS;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[kq + e][r] = ra[e];
-    } else {
-      int kr = tid / 16, iq = (tid % 16) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[kr][iq + e] = ra[e];
+    for (int e = 0; e < G::LA; ++e) {
+      const int v = tid + 256 * e;
+      if (!ta) {
+        const int row = v / (GK / 2), kv = v % (GK / 2);
+        as[(2 * kv) * G::AS + row] = ra[e].x;
+        as[(2 * kv + 1) * G::AS + row] = ra[e].y;
+      } else {
+        const int kr = v / (BM / 2), iv = v % (BM / 2);
+        *reinterpret_cast<v2d*>(as + kr * G::AS + 2 * iv) = ra[e];
+      }
     }
-    if (!tb) {
-      int kr = tid / 16, jq = (tid % 16) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[kr][jq + e] = rb[e];
-    } else {
-      int r = tid / 4, kq = (tid % 4) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[kq + e][r] = rb[e];
+    for (int e = 0; e < G::LB; ++e) {
+      const int v = tid + 256 * e;
+      if (!tb) {
+        const int kr = v / (BN / 2), jv = v % (BN / 2);
+        *reinterpret_cast<v2d*>(bs + kr * G::BS + 2 * jv) = rb[e];
+      } else {
+        const int col = v / (GK / 2), kv = v % (GK / 2);
+        bs[(2 * kv) * G::BS + col] = rb[e].x;
+        bs[(2 * kv + 1) * G::BS + col] = rb[e].y;
+      }
     }
   };
 
-  if (klo < khi) load_tiles(klo);
+  if (klo < khi) {
+    load(klo);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = klo; k0 < khi; k0 += GK) {
-    __syncthreads();
-    store_tiles();
-    __syncthreads();
-    if (k0 + GK < khi) load_tiles(k0 + GK);
+    const bool more = k0 + GK < khi;
+    if (more) load(k0 + GK);
+    const double* as = As + buf * GK * G::AS;
+    const double* bs = Bs + buf * GK * G::BS;
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int kr = kk * 4 + lane / 16;
-      double a0 = As[kr][wr + (lane % 16)];
-      double a1 = As[kr][wr + 16 + (lane % 16)];
-      double b0 = Bs[kr][wc + (lane % 16)];
-      double b1 = Bs[kr][wc + 16 + (lane % 16)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double af[G::FM], bf[G::FN];
+#pragma unroll
+      for (int a = 0; a < G::FM; ++a) af[a] = as[kr * G::AS + wr + a * 16 + lane % 16];
+#pragma unroll
+      for (int b = 0; b < G::FN; ++b) bf[b] = bs[kr * G::BS + wc + b * 16 + lane % 16];
+#pragma unroll
+      for (int a = 0; a < G::FM; ++a)
+#pragma unroll
+        for (int b = 0; b < G::FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   // f64 16x16x4 result layout: register r of lane l holds D[4 r + l / 16][l % 16]
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < G::FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < G::FN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int gi = i0 + wr + a * 16 + 4 * r + lane / 16;
-        int gj = j0 + wc + b * 16 + (lane % 16);
-        if (gi < M && gj < N) {
+        const int gi = i0 + wr + a * 16 + 4 * r + lane / 16;
+        const int gj = j0 + wc + b * 16 + (lane % 16);
+        if (gi < M && gj < N && (!(flags & kOutLower) || gj <= gi)) {
           double v = alpha * acc[a][b][r];
           double* cp = C + (size_t)gi * ldc + gj;
           if (beta != 0.0) v += beta * (*cp);
@@ -139,28 +181,50 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       }
 }
 
+// Tile shape of a launch covering `tiles128` tiles of 128 x 128: the large tile
+// when it still gives every CU about one tile, else 64 x 64 (four times as many).
+static bool use_big_tile(long long tiles128) { return tiles128 >= (long long)dev_info().cu_count * 3 / 4; }
+
+static long long active_tiles(int M, int N, int bm, int bn, int flags) {
+  const long long gy = (M + bm - 1) / bm, gx = (N + bn - 1) / bn;
+  if (!(flags & kOutLower)) return gx * gy;
+  long long t = 0;  // tiles on or below the diagonal
+  for (long long y = 0; y < gy; ++y) t += std::min(gx, (y * bm + bm - 1) / bn + 1);
+  return t;
+}
+
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                        int lda, int ta, const double* __restrict__ B, int ldb, int tb,
                                                        double beta, double* __restrict__ C, int ldc, int flags) {
-  gemm_body(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags, blockIdx.x, blockIdx.y);
+  gemm_body<BM, BN>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags, blockIdx.x, blockIdx.y);
 }
 
 // One GEMM per blockIdx.z, same op/scalars for all; tiles outside a problem's
 // M x N exit at once.
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_f64_batched_kernel(const GemmDesc* __restrict__ descs, int ta, int tb,
                                                                double alpha, double beta, int flags) {
   const GemmDesc g = descs[blockIdx.z];
-  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
-  gemm_body(g.M, g.N, g.K, alpha, g.A, g.lda, ta, g.B, g.ldb, tb, beta, g.C, g.ldc, flags, blockIdx.x, blockIdx.y);
+  if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
+  gemm_body<BM, BN>(g.M, g.N, g.K, alpha, g.A, g.lda, ta, g.B, g.ldb, tb, beta, g.C, g.ldc, flags, blockIdx.x,
+                    blockIdx.y);
 }
 
 hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
                     const double* B, int ldb, double beta, double* C, int ldc, int flags) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if ((M + GB - 1) / GB > 65535) return hipErrorInvalidValue;
-  dim3 grid((N + GB - 1) / GB, (M + GB - 1) / GB);
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc,
-                     flags);
+  if (use_big_tile(active_tiles(M, N, 128, 128, flags))) {
+    using G = GemmTile<128, 128>;
+    if ((M + 127) / 128 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), G::kLdsBytes,
+                       st, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
+  } else {
+    using G = GemmTile<64, 64>;
+    if ((M + 63) / 64 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), G::kLdsBytes, st,
+                       M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
+  }
   return hipGetLastError();
 }
 
@@ -177,31 +241,41 @@ struct GemmArgs {
   int ldc, flags;
 };
 
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_f64_pair_kernel(GemmArgs g0, GemmArgs g1) {
   const GemmArgs g = blockIdx.z == 0 ? g0 : g1;
-  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
-  gemm_body(g.M, g.N, g.K, g.alpha, g.A, g.lda, g.ta, g.B, g.ldb, g.tb, g.beta, g.C, g.ldc, g.flags, blockIdx.x,
-            blockIdx.y);
+  if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
+  gemm_body<BM, BN>(g.M, g.N, g.K, g.alpha, g.A, g.lda, g.ta, g.B, g.ldb, g.tb, g.beta, g.C, g.ldc, g.flags,
+                    blockIdx.x, blockIdx.y);
 }
 
 static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmArgs& g1) {
-  const int gx = (std::max(g0.N, g1.N) + GB - 1) / GB, gy = (std::max(g0.M, g1.M) + GB - 1) / GB;
-  if (gx <= 0 || gy <= 0) return hipSuccess;
-  if (gy > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemm_f64_pair_kernel, dim3(gx, gy, 2), dim3(256), 0, st, g0, g1);
+  const int mx = std::max(g0.M, g1.M), nx = std::max(g0.N, g1.N);
+  if (mx <= 0 || nx <= 0) return hipSuccess;
+  const long long t128 = active_tiles(g0.M, g0.N, 128, 128, g0.flags) + active_tiles(g1.M, g1.N, 128, 128, g1.flags);
+  if (use_big_tile(t128)) {
+    if ((mx + 127) / 128 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<128, 128>), dim3((nx + 127) / 128, (mx + 127) / 128, 2), dim3(256),
+                       kLdsBig, st, g0, g1);
+  } else {
+    if ((mx + 63) / 64 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<64, 64>), dim3((nx + 63) / 64, (mx + 63) / 64, 2), dim3(256),
+                       kLdsSmall, st, g0, g1);
+  }
   return hipGetLastError();
 }
 
 // Batched form: blockIdx.z < count0 takes d0[z] with o0, the rest d1[z - count0] with o1.
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_f64_batched_pair_kernel(const GemmDesc* __restrict__ d0, int count0,
                                                                     GemmOp o0, const GemmDesc* __restrict__ d1,
                                                                     GemmOp o1) {
   const int z = blockIdx.z;
   const GemmDesc g = z < count0 ? d0[z] : d1[z - count0];
   const GemmOp o = z < count0 ? o0 : o1;
-  if ((int)blockIdx.y * GB >= g.M || (int)blockIdx.x * GB >= g.N) return;
-  gemm_body(g.M, g.N, g.K, o.alpha, g.A, g.lda, o.ta, g.B, g.ldb, o.tb, o.beta, g.C, g.ldc, o.flags, blockIdx.x,
-            blockIdx.y);
+  if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
+  gemm_body<BM, BN>(g.M, g.N, g.K, o.alpha, g.A, g.lda, o.ta, g.B, g.ldb, o.tb, o.beta, g.C, g.ldc, o.flags,
+                    blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,181 +286,187 @@ constexpr int LEAF = 64;
 // matrix the computed pivot is a rounding residue of order eps * ||A||.
 constexpr double kPivRel = 1e-13;
 
-// Leaf: right-looking LDL^T of a <= 64 x 64 SPD block held in registers, then
-// L = L_1 D^{1/2} and X = L^{-1} = D^{-1/2} L_1^{-1}.  Thread t owns the 4 x 4
-// sub-block (rows 4 (t / 16) .., cols 4 (t % 16) ..) of both A and X.  Column j
-// of the elimination applies
-//     a_ik -= (a_ij / a_jj) a_kj   (j < k <= i),    x_ik -= (a_ij / a_jj) x_jk   (i > j),
-// with X starting as I (its rows only mix with earlier rows, so it stays lower
-// triangular).  The columns are taken four at a time: the owners of column
-// block J publish it (and the owners of rows 4J..4J+3 those rows of X) in LDS,
-// one barrier, and then every thread eliminates the 4 x 4 diagonal block and
-// the block's part of the rows it needs, and applies the four column steps to
-// its sub-blocks.  Each entry sees the same updates in the same order as with
-// one column per step, with one barrier per four columns.
+// Leaf: right-looking LDL^T of a <= 64 x 64 SPD block, then L = L_1 D^{1/2} and
+// X = L^{-1} = D^{-1/2} L_1^{-1} (X starts as I and takes the same row
+// operations, so it stays lower triangular).  The block is held as 16 x 16
+// tiles in the accumulators of v_mfma_f64_16x16x4f64: wavefront I owns tile row
+// I of A and of X (tiles K <= I).  Columns are eliminated four at a time.  For
+// column block J (columns 4J .. 4J+3) the owners publish those columns of A and
+// rows 4J .. 4J+3 of X in LDS; after one barrier every lane eliminates the 4 x 4
+// diagonal block itself, and a row i below it passes through the block's four
+// steps (its eliminated values ev_i and multipliers cf_i = ev_i / d).  The
+// updates of the trailing columns, a_ik -= sum_p cf_ip ev_kp, and of the rows
+// of X below the block, x_i -= sum_p cf_ip xf_p, are rank-4 products: one MFMA
+// per 16 x 16 tile, with the k = 4 operand slots holding p.
+__device__ __forceinline__ double sel4(const double (&v)[4], int p) {
+  return p == 0 ? v[0] : p == 1 ? v[1] : p == 2 ? v[2] : v[3];
+}
+
 __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
                                                    int nb, int* __restrict__ info, int code,
                                                    const double* __restrict__ dmax) {
-  __shared__ double pan[2][LEAF][4];  // column block J of A (rows >= 4J), double-buffered
+  __shared__ double pan[2][LEAF][4];   // columns 4J..4J+3 of A (rows >= 4J), double-buffered
   __shared__ double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J
   __shared__ double piv[LEAF];
-  const int t = threadIdx.x, tr = t >> 4, tc = t & 15, r0 = tr * 4, c0 = tc * 4;
+  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  // accumulator layout: register r of lane l holds tile entry (4 r + lr, lc)
   const double pmin = kPivRel * (*dmax);
-  double a[4][4], x[4][4];
+  v4d accA[4], accX[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int K = 0; K < 4; ++K)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = r0 + r, k = c0 + c;
-      a[r][c] = (i < nb && k <= i) ? A[(size_t)i * lda + k] : 0.0;
-      x[r][c] = (i == k && i < nb) ? 1.0 : 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + 4 * r + lr, k = 16 * K + lc;
+      accA[K][r] = (K <= I && i < nb && k <= i) ? A[(size_t)i * lda + k] : 0.0;
+      accX[K][r] = (i == k && i < nb) ? 1.0 : 0.0;
     }
   bool bad = false;
   const int nblk = (nb + 3) / 4;
-  for (int J = 0; J < nblk; ++J) {
-    const int buf = J & 1, j0 = 4 * J;
-    if (tc == J && tr >= J) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) pan[buf][r0 + r][q] = a[r][q];
-    }
-    if (tr == J) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) xrow[buf][r][c0 + c] = x[r][c];
-    }
-    __syncthreads();
-    // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
-    // at its own column step (E[p][p] is the pivot d_p).
-    double E[4][4], dinv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? pan[buf][j0 + i][q] : 0.0;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      double d = E[p][p];
-      if (j0 + p < nb) {
-        if (!(d > pmin) || !isfinite(d)) {  // same decision in every thread
-          bad = true;
-          d = 1.0;
-        }
-      } else {
-        d = 1.0;  // past the block's end: the row and column are zero
-      }
-      E[p][p] = d;
-      dinv[p] = 1.0 / d;
-#pragma unroll
-      for (int i = p + 1; i < 4; ++i) {
-        const double coef = E[i][p] * dinv[p];
-#pragma unroll
-        for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
-      }
-    }
-    if (t == 0) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) piv[j0 + p] = E[p][p];
-    }
-    // Row i >= j0 + 4 through the block's four steps: ev[p] = eliminated a_{i, j0+p},
-    // cf[p] = ev[p] / d_p (the multiplier of step j0 + p).
-    auto row_steps = [&](int i, double (&ev)[4], double (&cf)[4]) {
-      double g[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) g[q] = pan[buf][i][q];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-#pragma unroll
-        for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
-        ev[p] = g[p];
-        cf[p] = g[p] * dinv[p];
-      }
-    };
-    double cfr[4][4], evr[4][4];  // this thread's rows r0 + r
-    if (tr > J) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) row_steps(min(r0 + r, LEAF - 1), evr[r], cfr[r]);
-    }
-    // A: the owners of the column block keep its eliminated values; sub-blocks right of
-    // it and on or below the diagonal take the four rank-one updates.
-    if (tc == J && tr == J) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q <= r; ++q) a[r][q] = E[r][q];
-    } else if (tc == J && tr > J) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r0 + r < nb) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[r][q] = evr[r][q];
-        }
-    } else if (tc > J && tr >= tc) {
-      double evc[4][4], cfc[4][4];  // the rows k = c0 + c (columns of this sub-block)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) row_steps(c0 + c, evc[c], cfc[c]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = r0 + r;
-        if (i >= nb) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (c0 + c > i) continue;
-#pragma unroll
-          for (int p = 0; p < 4; ++p) a[r][c] -= cfr[r][p] * evc[c][p];
-        }
-      }
-    }
-    // X: rows j0..j0+3 first eliminate among themselves, then rows below take them.
-    if (tr >= J) {
-      double xf[4][4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) xf[p][c] = xrow[buf][p][c0 + c];
-#pragma unroll
-      for (int p = 1; p < 4; ++p)
-#pragma unroll
-        for (int pp = 0; pp < p; ++pp) {
-          const double l = E[p][pp] * dinv[pp];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) xf[p][c] -= l * xf[pp][c];
-        }
-      if (tr == J) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (r0 + r < nb) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) x[r][c] = xf[r][c];
-          }
-      } else {
+  for (int K0 = 0; K0 < 4; ++K0) {
+    for (int jj = 0; jj < 4; ++jj) {
+      const int J = 4 * K0 + jj;
+      if (J >= nblk) break;
+      const int buf = J & 1, j0 = 4 * J, c0 = 4 * jj;
+      if (I >= K0 && lc >= c0 && lc < c0 + 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (r0 + r >= nb) continue;
+          const int i = 16 * I + 4 * r + lr;
+          if (i >= j0) pan[buf][i][lc - c0] = accA[K0][r];
+        }
+      }
+      if (I == K0) {
 #pragma unroll
-          for (int p = 0; p < 4; ++p)
+        for (int K = 0; K <= K0; ++K) xrow[buf][lr][16 * K + lc] = accX[K][jj];
+      }
+      __syncthreads();
+      // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
+      // at its own column step (E[p][p] is the pivot d_p).
+      double E[4][4], dinv[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) x[r][c] -= cfr[r][p] * xf[p][c];
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? pan[buf][j0 + i][q] : 0.0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        double d = E[p][p];
+        if (j0 + p < nb) {
+          if (!(d > pmin) || !isfinite(d)) {  // same decision in every thread
+            bad = true;
+            d = 1.0;
+          }
+        } else {
+          d = 1.0;  // past the block's end: the row and column are zero
+        }
+        E[p][p] = d;
+        dinv[p] = 1.0 / d;
+#pragma unroll
+        for (int i = p + 1; i < 4; ++i) {
+          const double coef = E[i][p] * dinv[p];
+#pragma unroll
+          for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
+        }
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) piv[j0 + p] = E[p][p];
+      }
+      // Row i >= j0 + 4 through the block's four steps: ev[p] = eliminated a_{i, j0+p},
+      // cf[p] = ev[p] / d_p (the multiplier of step j0 + p).
+      auto row_steps = [&](int i, double (&ev)[4], double (&cf)[4]) {
+        double g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = pan[buf][i][q];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+          for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
+          ev[p] = g[p];
+          cf[p] = g[p] * dinv[p];
+        }
+      };
+      // Row j0 + p of X after the block's steps among its own rows, column k.
+      auto xf_of = [&](int p, int k) {
+        double f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          f[q] = xrow[buf][q][k];
+#pragma unroll
+          for (int qq = 0; qq < q; ++qq) {
+            const double lq = E[q][qq] * dinv[qq];
+            f[q] -= lq * f[qq];
+          }
+        }
+        return sel4(f, p);
+      };
+      if (I >= K0) {
+        // A operand: -cf of row 16 I + lc, slot p = lr (rows of the block or above: no update)
+        const int ia = 16 * I + lc;
+        double aop = 0.0;
+        if (ia > j0 + 3) {
+          double ev[4], cf[4];
+          row_steps(ia, ev, cf);
+          aop = -sel4(cf, lr);
+        }
+#pragma unroll
+        for (int K = K0; K < 4; ++K) {
+          if (K <= I) {
+            // B operand: ev of row 16 K + lc (a trailing column), slot p = lr
+            const int kb = 16 * K + lc;
+            double bop = 0.0;
+            if (kb > j0 + 3) {
+              double ev[4], cf[4];
+              row_steps(kb, ev, cf);
+              bop = sel4(ev, lr);
+            }
+            accA[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, accA[K], 0, 0, 0);
+          }
+        }
+        // the block's own columns keep their eliminated values
+        if (lc >= c0 && lc < c0 + 4) {
+          const int p = lc - c0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * I + 4 * r + lr;
+            if (i > j0 + 3) {
+              double ev[4], cf[4];
+              row_steps(i, ev, cf);
+              accA[K0][r] = sel4(ev, p);
+            } else if (i >= j0) {
+              const int q = i - j0;
+              double e = 0.0;
+#pragma unroll
+              for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+                for (int pp = 0; pp <= qq; ++pp)
+                  if (qq == q && pp == p) e = E[qq][pp];
+              accA[K0][r] = e;
+            }
+          }
+        }
+        // X: rows below the block take x_i -= sum_p cf_ip xf_p; the block's rows become xf
+#pragma unroll
+        for (int K = 0; K <= K0; ++K) {
+          const double xv = xf_of(lr, 16 * K + lc);
+          accX[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, xv, accX[K], 0, 0, 0);
+          if (I == K0) accX[K][jj] = xv;
         }
       }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = r0 + r;
-    if (i >= nb) continue;
-    const double si = sqrt(piv[i]);
+  for (int K = 0; K < 4; ++K) {
+    if (K > I) continue;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = c0 + c;
-      if (k >= nb) continue;
-      if (k <= i) A[(size_t)i * lda + k] = a[r][c] / sqrt(piv[k]);
-      X[(size_t)i * ldx + k] = x[r][c] / si;
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + 4 * r + lr, k = 16 * K + lc;
+      if (i >= nb || k >= nb) continue;
+      if (k <= i) A[(size_t)i * lda + k] = accA[K][r] / sqrt(piv[k]);
+      X[(size_t)i * ldx + k] = accX[K][r] / sqrt(piv[i]);
     }
   }
-  if (t == 0 && bad) *info = code;
+  if (tid == 0 && bad) *info = code;
 }
 
 __global__ void __launch_bounds__(256) chol_inv_leaf_kernel(double* __restrict__ A, int lda, double* __restrict__ X,
@@ -512,11 +592,15 @@ void BatchedOps::gemm(int ta, int tb, double alpha, double beta, int flags, cons
     nx = std::max(nx, g.N);
   }
   if (mx <= 0 || nx <= 0) return;
+  long long t128 = 0;
+  for (const GemmDesc& g : d) t128 += active_tiles(g.M, g.N, 128, 128, flags);
   Op o{};
   o.kind = 1;
   o.count = (int)d.size();
-  o.gx = (nx + GB - 1) / GB;
-  o.gy = (mx + GB - 1) / GB;
+  o.big = use_big_tile(t128) ? 1 : 0;
+  const int tb_ = o.big ? 128 : 64;
+  o.gx = (nx + tb_ - 1) / tb_;
+  o.gy = (mx + tb_ - 1) / tb_;
   o.g0 = GemmOp{ta, tb, flags, alpha, beta};
   o.off = push(d);
   ops_.push_back(o);
@@ -536,12 +620,17 @@ void BatchedOps::gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, co
       nx = std::max(nx, g.N);
     }
   if (mx <= 0 || nx <= 0) return;
+  long long t128 = 0;
+  for (const GemmDesc& g : d0) t128 += active_tiles(g.M, g.N, 128, 128, o0.flags);
+  for (const GemmDesc& g : d1) t128 += active_tiles(g.M, g.N, 128, 128, o1.flags);
   Op o{};
   o.kind = 3;
   o.count = (int)d0.size();
   o.count2 = (int)d1.size();
-  o.gx = (nx + GB - 1) / GB;
-  o.gy = (mx + GB - 1) / GB;
+  o.big = use_big_tile(t128) ? 1 : 0;
+  const int tb_ = o.big ? 128 : 64;
+  o.gx = (nx + tb_ - 1) / tb_;
+  o.gy = (mx + tb_ - 1) / tb_;
   o.g0 = o0;
   o.g1 = o1;
   o.off = push(d0);
@@ -630,18 +719,31 @@ hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
         hipLaunchKernelGGL(chol_inv_leaf_batched_kernel, dim3(o.count), dim3(256), 0, st,
                            reinterpret_cast<const LeafDesc*>(base + o.off));
         break;
-      case 1:
+      case 1: {
         if (o.gy > 65535) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(gemm_f64_batched_kernel, dim3(o.gx, o.gy, o.count), dim3(256), 0, st,
-                           reinterpret_cast<const GemmDesc*>(base + o.off), o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
-                           o.g0.flags);
+        const GemmDesc* d = reinterpret_cast<const GemmDesc*>(base + o.off);
+        if (o.big)
+          hipLaunchKernelGGL((gemm_f64_batched_kernel<128, 128>), dim3(o.gx, o.gy, o.count), dim3(256),
+                             kLdsBig, st, d, o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
+                             o.g0.flags);
+        else
+          hipLaunchKernelGGL((gemm_f64_batched_kernel<64, 64>), dim3(o.gx, o.gy, o.count), dim3(256),
+                             kLdsSmall, st, d, o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
+                             o.g0.flags);
         break;
-      case 3:
+      }
+      case 3: {
         if (o.gy > 65535 || o.count + o.count2 > 65535) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(gemm_f64_batched_pair_kernel, dim3(o.gx, o.gy, o.count + o.count2), dim3(256), 0, st,
-                           reinterpret_cast<const GemmDesc*>(base + o.off), o.count, o.g0,
-                           reinterpret_cast<const GemmDesc*>(base + o.off2), o.g1);
+        const GemmDesc* d0 = reinterpret_cast<const GemmDesc*>(base + o.off);
+        const GemmDesc* d1 = reinterpret_cast<const GemmDesc*>(base + o.off2);
+        if (o.big)
+          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<128, 128>), dim3(o.gx, o.gy, o.count + o.count2),
+                             dim3(256), kLdsBig, st, d0, o.count, o.g0, d1, o.g1);
+        else
+          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<64, 64>), dim3(o.gx, o.gy, o.count + o.count2),
+                             dim3(256), kLdsSmall, st, d0, o.count, o.g0, d1, o.g1);
         break;
+      }
       default:
         hipLaunchKernelGGL(diag_max_batched_kernel, dim3(o.count), dim3(256), 0, st,
                            reinterpret_cast<const DiagDesc*>(base + o.off));

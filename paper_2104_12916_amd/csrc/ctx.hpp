@@ -39,6 +39,17 @@ class Arena {
 };
 
 constexpr int kProfOps = 6;
+
+// Buffers and shape a captured poll chunk of CG steps was recorded with.
+struct CgGraphKey {
+  size_t elem;
+  int prec;
+  const void *dvec, *wts, *x;
+  int poll;
+  bool operator==(const CgGraphKey& o) const {
+    return elem == o.elem && prec == o.prec && dvec == o.dvec && wts == o.wts && x == o.x && poll == o.poll;
+  }
+};
 constexpr int kStatsStride = 64;  // doubles per QP in the stats record
 
 }  // namespace qpg
@@ -112,6 +123,8 @@ struct qp_ctx {
   qpg::GemvWork<double> w64{};
   void* sympart = nullptr;  // per-workgroup partials of the one-pass K0 product
   size_t sympart_bytes = 0;
+  void* phpart = nullptr;  // per-workgroup partials of the one-pass P_H apply X_P^T X_P r
+  size_t phpart_bytes = 0;
   qpg::GemvWork<float> w32{};
   double* bpart = nullptr;  // per-workgroup partials of p^T q
   int bpart_cap = 0;
@@ -125,6 +138,8 @@ struct qp_ctx {
   double prof_ms[qpg::kProfOps] = {};
   long long prof_n[qpg::kProfOps] = {};
   bool prof_ready = false;
+  // captured poll chunks of CG steps (options.cg_graph)
+  std::vector<std::pair<qpg::CgGraphKey, hipGraphExec_t>> cg_graphs;
   // pinned host mirrors
   qpg::PcgScalars* h_sc = nullptr;
   qpg::IpmScalars* h_isc = nullptr;
@@ -164,6 +179,7 @@ void upload_matrix(qp_ctx* ctx, double* dst, int ldd, const double* src, int row
 void upload_vec(qp_ctx* ctx, double* dst, const double* src, int n, qp_mem where);
 void download_vec(qp_ctx* ctx, double* dst, const double* src, int n, qp_mem where);
 void sync(qp_ctx* ctx);
+void release_cg_graphs(qp_ctx* ctx);
 bool finite_all(const double* v, size_t n);
 qp_status check_problem(int n, int m1, int m2, const double* H, const double* c, const double* A, const double* b,
                         const double* C, const double* d, qp_mem where);
@@ -192,6 +208,9 @@ inline bool op_transposed(const qp_ctx* ctx) { return tune().op_t && !kf_explici
 inline bool op_fused(const qp_ctx* ctx) {
   return tune().k0_sym && !kf_explicit(ctx) && !ctx->master && ctx->n <= k0_sym_max_n<double>();
 }
+// The P_H apply z = X_P^T (X_P r) runs as one pass over X_P (the one-pass sweep
+// with N = n = m2 and no sign flips) instead of a row and a column sweep.
+inline bool ph_fused(const qp_ctx* ctx) { return tune().k0_sym && ctx->m2 <= k0_sym_max_n<double>(); }
 inline bool store_mt(const qp_ctx* ctx) { return (op_transposed(ctx) && !op_fused(ctx)) || ctx->keep_mt; }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);

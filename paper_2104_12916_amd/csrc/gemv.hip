@@ -674,35 +674,61 @@ __global__ void __launch_bounds__(BT) bk0_sym_kernel(const SymDesc<T>* __restric
     k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j], d.skip);
 }
 
-// Columns grp*16 .. +15 of w = sum over g of part[g].
+// Columns grp*16 .. +15 of w = sum over g of part[g].  Thread t adds column
+// pair t % 8 of the partials g = t / 8 + 32 j; its 16 loads of a round are in
+// flight together (16-byte pairs; rows are 64-element aligned), and the 32 row
+// groups are then combined by a fixed butterfly and a fixed sum over the four
+// wavefronts, so the order of the additions never depends on timing.
+template <typename T>
+struct Pair2 {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
 template <typename T>
 __device__ __forceinline__ void k0_sym_reduce_body(const T* __restrict__ part, int ldp, int G, int n,
                                                    T* __restrict__ w, const int* __restrict__ skip, int grp) {
+  using P2 = typename Pair2<T>::type;
+  constexpr int kPairs = kRedCols / 2, kGroups = 256 / kPairs, kInFlight = 16;
   const int sk = skip ? *skip : 0;  // tested once the partial loads are in flight
-  const int c = threadIdx.x % kRedCols, t = threadIdx.x / kRedCols;
-  const int col = grp * kRedCols + c;
-  constexpr int S = 256 / kRedCols;
-  T acc[4] = {T(0), T(0), T(0), T(0)};
+  const int c = threadIdx.x % kPairs, q = threadIdx.x / kPairs;
+  const int col = grp * kRedCols + 2 * c;
+  P2 acc[kInFlight];
+#pragma unroll
+  for (int j = 0; j < kInFlight; ++j) acc[j] = P2{T(0), T(0)};
   if (col < n) {
-    int g = t;
-    for (; g + 3 * S < G; g += 4 * S) {
-      T v[4];
+    const T* base = part + col;
+    for (int g0 = q; g0 < G; g0 += kGroups * kInFlight) {
+      P2 v[kInFlight];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = part[(size_t)(g + k * S) * ldp + col];
+      for (int j = 0; j < kInFlight; ++j) {
+        const int g = g0 + kGroups * j;
+        v[j] = g < G ? *reinterpret_cast<const P2*>(base + (size_t)g * ldp) : P2{T(0), T(0)};
+      }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] += v[k];
+      for (int j = 0; j < kInFlight; ++j) acc[j] += v[j];
     }
-    for (; g < G; g += S) acc[0] += part[(size_t)g * ldp + col];
   }
   if (sk) return;
-  T s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
-  for (int off = 32; off >= kRedCols; off >>= 1) s += __shfl_xor(s, off, kWave);
-  __shared__ T sh[4][kRedCols];
+  for (int h = kInFlight / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int j = 0; j < h; ++j) acc[j] += acc[j + h];
+  P2 s = acc[0];
+  // lanes of one column pair are kPairs apart inside the wavefront
+#pragma unroll
+  for (int off = 32; off >= kPairs; off >>= 1) {
+    s.x += __shfl_xor(s.x, off, kWave);
+    s.y += __shfl_xor(s.y, off, kWave);
+  }
+  __shared__ P2 sh[4][kPairs];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane < kRedCols) sh[wave][lane] = s;
+  if (lane < kPairs) sh[wave][lane] = s;
   __syncthreads();
-  if (threadIdx.x < kRedCols && col < n) w[col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+  if (threadIdx.x < kPairs && col < n) {
+    const P2 t = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+    w[col] = t.x;
+    if (col + 1 < n) w[col + 1] = t.y;
+  }
 }
 
 template <typename T>

@@ -147,7 +147,7 @@ class BatchedOps {
 
  private:
   struct Op {
-    int kind, count, count2, gx, gy;
+    int kind, count, count2, gx, gy, big;
     GemmOp g0, g1;
     size_t off, off2;
   };

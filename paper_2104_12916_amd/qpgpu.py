@@ -40,6 +40,7 @@ class qp_options(ct.Structure):
         ("tau", ct.c_double), ("max_ipm", ct.c_int), ("max_pcg", ct.c_int),
         ("poll_every", ct.c_int), ("prec", ct.c_int), ("precision", ct.c_int),
         ("verbose", ct.c_int), ("profile", ct.c_int), ("kf_form", ct.c_int), ("ph_form", ct.c_int),
+        ("cg_graph", ct.c_int),
     ]
 
 
