@@ -160,6 +160,24 @@ qp_status qp_setup(qp_ctx** out, int n, int m1, int m2, const double* H, const d
  * QP_E_NOT_SPD / QP_E_RANK when a Cholesky pivot is not positive. */
 qp_status qp_factor_K0(qp_ctx* ctx);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): qp_factor_K0 with the same kernels and the
+ * same results, bitwise, but its set-up scratch (the working copy of H, W^T,
+ * A H^{-1} A^T, the recursion temporaries, C L_H^{-T} for P_H, Y for the
+ * explicit operator) taken from a fixed device array of
+ * QPGPU_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Calls no hipMalloc/hipFree.  QP_E_INVALID (nothing
+ * run, the context unchanged) when the QP's scratch exceeds that size (about
+ * n <= 1500 at m1 = n/4, m2 = n/2, P_H); QP_E_STATE for contexts of a batch or
+ * a shared set.  The array is shared by every call on one GPU: the library
+ * serializes its own calls per device, and the call returns after its stream
+ * is idle, so the next call finds it free; what a call leaves there is
+ * overwritten before it is read.  Calls that overlapped on one GPU without
+ * that lock (e.g. from two copies of the library in one process) would race.
+ * Synchronizes the context's stream, so it cannot be captured in a graph. */
+#define QPGPU_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+qp_status qp_factor_K0_static(qp_ctx* ctx);
+
 /* out = K0^{-1} rhs (both n + m1 long) with the stored factor.  Requires
  * qp_factor_K0.  Used by the IPM for r_nu and the recovery of eq. schur-delta-x. */
 qp_status qp_k0_solve(qp_ctx* ctx, const double* rhs, double* out, qp_mem where);

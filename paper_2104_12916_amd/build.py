@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqpgpu.so")
 SOURCES = ["api.hip", "batch.hip", "shared.hip", "gemv.hip", "blas.hip", "pcg.hip", "ipm.hip", "block.hip", "stream.hip",
-           "tune.hip"]
+           "tune.hip", "noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -450,6 +450,21 @@ void free_factor_scratch(qp_ctx* ctx) {
   }
 }
 
+size_t factor_scratch_bytes(qp_ctx* ctx) { return layout_bytes(ctx, true); }
+
+void place_factor_scratch(qp_ctx* ctx, char* base) {
+  size_t off = 0;
+  layout_factor_scratch(ctx, [&](size_t bytes) -> void* {
+    void* p = base + off;
+    off += round_bytes(bytes);
+    return p;
+  });
+}
+
+void forget_factor_scratch(qp_ctx* ctx) {
+  for (double** p : {&ctx->fHw, &ctx->fWt, &ctx->fS, &ctx->fG, &ctx->ftmp, &ctx->fYt, &ctx->fY}) *p = nullptr;
+}
+
 size_t footprint_bytes(int n, int m1, int m2, const qp_options& o, bool pooled, bool with_scratch) {
   qp_ctx tmp;
   init_dims(&tmp, n, m1, m2, o);

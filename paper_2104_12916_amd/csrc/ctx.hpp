@@ -193,6 +193,11 @@ void alloc_all(qp_ctx* ctx);
 // Factorization scratch held from admission until the factor is done (batch).
 void alloc_factor_scratch(qp_ctx* ctx);
 void free_factor_scratch(qp_ctx* ctx);
+// The same scratch placed in caller-provided device memory of factor_scratch_bytes
+// bytes (256-byte aligned), and the pointers cleared again without freeing.
+size_t factor_scratch_bytes(qp_ctx* ctx);
+void place_factor_scratch(qp_ctx* ctx, char* base);
+void forget_factor_scratch(qp_ctx* ctx);
 // Device bytes alloc_all (+ the factorization scratch) takes, rounded as dalloc rounds.
 size_t footprint_bytes(int n, int m1, int m2, const qp_options& o, bool pooled, bool with_scratch);
 void upload_problem(qp_ctx* ctx, const double* H, const double* c, const double* A, const double* b,

@@ -30,8 +30,10 @@ EXPORTS = (
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
     "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
     "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_shared_last_error", "qp_shared_destroy",
-    "qp_tune_set", "qp_tune_get", "qp_hbm_read_time",
+    "qp_tune_set", "qp_tune_get", "qp_hbm_read_time", "qp_factor_K0_static",
 )
+# bytes of the fixed device array qp_factor_K0_static takes its scratch from (QPGPU_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class qp_options(ct.Structure):
@@ -76,6 +78,7 @@ def lib():
     L.qp_default_options.restype = None
     L.qp_setup.argtypes = [ct.POINTER(P), I, I, I, P, P, P, P, P, P, I, ct.POINTER(qp_options), P]
     L.qp_factor_K0.argtypes = [P]
+    L.qp_factor_K0_static.argtypes = [P]
     L.qp_k0_solve.argtypes = [P, P, P, I]
     L.qp_kf_apply.argtypes = [P, P, P, P, I]
     L.qp_pcg_solve.argtypes = [P, P, P, P, I, I, D, I, ct.POINTER(qp_pcg_info)]
@@ -120,7 +123,8 @@ def lib():
     L.qp_tune_set.argtypes = [ct.c_char_p]
     L.qp_tune_get.argtypes = [ct.c_char_p, ct.c_size_t, ct.POINTER(ct.c_size_t)]
     L.qp_hbm_read_time.argtypes = [ct.c_size_t, I, I, ct.POINTER(D)]
-    for name in ("qp_setup", "qp_factor_K0", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve", "qp_ipm_solve",
+    for name in ("qp_setup", "qp_factor_K0", "qp_factor_K0_static", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve",
+                 "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
                  "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get",
                  "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_tune_set", "qp_tune_get",
@@ -247,6 +251,10 @@ def qp_setup(H, c, A, b, C, d, opt: qp_options | None = None, stream=None):
 
 def qp_factor_K0(ctx) -> int:
     return lib().qp_factor_K0(ctx)
+
+
+def qp_factor_K0_static(ctx) -> int:
+    return lib().qp_factor_K0_static(ctx)
 
 
 def qp_k0_solve(ctx, rhs, out) -> int:
@@ -519,8 +527,9 @@ class Solver:
             raise QpError(st, qp_last_error(self.ctx))
         return st
 
-    def factor(self):
-        return self.check(qp_factor_K0(self.ctx))
+    def factor(self, static=False):
+        """qp_factor_K0, or with static=True qp_factor_K0_static (no device allocation)."""
+        return self.check((qp_factor_K0_static if static else qp_factor_K0)(self.ctx))
 
     def k0_solve(self, rhs):
         out = np.empty_like(rhs)

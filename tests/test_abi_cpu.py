@@ -80,9 +80,16 @@ def test_setup_rejects_invalid_input_before_device_work(case):
 def test_null_context_calls_are_rejected():
     L = qpgpu.lib()
     assert L.qp_factor_K0(None) == qpgpu.QP_E_INVALID
+    assert L.qp_factor_K0_static(None) == qpgpu.QP_E_INVALID
     assert L.qp_ipm_solve(None, None, None, None, None, 0, None) == qpgpu.QP_E_INVALID
     assert L.qp_pcg_solve(None, None, None, None, 0, 1, 1e-8, 0, None) == qpgpu.QP_E_INVALID
     assert L.qp_ctx_bytes(None) == 0
+
+
+def test_static_scratch_size_matches_the_header():
+    text = open(os.path.join(ROOT, "include", "qpgpu.h")).read()
+    m = re.search(r"#define QPGPU_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == qpgpu.STATIC_SCRATCH_BYTES
 
 
 def test_binding_marshalling_rejects_wrong_dtypes():
