@@ -3,7 +3,8 @@
 For each size bucket n <= N (default N = 512, 1024, 2048, 4096) it builds a
 seeded dense Gaussian QP of the low-dof shape (m1 = 3n/4, m2 = n/2), factorizes
 it, and minimizes the device time of one whole P_L CG step (qp_op_time op 4: the
-C^T p sweep, the one-pass K0 product, q = C w + D p and the update) over the
+C^T p sweep, the one-pass K0 product, q = C w + D p and the update, or the
+folded step when cg_fold is set) over the
 kernel-shape keys by coordinate descent (two passes; every timing is the median
 of three).  Larger n use the base entry.  The result goes to
 autotune_gfx950.txt beside libqpgpu.so (or --out), which the library reads at
@@ -28,6 +29,7 @@ SPACE = [
     ("sym_pipe", [0, 1]),
     ("ld_nt", [0, 1, 2, 3]),
     ("upd_threads", [256, 512, 1024]),
+    ("cg_fold", [0, 1]),
 ]
 
 

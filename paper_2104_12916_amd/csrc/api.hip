@@ -340,6 +340,10 @@ static void layout_buffers(qp_ctx* ctx, Get&& get) {
   D(ctx->w64.part, part64);
   ctx->w64.part_elems = part64;
   D(ctx->bpart, ctx->bpart_cap);
+  if (!ctx->pooled) {
+    ctx->fold_cap = std::max(ctx->bpart_cap, k0_sym_reduce_grid(std::max(n, m2)) + 1);
+    D(ctx->fold, 4 * (size_t)ctx->fold_cap);
+  }
   ctx->isc = static_cast<IpmScalars*>(get(sizeof(IpmScalars)));
   if (!ctx->pooled) {
     ctx->sc = static_cast<PcgScalars*>(get(sizeof(PcgScalars)));
@@ -717,6 +721,50 @@ struct PcgResult {
   int done = 0;
 };
 
+// Partials of the folded CG step in the context's buffer (counts = the grids of
+// the kernels that write them).
+template <typename T>
+static FoldParts fold_parts(qp_ctx* ctx, int prec) {
+  const int cap = ctx->fold_cap, n = ctx->n, m2 = ctx->m2;
+  FoldParts fp{};
+  fp.al = ctx->fold;
+  fp.nal = k0_sym_reduce_grid(n);
+  fp.rz = ctx->fold + cap;
+  fp.nrz = prec == kPrecH ? k0_sym_reduce_grid(m2) : pcg_q_grid<T>(m2);
+  fp.rr = ctx->fold + 2 * (size_t)cap;
+  fp.wm = ctx->fold + 3 * (size_t)cap;
+  fp.nrw = pcg_q_grid<T>(m2);
+  if (fp.nal > cap || fp.nrz > cap || fp.nrw > cap) {
+    set_err(ctx, "folded CG step partials exceed their buffer (%d, %d, %d > %d)", fp.nal, fp.nrz, fp.nrw, cap);
+    throw Fail{QP_E_DEVICE};
+  }
+  return fp;
+}
+
+// One folded CG step (cg_folded): C^T sweep with the previous update's test and
+// beta, one pass over M and the sum of its partials with those of p^T q, the q
+// sweep with the vector update, and for P_H the one-pass X_P apply.
+template <typename T>
+static void fold_step(qp_ctx* ctx, const PcgBufs<T>& B, int prec, const FoldParts& fp, const EventPair* ev) {
+  hipStream_t st = ctx->stream;
+  const int n = ctx->n, m2 = ctx->m2;
+  const int* skip = &ctx->sc->done;
+  HIPCHK(ctx, fold_ct<T>(st, B.CT, ctx->ldm2, n, m2, B.z, B.p, B.u, ctx->sc, fp, ev ? &ev[0] : nullptr));
+  T* part = static_cast<T*>(ctx->sympart);
+  HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.Linv, ctx->ldN, ctx->N, n, B.u, part, ctx->sympart_bytes / sizeof(T),
+                                     skip, ev ? &ev[1] : nullptr));
+  HIPCHK(ctx, launch_k0_sym_reduce_fold<T>(st, ctx->N, n, part, B.w, ctx->sc, B.u, B.z, B.p, B.dvec, m2, fp.al,
+                                           fp.nal, ev ? &ev[2] : nullptr));
+  HIPCHK(ctx, fold_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, B.x, B.r, B.z, B.wts, prec, ctx->sc, fp,
+                        ev ? &ev[3] : nullptr));
+  if (prec == kPrecH) {
+    T* pp = static_cast<T*>(ctx->phpart);
+    HIPCHK(ctx, launch_k0_sym_sweep<T>(st, B.XP, ctx->ldm2, m2, m2, B.r, pp, ctx->phpart_bytes / sizeof(T), skip,
+                                       ev ? &ev[4] : nullptr));
+    HIPCHK(ctx, launch_ph_reduce_fold<T>(st, m2, pp, B.z, ctx->sc, B.r, fp.rz, fp.nrz, ev ? &ev[5] : nullptr));
+  }
+}
+
 // Executable graph of one poll chunk for these buffers: captured from `record`
 // (which only launches kernels) on the context's stream the first time.
 template <typename F>
@@ -767,6 +815,8 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
   };
   if (prec == kPrecH) ph_apply(1, nullptr);
   const int poll = ctx->opt.poll_every > 0 ? ctx->opt.poll_every : 32;
+  const bool fold = !expl && cg_folded(ctx, prec);
+  const FoldParts fp = fold ? fold_parts<T>(ctx, prec) : FoldParts{};
   PcgResult res;
   long long launched = 0;
   const bool prof = ctx->opt.profile != 0;
@@ -786,6 +836,11 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
     }
     launched += poll;
     auto chunk = [&](bool sampled) {
+      if (fold) {
+        for (int k = 0; k < poll; ++k) fold_step<T>(ctx, B, prec, fp, (sampled && k == 0) ? ctx->prof_ev : nullptr);
+        HIPCHK(ctx, fold_test(st, ctx->sc, fp));
+        return;
+      }
       for (int k = 0; k < poll; ++k) {
         const EventPair* ev = (sampled && k == 0) ? ctx->prof_ev : nullptr;
         if (expl) {
@@ -1406,6 +1461,10 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
                                             nullptr, 0));
             break;
           case 4: {
+            if (cg_folded(ctx, kPrecL)) {
+              fold_step<T>(ctx, B, kPrecL, fold_parts<T>(ctx, kPrecL), nullptr);
+              break;
+            }
             const int* skip = &ctx->sc->done;
             op_sweeps<T>(ctx, B, skip, nullptr);
             HIPCHK(ctx, pcg_q<T>(st, B.C, ctx->ldn, m2, n, B.w, B.dvec, B.p, B.q, ctx->sc, ctx->bpart,

@@ -1071,6 +1071,9 @@ void launch_chunk(qp_batch* B, const std::vector<Slot*>& pool, int poll, bool sa
     s->launched += poll;
     items.push_back(it);
   }
+  // largest QPs first: their workgroups start first and the small ones fill in behind
+  std::stable_sort(items.begin(), items.end(),
+                   [](const BItem<T>* a, const BItem<T>* b) { return a->ctx->n > b->ctx->n; });
   StepLists<T> L;
   build_lists<T>(B, items, L);
   qp_ctx* sk = &B->sink;

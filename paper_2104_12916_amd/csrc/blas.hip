@@ -1,10 +1,13 @@
 // Dense FP64 factorization kernels for the once-per-QP setup (gfx950 MFMA).
 //
-//   gemm_f64      C = alpha op(A) op(B) + beta C, 64x64 tiles, v_mfma_f64_16x16x4
-//                 through LDS; optional "lower only" output (SYRK-shaped updates)
-//                 and k-range trimming for triangular operands.
-//   chol_inv_leaf one workgroup factors a <= 64 x 64 SPD block in LDS and inverts
-//                 the Cholesky factor (LL^T = A, X = L^{-1}).
+//   gemm_f64      C = alpha op(A) op(B) + beta C, 128x64 or 64x64 tiles,
+//                 v_mfma_f64_16x16x4 over double-buffered LDS slabs; optional
+//                 "lower only" output (SYRK-shaped updates) and k-range trimming
+//                 for triangular operands.
+//   chol_inv_leaf one workgroup factors a <= 64 x 64 SPD block held in MFMA
+//                 accumulators and inverts the Cholesky factor (LL^T = A, X = L^{-1}).
+//   chol_inv_node one workgroup runs a whole node of <= 128 rows (two leaves and
+//                 the three products between them, operands in LDS).
 //   chol_inv      recursive blocked driver: with A = [A11 .; A21 A22],
 //                   (L11, X11) = chol_inv(A11);  L21 = A21 X11^T;
 //                   A22 -= L21 L21^T and T = L21 X11 (one launch);
@@ -41,7 +44,7 @@ struct GemmTile {
   static constexpr int AS = BM + GPAD, BS = BN + GPAD;
   static constexpr size_t kLdsBytes = 2 * GK * (AS + BS) * sizeof(double);
 };
-constexpr size_t kLdsBig = GemmTile<128, 128>::kLdsBytes, kLdsSmall = GemmTile<64, 64>::kLdsBytes;
+constexpr size_t kLdsBig = GemmTile<128, 64>::kLdsBytes, kLdsSmall = GemmTile<64, 64>::kLdsBytes;
 
 // Elements idx, idx+1 of row p (zero at or past lim); one 16-byte load when allowed.
 __device__ __forceinline__ v2d ld_pair(const double* __restrict__ p, int idx, int lim, bool vec) {
@@ -181,9 +184,28 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       }
 }
 
-// Tile shape of a launch covering `tiles128` tiles of 128 x 128: the large tile
-// when it still gives every CU about one tile, else 64 x 64 (four times as many).
-static bool use_big_tile(long long tiles128) { return tiles128 >= (long long)dev_info().cu_count * 3 / 4; }
+// Tile shape of a launch covering `tiles` tiles of 128 x 64: that shape (two
+// workgroups per CU) when it gives every CU at least about one and a half of
+// them, else 64 x 64 (twice as many tiles, more workgroups per CU).
+static bool use_big_tile(long long tiles) { return tiles >= (long long)dev_info().cu_count * 3 / 2; }
+
+// Order of the tiles of a GEMM with a triangular operand, whose tiles' k ranges
+// grow or shrink along one axis: the first half of the linear block indices takes
+// the tiles from the heaviest down, the second half from the lightest up, so the
+// workgroups dispatched together pair a long tile with a short one.  A bijection
+// of the grid; other GEMMs keep the plain order.
+__device__ __forceinline__ int2 tile_of_block(int flags) {
+  const int tri = flags & (kALower | kBUpper | kBLower | kAUpper);
+  if (tri != kALower && tri != kBUpper && tri != kBLower && tri != kAUpper)
+    return make_int2((int)blockIdx.x, (int)blockIdx.y);
+  const int gx = gridDim.x, gy = gridDim.y, total = gx * gy, half = total / 2;
+  const int b = (int)blockIdx.y * gx + (int)blockIdx.x;
+  const int idx = b < half ? b : total - 1 - (b - half);  // rank by work, heaviest first
+  if (tri == kALower) return make_int2(idx % gx, gy - 1 - idx / gx);  // work grows with the tile row
+  if (tri == kAUpper) return make_int2(idx % gx, idx / gx);           // work shrinks with the tile row
+  if (tri == kBUpper) return make_int2(gx - 1 - idx / gy, idx % gy);  // work grows with the tile column
+  return make_int2(idx / gy, idx % gy);                               // kBLower: shrinks with the column
+}
 
 static long long active_tiles(int M, int N, int bm, int bn, int flags) {
   const long long gy = (M + bm - 1) / bm, gx = (N + bn - 1) / bn;
@@ -194,16 +216,18 @@ static long long active_tiles(int M, int N, int bm, int bn, int flags) {
 }
 
 template <int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                                       int lda, int ta, const double* __restrict__ B, int ldb, int tb,
-                                                       double beta, double* __restrict__ C, int ldc, int flags) {
-  gemm_body<BM, BN>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(256, 2) gemm_f64_kernel(int M, int N, int K, double alpha,
+                                                          const double* __restrict__ A, int lda, int ta,
+                                                          const double* __restrict__ B, int ldb, int tb, double beta,
+                                                          double* __restrict__ C, int ldc, int flags) {
+  const int2 t = tile_of_block(flags);
+  gemm_body<BM, BN>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags, t.x, t.y);
 }
 
 // One GEMM per blockIdx.z, same op/scalars for all; tiles outside a problem's
 // M x N exit at once.
 template <int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_f64_batched_kernel(const GemmDesc* __restrict__ descs, int ta, int tb,
+__global__ void __launch_bounds__(256, 2) gemm_f64_batched_kernel(const GemmDesc* __restrict__ descs, int ta, int tb,
                                                                double alpha, double beta, int flags) {
   const GemmDesc g = descs[blockIdx.z];
   if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
@@ -214,10 +238,10 @@ __global__ void __launch_bounds__(256) gemm_f64_batched_kernel(const GemmDesc* _
 hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
                     const double* B, int ldb, double beta, double* C, int ldc, int flags) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (use_big_tile(active_tiles(M, N, 128, 128, flags))) {
-    using G = GemmTile<128, 128>;
+  if (use_big_tile(active_tiles(M, N, 128, 64, flags))) {
+    using G = GemmTile<128, 64>;
     if ((M + 127) / 128 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3((N + 127) / 128, (M + 127) / 128), dim3(256), G::kLdsBytes,
+    hipLaunchKernelGGL((gemm_f64_kernel<128, 64>), dim3((N + 63) / 64, (M + 127) / 128), dim3(256), G::kLdsBytes,
                        st, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
   } else {
     using G = GemmTile<64, 64>;
@@ -242,7 +266,7 @@ struct GemmArgs {
 };
 
 template <int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_f64_pair_kernel(GemmArgs g0, GemmArgs g1) {
+__global__ void __launch_bounds__(256, 2) gemm_f64_pair_kernel(GemmArgs g0, GemmArgs g1) {
   const GemmArgs g = blockIdx.z == 0 ? g0 : g1;
   if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
   gemm_body<BM, BN>(g.M, g.N, g.K, g.alpha, g.A, g.lda, g.ta, g.B, g.ldb, g.tb, g.beta, g.C, g.ldc, g.flags,
@@ -252,10 +276,10 @@ __global__ void __launch_bounds__(256) gemm_f64_pair_kernel(GemmArgs g0, GemmArg
 static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmArgs& g1) {
   const int mx = std::max(g0.M, g1.M), nx = std::max(g0.N, g1.N);
   if (mx <= 0 || nx <= 0) return hipSuccess;
-  const long long t128 = active_tiles(g0.M, g0.N, 128, 128, g0.flags) + active_tiles(g1.M, g1.N, 128, 128, g1.flags);
-  if (use_big_tile(t128)) {
+  const long long tb = active_tiles(g0.M, g0.N, 128, 64, g0.flags) + active_tiles(g1.M, g1.N, 128, 64, g1.flags);
+  if (use_big_tile(tb)) {
     if ((mx + 127) / 128 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_pair_kernel<128, 128>), dim3((nx + 127) / 128, (mx + 127) / 128, 2), dim3(256),
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<128, 64>), dim3((nx + 63) / 64, (mx + 127) / 128, 2), dim3(256),
                        kLdsBig, st, g0, g1);
   } else {
     if ((mx + 63) / 64 > 65535) return hipErrorInvalidValue;
@@ -267,7 +291,7 @@ static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmAr
 
 // Batched form: blockIdx.z < count0 takes d0[z] with o0, the rest d1[z - count0] with o1.
 template <int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_f64_batched_pair_kernel(const GemmDesc* __restrict__ d0, int count0,
+__global__ void __launch_bounds__(256, 2) gemm_f64_batched_pair_kernel(const GemmDesc* __restrict__ d0, int count0,
                                                                     GemmOp o0, const GemmDesc* __restrict__ d1,
                                                                     GemmOp o1) {
   const int z = blockIdx.z;
@@ -298,20 +322,22 @@ constexpr double kPivRel = 1e-13;
 // updates of the trailing columns, a_ik -= sum_p cf_ip ev_kp, and of the rows
 // of X below the block, x_i -= sum_p cf_ip xf_p, are rank-4 products: one MFMA
 // per 16 x 16 tile, with the k = 4 operand slots holding p.
-__device__ __forceinline__ double sel4(const double (&v)[4], int p) {
-  return p == 0 ? v[0] : p == 1 ? v[1] : p == 2 ? v[2] : v[3];
-}
 
-__device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
-                                                   int nb, int* __restrict__ info, int code,
-                                                   const double* __restrict__ dmax) {
-  __shared__ double pan[2][LEAF][4];   // columns 4J..4J+3 of A (rows >= 4J), double-buffered
-  __shared__ double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J
-  __shared__ double piv[LEAF];
+// LDS of the leaf elimination.
+struct LeafShared {
+  double pan[2][LEAF][4];   // columns 4J..4J+3 of A (rows >= 4J), double-buffered
+  double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J
+  double ev[LEAF][5];       // rows through block J's four steps: eliminated values (padded row)
+  double cf[LEAF][5];       // and multipliers
+  double xf[4][LEAF];       // rows 4J..4J+3 of X after the block's steps among themselves
+  double piv[LEAF];         // pivots d
+};
+
+// Accumulator layout of a 64 x 64 block over the four wavefronts: wavefront I
+// holds tiles (I, K), K <= I; register r of lane l holds tile entry (4 r + l / 16, l % 16).
+__device__ __forceinline__ void leaf_load(const double* __restrict__ A, int lda, int nb, v4d (&accA)[4],
+                                          v4d (&accX)[4]) {
   const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
-  // accumulator layout: register r of lane l holds tile entry (4 r + lr, lc)
-  const double pmin = kPivRel * (*dmax);
-  v4d accA[4], accX[4];
 #pragma unroll
   for (int K = 0; K < 4; ++K)
 #pragma unroll
@@ -320,6 +346,19 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
       accA[K][r] = (K <= I && i < nb && k <= i) ? A[(size_t)i * lda + k] : 0.0;
       accX[K][r] = (i == k && i < nb) ? 1.0 : 0.0;
     }
+}
+
+// The elimination on the accumulators (entries past nb must be zero; entries
+// above the diagonal are never read).  Per column block: the owners publish the
+// block's columns of A and rows of X (barrier); wavefront 0 passes every row
+// below the block through its four steps (ev, cf) and wavefront 1 eliminates the
+// block's rows of X among themselves (xf), each thread redoing the 4 x 4
+// diagonal block (barrier); then the rank-4 MFMA updates read ev, cf and xf.
+// Returns true when a pivot is rejected.
+__device__ __forceinline__ bool leaf_core(LeafShared& sh, int nb, const double* __restrict__ dmax, v4d (&accA)[4],
+                                          v4d (&accX)[4]) {
+  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const double pmin = kPivRel * (*dmax);
   bool bad = false;
   const int nblk = (nb + 3) / 4;
 #pragma unroll
@@ -332,12 +371,12 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * I + 4 * r + lr;
-          if (i >= j0) pan[buf][i][lc - c0] = accA[K0][r];
+          if (i >= j0) sh.pan[buf][i][lc - c0] = accA[K0][r];
         }
       }
       if (I == K0) {
 #pragma unroll
-        for (int K = 0; K <= K0; ++K) xrow[buf][lr][16 * K + lc] = accX[K][jj];
+        for (int K = 0; K <= K0; ++K) sh.xrow[buf][lr][16 * K + lc] = accX[K][jj];
       }
       __syncthreads();
       // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
@@ -346,7 +385,7 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? pan[buf][j0 + i][q] : 0.0;
+        for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? sh.pan[buf][j0 + i][q] : 0.0;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         double d = E[p][p];
@@ -367,59 +406,55 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
           for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
         }
       }
-      if (tid == 0) {
+      if (I == 0) {
+        // row l below the block through the block's four steps: ev[p] = eliminated
+        // a_{l, j0+p}, cf[p] = ev[p] / d_p (the multiplier of step j0 + p)
+        if (l > j0 + 3) {
+          double g[4], cf[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) piv[j0 + p] = E[p][p];
-      }
-      // Row i >= j0 + 4 through the block's four steps: ev[p] = eliminated a_{i, j0+p},
-      // cf[p] = ev[p] / d_p (the multiplier of step j0 + p).
-      auto row_steps = [&](int i, double (&ev)[4], double (&cf)[4]) {
-        double g[4];
+          for (int q = 0; q < 4; ++q) g[q] = sh.pan[buf][l][q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = pan[buf][i][q];
+          for (int p = 0; p < 4; ++p) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+            for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
+            cf[p] = g[p] * dinv[p];
+            sh.ev[l][p] = g[p];
+            sh.cf[l][p] = cf[p];
+          }
+        } else {
 #pragma unroll
-          for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
-          ev[p] = g[p];
-          cf[p] = g[p] * dinv[p];
+          for (int p = 0; p < 4; ++p) {
+            sh.ev[l][p] = 0.0;
+            sh.cf[l][p] = 0.0;
+          }
         }
-      };
-      // Row j0 + p of X after the block's steps among its own rows, column k.
-      auto xf_of = [&](int p, int k) {
+        if (tid == 0) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p) sh.piv[j0 + p] = E[p][p];
+        }
+      } else if (I == 1) {
+        // column l of rows j0..j0+3 of X after their own four steps
         double f[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          f[q] = xrow[buf][q][k];
+          f[q] = sh.xrow[buf][q][l];
 #pragma unroll
           for (int qq = 0; qq < q; ++qq) {
             const double lq = E[q][qq] * dinv[qq];
             f[q] -= lq * f[qq];
           }
+          sh.xf[q][l] = f[q];
         }
-        return sel4(f, p);
-      };
+      }
+      __syncthreads();
       if (I >= K0) {
-        // A operand: -cf of row 16 I + lc, slot p = lr (rows of the block or above: no update)
-        const int ia = 16 * I + lc;
-        double aop = 0.0;
-        if (ia > j0 + 3) {
-          double ev[4], cf[4];
-          row_steps(ia, ev, cf);
-          aop = -sel4(cf, lr);
-        }
+        // A operand: -cf of row 16 I + lc, slot p = lr (zero for the block's rows and above)
+        const double aop = -sh.cf[16 * I + lc][lr];
 #pragma unroll
         for (int K = K0; K < 4; ++K) {
           if (K <= I) {
             // B operand: ev of row 16 K + lc (a trailing column), slot p = lr
-            const int kb = 16 * K + lc;
-            double bop = 0.0;
-            if (kb > j0 + 3) {
-              double ev[4], cf[4];
-              row_steps(kb, ev, cf);
-              bop = sel4(ev, lr);
-            }
-            accA[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, accA[K], 0, 0, 0);
+            accA[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sh.ev[16 * K + lc][lr], accA[K], 0, 0, 0);
           }
         }
         // the block's own columns keep their eliminated values
@@ -429,9 +464,7 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
           for (int r = 0; r < 4; ++r) {
             const int i = 16 * I + 4 * r + lr;
             if (i > j0 + 3) {
-              double ev[4], cf[4];
-              row_steps(i, ev, cf);
-              accA[K0][r] = sel4(ev, p);
+              accA[K0][r] = sh.ev[i][p];
             } else if (i >= j0) {
               const int q = i - j0;
               double e = 0.0;
@@ -447,7 +480,7 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
         // X: rows below the block take x_i -= sum_p cf_ip xf_p; the block's rows become xf
 #pragma unroll
         for (int K = 0; K <= K0; ++K) {
-          const double xv = xf_of(lr, 16 * K + lc);
+          const double xv = sh.xf[lr][16 * K + lc];
           accX[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, xv, accX[K], 0, 0, 0);
           if (I == K0) accX[K][jj] = xv;
         }
@@ -455,6 +488,15 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
     }
   }
   __syncthreads();
+  return bad;
+}
+
+// L = L_1 D^{1/2} into A and X = D^{-1/2} L_1^{-1} into X (rows and columns < nb);
+// with xs, also X into xs (64 x ldxs, LDS).
+__device__ __forceinline__ void leaf_store(const LeafShared& sh, double* __restrict__ A, int lda,
+                                           double* __restrict__ X, int ldx, int nb, const v4d (&accA)[4],
+                                           const v4d (&accX)[4], double* xs = nullptr, int ldxs = 0) {
+  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
 #pragma unroll
   for (int K = 0; K < 4; ++K) {
     if (K > I) continue;
@@ -462,11 +504,23 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + 4 * r + lr, k = 16 * K + lc;
       if (i >= nb || k >= nb) continue;
-      if (k <= i) A[(size_t)i * lda + k] = accA[K][r] / sqrt(piv[k]);
-      X[(size_t)i * ldx + k] = accX[K][r] / sqrt(piv[i]);
+      if (k <= i) A[(size_t)i * lda + k] = accA[K][r] / sqrt(sh.piv[k]);
+      const double x = accX[K][r] / sqrt(sh.piv[i]);
+      X[(size_t)i * ldx + k] = x;
+      if (xs) xs[i * ldxs + k] = x;
     }
   }
-  if (tid == 0 && bad) *info = code;
+}
+
+__device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
+                                                   int nb, int* __restrict__ info, int code,
+                                                   const double* __restrict__ dmax) {
+  __shared__ LeafShared sh;
+  v4d accA[4], accX[4];
+  leaf_load(A, lda, nb, accA, accX);
+  const bool bad = leaf_core(sh, nb, dmax, accA, accX);
+  leaf_store(sh, A, lda, X, ldx, nb, accA, accX);
+  if (threadIdx.x == 0 && bad) *info = code;
 }
 
 __global__ void __launch_bounds__(256) chol_inv_leaf_kernel(double* __restrict__ A, int lda, double* __restrict__ X,
@@ -478,6 +532,112 @@ __global__ void __launch_bounds__(256) chol_inv_leaf_kernel(double* __restrict__
 __global__ void __launch_bounds__(256) chol_inv_leaf_batched_kernel(const LeafDesc* __restrict__ descs) {
   const LeafDesc d = descs[blockIdx.x];
   chol_inv_leaf_body(d.A, d.lda, d.X, d.ldx, d.nb, d.info, d.code, d.dmax);
+}
+
+// Node of 64 < n <= 128 rows in one workgroup, the recursive driver's steps
+// for one node: (L11, X11) = leaf(A11); L21 = A21 X11^T; A22 -= L21 L21^T and
+// T = L21 X11; (L22, X22) = leaf(A22); X21 = -X22 T.  A21, X11, L21, T and X22
+// stay in LDS, and A22 is updated in the accumulators the second leaf starts
+// from, so a node costs one launch instead of two leaves and three GEMMs.
+constexpr int NLD = LEAF + 1;  // LDS row stride (doubles)
+struct NodeShared {
+  LeafShared leaf;
+  double a[LEAF * NLD];   // A21, later X22
+  double x[LEAF * NLD];   // X11
+  double lt[LEAF * NLD];  // L21
+  double t[LEAF * NLD];   // T
+};
+
+// acc[K] (tile (I, K) of a 64 x 64 product, wavefront I; K <= kmax_tile) += sign *
+// sum_k opA(i, k) opB(k, j) over k < 64, operands read from LDS.
+template <typename FA, typename FB>
+__device__ __forceinline__ void node_mm(v4d (&acc)[4], int ktiles, double sign, FA&& opA, FB&& opB) {
+  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+#pragma unroll 4
+  for (int k0 = 0; k0 < LEAF; k0 += 4) {
+    const double a = sign * opA(16 * I + lc, k0 + lr);
+#pragma unroll
+    for (int K = 0; K < 4; ++K)
+      if (K < ktiles) acc[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, opB(k0 + lr, 16 * K + lc), acc[K], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
+                                                   int n, int* __restrict__ info, int code,
+                                                   const double* __restrict__ dmax) {
+  __shared__ NodeShared sh;
+  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int n2 = n - LEAF;
+  double* A21 = A + (size_t)LEAF * lda;
+  double* A22 = A21 + LEAF;
+  double* X21 = X + (size_t)LEAF * ldx;
+  double* X22 = X21 + LEAF;
+  // A21 into LDS (rows past n2 zero); X11's tile zeroed, the first leaf writes its
+  // lower triangle and the products below read all of it
+  for (int e = tid; e < LEAF * LEAF; e += 256) {
+    const int i = e / LEAF, k = e % LEAF;
+    sh.a[i * NLD + k] = i < n2 ? A21[(size_t)i * lda + k] : 0.0;
+    sh.x[i * NLD + k] = 0.0;
+  }
+  v4d accA[4], accX[4];
+  leaf_load(A, lda, LEAF, accA, accX);
+  bool bad = leaf_core(sh.leaf, LEAF, dmax, accA, accX);
+  leaf_store(sh.leaf, A, lda, X, ldx, LEAF, accA, accX, sh.x, NLD);
+  __syncthreads();
+  // L21 = A21 X11^T
+  v4d acc[4];
+#pragma unroll
+  for (int K = 0; K < 4; ++K) acc[K] = v4d{0, 0, 0, 0};
+  node_mm(acc, 4, 1.0, [&](int i, int k) { return sh.a[i * NLD + k]; },
+          [&](int k, int j) { return sh.x[j * NLD + k]; });
+#pragma unroll
+  for (int K = 0; K < 4; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh.lt[(16 * I + 4 * r + lr) * NLD + 16 * K + lc] = acc[K][r];
+  __syncthreads();
+  // A22 -= L21 L21^T on the accumulators of the second leaf (tiles K <= I)
+  leaf_load(A22, lda, n2, accA, accX);
+  node_mm(accA, I + 1, -1.0, [&](int i, int k) { return sh.lt[i * NLD + k]; },
+          [&](int k, int j) { return sh.lt[j * NLD + k]; });
+  // T = L21 X11
+#pragma unroll
+  for (int K = 0; K < 4; ++K) acc[K] = v4d{0, 0, 0, 0};
+  node_mm(acc, 4, 1.0, [&](int i, int k) { return sh.lt[i * NLD + k]; },
+          [&](int k, int j) { return sh.x[k * NLD + j]; });
+#pragma unroll
+  for (int K = 0; K < 4; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh.t[(16 * I + 4 * r + lr) * NLD + 16 * K + lc] = acc[K][r];
+  // (L22, X22) = leaf(A22); X22 also into LDS (over A21, which is no longer read)
+  bad = leaf_core(sh.leaf, n2, dmax, accA, accX) || bad;
+  for (int e = tid; e < LEAF * LEAF; e += 256) sh.a[(e / LEAF) * NLD + e % LEAF] = 0.0;
+  __syncthreads();
+  leaf_store(sh.leaf, A22, lda, X22, ldx, n2, accA, accX, sh.a, NLD);
+  __syncthreads();
+  // X21 = -X22 T
+#pragma unroll
+  for (int K = 0; K < 4; ++K) acc[K] = v4d{0, 0, 0, 0};
+  node_mm(acc, 4, -1.0, [&](int i, int k) { return sh.a[i * NLD + k]; },
+          [&](int k, int j) { return sh.t[k * NLD + j]; });
+#pragma unroll
+  for (int K = 0; K < 4; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + 4 * r + lr, j = 16 * K + lc;
+      if (i < n2) X21[(size_t)i * ldx + j] = acc[K][r];
+    }
+  if (tid == 0 && bad) *info = code;
+}
+
+__global__ void __launch_bounds__(256) chol_inv_node_kernel(double* __restrict__ A, int lda, double* __restrict__ X,
+                                                            int ldx, int n, int* __restrict__ info, int code,
+                                                            const double* __restrict__ dmax) {
+  chol_inv_node_body(A, lda, X, ldx, n, info, code, dmax);
+}
+
+__global__ void __launch_bounds__(256) chol_inv_node_batched_kernel(const LeafDesc* __restrict__ descs) {
+  const LeafDesc d = descs[blockIdx.x];
+  chol_inv_node_body(d.A, d.lda, d.X, d.ldx, d.nb, d.info, d.code, d.dmax);
 }
 
 __global__ void fill2d_kernel(double* __restrict__ X, int ld, int rows, int cols, double v) {
@@ -513,6 +673,10 @@ static hipError_t chol_inv_rec(hipStream_t st, double* A, int lda, double* X, in
   hipError_t e;
   if (n <= LEAF) {
     hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(256), 0, st, A, lda, X, ldx, n, info, code, dmax);
+    return hipGetLastError();
+  }
+  if (n <= 2 * LEAF) {  // split at LEAF like the general node, in one workgroup
+    hipLaunchKernelGGL(chol_inv_node_kernel, dim3(1), dim3(256), 0, st, A, lda, X, ldx, n, info, code, dmax);
     return hipGetLastError();
   }
   const int n1 = split_of(n);
@@ -592,15 +756,14 @@ void BatchedOps::gemm(int ta, int tb, double alpha, double beta, int flags, cons
     nx = std::max(nx, g.N);
   }
   if (mx <= 0 || nx <= 0) return;
-  long long t128 = 0;
-  for (const GemmDesc& g : d) t128 += active_tiles(g.M, g.N, 128, 128, flags);
+  long long tiles = 0;
+  for (const GemmDesc& g : d) tiles += active_tiles(g.M, g.N, 128, 64, flags);
   Op o{};
   o.kind = 1;
   o.count = (int)d.size();
-  o.big = use_big_tile(t128) ? 1 : 0;
-  const int tb_ = o.big ? 128 : 64;
-  o.gx = (nx + tb_ - 1) / tb_;
-  o.gy = (mx + tb_ - 1) / tb_;
+  o.big = use_big_tile(tiles) ? 1 : 0;
+  o.gx = (nx + 63) / 64;
+  o.gy = o.big ? (mx + 127) / 128 : (mx + 63) / 64;
   o.g0 = GemmOp{ta, tb, flags, alpha, beta};
   o.off = push(d);
   ops_.push_back(o);
@@ -620,17 +783,16 @@ void BatchedOps::gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, co
       nx = std::max(nx, g.N);
     }
   if (mx <= 0 || nx <= 0) return;
-  long long t128 = 0;
-  for (const GemmDesc& g : d0) t128 += active_tiles(g.M, g.N, 128, 128, o0.flags);
-  for (const GemmDesc& g : d1) t128 += active_tiles(g.M, g.N, 128, 128, o1.flags);
+  long long tiles = 0;
+  for (const GemmDesc& g : d0) tiles += active_tiles(g.M, g.N, 128, 64, o0.flags);
+  for (const GemmDesc& g : d1) tiles += active_tiles(g.M, g.N, 128, 64, o1.flags);
   Op o{};
   o.kind = 3;
   o.count = (int)d0.size();
   o.count2 = (int)d1.size();
-  o.big = use_big_tile(t128) ? 1 : 0;
-  const int tb_ = o.big ? 128 : 64;
-  o.gx = (nx + tb_ - 1) / tb_;
-  o.gy = (mx + tb_ - 1) / tb_;
+  o.big = use_big_tile(tiles) ? 1 : 0;
+  o.gx = (nx + 63) / 64;
+  o.gy = o.big ? (mx + 127) / 128 : (mx + 63) / 64;
   o.g0 = o0;
   o.g1 = o1;
   o.off = push(d0);
@@ -642,8 +804,9 @@ void BatchedOps::gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, co
 // every node a job takes the part of the node inside its own n (possibly none),
 // which is exactly the node chol_inv_rec visits for that job alone.
 void BatchedOps::rec(const std::vector<CholJob>& jobs, int off, int len) {
-  if (len <= LEAF) {
-    std::vector<LeafDesc> d;
+  if (len <= 2 * LEAF) {
+    // a job's part of the node: a leaf when it has at most LEAF rows, else a fused node
+    std::vector<LeafDesc> leaves, nodes;
     for (const CholJob& j : jobs) {
       const int nb = std::min(len, j.n - off);
       if (nb <= 0) continue;
@@ -656,14 +819,17 @@ void BatchedOps::rec(const std::vector<CholJob>& jobs, int off, int len) {
       l.ldx = j.ldx;
       l.nb = nb;
       l.code = j.code;
-      d.push_back(l);
+      (nb <= LEAF ? leaves : nodes).push_back(l);
     }
-    if (d.empty()) return;
-    Op o{};
-    o.kind = 0;
-    o.count = (int)d.size();
-    o.off = push(d);
-    ops_.push_back(o);
+    for (int kind : {0, 4}) {
+      const std::vector<LeafDesc>& d = kind == 0 ? leaves : nodes;
+      if (d.empty()) continue;
+      Op o{};
+      o.kind = kind;
+      o.count = (int)d.size();
+      o.off = push(d);
+      ops_.push_back(o);
+    }
     return;
   }
   const int n1 = len / 2;
@@ -719,11 +885,15 @@ hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
         hipLaunchKernelGGL(chol_inv_leaf_batched_kernel, dim3(o.count), dim3(256), 0, st,
                            reinterpret_cast<const LeafDesc*>(base + o.off));
         break;
+      case 4:
+        hipLaunchKernelGGL(chol_inv_node_batched_kernel, dim3(o.count), dim3(256), 0, st,
+                           reinterpret_cast<const LeafDesc*>(base + o.off));
+        break;
       case 1: {
         if (o.gy > 65535) return hipErrorInvalidValue;
         const GemmDesc* d = reinterpret_cast<const GemmDesc*>(base + o.off);
         if (o.big)
-          hipLaunchKernelGGL((gemm_f64_batched_kernel<128, 128>), dim3(o.gx, o.gy, o.count), dim3(256),
+          hipLaunchKernelGGL((gemm_f64_batched_kernel<128, 64>), dim3(o.gx, o.gy, o.count), dim3(256),
                              kLdsBig, st, d, o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
                              o.g0.flags);
         else
@@ -737,7 +907,7 @@ hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
         const GemmDesc* d0 = reinterpret_cast<const GemmDesc*>(base + o.off);
         const GemmDesc* d1 = reinterpret_cast<const GemmDesc*>(base + o.off2);
         if (o.big)
-          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<128, 128>), dim3(o.gx, o.gy, o.count + o.count2),
+          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<128, 64>), dim3(o.gx, o.gy, o.count + o.count2),
                              dim3(256), kLdsBig, st, d0, o.count, o.g0, d1, o.g1);
         else
           hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<64, 64>), dim3(o.gx, o.gy, o.count + o.count2),

@@ -28,7 +28,8 @@ struct PcgScalars {
   int iter;        // completed CG steps
   int maxit;
   int done;        // 1 converged, 2 iteration cap, 3 breakdown (p^T q <= 0)
-  int pad;
+  int fresh;       // folded-update step (cg_fold): 1 until the first update of a solve
+  double rho_next; // folded-update step: r^T z of the current z, the rho of the step's alpha
 };
 
 // Triangular shape of a matrix operand.
@@ -67,6 +68,11 @@ struct Tune {
   int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
                           // 1 us faster per CG step than 1024 at m2 = 2048)
   int mv_rt = 1;         // multi-vector sweeps of the block PCG: rows per thread (1 or 2)
+  int cg_fold = 0;       // 1: single-QP implicit CG step with the vector update folded into the
+                         // operator sweeps (C^T sweep, sum of the one-pass partials, q sweep): one
+                         // launch fewer per step, but the C^T sweep reads z and p and reduces the
+                         // previous step's partials (n = 4096, m2 = 2048: 70.2 vs 68.6 us per step;
+                         // n = 200: 3-4 % faster); 0 keeps the separate update kernel
   int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
                         // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
                         // more than the 256 MB last-level cache holds; loading M plainly and C, C^T

@@ -128,6 +128,8 @@ struct qp_ctx {
   qpg::GemvWork<float> w32{};
   double* bpart = nullptr;  // per-workgroup partials of p^T q
   int bpart_cap = 0;
+  double* fold = nullptr;  // partials handed between the kernels of the folded CG step (4 x fold_cap)
+  int fold_cap = 0;
   qpg::PcgScalars* sc = nullptr;
   qpg::IpmScalars* isc = nullptr;
   double* stats = nullptr;
@@ -216,6 +218,14 @@ inline bool op_fused(const qp_ctx* ctx) {
 // The P_H apply z = X_P^T (X_P r) runs as one pass over X_P (the one-pass sweep
 // with N = n = m2 and no sign flips) instead of a row and a column sweep.
 inline bool ph_fused(const qp_ctx* ctx) { return tune().k0_sym && ctx->m2 <= k0_sym_max_n<double>(); }
+// The CG step of this solve folds the vector update into its operator sweeps
+// (pcg.hpp, FoldParts): single-QP implicit step over the stored C^T with the
+// one-pass K0 product, and for P_H the one-pass X_P apply.
+inline bool cg_folded(const qp_ctx* ctx, int prec) {
+  return tune().cg_fold && ctx->fold && tune().op_t && tune().k0_sym && !ctx->master &&
+         ctx->opt.kf_form == QP_KF_IMPLICIT && ctx->n <= k0_sym_max_n<double>() && !ctx->c_identity &&
+         (prec != kPrecH || ctx->m2 <= k0_sym_max_n<double>());
+}
 inline bool store_mt(const qp_ctx* ctx) { return (op_transposed(ctx) && !op_fused(ctx)) || ctx->keep_mt; }
 void ph_setup(qp_ctx* ctx);
 void ph_factor(qp_ctx* ctx, const double* dvec);

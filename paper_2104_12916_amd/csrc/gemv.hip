@@ -684,9 +684,12 @@ struct Pair2 {
   typedef T type __attribute__((ext_vector_type(2)));
 };
 
+// Returns, in the threads that wrote them (t < 8), the two columns written
+// (zeros elsewhere); false when the skip flag was set (nothing written).
 template <typename T>
-__device__ __forceinline__ void k0_sym_reduce_body(const T* __restrict__ part, int ldp, int G, int n,
-                                                   T* __restrict__ w, const int* __restrict__ skip, int grp) {
+__device__ __forceinline__ bool k0_sym_reduce_body(const T* __restrict__ part, int ldp, int G, int n,
+                                                   T* __restrict__ w, const int* __restrict__ skip, int grp,
+                                                   typename Pair2<T>::type* out = nullptr) {
   using P2 = typename Pair2<T>::type;
   constexpr int kPairs = kRedCols / 2, kGroups = 256 / kPairs, kInFlight = 16;
   const int sk = skip ? *skip : 0;  // tested once the partial loads are in flight
@@ -708,7 +711,7 @@ __device__ __forceinline__ void k0_sym_reduce_body(const T* __restrict__ part, i
       for (int j = 0; j < kInFlight; ++j) acc[j] += v[j];
     }
   }
-  if (sk) return;
+  if (sk) return false;
 #pragma unroll
   for (int h = kInFlight / 2; h >= 1; h >>= 1)
 #pragma unroll
@@ -724,11 +727,69 @@ __device__ __forceinline__ void k0_sym_reduce_body(const T* __restrict__ part, i
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (lane < kPairs) sh[wave][lane] = s;
   __syncthreads();
+  P2 res = P2{T(0), T(0)};
   if (threadIdx.x < kPairs && col < n) {
     const P2 t = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
     w[col] = t.x;
-    if (col + 1 < n) w[col + 1] = t.y;
+    res.x = t.x;
+    if (col + 1 < n) {
+      w[col + 1] = t.y;
+      res.y = t.y;
+    }
   }
+  if (out) *out = res;
+  return true;
+}
+
+// The sum of the one-pass partials inside the folded CG step, with one more
+// per-workgroup partial: the K0 sum adds u^T w over its 16 columns and
+// p_new^T D p_new over its share of the m2 entries (p_new = z + beta p_old), so
+// the q sweep gets p^T q = u^T w + p^T D p from these partials; the P_H sum adds
+// r^T z over its columns.
+template <typename T>
+__global__ void __launch_bounds__(256) k0_sym_reduce_fold_kernel(const T* __restrict__ part, int ldp, int G, int n,
+                                                                 T* __restrict__ w, const PcgScalars* __restrict__ sc,
+                                                                 const T* __restrict__ u, const T* __restrict__ z,
+                                                                 const T* __restrict__ p,
+                                                                 const T* __restrict__ dvec, int m2,
+                                                                 double* __restrict__ al) {
+  __shared__ double sh[16];
+  if (sc->done) return;
+  typename Pair2<T>::type t;
+  k0_sym_reduce_body<T>(part, ldp, G, n, w, nullptr, blockIdx.x, &t);
+  double s = 0;
+  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
+  if (threadIdx.x < kRedCols / 2 && col < n) {
+    s = (double)u[col] * t.x;
+    if (col + 1 < n) s += (double)u[col + 1] * t.y;
+  }
+  const T bt = (T)sc->beta;
+  const int share = (m2 + gridDim.x - 1) / gridDim.x;
+  const int j1 = min(m2, (int)(blockIdx.x + 1) * share);
+  for (int j = blockIdx.x * share + threadIdx.x; j < j1; j += blockDim.x) {
+    const T pj = z[j] + bt * p[j];
+    s += (double)dvec[j] * pj * pj;
+  }
+  s = block_sum<double>(s, sh);
+  if (threadIdx.x == 0) al[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) ph_reduce_fold_kernel(const T* __restrict__ part, int ldp, int G, int m2,
+                                                             T* __restrict__ z, const PcgScalars* __restrict__ sc,
+                                                             const T* __restrict__ r, double* __restrict__ rz) {
+  __shared__ double sh[16];
+  if (sc->done) return;
+  typename Pair2<T>::type t;
+  k0_sym_reduce_body<T>(part, ldp, G, m2, z, nullptr, blockIdx.x, &t);
+  double s = 0;
+  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
+  if (threadIdx.x < kRedCols / 2 && col < m2) {
+    s = (double)r[col] * t.x;
+    if (col + 1 < m2) s += (double)r[col + 1] * t.y;
+  }
+  s = block_sum<double>(s, sh);
+  if (threadIdx.x == 0) rz[blockIdx.x] = s;
 }
 
 template <typename T>
@@ -882,6 +943,31 @@ hipError_t launch_k0_sym_reduce(hipStream_t st, int N, int n, const T* part, T* 
   return hipGetLastError();
 }
 
+int k0_sym_reduce_grid(int n) { return (n + kRedCols - 1) / kRedCols; }
+
+template <typename T>
+hipError_t launch_k0_sym_reduce_fold(hipStream_t st, int N, int n, const T* part, T* w, const PcgScalars* sc,
+                                     const T* u, const T* z, const T* p, const T* dvec, int m2, double* al, int nal,
+                                     const EventPair* ev) {
+  if (n <= 0) return hipSuccess;
+  const int grid = k0_sym_reduce_grid(n);
+  if (grid > nal) return hipErrorInvalidValue;
+  QPG_LAUNCH(k0_sym_reduce_fold_kernel<T>, dim3(grid), dim3(256), 0u, st, ev, part, k0_sym_ldp(n),
+             k0_sym_grid<T>(N, n), n, w, sc, u, z, p, dvec, m2, al);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ph_reduce_fold(hipStream_t st, int m2, const T* part, T* z, const PcgScalars* sc, const T* r,
+                                 double* rz, int nrz, const EventPair* ev) {
+  if (m2 <= 0) return hipSuccess;
+  const int grid = k0_sym_reduce_grid(m2);
+  if (grid > nrz) return hipErrorInvalidValue;
+  QPG_LAUNCH(ph_reduce_fold_kernel<T>, dim3(grid), dim3(256), 0u, st, ev, part, k0_sym_ldp(m2),
+             k0_sym_grid<T>(m2, m2), m2, z, sc, r, rz);
+  return hipGetLastError();
+}
+
 // ---- transposes ---------------------------------------------------------------
 // dst = src^T (src rows x cols, row-major), optionally rounded to float32;
 // 32 x 32 tiles through LDS so both sides are coalesced.
@@ -957,6 +1043,11 @@ hipError_t btranspose_2d(hipStream_t st, const TransDesc* d, int count, int max_
   template hipError_t launch_k0_sym_sweep<T>(hipStream_t, const T*, int, int, int, const T*, T*, size_t,          \
                                              const int*, const EventPair*);                                      \
   template hipError_t launch_k0_sym_reduce<T>(hipStream_t, int, int, const T*, T*, const int*, const EventPair*);  \
+  template hipError_t launch_k0_sym_reduce_fold<T>(hipStream_t, int, int, const T*, T*, const PcgScalars*,       \
+                                                   const T*, const T*, const T*, const T*, int, double*, int,    \
+                                                   const EventPair*);                                             \
+  template hipError_t launch_ph_reduce_fold<T>(hipStream_t, int, const T*, T*, const PcgScalars*, const T*,       \
+                                               double*, int, const EventPair*);                                   \
   template int bk0_sym_grid<T>(int, int);                                                                         \
   template int k0_sym_width<T>(int);                                                                              \
   template bool fill_sym_desc<T>(SymDesc<T>&, const T*, int, int, int, const T*, T*, T*, size_t, const int*);     \

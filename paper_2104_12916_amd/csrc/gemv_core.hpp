@@ -123,6 +123,54 @@ __device__ __forceinline__ T row_dot_gx(const T* __restrict__ a, const T* __rest
   return wave_sum<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
+// Two dot products of one matrix row with x1 and x2 (both read through the caches
+// as 16-byte vectors, zero at or past xlen): the row is loaded once.  Full sums
+// in every lane.
+template <typename T, int U = 4, bool NT = true>
+__device__ __forceinline__ void row_dot2_gx(const T* __restrict__ a, const T* __restrict__ x1,
+                                            const T* __restrict__ x2, int lenR, int xlen, int lane, T& d1, T& d2) {
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CH = kWave * VE;
+  T acc1[2] = {0, 0}, acc2[2] = {0, 0};
+  int j = lane * VE;
+  const V* av = reinterpret_cast<const V*>(a);
+  auto xload = [&](const T* __restrict__ x, int jj, T* t) {
+    if (jj + VE <= xlen) {
+      const V w = *reinterpret_cast<const V*>(x + jj);
+      __builtin_memcpy(t, &w, sizeof(V));
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) t[e] = (jj + e < xlen) ? x[jj + e] : T(0);
+    }
+  };
+  for (; j + (U - 1) * CH < lenR; j += U * CH) {
+    V v[U];
+    T t1[U][VE], t2[U][VE];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = ld16<V, NT>(av + (j + u * CH) / VE);
+      xload(x1, j + u * CH, t1[u]);
+      xload(x2, j + u * CH, t2[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc1[u % 2] += dot16<V, T>(v[u], t1[u]);
+      acc2[u % 2] += dot16<V, T>(v[u], t2[u]);
+    }
+  }
+  for (; j < lenR; j += CH) {
+    V v0 = ld16<V, NT>(av + j / VE);
+    T t1[VE], t2[VE];
+    xload(x1, j, t1);
+    xload(x2, j, t2);
+    acc1[0] += dot16<V, T>(v0, t1);
+    acc2[0] += dot16<V, T>(v0, t2);
+  }
+  d1 = wave_sum<T>(acc1[0] + acc1[1]);
+  d2 = wave_sum<T>(acc2[0] + acc2[1]);
+}
+
 template <typename T>
 __device__ __forceinline__ int round_chunk(int len, int ld) {
   constexpr int CH = kWave * Vec16<T>::n;

@@ -32,6 +32,18 @@ template <typename T>
 int k0_sym_grid(int N, int n);
 int k0_sym_ldp(int n);
 size_t k0_sym_part_elems(int n);  // partial elements for any tune().sym_wg
+// Workgroups of the sum of the one-pass partials of an n-column product.
+int k0_sym_reduce_grid(int n);
+// The same sum inside the folded CG step (pcg.hpp): with the partials of
+// p^T q = u^T w + p_new^T D p_new into al (one per workgroup), or, over the
+// partials of the P_H apply (N = n = m2), with the partials of r^T z into rz.
+template <typename T>
+hipError_t launch_k0_sym_reduce_fold(hipStream_t st, int N, int n, const T* part, T* w, const PcgScalars* sc,
+                                     const T* u, const T* z, const T* p, const T* dvec, int m2, double* al, int nal,
+                                     const EventPair* ev);
+template <typename T>
+hipError_t launch_ph_reduce_fold(hipStream_t st, int m2, const T* part, T* z, const PcgScalars* sc, const T* r,
+                                 double* rz, int nrz, const EventPair* ev);
 template <typename T>
 hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n, const T* u, T* part,
                                size_t part_elems, const int* skip, const EventPair* ev = nullptr);

@@ -71,6 +71,8 @@ __device__ __forceinline__ void init_body(int m2, const T* __restrict__ b, const
     sc->maxit = maxit;
     sc->iter = 0;
     sc->rho = rz;
+    sc->rho_next = rz;
+    sc->fresh = 1;
     sc->alpha = sc->beta = sc->pq = 0;
     sc->done = (bb == 0.0 || bb <= sc->tol2 || (wtol >= 0.0 && wm <= wtol)) ? 1 : 0;
     if (!sc->done && maxit <= 0) sc->done = 2;
@@ -400,6 +402,207 @@ hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, i
   return hipGetLastError();
 }
 
+// ---- folded-update CG step ------------------------------------------------------
+// Scalars of the solve read at a kernel's entry.
+struct FoldState {
+  double rho, tol2, wtol;
+  int iter, maxit;
+};
+
+// Stop test of the update the last q sweep made, from its partials in a fixed
+// order, so every workgroup that calls it gets the same rz, rr, wm and code.
+__device__ __forceinline__ int fold_reduce_test(const FoldParts& fp, const FoldState& s, double& rz, double& rr,
+                                                double& wm, double (*sh3)[16]) {
+  rz = 0;
+  rr = 0;
+  wm = 0;
+  for (int b = threadIdx.x; b < fp.nrz; b += blockDim.x) rz += fp.rz[b];
+  for (int b = threadIdx.x; b < fp.nrw; b += blockDim.x) {
+    rr += fp.rr[b];
+    wm = fmax(wm, fp.wm[b]);
+  }
+  block_sum2_max1(rz, rr, wm, sh3);
+  if (rr <= s.tol2 || (s.wtol >= 0.0 && wm <= s.wtol)) return 1;
+  if (s.iter + 1 >= s.maxit) return 2;
+  return 0;
+}
+
+// u = C^T p_new with p_new = z + beta p_old, as C^T z + beta C^T p_old: both dots
+// of a row of the stored C^T from one load of the row.  beta = rho' / rho comes
+// from the partials of rho' = r^T z, reduced by every workgroup after its first
+// row; workgroup 0 records the update in the solve's scalars.
+template <typename T, int U>
+__global__ void __launch_bounds__(256) fold_ct_kernel(const T* __restrict__ CT, int ldct, int n, int m2,
+                                                      const T* __restrict__ z, const T* __restrict__ p,
+                                                      T* __restrict__ u, PcgScalars* __restrict__ sc, FoldParts fp,
+                                                      int nt) {
+  __shared__ double sh3[3][16];
+  if (sc->done) return;
+  const int fresh = sc->fresh;
+  const FoldState s{sc->rho, sc->tol2, sc->wtol, sc->iter, sc->maxit};
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
+  const int lenR = round_chunk<T>(m2, ldct);
+  const int stride = gridDim.x * waves;
+  auto dots = [&](int i, T& d1, T& d2) {
+    const T* row = CT + (size_t)i * ldct;
+    if (nt)
+      row_dot2_gx<T, U, true>(row, z, p, lenR, m2, lane, d1, d2);
+    else
+      row_dot2_gx<T, U, false>(row, z, p, lenR, m2, lane, d1, d2);
+  };
+  int i = blockIdx.x * waves + wave;
+  T d1 = 0, d2 = 0;
+  if (i < n) dots(i, d1, d2);
+  double beta = 0.0;  // the first step of a solve: p = z from the initialisation
+  if (!fresh) {
+    double rz, rr, wm;
+    const int dn = fold_reduce_test(fp, s, rz, rr, wm, sh3);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rr = rr;
+      sc->wmax = wm;
+      sc->iter = s.iter + 1;
+      if (dn) {
+        sc->done = dn;
+      } else {
+        sc->beta = rz / s.rho;
+        sc->rho_next = rz;
+      }
+    }
+    if (dn) return;
+    beta = rz / s.rho;
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rho_next = s.rho;
+  }
+  const T bt = (T)beta;
+  if (i < n && lane == 0) u[i] = d1 + bt * d2;
+  for (i += stride; i < n; i += stride) {
+    dots(i, d1, d2);
+    if (lane == 0) u[i] = d1 + bt * d2;
+  }
+}
+
+// q = C w + D p_new, p = p_new = z + beta p_old, alpha = rho / p^T q (p^T q from
+// the partials of the K0 sum), dnu += alpha p, r -= alpha q, z = P_L^{-1} r (or
+// r without a preconditioner; P_H computes z afterwards), and the per-workgroup
+// partials of the next stop test.  Workgroup 0 records alpha and rho.
+template <typename T, int U>
+__global__ void __launch_bounds__(256) fold_q_kernel(const T* __restrict__ C, int ldc, int m2, int n,
+                                                     const T* __restrict__ w, const T* __restrict__ dvec,
+                                                     T* __restrict__ p, T* __restrict__ q, T* __restrict__ x,
+                                                     T* __restrict__ r, T* __restrict__ z, const T* __restrict__ wts,
+                                                     int prec, PcgScalars* __restrict__ sc, FoldParts fp, int nt) {
+  __shared__ double sh[16];
+  __shared__ double sh3[3][16];
+  if (sc->done) return;
+  const double rho = sc->rho_next;
+  const T bt = (T)sc->beta;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
+  const int lenR = round_chunk<T>(n, ldc);
+  const int stride = gridDim.x * waves;
+  auto dot = [&](int i) {
+    const T* row = C + (size_t)i * ldc;
+    return nt ? row_dot_gx<T, U>(row, w, lenR, n, lane) : row_dot_gx<T, U, false>(row, w, lenR, n, lane);
+  };
+  int i = blockIdx.x * waves + wave;
+  T v = 0;
+  if (i < m2) v = dot(i);
+  double pq = 0;
+  for (int b = threadIdx.x; b < fp.nal; b += blockDim.x) pq += fp.al[b];
+  pq = block_sum<double>(pq, sh);
+  if (!(pq > 0.0) || !isfinite(pq)) {  // the same decision in every workgroup
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->done = 3;
+    }
+    return;
+  }
+  const T a = (T)(rho / pq);
+  double rz = 0, rr = 0, wm = 0;
+  auto upd = [&](int ii, T vv) {
+    const T di = dvec[ii];
+    const T pi = z[ii] + bt * p[ii];
+    const T qi = vv + di * pi;
+    p[ii] = pi;
+    q[ii] = qi;
+    x[ii] += a * pi;
+    const T ri = r[ii] - a * qi;
+    r[ii] = ri;
+    rr += (double)ri * ri;
+    if (wts) wm = fmax(wm, fabs((double)wts[ii] * ri));
+    if (prec != kPrecH) {
+      const T zi = (prec == kPrecL) ? ri / di : ri;
+      z[ii] = zi;
+      rz += (double)ri * zi;
+    }
+  };
+  if (i < m2 && lane == 0) upd(i, v);
+  for (i += stride; i < m2; i += stride) {
+    v = dot(i);
+    if (lane == 0) upd(i, v);
+  }
+  block_sum2_max1(rz, rr, wm, sh3);
+  if (threadIdx.x == 0) {
+    if (prec != kPrecH) fp.rz[blockIdx.x] = rz;
+    fp.rr[blockIdx.x] = rr;
+    fp.wm[blockIdx.x] = wm;
+    if (blockIdx.x == 0) {
+      sc->pq = pq;
+      sc->alpha = rho / pq;
+      sc->rho = rho;
+      sc->fresh = 0;
+    }
+  }
+}
+
+// The stop test of the last update of a chunk (same code as fold_ct's), so the
+// host's poll sees a finished solve; leaves the scalars alone otherwise.
+__global__ void __launch_bounds__(256) fold_test_kernel(PcgScalars* __restrict__ sc, FoldParts fp) {
+  __shared__ double sh3[3][16];
+  if (sc->done || sc->fresh) return;
+  const FoldState s{sc->rho, sc->tol2, sc->wtol, sc->iter, sc->maxit};
+  double rz, rr, wm;
+  const int dn = fold_reduce_test(fp, s, rz, rr, wm, sh3);
+  if (dn && threadIdx.x == 0) {
+    sc->rr = rr;
+    sc->wmax = wm;
+    sc->iter = s.iter + 1;
+    sc->done = dn;
+  }
+}
+
+template <typename T>
+hipError_t fold_ct(hipStream_t st, const T* CT, int ldct, int n, int m2, const T* z, const T* p, T* u,
+                   PcgScalars* sc, const FoldParts& fp, const EventPair* ev) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(gemv_rows_grid<T>(n));
+  const int nt = tune().ld_nt & 1;
+  if (tune().rows_unroll == 8)
+    QPG_LAUNCH((fold_ct_kernel<T, 8>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
+  else
+    QPG_LAUNCH((fold_ct_kernel<T, 4>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fold_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, T* p, T* q, T* x,
+                  T* r, T* z, const T* wts, int prec, PcgScalars* sc, const FoldParts& fp, const EventPair* ev) {
+  const int grid = pcg_q_grid<T>(m2);
+  if (grid > fp.nrw || (prec != kPrecH && grid > fp.nrz)) return hipErrorInvalidValue;
+  const int nt = tune().ld_nt & 1;
+  if (tune().rows_unroll == 8)
+    QPG_LAUNCH((fold_q_kernel<T, 8>), dim3(grid), dim3(256), 0u, st, ev, C, ldc, m2, n, w, dvec, p, q, x, r, z, wts,
+               prec, sc, fp, nt);
+  else
+    QPG_LAUNCH((fold_q_kernel<T, 4>), dim3(grid), dim3(256), 0u, st, ev, C, ldc, m2, n, w, dvec, p, q, x, r, z, wts,
+               prec, sc, fp, nt);
+  return hipGetLastError();
+}
+
+hipError_t fold_test(hipStream_t st, PcgScalars* sc, const FoldParts& fp) {
+  hipLaunchKernelGGL(fold_test_kernel, dim3(1), dim3(256), 0, st, sc, fp);
+  return hipGetLastError();
+}
+
 // ---- batched launchers ------------------------------------------------------
 int bpcg_q_blocks(int m2) { return m2 > 16 ? (m2 + 15) / 16 : 1; }
 
@@ -448,7 +651,11 @@ hipError_t bpcg_ph_update(hipStream_t st, const PcgDesc<T>* d, int ndesc, int in
   template hipError_t bpcg_init<T>(hipStream_t, const PcgDesc<T>*, int);                                          \
   template hipError_t bpcg_q<T>(hipStream_t, const PcgDesc<T>*, const int*, int, int, size_t, const EventPair*);  \
   template hipError_t bpcg_update<T>(hipStream_t, const PcgDesc<T>*, int);                                        \
-  template hipError_t bpcg_ph_update<T>(hipStream_t, const PcgDesc<T>*, int, int);
+  template hipError_t bpcg_ph_update<T>(hipStream_t, const PcgDesc<T>*, int, int);                             \
+  template hipError_t fold_ct<T>(hipStream_t, const T*, int, int, int, const T*, const T*, T*, PcgScalars*,       \
+                                 const FoldParts&, const EventPair*);                                             \
+  template hipError_t fold_q<T>(hipStream_t, const T*, int, int, int, const T*, const T*, T*, T*, T*, T*, T*,     \
+                                const T*, int, PcgScalars*, const FoldParts&, const EventPair*);
 QPG_PCG_INST(double)
 QPG_PCG_INST(float)
 

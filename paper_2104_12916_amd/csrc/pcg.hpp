@@ -22,6 +22,29 @@ hipError_t pcg_update(hipStream_t st, int m2, const double* bpart, const T* dvec
                       const T* wts, int prec, PcgScalars* sc);
 template <typename T>
 hipError_t pcg_ph_update(hipStream_t st, int m2, const T* r, const T* z, T* p, int init, PcgScalars* sc);
+// ---- CG step with the vector update folded into the operator sweeps ------------
+// The step's kernels: fold_ct (u = C^T z + beta C^T p_old, and the stop test and
+// beta of the previous update from its partials), the one-pass K0 product and the
+// sum of its partials with the partials of p^T q = u^T w + p^T D p, then fold_q
+// (q = C w + D p, p = z + beta p_old, alpha, dnu, r, z and the partials of the
+// next test); with P_H the one-pass X_P apply and its sum with the partials of
+// r^T z.  fold_test closes a chunk of steps so the host sees a stop at once.
+struct FoldParts {
+  double* al;  // partials of p^T q (u^T w + p^T D p), one per workgroup of the K0 sum
+  int nal;
+  double* rz;  // partials of r^T z (q sweep, or the sum of the P_H apply)
+  int nrz;
+  double *rr, *wm;  // partials of ||r||^2 and max |w r| (q sweep)
+  int nrw;
+};
+template <typename T>
+hipError_t fold_ct(hipStream_t st, const T* CT, int ldct, int n, int m2, const T* z, const T* p, T* u,
+                   PcgScalars* sc, const FoldParts& fp, const EventPair* ev);
+template <typename T>
+hipError_t fold_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w, const T* dvec, T* p, T* q, T* x,
+                  T* r, T* z, const T* wts, int prec, PcgScalars* sc, const FoldParts& fp, const EventPair* ev);
+hipError_t fold_test(hipStream_t st, PcgScalars* sc, const FoldParts& fp);
+
 // batched forms: descriptor list in device memory, one solve per entry
 int bpcg_q_blocks(int m2);
 template <typename T>

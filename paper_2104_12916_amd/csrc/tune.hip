@@ -60,6 +60,7 @@ bool parse_keys(const std::string& spec, Tune& t, bool alloc) {
     else if (k == "ld_nt") ok = v >= 0 && v <= 3, t.ld_nt = v;
     else if (k == "upd_threads") ok = v == 256 || v == 512 || v == 1024, t.upd_threads = v;
     else if (k == "mv_rt") ok = v == 1 || v == 2, t.mv_rt = v;
+    else if (k == "cg_fold") ok = v == 0 || v == 1, t.cg_fold = v;
     else if (alloc && k == "ld_pad") ok = v >= 0 && v <= 1024 && v % 64 == 0, t.ld_pad = v;
     else if (alloc && k == "op_t") ok = v == 0 || v == 1, t.op_t = v;
     else if (alloc && k == "k0_sym") ok = v == 0 || v == 1, t.k0_sym = v;
@@ -147,9 +148,9 @@ std::string format_tune(const Tune& t, bool alloc) {
   char b[512];
   snprintf(b, sizeof(b),
            "rows_bpc=%d,rows_unroll=%d,cols_bpc=%d,cols_unroll=%d,qe_stage=%d,rows_stage=%d,brows_stage=%d,"
-           "brows_unroll=%d,sym_wg=%d,sym_rows=%d,sym_pipe=%d,ld_nt=%d,upd_threads=%d,mv_rt=%d",
+           "brows_unroll=%d,sym_wg=%d,sym_rows=%d,sym_pipe=%d,ld_nt=%d,upd_threads=%d,mv_rt=%d,cg_fold=%d",
            t.rows_bpc, t.rows_unroll, t.cols_bpc, t.cols_unroll, t.qe_stage, t.rows_stage, t.brows_stage,
-           t.brows_unroll, t.sym_wg, t.sym_rows, t.sym_pipe, t.ld_nt, t.upd_threads, t.mv_rt);
+           t.brows_unroll, t.sym_wg, t.sym_rows, t.sym_pipe, t.ld_nt, t.upd_threads, t.mv_rt, t.cg_fold);
   std::string s(b);
   if (alloc) {
     snprintf(b, sizeof(b), ",ld_pad=%d,op_t=%d,k0_sym=%d", t.ld_pad, t.op_t, t.k0_sym);

@@ -100,8 +100,11 @@ def test_diag_ph_step_count_follows_the_oracle(gpu, kind, n, m1, m2):
     s.factor()
     dnu, info = s.pcg(dvec, rhs, prec=PH, rtol=1e-6)
     s.close()
-    # long float64 CG runs may drift by a few steps between two summation orders
-    assert abs(info.iters - counts["diag"]) <= max(1, 0.05 * counts["diag"]), (info.iters, counts)
+    # CG steps past the distinct-eigenvalue bound are set by rounding (the ill-conditioned
+    # instance takes ~4 m2 steps): two summation orders drift apart by several percent,
+    # while the two preconditioners differ by a factor of twenty
+    assert abs(info.iters - counts["diag"]) <= max(1, 0.10 * counts["diag"]), (info.iters, counts)
+    assert abs(info.iters - counts["diag"]) * 4 < abs(info.iters - counts["exact"]), (info.iters, counts)
     ref = sla.cho_solve(sla.cho_factor(K), rhs)
     assert relerr(dnu, ref) <= 1e-4
 

@@ -48,9 +48,9 @@ def test_serving_trace_matches_oracle_and_solo_runs(gpu, trace):
         assert abs(r.info.rel_kkt - score) <= 1e-12 + 1e-6 * score
     summ = serve.latency_summary(res)
     assert summ["count"] == 24 and 0 < summ["p50_ms"] <= summ["p99_ms"] <= summ["max_ms"]
-    # every request alone gives the same bits
+    # every request alone (in an arena of its own footprint) gives the same bits
     for k, qp in enumerate(qps):
-        with serve.Server(0, **OPTS) as solo:
+        with serve.Server(fps[k], **OPTS) as solo:
             (a,) = solo.run([qp.arrays()])
         r = res[k]
         assert np.array_equal(a.x, r.x) and np.array_equal(a.lam, r.lam), k
