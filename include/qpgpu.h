@@ -228,6 +228,19 @@ qp_status qp_op_time(qp_ctx* ctx, int op, qp_precision precision, int reps, doub
  * QP_E_NOMEM if the buffer does not fit, QP_E_DEVICE on a HIP error. */
 qp_status qp_hbm_read_time(size_t bytes, int wg_per_cu, int reps, double* avg_ms);
 
+/* Diagnostic: average device time (ms) of `reps` back-to-back runs of a dense
+ * float64 kernel of the factorization (Sec. 4.1, the single factorization of the
+ * fixed block and of P_H) on the current device, with operands of size n
+ * (1..16384) that it allocates, fills deterministically and frees:
+ *   op 0  C = A B^T, n x n x n (the GEMM of the factorization)
+ *   op 1  the same with B^T upper triangular (k range trimmed per tile)
+ *   op 2  X = chol(P)^{-1} of an n x n SPD P (the recursive Cholesky-inverse,
+ *         leaves, fused nodes and GEMMs; P restored by a copy before each run,
+ *         whose time is included)
+ * QP_E_INVALID for bad arguments, QP_E_NOMEM if the operands do not fit,
+ * QP_E_NOT_SPD if op 2 rejects a pivot, QP_E_DEVICE on a HIP error. */
+qp_status qp_dense_time(int op, int n, int reps, double* avg_ms);
+
 /* Launch-shape table (workgroups per CU, loads in flight, one-pass sweep shape,
  * update width, cache policy of the matrix loads) of the streaming kernels, per
  * size bucket: calls on one QP use the bucket of its n, batches the base entry.

@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 SPACE = [
     ("rows_bpc", [2, 4, 6, 8]),
-    ("rows_unroll", [4, 8]),
+    ("rows_unroll", [4, 8, 16]),
     ("sym_wg", [1, 2, 3, 4]),
     ("sym_rows", [2, 4]),
     ("sym_pipe", [0, 1]),

@@ -1,6 +1,6 @@
 // Dense FP64 factorization kernels for the once-per-QP setup (gfx950 MFMA).
 //
-//   gemm_f64      C = alpha op(A) op(B) + beta C, 128x64 or 64x64 tiles,
+//   gemm_f64      C = alpha op(A) op(B) + beta C, 64x64 or 32x32 tiles,
 //                 v_mfma_f64_16x16x4 over double-buffered LDS slabs; optional
 //                 "lower only" output (SYRK-shaped updates) and k-range trimming
 //                 for triangular operands.
@@ -32,11 +32,12 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // per slab separates the buffers.  Each element of C is summed in the same order
 // (k = klo, klo + 4, ... through the same instruction) whatever the tile shape,
 // so the shape can be chosen per launch without changing results.
-constexpr int GK = 16;    // k slab
 constexpr int GPAD = 4;   // LDS row padding (doubles)
 
-template <int BM, int BN>
+// BK: depth of a k slab (16 measured fastest for both tile shapes in use).
+template <int BM, int BN, int BK = 16>
 struct GemmTile {
+  static constexpr int GK = BK;                     // k slab
   static constexpr int WM = BM / 2, WN = BN / 2;    // per-wavefront block
   static constexpr int FM = WM / 16, FN = WN / 16;  // MFMA blocks per wavefront
   static constexpr int LA = BM * GK / 2 / 256;      // 16-byte loads per thread, A slab
@@ -44,7 +45,7 @@ struct GemmTile {
   static constexpr int AS = BM + GPAD, BS = BN + GPAD;
   static constexpr size_t kLdsBytes = 2 * GK * (AS + BS) * sizeof(double);
 };
-constexpr size_t kLdsBig = GemmTile<128, 64>::kLdsBytes, kLdsSmall = GemmTile<64, 64>::kLdsBytes;
+constexpr size_t kLds64 = GemmTile<64, 64>::kLdsBytes, kLds32 = GemmTile<32, 32>::kLdsBytes;
 
 // Elements idx, idx+1 of row p (zero at or past lim); one 16-byte load when allowed.
 __device__ __forceinline__ v2d ld_pair(const double* __restrict__ p, int idx, int lim, bool vec) {
@@ -55,11 +56,12 @@ __device__ __forceinline__ v2d ld_pair(const double* __restrict__ p, int idx, in
   return r;
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int BK = GemmTile<BM, BN>::GK>
 __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
                                           int ta, const double* __restrict__ B, int ldb, int tb, double beta,
                                           double* __restrict__ C, int ldc, int flags, int bx, int by) {
-  using G = GemmTile<BM, BN>;
+  using G = GemmTile<BM, BN, BK>;
+  constexpr int GK = G::GK;
   const int i0 = by * BM, j0 = bx * BN;
   if ((flags & kOutLower) && j0 > i0 + BM - 1) return;
   extern __shared__ double lds[];
@@ -184,10 +186,13 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       }
 }
 
-// Tile shape of a launch covering `tiles` tiles of 128 x 64: that shape (two
-// workgroups per CU) when it gives every CU at least about one and a half of
-// them, else 64 x 64 (twice as many tiles, more workgroups per CU).
-static bool use_big_tile(long long tiles) { return tiles >= (long long)dev_info().cu_count * 3 / 2; }
+// Tile shape of a launch covering `tiles` tiles of 64 x 64: that shape when it
+// gives every CU at least four of them, else 32 x 32 (four times as many
+// workgroups: a launch with few tiles is bound by the matrix cores of the CUs it
+// occupies and by unhidden load latency, not by the smaller tile's extra L2
+// traffic).  Measured on FP64 A B^T: 32 x 32 wins up to n = 1024 (80 us there
+// against 128 us), 64 x 64 from n = 2048 (417 us against 515 us).
+static bool use_tile64(long long tiles64) { return tiles64 >= (long long)dev_info().cu_count * 4; }
 
 // Order of the tiles of a GEMM with a triangular operand, whose tiles' k ranges
 // grow or shrink along one axis: the first half of the linear block indices takes
@@ -238,16 +243,14 @@ __global__ void __launch_bounds__(256, 2) gemm_f64_batched_kernel(const GemmDesc
 hipError_t gemm_f64(hipStream_t st, int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
                     const double* B, int ldb, double beta, double* C, int ldc, int flags) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (use_big_tile(active_tiles(M, N, 128, 64, flags))) {
-    using G = GemmTile<128, 64>;
-    if ((M + 127) / 128 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_kernel<128, 64>), dim3((N + 63) / 64, (M + 127) / 128), dim3(256), G::kLdsBytes,
-                       st, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
-  } else {
-    using G = GemmTile<64, 64>;
+  if (use_tile64(active_tiles(M, N, 64, 64, flags))) {
     if ((M + 63) / 64 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), G::kLdsBytes, st,
-                       M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
+    hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), kLds64, st, M, N,
+                       K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
+  } else {
+    if ((M + 31) / 32 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_kernel<32, 32>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), kLds32, st, M, N,
+                       K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, flags);
   }
   return hipGetLastError();
 }
@@ -276,15 +279,15 @@ __global__ void __launch_bounds__(256, 2) gemm_f64_pair_kernel(GemmArgs g0, Gemm
 static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmArgs& g1) {
   const int mx = std::max(g0.M, g1.M), nx = std::max(g0.N, g1.N);
   if (mx <= 0 || nx <= 0) return hipSuccess;
-  const long long tb = active_tiles(g0.M, g0.N, 128, 64, g0.flags) + active_tiles(g1.M, g1.N, 128, 64, g1.flags);
-  if (use_big_tile(tb)) {
-    if ((mx + 127) / 128 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_pair_kernel<128, 64>), dim3((nx + 63) / 64, (mx + 127) / 128, 2), dim3(256),
-                       kLdsBig, st, g0, g1);
-  } else {
+  const long long tb = active_tiles(g0.M, g0.N, 64, 64, g0.flags) + active_tiles(g1.M, g1.N, 64, 64, g1.flags);
+  if (use_tile64(tb)) {
     if ((mx + 63) / 64 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_f64_pair_kernel<64, 64>), dim3((nx + 63) / 64, (mx + 63) / 64, 2), dim3(256),
-                       kLdsSmall, st, g0, g1);
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<64, 64>), dim3((nx + 63) / 64, (mx + 63) / 64, 2), dim3(256), kLds64,
+                       st, g0, g1);
+  } else {
+    if ((mx + 31) / 32 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<32, 32>), dim3((nx + 31) / 32, (mx + 31) / 32, 2), dim3(256), kLds32,
+                       st, g0, g1);
   }
   return hipGetLastError();
 }
@@ -314,30 +317,33 @@ constexpr double kPivRel = 1e-13;
 // X = L^{-1} = D^{-1/2} L_1^{-1} (X starts as I and takes the same row
 // operations, so it stays lower triangular).  The block is held as 16 x 16
 // tiles in the accumulators of v_mfma_f64_16x16x4f64: wavefront I owns tile row
-// I of A and of X (tiles K <= I).  Columns are eliminated four at a time.  For
-// column block J (columns 4J .. 4J+3) the owners publish those columns of A and
-// rows 4J .. 4J+3 of X in LDS; after one barrier every lane eliminates the 4 x 4
-// diagonal block itself, and a row i below it passes through the block's four
-// steps (its eliminated values ev_i and multipliers cf_i = ev_i / d).  The
-// updates of the trailing columns, a_ik -= sum_p cf_ip ev_kp, and of the rows
-// of X below the block, x_i -= sum_p cf_ip xf_p, are rank-4 products: one MFMA
-// per 16 x 16 tile, with the k = 4 operand slots holding p.
+// I of A and of X (tiles K <= I).  Columns are eliminated four at a time, one
+// barrier per column block J (columns j0 = 4J .. 4J+3): the owners publish those
+// columns of A and rows j0 .. j0+3 of X in LDS; then every lane eliminates the
+// 4 x 4 diagonal block itself, and each wavefront passes the rows of its operand
+// tiles through the block's four steps (eliminated values ev_i and multipliers
+// cf_i = ev_i / d) and the block's rows of X through their own steps (xf).  The
+// updates of the trailing columns, a_ik -= sum_p cf_ip ev_kp, and of the rows of
+// X below the block, x_i -= sum_p cf_ip xf_p, are rank-4 products: one MFMA per
+// 16 x 16 tile, with the k = 4 operand slots holding p.  Finished columns of L go
+// straight to memory.  Each wavefront runs alone on its SIMD, so the code is
+// shaped for latency: the wavefront index is a scalar (uniform branches), lane
+// selections are selects, and the reciprocals of the pivots and of their square
+// roots are Newton-refined hardware estimates instead of IEEE divisions.
 
 // LDS of the leaf elimination.
-struct LeafShared {
+struct alignas(16) LeafLds {
   double pan[2][LEAF][4];   // columns 4J..4J+3 of A (rows >= 4J), double-buffered
-  double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J
-  double ev[LEAF][5];       // rows through block J's four steps: eliminated values (padded row)
-  double cf[LEAF][5];       // and multipliers
-  double xf[4][LEAF];       // rows 4J..4J+3 of X after the block's steps among themselves
-  double piv[LEAF];         // pivots d
+  double xrow[2][4][LEAF];  // rows 4J..4J+3 of X as they enter block J, double-buffered
+  double rs[LEAF];          // 1 / sqrt(pivot)
 };
 
 // Accumulator layout of a 64 x 64 block over the four wavefronts: wavefront I
 // holds tiles (I, K), K <= I; register r of lane l holds tile entry (4 r + l / 16, l % 16).
 __device__ __forceinline__ void leaf_load(const double* __restrict__ A, int lda, int nb, v4d (&accA)[4],
                                           v4d (&accX)[4]) {
-  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int I = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
   for (int K = 0; K < 4; ++K)
 #pragma unroll
@@ -348,141 +354,146 @@ __device__ __forceinline__ void leaf_load(const double* __restrict__ A, int lda,
     }
 }
 
-// The elimination on the accumulators (entries past nb must be zero; entries
-// above the diagonal are never read).  Per column block: the owners publish the
-// block's columns of A and rows of X (barrier); wavefront 0 passes every row
-// below the block through its four steps (ev, cf) and wavefront 1 eliminates the
-// block's rows of X among themselves (xf), each thread redoing the 4 x 4
-// diagonal block (barrier); then the rank-4 MFMA updates read ev, cf and xf.
-// Returns true when a pivot is rejected.
-__device__ __forceinline__ bool leaf_core(LeafShared& sh, int nb, const double* __restrict__ dmax, v4d (&accA)[4],
-                                          v4d (&accX)[4]) {
-  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+// v[s] for a lane-dependent s in 0..3 (selects; no indexed register access).
+__device__ __forceinline__ double sel4(double v0, double v1, double v2, double v3, int s) {
+  double r = v0;
+  r = s == 1 ? v1 : r;
+  r = s == 2 ? v2 : r;
+  r = s == 3 ? v3 : r;
+  return r;
+}
+
+// 1 / d and 1 / sqrt(d) for a positive normal d: the hardware estimate and two
+// Newton steps (relative error a few units in the last place).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);  // 1 - d y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Elimination of the accumulators loaded by leaf_load; writes L (rows and
+// columns < nb, k <= i) to A, keeps X = L_1^{-1} (unscaled) in accX and
+// 1 / sqrt(d) in sh.rs.  Returns true when a pivot is rejected.
+__device__ __forceinline__ bool leaf_elim(LeafLds& sh, double* __restrict__ A, int lda, int nb,
+                                          const double* __restrict__ dmax, v4d (&accA)[4], v4d (&accX)[4]) {
+  const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int I = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index, uniform
   const double pmin = kPivRel * (*dmax);
   bool bad = false;
   const int nblk = (nb + 3) / 4;
 #pragma unroll
   for (int K0 = 0; K0 < 4; ++K0) {
+#pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int J = 4 * K0 + jj;
-      if (J >= nblk) break;
-      const int buf = J & 1, j0 = 4 * J, c0 = 4 * jj;
-      if (I >= K0 && lc >= c0 && lc < c0 + 4) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * I + 4 * r + lr;
-          if (i >= j0) sh.pan[buf][i][lc - c0] = accA[K0][r];
-        }
-      }
-      if (I == K0) {
-#pragma unroll
-        for (int K = 0; K <= K0; ++K) sh.xrow[buf][lr][16 * K + lc] = accX[K][jj];
-      }
-      __syncthreads();
-      // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
-      // at its own column step (E[p][p] is the pivot d_p).
-      double E[4][4], dinv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? sh.pan[buf][j0 + i][q] : 0.0;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        double d = E[p][p];
-        if (j0 + p < nb) {
-          if (!(d > pmin) || !isfinite(d)) {  // same decision in every thread
-            bad = true;
-            d = 1.0;
-          }
-        } else {
-          d = 1.0;  // past the block's end: the row and column are zero
-        }
-        E[p][p] = d;
-        dinv[p] = 1.0 / d;
-#pragma unroll
-        for (int i = p + 1; i < 4; ++i) {
-          const double coef = E[i][p] * dinv[p];
-#pragma unroll
-          for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
-        }
-      }
-      if (I == 0) {
-        // row l below the block through the block's four steps: ev[p] = eliminated
-        // a_{l, j0+p}, cf[p] = ev[p] / d_p (the multiplier of step j0 + p)
-        if (l > j0 + 3) {
-          double g[4], cf[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) g[q] = sh.pan[buf][l][q];
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-#pragma unroll
-            for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
-            cf[p] = g[p] * dinv[p];
-            sh.ev[l][p] = g[p];
-            sh.cf[l][p] = cf[p];
-          }
-        } else {
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            sh.ev[l][p] = 0.0;
-            sh.cf[l][p] = 0.0;
-          }
-        }
-        if (tid == 0) {
-#pragma unroll
-          for (int p = 0; p < 4; ++p) sh.piv[j0 + p] = E[p][p];
-        }
-      } else if (I == 1) {
-        // column l of rows j0..j0+3 of X after their own four steps
-        double f[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          f[q] = sh.xrow[buf][q][l];
-#pragma unroll
-          for (int qq = 0; qq < q; ++qq) {
-            const double lq = E[q][qq] * dinv[qq];
-            f[q] -= lq * f[qq];
-          }
-          sh.xf[q][l] = f[q];
-        }
-      }
-      __syncthreads();
-      if (I >= K0) {
-        // A operand: -cf of row 16 I + lc, slot p = lr (zero for the block's rows and above)
-        const double aop = -sh.cf[16 * I + lc][lr];
-#pragma unroll
-        for (int K = K0; K < 4; ++K) {
-          if (K <= I) {
-            // B operand: ev of row 16 K + lc (a trailing column), slot p = lr
-            accA[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sh.ev[16 * K + lc][lr], accA[K], 0, 0, 0);
-          }
-        }
-        // the block's own columns keep their eliminated values
-        if (lc >= c0 && lc < c0 + 4) {
-          const int p = lc - c0;
+      if (J < nblk) {
+        const int buf = J & 1, j0 = 4 * J, c0 = 4 * jj;
+        if (I >= K0 && lc >= c0 && lc < c0 + 4) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = 16 * I + 4 * r + lr;
-            if (i > j0 + 3) {
-              accA[K0][r] = sh.ev[i][p];
-            } else if (i >= j0) {
-              const int q = i - j0;
-              double e = 0.0;
-#pragma unroll
-              for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-                for (int pp = 0; pp <= qq; ++pp)
-                  if (qq == q && pp == p) e = E[qq][pp];
-              accA[K0][r] = e;
-            }
+            if (i >= j0) sh.pan[buf][i][lc - c0] = accA[K0][r];
           }
         }
-        // X: rows below the block take x_i -= sum_p cf_ip xf_p; the block's rows become xf
+        if (I == K0) {
 #pragma unroll
-        for (int K = 0; K <= K0; ++K) {
-          const double xv = sh.xf[lr][16 * K + lc];
-          accX[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, xv, accX[K], 0, 0, 0);
-          if (I == K0) accX[K][jj] = xv;
+          for (int K = 0; K <= K0; ++K) sh.xrow[buf][lr][16 * K + lc] = accX[K][jj];
+        }
+        __syncthreads();
+        // Diagonal block: E[i][q] (q <= i) ends as the eliminated value of a_{j0+i, j0+q}
+        // at its own column step (E[p][p] is the pivot d_p).
+        double E[4][4], dinv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) E[i][q] = q <= i ? sh.pan[buf][j0 + i][q] : 0.0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          // a pivot past the block's end (zero row and column) or a rejected one
+          // (the same decision in every thread) is replaced by 1
+          const double d = E[p][p];
+          const bool live = j0 + p < nb, ok = d > pmin && isfinite(d);
+          bad = bad || (live && !ok);
+          E[p][p] = live && ok ? d : 1.0;
+          dinv[p] = rcp_nr(E[p][p]);
+#pragma unroll
+          for (int i = p + 1; i < 4; ++i) {
+            const double coef = E[i][p] * dinv[p];
+#pragma unroll
+            for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
+          }
+        }
+        const double rsl = rsq_nr(sel4(E[0][0], E[1][1], E[2][2], E[3][3], lr));  // column j0 + lr
+        if (I == 0 && lc == 0) sh.rs[j0 + lr] = rsl;
+        if (I >= K0) {
+          // Row 16 K + lc of each operand tile K (K0 <= K <= I) through the block's
+          // four steps; this lane keeps slot p = lr: the eliminated value (B operand)
+          // and, for its own tile row, the negated multiplier (A operand).  Rows at
+          // or above the block contribute zero.
+          double aop = 0.0, bop[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int K = K0; K < 4; ++K) {
+            if (K > I) continue;
+            const int row = 16 * K + lc;
+            const bool below = row > j0 + 3;
+            const v2d g01 = *reinterpret_cast<const v2d*>(&sh.pan[buf][row][0]);
+            const v2d g23 = *reinterpret_cast<const v2d*>(&sh.pan[buf][row][2]);
+            double g[4] = {g01.x, g01.y, g23.x, g23.y}, cf[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+#pragma unroll
+              for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
+              cf[p] = g[p] * dinv[p];
+            }
+            double ev = below ? sel4(g[0], g[1], g[2], g[3], lr) : 0.0;
+            bop[K] = ev;
+            if (K == I) {
+              aop = below ? -sel4(cf[0], cf[1], cf[2], cf[3], lr) : 0.0;
+              bool put = below;
+              if (K == K0) {
+                // rows of the diagonal block: L entries E[q][p] / sqrt(d_p), p = lr <= q
+                const int q = lc - c0;
+                const double e0 = sel4(E[0][0], E[1][0], E[2][0], E[3][0], q);
+                const double e1 = sel4(E[0][1], E[1][1], E[2][1], E[3][1], q);
+                const double e2 = sel4(E[0][2], E[1][2], E[2][2], E[3][2], q);
+                const double e3 = sel4(E[0][3], E[1][3], E[2][3], E[3][3], q);
+                const bool diag = q >= 0 && q < 4 && lr <= q;
+                ev = diag ? sel4(e0, e1, e2, e3, lr) : ev;
+                put = put || diag;
+              }
+              if (put && row < nb && j0 + lr < nb) A[(size_t)row * lda + j0 + lr] = ev * rsl;
+            }
+          }
+#pragma unroll
+          for (int K = K0; K < 4; ++K)
+            if (K <= I) accA[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[K], accA[K], 0, 0, 0);
+          // X: column 16 K + lc of the block's rows after their own steps (slot lr);
+          // rows below take x_i -= sum_p cf_ip xf_p, the block's rows become xf
+#pragma unroll
+          for (int K = 0; K <= K0; ++K) {
+            const int col = 16 * K + lc;
+            double f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              f[q] = sh.xrow[buf][q][col];
+#pragma unroll
+              for (int qq = 0; qq < q; ++qq) f[q] -= (E[q][qq] * dinv[qq]) * f[qq];
+            }
+            const double xv = sel4(f[0], f[1], f[2], f[3], lr);
+            accX[K] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, xv, accX[K], 0, 0, 0);
+            if (I == K0) accX[K][jj] = xv;
+          }
         }
       }
     }
@@ -491,12 +502,12 @@ __device__ __forceinline__ bool leaf_core(LeafShared& sh, int nb, const double* 
   return bad;
 }
 
-// L = L_1 D^{1/2} into A and X = D^{-1/2} L_1^{-1} into X (rows and columns < nb);
-// with xs, also X into xs (64 x ldxs, LDS).
-__device__ __forceinline__ void leaf_store(const LeafShared& sh, double* __restrict__ A, int lda,
-                                           double* __restrict__ X, int ldx, int nb, const v4d (&accA)[4],
-                                           const v4d (&accX)[4], double* xs = nullptr, int ldxs = 0) {
-  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+// X = D^{-1/2} L_1^{-1} (rows and columns < nb) into X, and with xs into LDS
+// (64 x ldxs).
+__device__ __forceinline__ void leaf_store_x(const LeafLds& sh, double* __restrict__ X, int ldx, int nb,
+                                             const v4d (&accX)[4], double* xs = nullptr, int ldxs = 0) {
+  const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int I = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
   for (int K = 0; K < 4; ++K) {
     if (K > I) continue;
@@ -504,22 +515,21 @@ __device__ __forceinline__ void leaf_store(const LeafShared& sh, double* __restr
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + 4 * r + lr, k = 16 * K + lc;
       if (i >= nb || k >= nb) continue;
-      if (k <= i) A[(size_t)i * lda + k] = accA[K][r] / sqrt(sh.piv[k]);
-      const double x = accX[K][r] / sqrt(sh.piv[i]);
+      const double x = accX[K][r] * sh.rs[i];
       X[(size_t)i * ldx + k] = x;
       if (xs) xs[i * ldxs + k] = x;
     }
   }
 }
 
-__device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
-                                                   int nb, int* __restrict__ info, int code,
-                                                   const double* __restrict__ dmax) {
-  __shared__ LeafShared sh;
+__device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int lda, double* __restrict__ X,
+                                                    int ldx, int nb, int* __restrict__ info, int code,
+                                                    const double* __restrict__ dmax) {
+  __shared__ LeafLds sh;
   v4d accA[4], accX[4];
   leaf_load(A, lda, nb, accA, accX);
-  const bool bad = leaf_core(sh, nb, dmax, accA, accX);
-  leaf_store(sh, A, lda, X, ldx, nb, accA, accX);
+  const bool bad = leaf_elim(sh, A, lda, nb, dmax, accA, accX);
+  leaf_store_x(sh, X, ldx, nb, accX);
   if (threadIdx.x == 0 && bad) *info = code;
 }
 
@@ -540,19 +550,13 @@ __global__ void __launch_bounds__(256) chol_inv_leaf_batched_kernel(const LeafDe
 // stay in LDS, and A22 is updated in the accumulators the second leaf starts
 // from, so a node costs one launch instead of two leaves and three GEMMs.
 constexpr int NLD = LEAF + 1;  // LDS row stride (doubles)
-struct NodeShared {
-  LeafShared leaf;
-  double a[LEAF * NLD];   // A21, later X22
-  double x[LEAF * NLD];   // X11
-  double lt[LEAF * NLD];  // L21
-  double t[LEAF * NLD];   // T
-};
 
 // acc[K] (tile (I, K) of a 64 x 64 product, wavefront I; K <= kmax_tile) += sign *
 // sum_k opA(i, k) opB(k, j) over k < 64, operands read from LDS.
 template <typename FA, typename FB>
 __device__ __forceinline__ void node_mm(v4d (&acc)[4], int ktiles, double sign, FA&& opA, FB&& opB) {
-  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int I = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll 4
   for (int k0 = 0; k0 < LEAF; k0 += 4) {
     const double a = sign * opA(16 * I + lc, k0 + lr);
@@ -562,11 +566,20 @@ __device__ __forceinline__ void node_mm(v4d (&acc)[4], int ktiles, double sign, 
   }
 }
 
+struct NodeShared {
+  LeafLds leaf;
+  double a[LEAF * NLD];   // A21, later X22
+  double x[LEAF * NLD];   // X11
+  double lt[LEAF * NLD];  // L21
+  double t[LEAF * NLD];   // T
+};
+
 __device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int lda, double* __restrict__ X, int ldx,
                                                    int n, int* __restrict__ info, int code,
                                                    const double* __restrict__ dmax) {
   __shared__ NodeShared sh;
-  const int tid = threadIdx.x, I = tid >> 6, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
+  const int I = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n2 = n - LEAF;
   double* A21 = A + (size_t)LEAF * lda;
   double* A22 = A21 + LEAF;
@@ -581,8 +594,8 @@ __device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int l
   }
   v4d accA[4], accX[4];
   leaf_load(A, lda, LEAF, accA, accX);
-  bool bad = leaf_core(sh.leaf, LEAF, dmax, accA, accX);
-  leaf_store(sh.leaf, A, lda, X, ldx, LEAF, accA, accX, sh.x, NLD);
+  bool bad = leaf_elim(sh.leaf, A, lda, LEAF, dmax, accA, accX);
+  leaf_store_x(sh.leaf, X, ldx, LEAF, accX, sh.x, NLD);
   __syncthreads();
   // L21 = A21 X11^T
   v4d acc[4];
@@ -609,10 +622,10 @@ __device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int l
 #pragma unroll
     for (int r = 0; r < 4; ++r) sh.t[(16 * I + 4 * r + lr) * NLD + 16 * K + lc] = acc[K][r];
   // (L22, X22) = leaf(A22); X22 also into LDS (over A21, which is no longer read)
-  bad = leaf_core(sh.leaf, n2, dmax, accA, accX) || bad;
+  bad = leaf_elim(sh.leaf, A22, lda, n2, dmax, accA, accX) || bad;
   for (int e = tid; e < LEAF * LEAF; e += 256) sh.a[(e / LEAF) * NLD + e % LEAF] = 0.0;
   __syncthreads();
-  leaf_store(sh.leaf, A22, lda, X22, ldx, n2, accA, accX, sh.a, NLD);
+  leaf_store_x(sh.leaf, X22, ldx, n2, accX, sh.a, NLD);
   __syncthreads();
   // X21 = -X22 T
 #pragma unroll
@@ -757,13 +770,14 @@ void BatchedOps::gemm(int ta, int tb, double alpha, double beta, int flags, cons
   }
   if (mx <= 0 || nx <= 0) return;
   long long tiles = 0;
-  for (const GemmDesc& g : d) tiles += active_tiles(g.M, g.N, 128, 64, flags);
+  for (const GemmDesc& g : d) tiles += active_tiles(g.M, g.N, 64, 64, flags);
   Op o{};
   o.kind = 1;
   o.count = (int)d.size();
-  o.big = use_big_tile(tiles) ? 1 : 0;
-  o.gx = (nx + 63) / 64;
-  o.gy = o.big ? (mx + 127) / 128 : (mx + 63) / 64;
+  o.tile64 = use_tile64(tiles) ? 1 : 0;
+  const int bt = o.tile64 ? 64 : 32;
+  o.gx = (nx + bt - 1) / bt;
+  o.gy = (mx + bt - 1) / bt;
   o.g0 = GemmOp{ta, tb, flags, alpha, beta};
   o.off = push(d);
   ops_.push_back(o);
@@ -784,15 +798,16 @@ void BatchedOps::gemm_pair(const GemmOp& o0, const std::vector<GemmDesc>& d0, co
     }
   if (mx <= 0 || nx <= 0) return;
   long long tiles = 0;
-  for (const GemmDesc& g : d0) tiles += active_tiles(g.M, g.N, 128, 64, o0.flags);
-  for (const GemmDesc& g : d1) tiles += active_tiles(g.M, g.N, 128, 64, o1.flags);
+  for (const GemmDesc& g : d0) tiles += active_tiles(g.M, g.N, 64, 64, o0.flags);
+  for (const GemmDesc& g : d1) tiles += active_tiles(g.M, g.N, 64, 64, o1.flags);
   Op o{};
   o.kind = 3;
   o.count = (int)d0.size();
   o.count2 = (int)d1.size();
-  o.big = use_big_tile(tiles) ? 1 : 0;
-  o.gx = (nx + 63) / 64;
-  o.gy = o.big ? (mx + 127) / 128 : (mx + 63) / 64;
+  o.tile64 = use_tile64(tiles) ? 1 : 0;
+  const int bt = o.tile64 ? 64 : 32;
+  o.gx = (nx + bt - 1) / bt;
+  o.gy = (mx + bt - 1) / bt;
   o.g0 = o0;
   o.g1 = o1;
   o.off = push(d0);
@@ -892,26 +907,24 @@ hipError_t BatchedOps::run(hipStream_t st, const void* d_bytes) const {
       case 1: {
         if (o.gy > 65535) return hipErrorInvalidValue;
         const GemmDesc* d = reinterpret_cast<const GemmDesc*>(base + o.off);
-        if (o.big)
-          hipLaunchKernelGGL((gemm_f64_batched_kernel<128, 64>), dim3(o.gx, o.gy, o.count), dim3(256),
-                             kLdsBig, st, d, o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
-                             o.g0.flags);
+        if (o.tile64)
+          hipLaunchKernelGGL((gemm_f64_batched_kernel<64, 64>), dim3(o.gx, o.gy, o.count), dim3(256), kLds64, st, d,
+                             o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta, o.g0.flags);
         else
-          hipLaunchKernelGGL((gemm_f64_batched_kernel<64, 64>), dim3(o.gx, o.gy, o.count), dim3(256),
-                             kLdsSmall, st, d, o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta,
-                             o.g0.flags);
+          hipLaunchKernelGGL((gemm_f64_batched_kernel<32, 32>), dim3(o.gx, o.gy, o.count), dim3(256), kLds32, st, d,
+                             o.g0.ta, o.g0.tb, o.g0.alpha, o.g0.beta, o.g0.flags);
         break;
       }
       case 3: {
         if (o.gy > 65535 || o.count + o.count2 > 65535) return hipErrorInvalidValue;
         const GemmDesc* d0 = reinterpret_cast<const GemmDesc*>(base + o.off);
         const GemmDesc* d1 = reinterpret_cast<const GemmDesc*>(base + o.off2);
-        if (o.big)
-          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<128, 64>), dim3(o.gx, o.gy, o.count + o.count2),
-                             dim3(256), kLdsBig, st, d0, o.count, o.g0, d1, o.g1);
-        else
+        if (o.tile64)
           hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<64, 64>), dim3(o.gx, o.gy, o.count + o.count2),
-                             dim3(256), kLdsSmall, st, d0, o.count, o.g0, d1, o.g1);
+                             dim3(256), kLds64, st, d0, o.count, o.g0, d1, o.g1);
+        else
+          hipLaunchKernelGGL((gemm_f64_batched_pair_kernel<32, 32>), dim3(o.gx, o.gy, o.count + o.count2),
+                             dim3(256), kLds32, st, d0, o.count, o.g0, d1, o.g1);
         break;
       }
       default:

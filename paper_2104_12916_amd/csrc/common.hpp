@@ -49,7 +49,7 @@ DevInfo& dev_info();
 // overrides the base entry (tune.hip).
 struct Tune {
   int rows_bpc = 4;     // gemv_rows / pcg_q: workgroups per CU (grid cap)
-  int rows_unroll = 8;  // 16-byte loads in flight per lane: 4 or 8
+  int rows_unroll = 8;  // 16-byte loads in flight per lane: 4, 8 or 16
   int cols_bpc = 2;     // gemv_cols: target workgroups per CU
   int cols_unroll = 8;  // gemv_cols: rows in flight per wave: 4 or 8
   int ld_pad = 64;      // elements added to every matrix leading dimension (multiple of 64);

@@ -218,7 +218,10 @@ static void launch_rows_tag(dim3 grid, size_t smem, hipStream_t st, const EventP
   const int stage = tune().rows_stage;
   const int nt = tune().ld_nt & 1;
   if (!stage) smem = 0;
-  if (tune().rows_unroll == 8)
+  if (tune().rows_unroll == 16)
+    QPG_LAUNCH((gemv_rows_kernel<T, TAG, 16>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
+               alpha, beta, y0, nsplit, skip, stage, nt);
+  else if (tune().rows_unroll == 8)
     QPG_LAUNCH((gemv_rows_kernel<T, TAG, 8>), grid, dim3(256), (uint32_t)smem, st, ev, A, lda, m, k, shape, x, y,
                alpha, beta, y0, nsplit, skip, stage, nt);
   else

@@ -159,7 +159,7 @@ class BatchedOps {
 
  private:
   struct Op {
-    int kind, count, count2, gx, gy, big;
+    int kind, count, count2, gx, gy, tile64;
     GemmOp g0, g1;
     size_t off, off2;
   };

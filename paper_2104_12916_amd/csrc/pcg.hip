@@ -368,7 +368,10 @@ hipError_t pcg_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w,
   const int grid = pcg_q_grid<T>(m2);
   if (grid > bpart_cap) return hipErrorInvalidValue;
   const int nt = tune().ld_nt & 1;
-  if (tune().rows_unroll == 8)
+  if (tune().rows_unroll == 16)
+    QPG_LAUNCH((pcg_q_kernel<T, 16>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
+               bpart, stage, nt);
+  else if (tune().rows_unroll == 8)
     QPG_LAUNCH((pcg_q_kernel<T, 8>), dim3(grid), dim3(256), (uint32_t)smem, st, ev, C, ldc, m2, n, w, dvec, p, q, sc,
                bpart, stage, nt);
   else
@@ -576,7 +579,7 @@ hipError_t fold_ct(hipStream_t st, const T* CT, int ldct, int n, int m2, const T
   if (n <= 0) return hipSuccess;
   const dim3 grid(gemv_rows_grid<T>(n));
   const int nt = tune().ld_nt & 1;
-  if (tune().rows_unroll == 8)
+  if (tune().rows_unroll >= 8)
     QPG_LAUNCH((fold_ct_kernel<T, 8>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
   else
     QPG_LAUNCH((fold_ct_kernel<T, 4>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
@@ -589,7 +592,7 @@ hipError_t fold_q(hipStream_t st, const T* C, int ldc, int m2, int n, const T* w
   const int grid = pcg_q_grid<T>(m2);
   if (grid > fp.nrw || (prec != kPrecH && grid > fp.nrz)) return hipErrorInvalidValue;
   const int nt = tune().ld_nt & 1;
-  if (tune().rows_unroll == 8)
+  if (tune().rows_unroll >= 8)
     QPG_LAUNCH((fold_q_kernel<T, 8>), dim3(grid), dim3(256), 0u, st, ev, C, ldc, m2, n, w, dvec, p, q, x, r, z, wts,
                prec, sc, fp, nt);
   else

@@ -10,6 +10,7 @@
 
 #include "../../include/qpgpu.h"
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace qpg {
 namespace {
@@ -37,8 +38,79 @@ __global__ void __launch_bounds__(kProbeBT) hbm_read_kernel(const v2d_probe_t* _
   out[(size_t)blockIdx.x * kProbeBT + threadIdx.x] = acc;  // one value per thread keeps every load live
 }
 
+// Deterministic operand entries in [-0.5, 0.5) (an integer hash of the index),
+// plus `shift` on the diagonal of a square n x n operand (ld columns).
+__global__ void dense_fill_kernel(double* __restrict__ a, int rows, int ld, int n, double shift, unsigned seed) {
+  const size_t total = (size_t)rows * ld;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ld), j = (int)(e % ld);
+    // symmetric in (i, j) so the square operand of the factorization is symmetric
+    unsigned h = (unsigned)(i < j ? i : j) * 2654435761u ^ (unsigned)(i < j ? j : i) * 40503u ^ seed;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    double v = (double)(h & 0xffffff) / 16777216.0 - 0.5;
+    if (i == j && i < n) v += shift;
+    a[e] = v;
+  }
+}
+
 }  // namespace
 }  // namespace qpg
+
+extern "C" qp_status qp_dense_time(int op, int n, int reps, double* avg_ms) {
+  if (!avg_ms || reps <= 0 || n < 1 || n > 16384 || op < 0 || op > 2) return QP_E_INVALID;
+  const int ld = (n + 255) / 256 * 256 + 64;
+  const size_t elems = (size_t)n * ld;
+  double *a = nullptr, *b = nullptr, *c = nullptr, *tmp = nullptr;
+  int* info = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  qp_status st = QP_OK;
+  float ms = 0.f;
+  const size_t tmp_elems = qpg::chol_inv_tmp_elems(n);
+  if (hipMalloc(&a, elems * sizeof(double)) != hipSuccess || hipMalloc(&b, elems * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c, elems * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tmp, tmp_elems * sizeof(double)) != hipSuccess || hipMalloc(&info, sizeof(int)) != hipSuccess) {
+    st = QP_E_NOMEM;
+  } else if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    st = QP_E_DEVICE;
+  } else {
+    const int grid = qpg::dev_info().cu_count * 4;
+    hipLaunchKernelGGL(qpg::dense_fill_kernel, dim3(grid), dim3(256), 0, nullptr, a, n, ld, n, op == 2 ? n : 0.0, 1u);
+    hipLaunchKernelGGL(qpg::dense_fill_kernel, dim3(grid), dim3(256), 0, nullptr, b, n, ld, n, 0.0, 2u);
+    auto run = [&]() -> hipError_t {
+      switch (op) {
+        case 0: return qpg::gemm_f64(nullptr, 0, 1, n, n, n, 1.0, a, ld, b, ld, 0.0, c, ld, qpg::kNone);
+        case 1: return qpg::gemm_f64(nullptr, 0, 1, n, n, n, 1.0, a, ld, b, ld, 0.0, c, ld, qpg::kBUpper);
+        default:
+          // the factorization overwrites its input: restore it from the copy in b first
+          if (hipMemcpyAsync(c, b, elems * sizeof(double), hipMemcpyDeviceToDevice, nullptr) != hipSuccess)
+            return hipErrorUnknown;
+          return qpg::chol_inv_f64(nullptr, c, ld, a, ld, n, tmp, info, 1);
+      }
+    };
+    if (op == 2)  // b keeps the SPD matrix, a receives the inverse factor
+      hipLaunchKernelGGL(qpg::dense_fill_kernel, dim3(grid), dim3(256), 0, nullptr, b, n, ld, n, (double)n, 1u);
+    bool ok = hipMemset(info, 0, sizeof(int)) == hipSuccess && run() == hipSuccess;  // warm-up
+    ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r) ok = run() == hipSuccess;
+    ok = ok && hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    int h_info = 0;
+    if (ok && op == 2) ok = hipMemcpy(&h_info, info, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok)
+      st = QP_E_DEVICE;
+    else if (h_info != 0)
+      st = QP_E_NOT_SPD;
+    else
+      *avg_ms = (double)ms / reps;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void* p : {(void*)a, (void*)b, (void*)c, (void*)tmp, (void*)info})
+    if (p) (void)hipFree(p);
+  return st;
+}
 
 extern "C" qp_status qp_hbm_read_time(size_t bytes, int wg_per_cu, int reps, double* avg_ms) {
   if (!avg_ms || reps <= 0 || bytes < 16 || bytes % 16 != 0 || wg_per_cu < 1 || wg_per_cu > 32)

@@ -47,7 +47,7 @@ bool parse_keys(const std::string& spec, Tune& t, bool alloc) {
     const int v = atoi(tok.c_str() + eq + 1);
     bool ok = true;
     if (k == "rows_bpc") ok = v >= 1 && v <= kMaxRowsBpc, t.rows_bpc = v;
-    else if (k == "rows_unroll") ok = v == 4 || v == 8, t.rows_unroll = v;
+    else if (k == "rows_unroll") ok = v == 4 || v == 8 || v == 16, t.rows_unroll = v;
     else if (k == "cols_bpc") ok = v >= 1 && v <= kMaxColsBpc, t.cols_bpc = v;
     else if (k == "cols_unroll") ok = v == 4 || v == 8, t.cols_unroll = v;
     else if (k == "qe_stage") ok = v == 0 || v == 1, t.qe_stage = v;

@@ -5,7 +5,11 @@ Sets up one workload instance, factorizes it, then launches each CG-step sweep
 solver) and, for counter calibration, one plain device-to-device copy of a known
 size.  Prints the event-timed averages.
 
-Usage: python -m paper_2104_12916_amd.profile_ops [--workload lowdof] [--reps 10]
+With --dense N it times the factorization kernels instead (qp_dense_time): the
+n^3 GEMM, the GEMM with a triangular operand and the Cholesky-inverse of size N,
+with their rates (flops of the product, of the Cholesky alone for op 2).
+
+Usage: python -m paper_2104_12916_amd.profile_ops [--workload lowdof] [--reps 10] [--dense N]
 """
 import argparse
 import os
@@ -23,7 +27,18 @@ def main():
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--dense", type=int, default=0, help="time the factorization kernels of this size")
     args = ap.parse_args()
+
+    if args.dense:
+        from paper_2104_12916_amd import qpgpu
+        n = args.dense
+        for op, name, flops in ((0, "GEMM C = A B^T", 2.0 * n ** 3), (1, "GEMM, B^T upper triangular", 1.0 * n ** 3),
+                                (2, "Cholesky-inverse", 2.0 * n ** 3 / 3.0)):
+            ms = qpgpu.dense_time(op, n, args.reps)
+            print(f"dense op {op} ({name}), n={n}: {ms:.3f} ms, {flops / (ms * 1e-3) / 1e12:.1f} TF/s "
+                  f"({100 * flops / (ms * 1e-3) / 78.6e12:.1f} % of 78.6)", flush=True)
+        return
 
     import torch
     import synth

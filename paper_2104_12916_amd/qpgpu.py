@@ -30,7 +30,7 @@ EXPORTS = (
     "qp_batch_query", "qp_batch_footprint", "qp_batch_last_error", "qp_batch_destroy", "qp_batch_profile_get",
     "qp_k0_one_pass", "qp_c_identity", "qp_ipm_cg_steps",
     "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_shared_last_error", "qp_shared_destroy",
-    "qp_tune_set", "qp_tune_get", "qp_hbm_read_time", "qp_factor_K0_static",
+    "qp_tune_set", "qp_tune_get", "qp_hbm_read_time", "qp_factor_K0_static", "qp_dense_time",
 )
 # bytes of the fixed device array qp_factor_K0_static takes its scratch from (QPGPU_STATIC_SCRATCH_BYTES)
 STATIC_SCRATCH_BYTES = 64 << 20
@@ -123,12 +123,13 @@ def lib():
     L.qp_tune_set.argtypes = [ct.c_char_p]
     L.qp_tune_get.argtypes = [ct.c_char_p, ct.c_size_t, ct.POINTER(ct.c_size_t)]
     L.qp_hbm_read_time.argtypes = [ct.c_size_t, I, I, ct.POINTER(D)]
+    L.qp_dense_time.argtypes = [I, I, I, ct.POINTER(D)]
     for name in ("qp_setup", "qp_factor_K0", "qp_factor_K0_static", "qp_k0_solve", "qp_kf_apply", "qp_pcg_solve",
                  "qp_ipm_solve",
                  "qp_op_time", "qp_profile_get", "qp_batch_create", "qp_batch_admit", "qp_batch_step",
                  "qp_batch_finished", "qp_batch_collect", "qp_batch_query", "qp_batch_profile_get",
                  "qp_shared_setup", "qp_shared_pcg_solve", "qp_shared_ipm_solve", "qp_tune_set", "qp_tune_get",
-                 "qp_hbm_read_time"):
+                 "qp_hbm_read_time", "qp_dense_time"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -194,6 +195,16 @@ def tune_get() -> str:
     if st != QP_OK:
         raise QpError(st, "qp_tune_get failed")
     return buf.value.decode()
+
+
+def dense_time(op: int, n: int, reps: int = 10) -> float:
+    """Average ms of one run of a factorization kernel of size n (qp_dense_time):
+    op 0 GEMM n^3, op 1 GEMM with a triangular operand, op 2 Cholesky-inverse."""
+    ms = ct.c_double(0.0)
+    st = lib().qp_dense_time(op, n, reps, ct.byref(ms))
+    if st != QP_OK:
+        raise QpError(st, "qp_dense_time failed")
+    return ms.value
 
 
 def hbm_read_time(nbytes: int, wg_per_cu: int = 8, reps: int = 20) -> float:
