@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <unordered_map>
 
 #include "ctx.hpp"
@@ -136,12 +137,17 @@ namespace {
 // ---- descriptor staging ---------------------------------------------------------
 struct Packer {
   std::vector<std::pair<const void*, size_t>> parts;
+  std::deque<std::vector<int>> owned;  // tables built for the upload (stable addresses)
   size_t total = 0;
   size_t add(const void* p, size_t bytes) {
     size_t off = total;
     parts.emplace_back(p, bytes);
     total += (bytes + 255) / 256 * 256;
     return off;
+  }
+  size_t add_owned(std::vector<int>&& v) {
+    owned.push_back(std::move(v));
+    return add(owned.back().data(), owned.back().size() * sizeof(int));
   }
 };
 
@@ -367,13 +373,32 @@ void build_lists(qp_batch* B, std::vector<BItem<T>*>& act, StepLists<T>& L) {
       L.ph.push_back(pd);
     }
   }
+  // every prefix table has one entry per descriptor of its list, then its block map
+  if (L.c1p.size() != L.c1.size() || L.c1r.size() != L.c1.size() || L.c3p.size() != L.c3.size() ||
+      L.c3r.size() != L.c3.size() || L.c5p.size() != L.c5.size() || L.c5r.size() != L.c5.size() ||
+      L.r1p.size() != L.r1.size() || L.r2p.size() != L.r2.size() || L.r3p.size() != L.r3.size() ||
+      L.r4p.size() != L.r4.size() || L.qp.size() != L.pd.size() || L.syp.size() != L.sy.size() ||
+      L.syr.size() != L.sy.size() || L.sphp.size() != L.sph.size() || L.sphr.size() != L.sph.size()) {
+    set_err(sk, "batched launch lists are inconsistent");
+    throw Fail{QP_E_DEVICE};
+  }
   Packer pk;
   auto V = [&](auto& v) { return pk.add(v.data(), v.size() * sizeof(v[0])); };
+  auto M = [&](const std::vector<int>& prefix, int total) {
+    std::vector<int> m = with_block_map(prefix, total);
+    if (m.size() != prefix.size() + (size_t)total) {
+      set_err(sk, "batched launch too large for its block map (%d descriptors, %d blocks)", (int)prefix.size(),
+              total);
+      throw Fail{QP_E_DEVICE};
+    }
+    return pk.add_owned(std::move(m));
+  };
   size_t o_c1 = V(L.c1), o_c3 = V(L.c3), o_c5 = V(L.c5), o_r1 = V(L.r1), o_r2 = V(L.r2), o_r3 = V(L.r3),
          o_r4 = V(L.r4), o_pd = V(L.pd), o_ph = V(L.ph), o_sy = V(L.sy), o_sph = V(L.sph);
-  size_t o_c1p = V(L.c1p), o_c1r = V(L.c1r), o_c3p = V(L.c3p), o_c3r = V(L.c3r), o_c5p = V(L.c5p),
-         o_c5r = V(L.c5r), o_r1p = V(L.r1p), o_r2p = V(L.r2p), o_r3p = V(L.r3p), o_r4p = V(L.r4p), o_qp = V(L.qp),
-         o_syp = V(L.syp), o_syr = V(L.syr), o_sphp = V(L.sphp), o_sphr = V(L.sphr);
+  size_t o_c1p = M(L.c1p, L.c1pt), o_c1r = M(L.c1r, L.c1rt), o_c3p = M(L.c3p, L.c3pt), o_c3r = M(L.c3r, L.c3rt),
+         o_c5p = M(L.c5p, L.c5pt), o_c5r = M(L.c5r, L.c5rt), o_r1p = M(L.r1p, L.r1t), o_r2p = M(L.r2p, L.r2t),
+         o_r3p = M(L.r3p, L.r3t), o_r4p = M(L.r4p, L.r4t), o_qp = M(L.qp, L.qt), o_syp = M(L.syp, L.sypt),
+         o_syr = M(L.syr, L.syrt), o_sphp = M(L.sphp, L.sphpt), o_sphr = M(L.sphr, L.sphrt);
   const char* base = stage_upload(B, pk);
   L.dsy = reinterpret_cast<const SymDesc<T>*>(base + o_sy);
   L.dsyp = reinterpret_cast<const int*>(base + o_syp);
@@ -468,6 +493,14 @@ IpmDesc ipm_desc_of(qp_ctx* c) {
   return q;
 }
 
+// A launch's prefix table with its block map (desc.hpp); a list too large for the
+// map's encoding is refused.
+static size_t pack_prefix(Packer& pk, const std::vector<int>& prefix, int total) {
+  std::vector<int> m = with_block_map(prefix, total);
+  if (m.size() != prefix.size() + (size_t)total) throw Fail{QP_E_DEVICE};
+  return pk.add_owned(std::move(m));
+}
+
 // One batched row sweep, one batched column sweep (float64), and the list of
 // pool entries of the batched vector kernels.
 struct RowsL {
@@ -487,7 +520,7 @@ struct RowsL {
   }
   void pack(Packer& pk) {
     od = pk.add(d.data(), d.size() * sizeof(d[0]));
-    op = pk.add(p.data(), p.size() * sizeof(int));
+    op = pack_prefix(pk, p, t);
   }
   void launch(qp_batch* B, const char* base, int tag) const {
     HIPCHK(&B->sink, launch_bgemv_rows<double>(B->stream, reinterpret_cast<const RowsDesc<double>*>(base + od),
@@ -517,8 +550,8 @@ struct ColsL {
   }
   void pack(Packer& pk) {
     od = pk.add(d.data(), d.size() * sizeof(d[0]));
-    op = pk.add(p.data(), p.size() * sizeof(int));
-    orr = pk.add(r.data(), r.size() * sizeof(int));
+    op = pack_prefix(pk, p, tp);
+    orr = pack_prefix(pk, r, tr);
   }
   void launch(qp_batch* B, const char* base, int tag) const {
     HIPCHK(&B->sink, launch_bgemv_cols<double>(B->stream, reinterpret_cast<const ColsDesc<double>*>(base + od),

@@ -313,9 +313,10 @@ constexpr int LEAF = 64;
 // matrix the computed pivot is a rounding residue of order eps * ||A||.
 constexpr double kPivRel = 1e-13;
 
-// Leaf: right-looking LDL^T of a <= 64 x 64 SPD block, then L = L_1 D^{1/2} and
-// X = L^{-1} = D^{-1/2} L_1^{-1} (X starts as I and takes the same row
-// operations, so it stays lower triangular).  The block is held as 16 x 16
+// Leaf: right-looking LDL^T of a <= 64 x 64 SPD block A = L_1 D L_1^T, giving
+// X = L^{-1} = D^{-1/2} L_1^{-1} for the Cholesky factor L = L_1 D^{1/2} (X starts
+// as I and takes the same row operations, so it stays lower triangular; L itself
+// is not stored, the callers use only its inverse).  The block is held as 16 x 16
 // tiles in the accumulators of v_mfma_f64_16x16x4f64: wavefront I owns tile row
 // I of A and of X (tiles K <= I).  Columns are eliminated four at a time, one
 // barrier per column block J (columns j0 = 4J .. 4J+3): the owners publish those
@@ -325,11 +326,11 @@ constexpr double kPivRel = 1e-13;
 // cf_i = ev_i / d) and the block's rows of X through their own steps (xf).  The
 // updates of the trailing columns, a_ik -= sum_p cf_ip ev_kp, and of the rows of
 // X below the block, x_i -= sum_p cf_ip xf_p, are rank-4 products: one MFMA per
-// 16 x 16 tile, with the k = 4 operand slots holding p.  Finished columns of L go
-// straight to memory.  Each wavefront runs alone on its SIMD, so the code is
-// shaped for latency: the wavefront index is a scalar (uniform branches), lane
-// selections are selects, and the reciprocals of the pivots and of their square
-// roots are Newton-refined hardware estimates instead of IEEE divisions.
+// 16 x 16 tile, with the k = 4 operand slots holding p.  Each wavefront runs
+// alone on its SIMD, so the code is shaped for latency: the wavefront index is a
+// scalar (uniform branches), lane selections are selects, and the reciprocals of
+// the pivots and of their square roots are Newton-refined hardware estimates
+// instead of IEEE divisions.
 
 // LDS of the leaf elimination.
 struct alignas(16) LeafLds {
@@ -382,11 +383,11 @@ __device__ __forceinline__ double rsq_nr(double d) {
   return y;
 }
 
-// Elimination of the accumulators loaded by leaf_load; writes L (rows and
-// columns < nb, k <= i) to A, keeps X = L_1^{-1} (unscaled) in accX and
-// 1 / sqrt(d) in sh.rs.  Returns true when a pivot is rejected.
-__device__ __forceinline__ bool leaf_elim(LeafLds& sh, double* __restrict__ A, int lda, int nb,
-                                          const double* __restrict__ dmax, v4d (&accA)[4], v4d (&accX)[4]) {
+// Elimination of the accumulators loaded by leaf_load; keeps X = L_1^{-1}
+// (unscaled) in accX and 1 / sqrt(d) in sh.rs (L itself is not an output: the
+// callers use only the inverse factor).  Returns true when a pivot is rejected.
+__device__ __forceinline__ bool leaf_elim(LeafLds& sh, int nb, const double* __restrict__ dmax, v4d (&accA)[4],
+                                          v4d (&accX)[4]) {
   const int tid = threadIdx.x, l = tid & 63, lr = l >> 4, lc = l & 15;
   const int I = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index, uniform
   const double pmin = kPivRel * (*dmax);
@@ -434,8 +435,7 @@ __device__ __forceinline__ bool leaf_elim(LeafLds& sh, double* __restrict__ A, i
             for (int k = p + 1; k <= i; ++k) E[i][k] -= coef * E[k][p];
           }
         }
-        const double rsl = rsq_nr(sel4(E[0][0], E[1][1], E[2][2], E[3][3], lr));  // column j0 + lr
-        if (I == 0 && lc == 0) sh.rs[j0 + lr] = rsl;
+        if (I == 0 && lc == 0) sh.rs[j0 + lr] = rsq_nr(sel4(E[0][0], E[1][1], E[2][2], E[3][3], lr));
         if (I >= K0) {
           // Row 16 K + lc of each operand tile K (K0 <= K <= I) through the block's
           // four steps; this lane keeps slot p = lr: the eliminated value (B operand)
@@ -456,24 +456,8 @@ __device__ __forceinline__ bool leaf_elim(LeafLds& sh, double* __restrict__ A, i
               for (int pp = 0; pp < p; ++pp) g[p] -= cf[pp] * E[p][pp];
               cf[p] = g[p] * dinv[p];
             }
-            double ev = below ? sel4(g[0], g[1], g[2], g[3], lr) : 0.0;
-            bop[K] = ev;
-            if (K == I) {
-              aop = below ? -sel4(cf[0], cf[1], cf[2], cf[3], lr) : 0.0;
-              bool put = below;
-              if (K == K0) {
-                // rows of the diagonal block: L entries E[q][p] / sqrt(d_p), p = lr <= q
-                const int q = lc - c0;
-                const double e0 = sel4(E[0][0], E[1][0], E[2][0], E[3][0], q);
-                const double e1 = sel4(E[0][1], E[1][1], E[2][1], E[3][1], q);
-                const double e2 = sel4(E[0][2], E[1][2], E[2][2], E[3][2], q);
-                const double e3 = sel4(E[0][3], E[1][3], E[2][3], E[3][3], q);
-                const bool diag = q >= 0 && q < 4 && lr <= q;
-                ev = diag ? sel4(e0, e1, e2, e3, lr) : ev;
-                put = put || diag;
-              }
-              if (put && row < nb && j0 + lr < nb) A[(size_t)row * lda + j0 + lr] = ev * rsl;
-            }
+            bop[K] = below ? sel4(g[0], g[1], g[2], g[3], lr) : 0.0;
+            if (K == I) aop = below ? -sel4(cf[0], cf[1], cf[2], cf[3], lr) : 0.0;
           }
 #pragma unroll
           for (int K = K0; K < 4; ++K)
@@ -528,7 +512,7 @@ __device__ __forceinline__ void chol_inv_leaf_body(double* __restrict__ A, int l
   __shared__ LeafLds sh;
   v4d accA[4], accX[4];
   leaf_load(A, lda, nb, accA, accX);
-  const bool bad = leaf_elim(sh, A, lda, nb, dmax, accA, accX);
+  const bool bad = leaf_elim(sh, nb, dmax, accA, accX);
   leaf_store_x(sh, X, ldx, nb, accX);
   if (threadIdx.x == 0 && bad) *info = code;
 }
@@ -594,7 +578,7 @@ __device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int l
   }
   v4d accA[4], accX[4];
   leaf_load(A, lda, LEAF, accA, accX);
-  bool bad = leaf_elim(sh.leaf, A, lda, LEAF, dmax, accA, accX);
+  bool bad = leaf_elim(sh.leaf, LEAF, dmax, accA, accX);
   leaf_store_x(sh.leaf, X, ldx, LEAF, accX, sh.x, NLD);
   __syncthreads();
   // L21 = A21 X11^T
@@ -622,7 +606,7 @@ __device__ __forceinline__ void chol_inv_node_body(double* __restrict__ A, int l
 #pragma unroll
     for (int r = 0; r < 4; ++r) sh.t[(16 * I + 4 * r + lr) * NLD + 16 * K + lc] = acc[K][r];
   // (L22, X22) = leaf(A22); X22 also into LDS (over A21, which is no longer read)
-  bad = leaf_elim(sh.leaf, A22, lda, n2, dmax, accA, accX) || bad;
+  bad = leaf_elim(sh.leaf, n2, dmax, accA, accX) || bad;
   for (int e = tid; e < LEAF * LEAF; e += 256) sh.a[(e / LEAF) * NLD + e % LEAF] = 0.0;
   __syncthreads();
   leaf_store_x(sh.leaf, X22, ldx, n2, accX, sh.a, NLD);

@@ -3,6 +3,8 @@
 // sizes.  A launch over a list of descriptors gets a prefix table of block
 // counts; block b serves descriptor j with prefix[j] <= b < prefix[j + 1].
 #pragma once
+#include <vector>
+
 #include "common.hpp"
 
 namespace qpg {
@@ -68,15 +70,34 @@ struct PcgDesc {
   int stage;      // 1: w staged in LDS; 0: w read from global memory (zero-padded to ldc)
 };
 
-// Map a flattened block index to its descriptor (binary search in prefix).
-__device__ __forceinline__ int desc_of_block(const int* __restrict__ prefix, int ndesc, int b) {
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= b) lo = mid;
-    else hi = mid - 1;
+// Block b of a flattened batched launch: its descriptor j and its index among
+// that descriptor's blocks.  The prefix table of a launch holds the ndesc
+// first-block offsets followed by one entry per block, local << 16 | j (see
+// with_block_map), so a workgroup finds its descriptor with one load instead of
+// a binary search of dependent loads.
+struct DescBlock {
+  int j, local;
+};
+__device__ __forceinline__ DescBlock desc_of_block(const int* __restrict__ prefix, int ndesc, int b) {
+  const int e = prefix[ndesc + b];
+  return DescBlock{e & 0xffff, e >> 16};
+}
+
+// The prefix table of a launch over `total` blocks as it is uploaded: the
+// first-block offsets, then the block map.  Empty when the encoding does not fit
+// (more than 65536 descriptors or 32768 blocks of one descriptor).
+inline std::vector<int> with_block_map(const std::vector<int>& prefix, int total) {
+  std::vector<int> out(prefix);
+  out.reserve(prefix.size() + (size_t)total);
+  const int nd = (int)prefix.size();
+  if (nd > 65536) return {};
+  for (int j = 0; j < nd; ++j) {
+    const int end = j + 1 < nd ? prefix[j + 1] : total;
+    if (end - prefix[j] > 32768) return {};
+    for (int b = prefix[j]; b < end; ++b) out.push_back(((b - prefix[j]) << 16) | j);
   }
-  return lo;
+  if ((int)out.size() != nd + total) return {};
+  return out;
 }
 
 }  // namespace qpg

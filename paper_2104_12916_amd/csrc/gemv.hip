@@ -165,20 +165,20 @@ __global__ void __launch_bounds__(256) gemv_cols_reduce_kernel(int k, int ps, in
 template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) bgemv_rows_kernel(const RowsDesc<T>* __restrict__ descs,
                                                          const int* __restrict__ prefix, int ndesc, int stage) {
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const RowsDesc<T> d = descs[j];
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const RowsDesc<T> d = descs[db.j];
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  rows_body<T, U>(d.A, d.lda, d.m, d.k, d.shape, d.x, d.y, d.alpha, d.beta, d.y0, d.nsplit, blockIdx.x - prefix[j],
-                  d.nblocks, stage ? reinterpret_cast<T*>(smem_raw) : nullptr, d.skip);
+  rows_body<T, U>(d.A, d.lda, d.m, d.k, d.shape, d.x, d.y, d.alpha, d.beta, d.y0, d.nsplit, db.local, d.nblocks,
+                  stage ? reinterpret_cast<T*>(smem_raw) : nullptr, d.skip);
 }
 
 template <typename T, int TAG, int U>
 __global__ void __launch_bounds__(256) bgemv_cols_part_kernel(const ColsDesc<T>* __restrict__ descs,
                                                               const int* __restrict__ prefix, int ndesc) {
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const ColsDesc<T> d = descs[j];
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const ColsDesc<T> d = descs[db.j];
   if (d.skip && *d.skip) return;
-  const int local = blockIdx.x - prefix[j];
+  const int local = db.local;
   cols_part_body<T, U>(d.A, d.lda, d.m, d.shape, d.x, d.part, d.rpc, local % d.tiles, local / d.tiles, d.tiles);
 }
 
@@ -186,11 +186,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) bgemv_cols_reduce_kernel(const ColsDesc<T>* __restrict__ descs,
                                                                 const int* __restrict__ prefix, int ndesc) {
   constexpr int CW = kWave * Vec16<T>::n;
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const ColsDesc<T> d = descs[j];
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const ColsDesc<T> d = descs[db.j];
   if (d.skip && *d.skip) return;
-  cols_reduce_body<T>(d.k, d.tiles * CW, d.shape, d.part, d.rpc, d.nchunks, d.y, d.alpha, d.beta, d.y0,
-                      blockIdx.x - prefix[j]);
+  cols_reduce_body<T>(d.k, d.tiles * CW, d.shape, d.part, d.rpc, d.nchunks, d.y, d.alpha, d.beta, d.y0, db.local);
 }
 
 // ---------------------------------------------------------------------------
@@ -668,13 +667,12 @@ __global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int
 template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
 __global__ void __launch_bounds__(BT) bk0_sym_kernel(const SymDesc<T>* __restrict__ descs,
                                                      const int* __restrict__ prefix, int ndesc) {
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const SymDesc<T> d = descs[j];
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const SymDesc<T> d = descs[db.j];
   if constexpr (PIPE)
-    k0_sym_body_pipe<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j],
-                                      d.skip);
+    k0_sym_body_pipe<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
   else
-    k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, blockIdx.x - prefix[j], d.skip);
+    k0_sym_body<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
 }
 
 // Columns grp*16 .. +15 of w = sum over g of part[g].  Thread t adds column
@@ -804,9 +802,9 @@ __global__ void __launch_bounds__(256) k0_sym_reduce_kernel(const T* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(256) bk0_sym_reduce_kernel(const SymDesc<T>* __restrict__ descs,
                                                              const int* __restrict__ prefix, int ndesc) {
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const SymDesc<T> d = descs[j];
-  k0_sym_reduce_body<T>(d.part, d.ldp, d.G, d.n, d.w, d.skip, blockIdx.x - prefix[j]);
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const SymDesc<T> d = descs[db.j];
+  k0_sym_reduce_body<T>(d.part, d.ldp, d.G, d.n, d.w, d.skip, db.local);
 }
 
 constexpr int kSymBT = 256;  // threads per workgroup of the one-pass sweep (512 measured slower)
@@ -821,7 +819,8 @@ template <typename T>
 int k0_sym_grid(int N, int n) {
   const int U = (n + 1) / 2 + (N - n);
   const int cap = dev_info().cu_count * tune().sym_wg;
-  return std::max(1, std::min(U, cap));
+  const int su = tune().sym_units;
+  return std::max(1, std::min((U + su - 1) / su, cap));
 }
 
 size_t k0_sym_part_elems(int n) { return (size_t)dev_info().cu_count * kMaxSymWg * k0_sym_ldp(n); }

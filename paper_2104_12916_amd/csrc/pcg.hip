@@ -325,10 +325,10 @@ __global__ void __launch_bounds__(kUpd) bpcg_init_kernel(const PcgDesc<T>* __res
 template <typename T, int U>
 __global__ void __launch_bounds__(256) bpcg_q_kernel(const PcgDesc<T>* __restrict__ descs,
                                                      const int* __restrict__ prefix, int ndesc) {
-  const int j = desc_of_block(prefix, ndesc, blockIdx.x);
-  const PcgDesc<T> d = descs[j];
+  const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
+  const PcgDesc<T> d = descs[db.j];
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  q_body<T, U>(d.C, d.ldc, d.m2, d.n, d.w, d.dvec, d.p, d.q, d.bpart, blockIdx.x - prefix[j], d.qblocks,
+  q_body<T, U>(d.C, d.ldc, d.m2, d.n, d.w, d.dvec, d.p, d.q, d.bpart, db.local, d.qblocks,
                reinterpret_cast<T*>(smem_raw), d.stage, &d.sc->done);
 }
 

@@ -7,10 +7,14 @@
            the CG-step sweeps, scaled by what the same counters read for the
            run's calibration copy of known size, stored in profiles/traffic.json
            with the hash of the kernel sources they were taken on
+  mfma     counter CSV of one rocprofv3 --pmc run with MfmaUtil and MfmaFlopsF64
+           (plus its kernel trace for the durations) -> markdown table of the
+           FP64 matrix-core use of each kernel
 
 Usage:
   python -m paper_2104_12916_amd.profile_summary stats CSV OUT.md --title T --cmd C [--note N] [--top 14]
   python -m paper_2104_12916_amd.profile_summary traffic --fetch F.csv --write W.csv --workload lowdof
+  python -m paper_2104_12916_amd.profile_summary mfma --counters C.csv --trace T.csv OUT.md --title T --cmd C
 """
 import argparse
 import csv
@@ -121,6 +125,47 @@ def traffic(args):
     print(json.dumps(out, indent=1))
 
 
+FP64_PEAK = 78.6e12  # dense FP64 MFMA, flop/s
+
+
+def mfma(args):
+    """Per kernel and grid size: dispatches, average duration, MFMA flops per dispatch
+    (MfmaFlopsF64), achieved rate and its share of the FP64 peak, and MfmaUtil
+    (matrix-core busy cycles over active cycles of all SIMDs)."""
+    vals = {}
+    names = {}
+    for r in csv.DictReader(open(args.counters)):
+        d = int(r["Dispatch_Id"])
+        vals.setdefault(d, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        names[d] = (r["Kernel_Name"], int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])))
+    dur = {}
+    for r in csv.DictReader(open(args.trace)):
+        dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    per = {}
+    for d, v in vals.items():
+        if "MfmaFlopsF64" not in v or v["MfmaFlopsF64"] <= 0 or d not in dur:
+            continue
+        k = (_short(names[d][0]), names[d][1])
+        e = per.setdefault(k, {"n": 0, "t": 0.0, "fl": 0.0, "util": 0.0})
+        e["n"] += 1
+        e["t"] += dur[d]
+        e["fl"] += v["MfmaFlopsF64"]
+        e["util"] += v.get("MfmaUtil", float("nan"))
+    lines = [f"# {args.title}", "", "Command (run from the repository root on one MI355X):", "", "```", args.cmd, "```",
+             ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += ["| kernel | workgroups | dispatches | avg us | MFMA GFLOP per dispatch | TF/s | of 78.6 TF/s | MfmaUtil % |",
+              "|---|---|---|---|---|---|---|---|"]
+    for (k, wg), e in sorted(per.items(), key=lambda kv: -kv[1]["t"]):
+        t, fl = e["t"] / e["n"], e["fl"] / e["n"]
+        lines.append(f"| `{k}` | {wg} | {e['n']} | {t * 1e6:.1f} | {fl / 1e9:.3f} | {fl / t / 1e12:.1f} | "
+                     f"{100 * fl / t / FP64_PEAK:.1f} % | {e['util'] / e['n']:.1f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -135,9 +180,18 @@ def main():
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
     b.add_argument("--workload", default="lowdof")
+    c = sub.add_parser("mfma")
+    c.add_argument("out")
+    c.add_argument("--counters", required=True)
+    c.add_argument("--trace", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--note", default="")
     args = ap.parse_args()
     if args.cmd_name == "stats":
         stats(args)
+    elif args.cmd_name == "mfma":
+        mfma(args)
     else:
         traffic(args)
 
