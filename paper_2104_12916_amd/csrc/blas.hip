@@ -38,6 +38,13 @@ constexpr int GPAD = 4;   // LDS row padding (doubles)
 template <int BM, int BN, int BK = 16>
 struct GemmTile {
   static constexpr int GK = BK;                     // k slab
+  // Slabs whose global loads are in flight in registers.  The large tile serves
+  // launches of at least four tiles per CU and hides load latency across its
+  // workgroups (one slab ahead keeps it at 96 VGPRs, five workgroups per CU; four
+  // ahead cost 150 VGPRs and 25 % at 2048^3).  The small tile serves launches too
+  // small for that, so it keeps eight slabs ahead (110 VGPRs): 1024^3 in 73 us
+  // against 79 us one slab ahead.
+  static constexpr int S = BM * BN >= 64 * 64 ? 1 : 8;
   static constexpr int WM = BM / 2, WN = BN / 2;    // per-wavefront block
   static constexpr int FM = WM / 16, FN = WN / 16;  // MFMA blocks per wavefront
   static constexpr int LA = BM * GK / 2 / 256;      // 16-byte loads per thread, A slab
@@ -86,17 +93,20 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
 #pragma unroll
     for (int b = 0; b < G::FN; ++b) acc[a][b] = v4d{0, 0, 0, 0};
 
-  v2d ra[G::LA], rb[G::LB];
-  auto load = [&](int k0) {
+  // Slab t (k0 = klo + t GK) goes through registers (stage t % S, its loads issued S
+  // slabs ahead) into LDS buffer t % 2; one barrier per slab.
+  constexpr int S = G::S;
+  v2d ra[S][G::LA], rb[S][G::LB];
+  auto load = [&](int k0, v2d (&xa)[G::LA], v2d (&xb)[G::LB]) {
 #pragma unroll
     for (int e = 0; e < G::LA; ++e) {
       const int v = tid + 256 * e;
       if (!ta) {  // op(A)[i][k] = A[i lda + k]: pairs along k
         const int row = v / (GK / 2), kv = v % (GK / 2), gi = i0 + row;
-        ra[e] = gi < M ? ld_pair(A + (size_t)gi * lda, k0 + 2 * kv, K, va) : v2d{0, 0};
+        xa[e] = gi < M ? ld_pair(A + (size_t)gi * lda, k0 + 2 * kv, K, va) : v2d{0, 0};
       } else {    // op(A)[i][k] = A[k lda + i]: pairs along i
         const int kr = v / (BM / 2), iv = v % (BM / 2), gk = k0 + kr;
-        ra[e] = gk < K ? ld_pair(A + (size_t)gk * lda, i0 + 2 * iv, M, va) : v2d{0, 0};
+        xa[e] = gk < K ? ld_pair(A + (size_t)gk * lda, i0 + 2 * iv, M, va) : v2d{0, 0};
       }
     }
 #pragma unroll
@@ -104,14 +114,14 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       const int v = tid + 256 * e;
       if (!tb) {  // op(B)[k][j] = B[k ldb + j]: pairs along j
         const int kr = v / (BN / 2), jv = v % (BN / 2), gk = k0 + kr;
-        rb[e] = gk < K ? ld_pair(B + (size_t)gk * ldb, j0 + 2 * jv, N, vb) : v2d{0, 0};
+        xb[e] = gk < K ? ld_pair(B + (size_t)gk * ldb, j0 + 2 * jv, N, vb) : v2d{0, 0};
       } else {    // op(B)[k][j] = B[j ldb + k]: pairs along k
         const int col = v / (GK / 2), kv = v % (GK / 2), gj = j0 + col;
-        rb[e] = gj < N ? ld_pair(B + (size_t)gj * ldb, k0 + 2 * kv, K, vb) : v2d{0, 0};
+        xb[e] = gj < N ? ld_pair(B + (size_t)gj * ldb, k0 + 2 * kv, K, vb) : v2d{0, 0};
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const v2d (&xa)[G::LA], const v2d (&xb)[G::LB]) {
     double* as = As + buf * GK * G::AS;
     double* bs = Bs + buf * GK * G::BS;
 #pragma unroll
@@ -119,11 +129,11 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       const int v = tid + 256 * e;
       if (!ta) {
         const int row = v / (GK / 2), kv = v % (GK / 2);
-        as[(2 * kv) * G::AS + row] = ra[e].x;
-        as[(2 * kv + 1) * G::AS + row] = ra[e].y;
+        as[(2 * kv) * G::AS + row] = xa[e].x;
+        as[(2 * kv + 1) * G::AS + row] = xa[e].y;
       } else {
         const int kr = v / (BM / 2), iv = v % (BM / 2);
-        *reinterpret_cast<v2d*>(as + kr * G::AS + 2 * iv) = ra[e];
+        *reinterpret_cast<v2d*>(as + kr * G::AS + 2 * iv) = xa[e];
       }
     }
 #pragma unroll
@@ -131,24 +141,15 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
       const int v = tid + 256 * e;
       if (!tb) {
         const int kr = v / (BN / 2), jv = v % (BN / 2);
-        *reinterpret_cast<v2d*>(bs + kr * G::BS + 2 * jv) = rb[e];
+        *reinterpret_cast<v2d*>(bs + kr * G::BS + 2 * jv) = xb[e];
       } else {
         const int col = v / (GK / 2), kv = v % (GK / 2);
-        bs[(2 * kv) * G::BS + col] = rb[e].x;
-        bs[(2 * kv + 1) * G::BS + col] = rb[e].y;
+        bs[(2 * kv) * G::BS + col] = xb[e].x;
+        bs[(2 * kv + 1) * G::BS + col] = xb[e].y;
       }
     }
   };
-
-  if (klo < khi) {
-    load(klo);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = klo; k0 < khi; k0 += GK) {
-    const bool more = k0 + GK < khi;
-    if (more) load(k0 + GK);
+  auto compute = [&](int buf) {
     const double* as = As + buf * GK * G::AS;
     const double* bs = Bs + buf * GK * G::BS;
 #pragma unroll
@@ -164,9 +165,28 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, double alpha, con
 #pragma unroll
         for (int b = 0; b < G::FN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+  };
+
+  const int T = klo < khi ? (khi - klo + GK - 1) / GK : 0;  // slabs
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+    if (u < T) load(klo + u * GK, ra[u], rb[u]);
+  if (T > 0) store(0, ra[0], rb[0]);
+  if (S < T) load(klo + S * GK, ra[0], rb[0]);
+  __syncthreads();
+  for (int t0 = 0; t0 < T; t0 += S) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int t = t0 + u;
+      if (t < T) {
+        compute(t & 1);
+        // slab t + 1 from its registers into the other buffer, then slab t + 1 + S into them
+        const int nx = (u + 1) % S;
+        if (t + 1 < T) store((t + 1) & 1, ra[nx], rb[nx]);
+        if (t + 1 + S < T) load(klo + (t + 1 + S) * GK, ra[nx], rb[nx]);
+        __syncthreads();
+      }
+    }
   }
   // f64 16x16x4 result layout: register r of lane l holds D[4 r + l / 16][l % 16]
 #pragma unroll
@@ -279,7 +299,19 @@ __global__ void __launch_bounds__(256, 2) gemm_f64_pair_kernel(GemmArgs g0, Gemm
 static hipError_t gemm_f64_pair(hipStream_t st, const GemmArgs& g0, const GemmArgs& g1) {
   const int mx = std::max(g0.M, g1.M), nx = std::max(g0.N, g1.N);
   if (mx <= 0 || nx <= 0) return hipSuccess;
-  const long long tb = active_tiles(g0.M, g0.N, 64, 64, g0.flags) + active_tiles(g1.M, g1.N, 64, 64, g1.flags);
+  const long long t0 = active_tiles(g0.M, g0.N, 64, 64, g0.flags), t1 = active_tiles(g1.M, g1.N, 64, 64, g1.flags);
+  const long long fill = (long long)dev_info().cu_count * 2;
+  if (t0 >= fill && t1 >= fill) {
+    // each fills the chip alone: two launches, each with its own tile shape and
+    // tile order (a shared grid would leave half the output-lower tiles idle and
+    // the triangular operand's tiles unsorted)
+    hipError_t e = gemm_f64(st, g0.ta, g0.tb, g0.M, g0.N, g0.K, g0.alpha, g0.A, g0.lda, g0.B, g0.ldb, g0.beta, g0.C,
+                            g0.ldc, g0.flags);
+    if (e != hipSuccess) return e;
+    return gemm_f64(st, g1.ta, g1.tb, g1.M, g1.N, g1.K, g1.alpha, g1.A, g1.lda, g1.B, g1.ldb, g1.beta, g1.C, g1.ldc,
+                    g1.flags);
+  }
+  const long long tb = t0 + t1;
   if (use_tile64(tb)) {
     if ((mx + 63) / 64 > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL((gemm_f64_pair_kernel<64, 64>), dim3((nx + 63) / 64, (mx + 63) / 64, 2), dim3(256), kLds64,

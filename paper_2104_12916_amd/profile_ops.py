@@ -9,7 +9,11 @@ With --dense N it times the factorization kernels instead (qp_dense_time): the
 n^3 GEMM, the GEMM with a triangular operand and the Cholesky-inverse of size N,
 with their rates (flops of the product, of the Cholesky alone for op 2).
 
-Usage: python -m paper_2104_12916_amd.profile_ops [--workload lowdof] [--reps 10] [--dense N]
+With --shared K it runs the block PCG of K QPs sharing the low-dof instance's H, A
+and C (qp_shared_pcg_solve, P_L, a fixed number of steps: --reps) twice, for a
+kernel trace of the multi-vector MFMA sweeps; it prints each sweep's matrix bytes.
+
+Usage: python -m paper_2104_12916_amd.profile_ops [--workload lowdof] [--reps 10] [--dense N] [--shared K]
 """
 import argparse
 import os
@@ -28,7 +32,29 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--dense", type=int, default=0, help="time the factorization kernels of this size")
+    ap.add_argument("--shared", type=int, default=0, help="block PCG over this many QPs sharing H, A, C")
     args = ap.parse_args()
+
+    if args.shared:
+        import time
+        import numpy as np
+        import synth
+        from paper_2104_12916_amd import qpgpu
+        qp = synth.workload("lowdof", seed=100)
+        n, m1, m2, k = qp.n, qp.m1, qp.m2, args.shared
+        sh = qpgpu.Shared(qp.H, qp.A, qp.C, prec=qpgpu.QP_PREC_LOW_DOF)
+        rng = np.random.default_rng(0)
+        dv, rh = rng.uniform(0.5, 2.0, (k, m2)), rng.standard_normal((k, m2))
+        mm = (n * (n + 1) // 2 + m1 * n) * 8
+        print(f"shared block PCG: k={k}, {args.reps} steps per run; matrix bytes per sweep: C^T {n * m2 * 8}, "
+              f"M {mm}, M^T {mm}, C {m2 * n * 8}", flush=True)
+        for r in range(2):
+            t0 = time.perf_counter()
+            sh.pcg(dv, rh, rtol=1e-300, maxit=args.reps, accept=(qpgpu.QP_OK, qpgpu.QP_E_NOCONV))
+            dt = time.perf_counter() - t0
+            print(f"run {r}: {dt * 1e3:.1f} ms, {dt / args.reps * 1e6:.1f} us per block step", flush=True)
+        sh.close()
+        return
 
     if args.dense:
         from paper_2104_12916_amd import qpgpu
