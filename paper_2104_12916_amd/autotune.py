@@ -30,7 +30,7 @@ SPACE = [
     ("sym_pipe", [0, 1]),
     ("ld_nt", [0, 1, 2, 3]),
     ("upd_threads", [256, 512, 1024]),
-    ("cg_fold", [0, 1]),
+    ("cg_fold", [2, 3]),  # bit 0 (P_L) is tuned; P_H stays folded
 ]
 
 

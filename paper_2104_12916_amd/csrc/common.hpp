@@ -70,11 +70,14 @@ struct Tune {
   int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
                           // 1 us faster per CG step than 1024 at m2 = 2048)
   int mv_rt = 1;         // multi-vector sweeps of the block PCG: rows per thread (1 or 2)
-  int cg_fold = 0;       // 1: single-QP implicit CG step with the vector update folded into the
-                         // operator sweeps (C^T sweep, sum of the one-pass partials, q sweep): one
-                         // launch fewer per step, but the C^T sweep reads z and p and reduces the
-                         // previous step's partials (n = 4096, m2 = 2048: 70.2 vs 68.6 us per step;
-                         // n = 200: 3-4 % faster); 0 keeps the separate update kernel
+  int cg_fold = 2;       // single-QP implicit CG step with the vector update folded into the
+                         // operator sweeps (C^T sweep, sum of the one-pass partials, q sweep, and
+                         // for P_H the sum of the X_P apply's partials): bit 0 for P_L and
+                         // unpreconditioned solves, bit 1 for P_H.  Two launches fewer per P_H
+                         // step (few-eq, n = m2 = 4096: 237.5 against 277 us per step end to end,
+                         // 4.45 against 3.82 solves/s); one fewer per P_L step, where the C^T sweep
+                         // also reduces the previous step's partials (low-dof n = 4096: 70.2 against
+                         // 68.6 us; n = 200: 3-4 % faster)
   int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
                         // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
                         // more than the 256 MB last-level cache holds; loading M plainly and C, C^T

@@ -222,7 +222,7 @@ inline bool ph_fused(const qp_ctx* ctx) { return tune().k0_sym && ctx->m2 <= k0_
 // (pcg.hpp, FoldParts): single-QP implicit step over the stored C^T with the
 // one-pass K0 product, and for P_H the one-pass X_P apply.
 inline bool cg_folded(const qp_ctx* ctx, int prec) {
-  return tune().cg_fold && ctx->fold && tune().op_t && tune().k0_sym && !ctx->master &&
+  return (tune().cg_fold & (prec == kPrecH ? 2 : 1)) && ctx->fold && tune().op_t && tune().k0_sym && !ctx->master &&
          ctx->opt.kf_form == QP_KF_IMPLICIT && ctx->n <= k0_sym_max_n<double>() && !ctx->c_identity &&
          (prec != kPrecH || ctx->m2 <= k0_sym_max_n<double>());
 }

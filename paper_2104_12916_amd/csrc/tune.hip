@@ -61,7 +61,7 @@ bool parse_keys(const std::string& spec, Tune& t, bool alloc) {
     else if (k == "ld_nt") ok = v >= 0 && v <= 3, t.ld_nt = v;
     else if (k == "upd_threads") ok = v == 256 || v == 512 || v == 1024, t.upd_threads = v;
     else if (k == "mv_rt") ok = v == 1 || v == 2, t.mv_rt = v;
-    else if (k == "cg_fold") ok = v == 0 || v == 1, t.cg_fold = v;
+    else if (k == "cg_fold") ok = v >= 0 && v <= 3, t.cg_fold = v;
     else if (alloc && k == "ld_pad") ok = v >= 0 && v <= 1024 && v % 64 == 0, t.ld_pad = v;
     else if (alloc && k == "op_t") ok = v == 0 || v == 1, t.op_t = v;
     else if (alloc && k == "k0_sym") ok = v == 0 || v == 1, t.k0_sym = v;
