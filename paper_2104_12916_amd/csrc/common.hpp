@@ -62,8 +62,11 @@ struct Tune {
                         // (0: column sweeps with per-chunk partials, no extra memory)
   int k0_sym = 1;       // one pass over M for M^T Sigma M u (n small enough for register rows)
   int sym_wg = 2;       // one-pass sweep: workgroups per CU (each writes one partial of w)
+  int bsym_units = 16;  // batched one-pass sweep: row units per workgroup (buffer layout: the
+                        // pooled partials are sized with it when a QP is admitted)
   int sym_units = 8;    // one-pass sweep: at least this many row units (about n entries
-                        // each) per workgroup, so the partials stay small against M
+                        // each) per workgroup, so the partials stay small against M (but at
+                        // least one workgroup per CU while there are units for it)
   int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
   int sym_pipe = 0;     // one-pass sweep: 1 issues the next 2 rows' loads before the current rows'
                         // reduction (rounds of 2 rows; sym_rows is then ignored)

@@ -817,10 +817,13 @@ int k0_sym_max_n() {
 
 template <typename T>
 int k0_sym_grid(int N, int n) {
+  // at least sym_units row units per workgroup, but never fewer workgroups than
+  // CUs while there are units for them (small problems are latency-bound)
   const int U = (n + 1) / 2 + (N - n);
-  const int cap = dev_info().cu_count * tune().sym_wg;
+  const int cus = dev_info().cu_count;
+  const int cap = cus * tune().sym_wg;
   const int su = tune().sym_units;
-  return std::max(1, std::min((U + su - 1) / su, cap));
+  return std::max(1, std::min(std::max((U + su - 1) / su, std::min(U, cus)), cap));
 }
 
 size_t k0_sym_part_elems(int n) { return (size_t)dev_info().cu_count * kMaxSymWg * k0_sym_ldp(n); }
@@ -867,14 +870,13 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
   return hipGetLastError();
 }
 
-// Batched forms: each QP gets about one workgroup per kSymUnitsPerWg row units
-// (many QPs share the launch), which keeps its partials near 1/16 of M.
-constexpr int kSymUnitsPerWg = 16;
-
+// Batched forms: each QP gets about one workgroup per bsym_units row units (many
+// QPs share the launch), which keeps its partials near 1/bsym_units of M.
 template <typename T>
 int bk0_sym_grid(int N, int n) {
   const int U = (n + 1) / 2 + (N - n);
-  return std::max(1, (U + kSymUnitsPerWg - 1) / kSymUnitsPerWg);
+  const int su = tune().bsym_units;
+  return std::max(1, (U + su - 1) / su);
 }
 
 template <typename T>
