@@ -25,58 +25,90 @@ namespace qpg {
 
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
-// Tile product on the FP64 matrix cores: a workgroup owns 64 rows (16 per wave)
-// and a slice of KS = 256 columns, and forms the 64 x 16 NB block of
-// A[rows, slice] X[slice, v] with v_mfma_f64_16x16x4 (lane l supplies
-// A[l % 16][k] and X[k][l % 16] of its step, register r of the result holds
-// row 4 r + l / 16, vector l % 16).  The slice is summed in a permuted order:
-// at step t lane quarter q = l / 16 takes column 8 (t / 2) + 2 q + t % 2, so one
-// 16-byte load gives a lane its columns of two steps and the four quarters of a
-// row read 64 adjacent bytes per instruction (16 half-lines per load instead of
+// Tile product on the FP64 matrix cores: a workgroup owns kMvRows = 64 rows (16 per
+// wave) and a slice of KS = 256 columns, and forms the 64 x 16 NB block of
+// A[rows, slice] X[slice, v] with v_mfma_f64_16x16x4 (lane l
+// supplies A[l % 16][k] and X[k][l % 16] of its step, register r of the result
+// holds row 4 r + l / 16, vector l % 16).  The slice is summed in a permuted
+// order: at step t lane quarter q = l / 16 takes column 8 (t / 2) + 2 q + t % 2, so
+// one 16-byte load gives a lane its columns of two steps and the four quarters of
+// a row read 64 adjacent bytes per instruction (16 half-lines per load instead of
 // 64 scattered pieces); loads are issued a batch ahead of the matrix
 // instructions.  The vectors are staged in LDS already in step order
-// (Bs[t][lane]: one contiguous 512-byte read per step, no bank conflicts).
+// (Bs[t][lane]: one contiguous 512-byte read per step, no bank conflicts), with
+// 16-byte loads of column pairs (k = 16 on a dense 4096 x 4096 sweep: 34.6 against
+// 36.2 us with 8-byte loads).  128 rows per workgroup (two MFMA blocks per
+// wavefront) win on that square sweep (32.3 us) but lose on the solver's shapes,
+// whose few row tiles then leave CUs without a second workgroup (M: 61 against
+// 54 us).
 constexpr int kMvKS = 256;                // columns per slice
 constexpr int kMvQ = kMvKS / 4;           // steps per slice (columns per lane quarter)
-constexpr int kMvBatch = 8;               // 16-byte loads per lane in flight (16 steps)
+constexpr int kMvBatch = 8;               // 16-byte loads per lane and row block in flight (16 steps)
+constexpr int kMvRows = 64;               // rows per workgroup
+constexpr int kMvRB = kMvRows / 64;       // 16-row MFMA blocks per wavefront
 
 template <int NB>
 __global__ void __launch_bounds__(256) mv_mfma_kernel(const double* __restrict__ A, int lda, int rows, int K,
                                                       int shape, const double* __restrict__ X, int ldx, int nv,
-                                                      double* __restrict__ part, int ldp) {
+                                                      int vx, double* __restrict__ part, int ldp) {
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const int r0 = blockIdx.x * 64, s = blockIdx.y;
+  const int r0 = blockIdx.x * kMvRows, s = blockIdx.y;
   const int c0 = s * kMvKS, c1 = min(K, c0 + kMvKS);
-  const int rlast = min(rows, r0 + 64) - 1;
+  const int rlast = min(rows, r0 + kMvRows) - 1;
   const bool empty = (shape == kLower && c0 > rlast) || (shape == kUpper && c1 <= r0);
   __shared__ __align__(16) double Bs[NB][kMvQ][kWave];
-  v4d_t acc[NB];
+  v4d_t acc[kMvRB][NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = v4d_t{0.0, 0.0, 0.0, 0.0};
-  const int row = r0 + wave * 16 + lane % 16;  // the row this lane supplies
+  for (int rb = 0; rb < kMvRB; ++rb)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[rb][b] = v4d_t{0.0, 0.0, 0.0, 0.0};
   const int q = lane / 16;
   if (!empty) {
-    // stage X[slice, v] in step order: slice column c = 8 u + 2 q + h is step t = 2 u + h of quarter q
-    for (int e = tid; e < NB * 16 * kMvKS; e += 256) {
-      const int c = e % kMvKS, vv = e / kMvKS;  // column of the slice (fastest: coalesced reads), vector
-      const int b = vv / 16, v = vv % 16, col = c0 + c;
-      const int t = 2 * (c / 8) + (c % 2), qq = (c % 8) / 2;
-      Bs[b][t][qq * 16 + v] = (vv < nv && col < c1) ? X[(size_t)vv * ldx + col] : 0.0;
-    }
-    const int len = shape == kLower ? min(row + 1, K) : K;
-    const int cend = min(len, c1);  // columns of this lane's row inside the slice
-    const double* arow = A + (size_t)min(row, rows - 1) * lda;
-    auto load_batch = [&](int t0, v2d_t* a) {
-#pragma unroll
-      for (int u = 0; u < kMvBatch; ++u) {
-        const int col = c0 + 8 * (t0 / 2 + u) + 2 * q;  // steps t0 + 2 u and t0 + 2 u + 1
-        if (row < rows && col < cend)
-          a[u] = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(arow + col));
-        else
-          a[u] = v2d_t{0.0, 0.0};
+    // stage X[slice, v] in step order: slice column c = 8 u + 2 q + h is step t = 2 u + h of quarter q;
+    // columns c, c + 1 (one 16-byte load) are steps t, t + 1 of the same quarter
+    if (vx) {
+      for (int e = tid; e < NB * 16 * kMvKS / 2; e += 256) {
+        const int cp = e % (kMvKS / 2), vv = e / (kMvKS / 2);
+        const int b = vv / 16, v = vv % 16, c = 2 * cp, col = c0 + c;
+        const int t = 2 * (c / 8), qq = (c % 8) / 2;
+        v2d_t x = v2d_t{0.0, 0.0};
+        if (vv < nv) {
+          if (col + 1 < c1) x = *reinterpret_cast<const v2d_t*>(X + (size_t)vv * ldx + col);
+          else if (col < c1) x.x = X[(size_t)vv * ldx + col];
+        }
+        Bs[b][t][qq * 16 + v] = x.x;
+        Bs[b][t + 1][qq * 16 + v] = x.y;
       }
+    } else {
+      for (int e = tid; e < NB * 16 * kMvKS; e += 256) {
+        const int c = e % kMvKS, vv = e / kMvKS;  // column of the slice (fastest: coalesced reads), vector
+        const int b = vv / 16, v = vv % 16, col = c0 + c;
+        const int t = 2 * (c / 8) + (c % 2), qq = (c % 8) / 2;
+        Bs[b][t][qq * 16 + v] = (vv < nv && col < c1) ? X[(size_t)vv * ldx + col] : 0.0;
+      }
+    }
+    int row[kMvRB], cend[kMvRB];
+    const double* arow[kMvRB];
+#pragma unroll
+    for (int rb = 0; rb < kMvRB; ++rb) {
+      row[rb] = r0 + wave * 16 * kMvRB + rb * 16 + lane % 16;  // the rows this lane supplies
+      const int len = shape == kLower ? min(row[rb] + 1, K) : K;
+      cend[rb] = min(len, c1);  // columns of the row inside the slice
+      arow[rb] = A + (size_t)min(row[rb], rows - 1) * lda;
+    }
+    auto load_batch = [&](int t0, v2d_t (*a)[kMvBatch]) {
+#pragma unroll
+      for (int rb = 0; rb < kMvRB; ++rb)
+#pragma unroll
+        for (int u = 0; u < kMvBatch; ++u) {
+          const int col = c0 + 8 * (t0 / 2 + u) + 2 * q;  // steps t0 + 2 u and t0 + 2 u + 1
+          if (row[rb] < rows && col < cend[rb])
+            a[rb][u] = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(arow[rb] + col));
+          else
+            a[rb][u] = v2d_t{0.0, 0.0};
+        }
     };
-    v2d_t cur[kMvBatch], nxt[kMvBatch];
+    v2d_t cur[kMvRB][kMvBatch], nxt[kMvRB][kMvBatch];
     load_batch(0, cur);
     __syncthreads();
 #pragma unroll 1
@@ -87,26 +119,34 @@ __global__ void __launch_bounds__(256) mv_mfma_kernel(const double* __restrict__
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int t = t0 + 2 * u + h;
-          const double a = h ? cur[u].y : cur[u].x;
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
-            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[b][t][lane], acc[b], 0, 0, 0);
+          for (int b = 0; b < NB; ++b) {
+            const double bx = Bs[b][t][lane];
+#pragma unroll
+            for (int rb = 0; rb < kMvRB; ++rb)
+              acc[rb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(h ? cur[rb][u].y : cur[rb][u].x, bx, acc[rb][b], 0,
+                                                                0, 0);
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < kMvBatch; ++u) cur[u] = nxt[u];
+      for (int rb = 0; rb < kMvRB; ++rb)
+#pragma unroll
+        for (int u = 0; u < kMvBatch; ++u) cur[rb][u] = nxt[rb][u];
     }
   }
-  // register r of lane l: row r0 + 16 wave + 4 r + l / 16, vector 16 b + l % 16
+  // register r of lane l of block rb: row r0 + 32 wave + 16 rb + 4 r + l / 16, vector 16 b + l % 16
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int v = 16 * b + lane % 16;
+  for (int rb = 0; rb < kMvRB; ++rb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = r0 + wave * 16 + 4 * r + lane / 16;
-      if (i < rows && v < nv) part[((size_t)s * nv + v) * ldp + i] = acc[b][r];
+    for (int b = 0; b < NB; ++b) {
+      const int v = 16 * b + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + wave * 16 * kMvRB + rb * 16 + 4 * r + lane / 16;
+        if (i < rows && v < nv) part[((size_t)s * nv + v) * ldp + i] = acc[rb][b][r];
+      }
     }
-  }
 }
 
 // Y_v[i] = (i >= nsplit ? -alpha : alpha) * sum over slices of part (slice order).
@@ -124,8 +164,10 @@ __global__ void __launch_bounds__(256) mv_reduce_kernel(const double* __restrict
 template <int NB>
 static void launch_mfma(hipStream_t st, const double* A, int lda, int rows, int K, int shape, const double* X,
                         int ldx, int nv, double* part, int ldp) {
-  const dim3 grid((rows + 63) / 64, (K + kMvKS - 1) / kMvKS);
-  hipLaunchKernelGGL((mv_mfma_kernel<NB>), grid, dim3(256), 0, st, A, lda, rows, K, shape, X, ldx, nv, part, ldp);
+  const dim3 grid((rows + kMvRows - 1) / kMvRows, (K + kMvKS - 1) / kMvKS);
+  const int vx = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && ldx % 2 == 0;  // 16-byte staging loads
+  hipLaunchKernelGGL((mv_mfma_kernel<NB>), grid, dim3(256), 0, st, A, lda, rows, K, shape, X, ldx, nv, vx, part,
+                     ldp);
 }
 
 size_t mv_part_elems(int rows, int K, int nv) {
