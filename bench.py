@@ -66,9 +66,15 @@ OP_NAMES = ["gemv_rows_kernel<T,1> (C^T p over stored C^T)", "gemv_rows_kernel<T
             "gemv_rows_kernel<T,4> (X_P r)", "gemv_cols_part_kernel<T,5> (X_P^T t)"]
 # with the one-pass K0 product, slots 1 and 2 hold its sweep and the sum of its partials, and
 # slots 4 and 5 the one-pass P_H apply X_P^T X_P r (m2 <= 4096) and the sum of its partials
-OP_NAMES_ONE_PASS = OP_NAMES[:1] + ["k0_sym_kernel<T> (M^T Sigma M u, one pass over M)",
-                                    "k0_sym_reduce_kernel<T> (sum of the per-workgroup partials of w)"] + OP_NAMES[3:4] + [
-    "k0_sym_kernel<T> over X_P (X_P^T X_P r, one pass)", "k0_sym_reduce_kernel<T> (sum of the partials of z)"]
+# (in the folded CG step, the default for P_H and for the n <= 4096 size bucket, slot 0 is
+# fold_ct_kernel, slot 2 k0_sym_reduce_fold_kernel, slot 3 fold_q_kernel and slot 5
+# ph_reduce_fold_kernel: the same matrices with the vector update folded in)
+OP_NAMES_ONE_PASS = ["gemv_rows_kernel<T,1> / fold_ct_kernel<T> (C^T p over stored C^T)",
+                     "k0_sym_kernel<T> (M^T Sigma M u, one pass over M)",
+                     "k0_sym_reduce[_fold]_kernel<T> (sum of the per-workgroup partials of w)",
+                     "pcg_q_kernel<T> / fold_q_kernel<T> (C w + D p)",
+                     "k0_sym_kernel<T> over X_P (X_P^T X_P r, one pass)",
+                     "k0_sym_reduce_kernel<T> / ph_reduce_fold_kernel<T> (sum of the partials of z)"]
 ONE_PASS_MAX = 4096  # widest operand of the float64 one-pass sweep
 
 
@@ -580,6 +586,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--kf", default="implicit", choices=["implicit", "explicit"],
                     help="how each CG step applies K_F (explicit: operator formed once per QP)")
+    ap.add_argument("--poll", type=int, default=0,
+                    help="CG steps between host polls (options.poll_every; 0: the library's adaptive chunks)")
     ap.add_argument("--cg-graph", type=int, default=0, choices=[0, 1],
                     help="1: replay each poll chunk of CG steps as a captured hipGraph (single-QP workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -628,7 +636,7 @@ def main():
         qp = synth.workload(args.workload, seed=sd)
         qps.append(qp)
         solvers.append(qpgpu.Solver(*qp.arrays(), prec=prec, precision=precision, profile=0 if args.cg_graph else 1,
-                                    kf_form=kf, cg_graph=args.cg_graph))
+                                    kf_form=kf, cg_graph=args.cg_graph, poll_every=args.poll))
     torch.cuda.synchronize()
 
     factor_s = []
@@ -765,7 +773,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if precision == qpgpu.QP_MIXED else "f64",
         "data": "synthetic (seeded dense Gaussian QPs resident in HBM)",
         "config": {"workload": f"{args.workload}: {w['desc']}", "seeds": seeds, "precond": prec_name,
-                   "precision": args.precision, "kf_form": args.kf, "cg_graph": args.cg_graph},
+                   "precision": args.precision, "kf_form": args.kf, "cg_graph": args.cg_graph, "poll": args.poll},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": dict(passed=ok, solves=len(outs), max_rel_kkt=worst_kkt, max_obj_rel_err=worst_obj),

@@ -98,7 +98,11 @@ typedef struct {
   double tau;       /* fraction of the step to the boundary (0.995)              */
   int max_ipm;      /* IPM iteration limit (200)                                 */
   int max_pcg;      /* CG iterations per reduced solve in the IPM; 0: 20 * m2     */
-  int poll_every;   /* CG steps launched between host polls of the stop flag (32) */
+  int poll_every;   /* CG steps launched between host polls of the stop flag;
+                       0 (default): single-QP solves size each chunk, up to
+                       the previous solve's step count on the context, then an
+                       eighth of the steps taken (8..512 steps), and batches,
+                       shared-matrix solves and captured graphs use 32         */
   qp_precond prec;  /* preconditioner used by qp_ipm_solve (QP_PREC_AUTO)        */
   qp_precision precision; /* QP_FP64                                              */
   int verbose;      /* 1: one line per IPM iteration on stderr                    */
@@ -107,7 +111,8 @@ typedef struct {
   qp_kf_form kf_form; /* how the CG step applies K_F (QP_KF_IMPLICIT)            */
   qp_ph_form ph_form; /* which H the few-equalities preconditioner uses (EXACT)   */
   int cg_graph;     /* 1: a single-QP solve captures its chunk of poll_every CG
-                       steps once as a hipGraph and replays it for every chunk
+                       steps (32 when poll_every is 0) once as a hipGraph and
+                       replays it for every chunk
                        (same kernels and arguments; no profile samples); 0: the
                        steps are launched one by one (0)                        */
 } qp_options;

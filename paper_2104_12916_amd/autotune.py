@@ -26,6 +26,7 @@ SPACE = [
     ("rows_unroll", [4, 8, 16]),
     ("sym_wg", [1, 2, 3, 4]),
     ("sym_units", [1, 4, 8, 16]),
+    ("sym_teams", [1, 2]),
     ("sym_rows", [2, 4]),
     ("sym_pipe", [0, 1]),
     ("ld_nt", [0, 1, 2, 3]),

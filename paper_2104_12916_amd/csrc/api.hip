@@ -814,7 +814,18 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
     HIPCHK(ctx, pcg_ph_update<T>(st, m2, B.r, B.z, B.p, init, ctx->sc));
   };
   if (prec == kPrecH) ph_apply(1, nullptr);
+  // Steps launched between host polls.  poll_every > 0 fixes the chunk.  With 0
+  // the previous solve's step count on this context is the prediction
+  // (consecutive reduced solves of an IPM take similar counts): chunks run up to
+  // it, then grow by an eighth of the steps taken (8 .. 512 steps each), so few
+  // steps are launched past the stop and a long solve pays few host round trips.
+  // A captured graph replays a fixed chunk of 32.
+  const bool adapt = ctx->opt.poll_every <= 0 && !ctx->opt.cg_graph;
   const int poll = ctx->opt.poll_every > 0 ? ctx->opt.poll_every : 32;
+  constexpr int kChunkMax = 512;
+  const int pred = ctx->last_cg;
+  int cn = poll;
+  if (adapt && pred > 0) cn = std::min(kChunkMax, std::max(4, pred));
   const bool fold = !expl && cg_folded(ctx, prec);
   const FoldParts fp = fold ? fold_parts<T>(ctx, prec) : FoldParts{};
   PcgResult res;
@@ -830,18 +841,18 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
   int iter_before = 0;
   for (;;) {
     // the device stops at maxit; a host bound guards against a stop flag that never arrives
-    if (launched > (long long)maxit + 2LL * poll) {
+    if (launched > (long long)maxit + 2LL * std::max(poll, kChunkMax)) {
       set_err(ctx, "PCG made no progress after %lld launched steps", launched);
       throw Fail{QP_E_DEVICE};
     }
-    launched += poll;
+    launched += cn;
     auto chunk = [&](bool sampled) {
       if (fold) {
-        for (int k = 0; k < poll; ++k) fold_step<T>(ctx, B, prec, fp, (sampled && k == 0) ? ctx->prof_ev : nullptr);
+        for (int k = 0; k < cn; ++k) fold_step<T>(ctx, B, prec, fp, (sampled && k == 0) ? ctx->prof_ev : nullptr);
         HIPCHK(ctx, fold_test(st, ctx->sc, fp));
         return;
       }
-      for (int k = 0; k < poll; ++k) {
+      for (int k = 0; k < cn; ++k) {
         const EventPair* ev = (sampled && k == 0) ? ctx->prof_ev : nullptr;
         if (expl) {
           // q = E p + D p: one row sweep over the explicit operator
@@ -880,9 +891,11 @@ static PcgResult run_pcg(qp_ctx* ctx, const PcgBufs<T>& B, const T* rhs, int pre
     }
     iter_before = ctx->h_sc->iter;
     if (ctx->h_sc->done) break;
+    if (adapt) cn = std::min(kChunkMax, std::max(8, std::max(iter_before / 8, pred - iter_before)));
   }
   res.iters = ctx->h_sc->iter;
   res.done = ctx->h_sc->done;
+  ctx->last_cg = res.iters;
   return res;
 }
 
@@ -1179,7 +1192,7 @@ void qp_default_options(qp_options* opt) {
   opt->tau = 0.995;
   opt->max_ipm = 200;
   opt->max_pcg = 0;
-  opt->poll_every = 32;
+  opt->poll_every = 0;
   opt->prec = QP_PREC_AUTO;
   opt->precision = QP_FP64;
   opt->verbose = 0;

@@ -67,20 +67,28 @@ struct Tune {
   int sym_units = 8;    // one-pass sweep: at least this many row units (about n entries
                         // each) per workgroup, so the partials stay small against M (but at
                         // least one workgroup per CU while there are units for it)
+  int sym_teams = 2;    // one-pass sweep: teams of 256 threads per workgroup (1 or 2), each
+                        // with its own rows and partial; a workgroup writes one partial of w
+                        // (fewer partials to write and sum; used when every CU still gets a
+                        // workgroup, never in the pipelined form)
   int sym_rows = 4;     // one-pass sweep: rows per block reduction (2 or 4)
   int sym_pipe = 0;     // one-pass sweep: 1 issues the next 2 rows' loads before the current rows'
                         // reduction (rounds of 2 rows; sym_rows is then ignored)
   int upd_threads = 512;  // threads of the single-workgroup PCG update (256, 512 or 1024; 512 measured
                           // 1 us faster per CG step than 1024 at m2 = 2048)
   int mv_rt = 1;         // multi-vector sweeps of the block PCG: rows per thread (1 or 2)
-  int cg_fold = 2;       // single-QP implicit CG step with the vector update folded into the
+  int cg_fold = 6;       // single-QP implicit CG step with the vector update folded into the
                          // operator sweeps (C^T sweep, sum of the one-pass partials, q sweep, and
                          // for P_H the sum of the X_P apply's partials): bit 0 for P_L and
                          // unpreconditioned solves, bit 1 for P_H.  Two launches fewer per P_H
-                         // step (few-eq, n = m2 = 4096: 237.5 against 277 us per step end to end,
-                         // 4.45 against 3.82 solves/s); one fewer per P_L step, where the C^T sweep
-                         // also reduces the previous step's partials (low-dof n = 4096: 70.2 against
-                         // 68.6 us; n = 200: 3-4 % faster)
+                         // step, one per P_L step, where the C^T sweep also reduces the previous
+                         // step's partials.  Bit 2: the folded C^T sweep takes C^T p_old from the
+                         // previous step's u instead of a second dot per row.  Measured whole
+                         // solves: few-eq (P_H) 4.86 solves/s with bits 1 and 2, 4.79 with bit 1,
+                         // 4.53 unfolded; low-dof (P_L, n = 4096) 67.2 us per CG step with bits 0
+                         // and 2 (set in that size bucket of the autotune cache), 68.7 with bit 0,
+                         // 69.9 unfolded; small P_L (n = 200) is faster unfolded (23.9 against 22.8
+                         // solves/s)
   int ld_nt = 1;        // non-temporal matrix loads: bit 0 single-problem row sweeps (and q = C w + D p),
                         // bit 1 the one-pass sweep; a clear bit uses plain loads.  A CG step streams
                         // more than the 256 MB last-level cache holds; loading M plainly and C, C^T

@@ -140,6 +140,7 @@ struct qp_ctx {
   double prof_ms[qpg::kProfOps] = {};
   long long prof_n[qpg::kProfOps] = {};
   bool prof_ready = false;
+  int last_cg = 0;  // CG steps of the last reduced solve (sizes the next solve's first poll chunk)
   // captured poll chunks of CG steps (options.cg_graph)
   std::vector<std::pair<qpg::CgGraphKey, hipGraphExec_t>> cg_graphs;
   // pinned host mirrors

@@ -432,9 +432,13 @@ hipError_t launch_bgemv_cols(hipStream_t st, const ColsDesc<T>* ddesc, const int
 //
 // Rows are dealt in units of about n entries: a pair (i, n-1-i) of the
 // triangular part or one row of the rectangular part; workgroup g takes units
-// [g U / G, (g+1) U / G).  The BT threads of a workgroup span the columns
-// (thread t owns columns c*BT*VE + t*VE .. + VE-1 of every row), so u and the
-// partial stay in registers, and R rows share one block reduction.
+// [g U / G, (g+1) U / G).  A team of BT threads spans the columns (thread t
+// owns columns c*BT*VE + t*VE .. + VE-1 of every row), so u and the partial stay
+// in registers, and R rows share one block reduction.  A workgroup of TM teams
+// deals its rows to them in turn, R at a time, and adds the teams' partials in
+// team order through LDS before writing its one partial: the same number of
+// loads in flight per CU as TM workgroups of one team, with 1/TM of the partials
+// to write and to sum.
 
 // Row of local ordinal q in a workgroup's unit range [u0, u1): np pairs first,
 // then the middle row of an odd n and the rectangular rows.
@@ -448,8 +452,8 @@ __device__ __forceinline__ int sym_row(int q, int u0, int np, int us, int n) {
   return uu < tri ? uu : n + (uu - tri);
 }
 
-// Workgroup g of G of one product.
-template <typename T, int BT, int K, int R, bool NT>
+// Workgroup g of G of one product (TM teams of BT threads).
+template <typename T, int BT, int K, int R, bool NT, int TM = 1>
 __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, int N, int n, const T* __restrict__ u,
                                             T* __restrict__ part, int ldp, int G, int g,
                                             const int* __restrict__ skip) {
@@ -458,7 +462,8 @@ __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, in
   constexpr int VE = Vec16<T>::n;
   constexpr int CHB = BT * VE;
   constexpr int NW = BT / kWave;
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int team = TM > 1 ? (int)threadIdx.x / BT : 0;  // uniform per wavefront
+  const int tid = (int)threadIdx.x % BT, wave = tid / kWave, lane = tid % kWave;
   const int P = n / 2, U = (n + 1) / 2 + (N - n);
   const int u0 = (int)((long long)g * U / G), u1 = (int)((long long)(g + 1) * U / G);
   const int np = max(0, min(u1, P) - u0);
@@ -474,9 +479,10 @@ __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, in
       acc[c][e] = T(0);
     }
   }
-  __shared__ T sh[2][R][NW];
+  __shared__ T sh[2][TM][R][NW];
   int buf = 0;
-  for (int q0 = 0; q0 < nrows; q0 += R) {
+  for (int qt = 0; qt < nrows; qt += TM * R) {  // the same trip count in every team
+    const int q0 = qt + team * R;
     V a[R][K];
     int rowi[R];
 #pragma unroll
@@ -511,14 +517,14 @@ __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, in
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const T s = wave_sum<T>(d[r]);
-      if (lane == 0) sh[buf][r][wave] = s;
+      if (lane == 0) sh[buf][team][r][wave] = s;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      T v = sh[buf][r][0];
+      T v = sh[buf][team][r][0];
 #pragma unroll
-      for (int w2 = 1; w2 < NW; ++w2) v += sh[buf][r][w2];
+      for (int w2 = 1; w2 < NW; ++w2) v += sh[buf][team][r][w2];
       if (rowi[r] >= n) v = -v;
 #pragma unroll
       for (int c = 0; c < K; ++c) {
@@ -527,6 +533,24 @@ __device__ __forceinline__ void k0_sym_body(const T* __restrict__ M, int ldm, in
       }
     }
     buf ^= 1;  // the next round writes the other buffer: one barrier per round suffices
+  }
+  if constexpr (TM > 1) {
+    // teams 1 .. TM-1 hand their partials to team 0, which adds them in team order
+    __shared__ T tp[TM - 1][K][VE][BT];
+    if (team > 0) {
+#pragma unroll
+      for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int e = 0; e < VE; ++e) tp[team - 1][c][e][tid] = acc[c][e];
+    }
+    __syncthreads();
+    if (team > 0) return;
+#pragma unroll
+    for (int t2 = 0; t2 < TM - 1; ++t2)
+#pragma unroll
+      for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[c][e] += tp[t2][c][e][tid];
   }
   T* pg = part + (size_t)g * ldp;
 #pragma unroll
@@ -654,14 +678,14 @@ __device__ __forceinline__ void k0_sym_body_pipe(const T* __restrict__ M, int ld
 
 // w_j = sum over g of part[g][j]: 16 columns per workgroup, 16 lanes per column
 // take g = t, t + 16, ... with four loads in flight, then a fixed butterfly.
-template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
-__global__ void __launch_bounds__(BT) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
-                                                    const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
-                                                    const int* __restrict__ skip) {
+template <typename T, int BT, int K, int R, bool NT, bool PIPE = false, int TM = 1>
+__global__ void __launch_bounds__(BT * TM) k0_sym_kernel(const T* __restrict__ M, int ldm, int N, int n,
+                                                         const T* __restrict__ u, T* __restrict__ part, int ldp,
+                                                         int G, const int* __restrict__ skip) {
   if constexpr (PIPE)
     k0_sym_body_pipe<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
   else
-    k0_sym_body<T, BT, K, R, NT>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
+    k0_sym_body<T, BT, K, R, NT, TM>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
 }
 
 template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
@@ -756,20 +780,36 @@ __global__ void __launch_bounds__(256) k0_sym_reduce_fold_kernel(const T* __rest
                                                                  double* __restrict__ al) {
   __shared__ double sh[16];
   if (sc->done) return;
-  typename Pair2<T>::type t;
-  k0_sym_reduce_body<T>(part, ldp, G, n, w, nullptr, blockIdx.x, &t);
-  double s = 0;
-  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
-  if (threadIdx.x < kRedCols / 2 && col < n) {
-    s = (double)u[col] * t.x;
-    if (col + 1 < n) s += (double)u[col + 1] * t.y;
-  }
+  // the vector entries this workgroup's two dot products need are loaded before
+  // the partial sums, so their latency hides behind the partials' (loads at
+  // indices clamped into the vectors, n, m2 >= 1, masked afterwards: a load under
+  // a branch is waited for at the branch's end)
   const T bt = (T)sc->beta;
+  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
+  const bool own = threadIdx.x < kRedCols / 2 && col < n;
+  const T ua = u[min(col, n - 1)], ub = u[min(col + 1, n - 1)];
+  const T u0 = own ? ua : T(0), u1 = (own && col + 1 < n) ? ub : T(0);
   const int share = (m2 + gridDim.x - 1) / gridDim.x;
-  const int j1 = min(m2, (int)(blockIdx.x + 1) * share);
-  for (int j = blockIdx.x * share + threadIdx.x; j < j1; j += blockDim.x) {
-    const T pj = z[j] + bt * p[j];
-    s += (double)dvec[j] * pj * pj;
+  const int j0 = blockIdx.x * share + threadIdx.x, j1 = min(m2, (int)(blockIdx.x + 1) * share);
+  double s = 0;
+  if (share <= (int)blockDim.x) {  // one entry per thread at most: its loads go first
+    const int jc = min(j0, m2 - 1);
+    const T zj = z[jc], pj0 = p[jc], dj = dvec[jc];
+    typename Pair2<T>::type t;
+    k0_sym_reduce_body<T>(part, ldp, G, n, w, nullptr, blockIdx.x, &t);
+    if (own) s = (double)u0 * t.x + (double)u1 * t.y;
+    if (j0 < j1) {
+      const T pj = zj + bt * pj0;
+      s += (double)dj * pj * pj;
+    }
+  } else {
+    typename Pair2<T>::type t;
+    k0_sym_reduce_body<T>(part, ldp, G, n, w, nullptr, blockIdx.x, &t);
+    if (own) s = (double)u0 * t.x + (double)u1 * t.y;
+    for (int j = j0; j < j1; j += blockDim.x) {
+      const T pj = z[j] + bt * p[j];
+      s += (double)dvec[j] * pj * pj;
+    }
   }
   s = block_sum<double>(s, sh);
   if (threadIdx.x == 0) al[blockIdx.x] = s;
@@ -781,13 +821,16 @@ __global__ void __launch_bounds__(256) ph_reduce_fold_kernel(const T* __restrict
                                                              const T* __restrict__ r, double* __restrict__ rz) {
   __shared__ double sh[16];
   if (sc->done) return;
+  // r is loaded before the partial sums
+  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
+  const bool own = threadIdx.x < kRedCols / 2 && col < m2;
+  const T r0 = r[min(col, m2 - 1)], r1 = r[min(col + 1, m2 - 1)];  // clamped, used only where own
   typename Pair2<T>::type t;
   k0_sym_reduce_body<T>(part, ldp, G, m2, z, nullptr, blockIdx.x, &t);
   double s = 0;
-  const int col = blockIdx.x * kRedCols + 2 * (int)threadIdx.x;
-  if (threadIdx.x < kRedCols / 2 && col < m2) {
-    s = (double)r[col] * t.x;
-    if (col + 1 < m2) s += (double)r[col + 1] * t.y;
+  if (own) {
+    s = (double)r0 * t.x;
+    if (col + 1 < m2) s += (double)r1 * t.y;
   }
   s = block_sum<double>(s, sh);
   if (threadIdx.x == 0) rz[blockIdx.x] = s;
@@ -815,28 +858,41 @@ int k0_sym_max_n() {
   return 8 * kSymBT * Vec16<T>::n;
 }
 
+// Teams of the one-pass sweep's workgroups and their number.  Teams are counted
+// as workgroups were: at least sym_units row units per team, but never fewer
+// teams than CUs while there are units for them (small problems are
+// latency-bound), at most sym_wg per CU.  They are grouped sym_teams to a
+// workgroup when that still leaves every CU a workgroup (not in the pipelined form).
 template <typename T>
-int k0_sym_grid(int N, int n) {
-  // at least sym_units row units per workgroup, but never fewer workgroups than
-  // CUs while there are units for them (small problems are latency-bound)
+static void k0_sym_shape(int N, int n, int& G, int& TM) {
   const int U = (n + 1) / 2 + (N - n);
   const int cus = dev_info().cu_count;
   const int cap = cus * tune().sym_wg;
   const int su = tune().sym_units;
-  return std::max(1, std::min(std::max((U + su - 1) / su, std::min(U, cus)), cap));
+  const int teams = std::max(1, std::min(std::max((U + su - 1) / su, std::min(U, cus)), cap));
+  TM = tune().sym_pipe ? 1 : tune().sym_teams;
+  if (TM > 1 && teams < cus * TM) TM = 1;
+  G = (teams + TM - 1) / TM;
+}
+
+template <typename T>
+int k0_sym_grid(int N, int n) {
+  int G, TM;
+  k0_sym_shape<T>(N, n, G, TM);
+  return G;
 }
 
 size_t k0_sym_part_elems(int n) { return (size_t)dev_info().cu_count * kMaxSymWg * k0_sym_ldp(n); }
 
-template <typename T, int BT, int R, bool NT, bool PIPE = false>
+template <typename T, int BT, int R, bool NT, bool PIPE = false, int TM = 1>
 static void launch_sym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const T* M, int ldm, int N, int n,
                          const T* u, T* part, int ldp, int G, const int* skip) {
-  const dim3 blk(BT);
+  const dim3 blk(BT * TM);
   switch (K) {
-    case 1: QPG_LAUNCH((k0_sym_kernel<T, BT, 1, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    case 2: QPG_LAUNCH((k0_sym_kernel<T, BT, 2, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    case 4: QPG_LAUNCH((k0_sym_kernel<T, BT, 4, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
-    default: QPG_LAUNCH((k0_sym_kernel<T, BT, 8, R, NT, PIPE>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    case 1: QPG_LAUNCH((k0_sym_kernel<T, BT, 1, R, NT, PIPE, TM>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 2: QPG_LAUNCH((k0_sym_kernel<T, BT, 2, R, NT, PIPE, TM>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    case 4: QPG_LAUNCH((k0_sym_kernel<T, BT, 4, R, NT, PIPE, TM>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip); break;
+    default: QPG_LAUNCH((k0_sym_kernel<T, BT, 8, R, NT, PIPE, TM>), grid, blk, 0u, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
   }
 }
 
@@ -846,12 +902,26 @@ hipError_t launch_k0_sym_sweep(hipStream_t st, const T* M, int ldm, int N, int n
   constexpr int VE = Vec16<T>::n;
   if (n <= 0) return hipSuccess;
   if (N < n || n > k0_sym_max_n<T>() || ldm < N || ldm % 64 != 0) return hipErrorInvalidValue;
-  const int G = k0_sym_grid<T>(N, n), ldp = k0_sym_ldp(n);
+  int G, TM;
+  k0_sym_shape<T>(N, n, G, TM);
+  const int ldp = k0_sym_ldp(n);
   if ((size_t)G * ldp > part_elems) return hipErrorInvalidValue;
   const int K = k0_sym_width<T>(n);
   const dim3 grid(G);
   const bool nt = tune().ld_nt & 2;
-  if (tune().sym_pipe) {  // pipelined rounds of 2 rows
+  if (TM == 2) {  // two teams per workgroup (rounds of sym_rows rows)
+    if (tune().sym_rows == 2) {
+      if (nt)
+        launch_sym_r<T, kSymBT, 2, true, false, 2>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+      else
+        launch_sym_r<T, kSymBT, 2, false, false, 2>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    } else {
+      if (nt)
+        launch_sym_r<T, kSymBT, 4, true, false, 2>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+      else
+        launch_sym_r<T, kSymBT, 4, false, false, 2>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
+    }
+  } else if (tune().sym_pipe) {  // pipelined rounds of 2 rows
     if (nt)
       launch_sym_r<T, kSymBT, 2, true, true>(K, grid, st, ev, M, ldm, N, n, u, part, ldp, G, skip);
     else

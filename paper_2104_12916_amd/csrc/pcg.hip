@@ -94,7 +94,14 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
   const int lenR = round_chunk<T>(n, ldc);
   if (stage) stage_x<T>(ws, w, n, lenR);  // else w is read through the caches
   double pq = 0;
-  for (int i = bid * waves + wave; i < m2; i += nb * waves) {
+  // p_i and d_i of a row are loaded before its dot (lane 0), so their latency
+  // hides behind the row's
+  // (unconditional loads at a clamped index, m2 >= 1: a load under a branch is
+  // waited for at the branch's end)
+  const int step = nb * waves;
+  int i = bid * waves + wave;
+  T pn = p[min(i, m2 - 1)], dn = dvec[min(i, m2 - 1)];
+  for (; i < m2; i += step) {
     T v;
     if (!C)  // C = I: q = w + D p
       v = w[i];
@@ -105,9 +112,13 @@ __device__ __forceinline__ void q_body(const T* __restrict__ C, int ldc, int m2,
       v = stage ? row_dot<T, U, false>(C + (size_t)i * ldc, ws, lenR, lane)
                 : row_dot_gx<T, U, false>(C + (size_t)i * ldc, w, lenR, n, lane);
     if (sk) return;
+    const T pi = pn, di = dn;
+    if (i + step < m2) {
+      pn = p[i + step];
+      dn = dvec[i + step];
+    }
     if (lane == 0) {
-      T pi = p[i];
-      T qi = v + dvec[i] * pi;
+      T qi = v + di * pi;
       q[i] = qi;
       pq += (double)pi * qi;
     }
@@ -412,15 +423,46 @@ struct FoldState {
   int iter, maxit;
 };
 
+// A thread's first kFoldPre partials of each kind, loaded at a kernel's entry
+// so that their latency overlaps the kernel's other loads.
+constexpr int kFoldPre = 2;
+struct FoldPre {
+  double rz[kFoldPre], rr[kFoldPre], wm[kFoldPre];
+};
+// Every load is issued unconditionally (indices clamped into the arrays, which
+// hold at least one entry) and masked afterwards: a load under a branch makes
+// the compiler wait for it at the branch's end, which would serialise them.
+__device__ __forceinline__ FoldPre fold_load(const FoldParts& fp) {
+  FoldPre f;
+  const int lz = max(fp.nrz - 1, 0), lw = max(fp.nrw - 1, 0);
+#pragma unroll
+  for (int k = 0; k < kFoldPre; ++k) {
+    const int b = threadIdx.x + k * blockDim.x;
+    const double vz = fp.rz[min(b, lz)], vr = fp.rr[min(b, lw)], vw = fp.wm[min(b, lw)];
+    f.rz[k] = b < fp.nrz ? vz : 0.0;
+    f.rr[k] = b < fp.nrw ? vr : 0.0;
+    f.wm[k] = b < fp.nrw ? vw : 0.0;
+  }
+  return f;
+}
+
 // Stop test of the update the last q sweep made, from its partials in a fixed
-// order, so every workgroup that calls it gets the same rz, rr, wm and code.
-__device__ __forceinline__ int fold_reduce_test(const FoldParts& fp, const FoldState& s, double& rz, double& rr,
-                                                double& wm, double (*sh3)[16]) {
+// order (the preloaded ones, then the rest), so every workgroup that calls it
+// gets the same rz, rr, wm and code.
+__device__ __forceinline__ int fold_reduce_test(const FoldParts& fp, const FoldPre& f, const FoldState& s,
+                                                double& rz, double& rr, double& wm, double (*sh3)[16]) {
   rz = 0;
   rr = 0;
   wm = 0;
-  for (int b = threadIdx.x; b < fp.nrz; b += blockDim.x) rz += fp.rz[b];
-  for (int b = threadIdx.x; b < fp.nrw; b += blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < kFoldPre; ++k) {
+    rz += f.rz[k];
+    rr += f.rr[k];
+    wm = fmax(wm, f.wm[k]);
+  }
+  const int b0 = threadIdx.x + kFoldPre * blockDim.x;
+  for (int b = b0; b < fp.nrz; b += blockDim.x) rz += fp.rz[b];
+  for (int b = b0; b < fp.nrw; b += blockDim.x) {
     rr += fp.rr[b];
     wm = fmax(wm, fp.wm[b]);
   }
@@ -433,25 +475,39 @@ __device__ __forceinline__ int fold_reduce_test(const FoldParts& fp, const FoldS
 // u = C^T p_new with p_new = z + beta p_old, as C^T z + beta C^T p_old: both dots
 // of a row of the stored C^T from one load of the row.  beta = rho' / rho comes
 // from the partials of rho' = r^T z, reduced by every workgroup after its first
-// row; workgroup 0 records the update in the solve's scalars.
-template <typename T, int U>
+// row; workgroup 0 records the update in the solve's scalars.  With recur set,
+// C^T p_old is the u of the previous step (C^T applied to the same p_old, which
+// the q sweep stored), so each row takes one dot, C^T z, and reads one vector:
+// u = C^T z + beta u_old.  The first step of a solve (p = z) takes u = C^T z.
+template <typename T, int U, bool RECUR>
 __global__ void __launch_bounds__(256) fold_ct_kernel(const T* __restrict__ CT, int ldct, int n, int m2,
                                                       const T* __restrict__ z, const T* __restrict__ p,
                                                       T* __restrict__ u, PcgScalars* __restrict__ sc, FoldParts fp,
                                                       int nt) {
   __shared__ double sh3[3][16];
+  // a stopped solve returns before any other load (the steps launched past a
+  // stop cost one launch each); then the partials of the last update's test are
+  // issued together with this wavefront's first row
   if (sc->done) return;
   const int fresh = sc->fresh;
   const FoldState s{sc->rho, sc->tol2, sc->wtol, sc->iter, sc->maxit};
+  const FoldPre pre = fold_load(fp);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
   const int lenR = round_chunk<T>(m2, ldct);
   const int stride = gridDim.x * waves;
+  // (the two forms are separate instantiations: the two-dot form needs twice
+  // the vector registers, which would cost the one-dot form its occupancy)
   auto dots = [&](int i, T& d1, T& d2) {
     const T* row = CT + (size_t)i * ldct;
-    if (nt)
+    if constexpr (RECUR) {
+      const T uo = u[i];  // unconditional (see fold_load)
+      d2 = fresh ? T(0) : uo;
+      d1 = nt ? row_dot_gx<T, U, true>(row, z, lenR, m2, lane) : row_dot_gx<T, U, false>(row, z, lenR, m2, lane);
+    } else if (nt) {
       row_dot2_gx<T, U, true>(row, z, p, lenR, m2, lane, d1, d2);
-    else
+    } else {
       row_dot2_gx<T, U, false>(row, z, p, lenR, m2, lane, d1, d2);
+    }
   };
   int i = blockIdx.x * waves + wave;
   T d1 = 0, d2 = 0;
@@ -459,7 +515,7 @@ __global__ void __launch_bounds__(256) fold_ct_kernel(const T* __restrict__ CT, 
   double beta = 0.0;  // the first step of a solve: p = z from the initialisation
   if (!fresh) {
     double rz, rr, wm;
-    const int dn = fold_reduce_test(fp, s, rz, rr, wm, sh3);
+    const int dn = fold_reduce_test(fp, pre, s, rz, rr, wm, sh3);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->rr = rr;
       sc->wmax = wm;
@@ -477,10 +533,10 @@ __global__ void __launch_bounds__(256) fold_ct_kernel(const T* __restrict__ CT, 
     sc->rho_next = s.rho;
   }
   const T bt = (T)beta;
-  if (i < n && lane == 0) u[i] = d1 + bt * d2;
+  if (i < n && lane == 0) u[i] = fresh ? d1 : d1 + bt * d2;
   for (i += stride; i < n; i += stride) {
     dots(i, d1, d2);
-    if (lane == 0) u[i] = d1 + bt * d2;
+    if (lane == 0) u[i] = fresh ? d1 : d1 + bt * d2;
   }
 }
 
@@ -496,7 +552,7 @@ __global__ void __launch_bounds__(256) fold_q_kernel(const T* __restrict__ C, in
                                                      int prec, PcgScalars* __restrict__ sc, FoldParts fp, int nt) {
   __shared__ double sh[16];
   __shared__ double sh3[3][16];
-  if (sc->done) return;
+  if (sc->done) return;  // before any other load (see fold_ct_kernel)
   const double rho = sc->rho_next;
   const T bt = (T)sc->beta;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave, waves = blockDim.x / kWave;
@@ -507,10 +563,16 @@ __global__ void __launch_bounds__(256) fold_q_kernel(const T* __restrict__ C, in
     return nt ? row_dot_gx<T, U>(row, w, lenR, n, lane) : row_dot_gx<T, U, false>(row, w, lenR, n, lane);
   };
   int i = blockIdx.x * waves + wave;
+  // the p^T q partials and the vector entries of this wavefront's first row are
+  // loaded before its dot, so their latency hides behind the row's
+  // (unconditional loads at clamped indices, masked afterwards: see fold_load)
+  const double a0 = fp.al[min((int)threadIdx.x, max(fp.nal - 1, 0))];
+  const int ic = min(i, m2 - 1);
+  const T e_d = dvec[ic], e_z = z[ic], e_p = p[ic], e_x = x[ic], e_r = r[ic], e_w = wts ? wts[ic] : T(0);
   T v = 0;
   if (i < m2) v = dot(i);
-  double pq = 0;
-  for (int b = threadIdx.x; b < fp.nal; b += blockDim.x) pq += fp.al[b];
+  double pq = (int)threadIdx.x < fp.nal ? a0 : 0.0;
+  for (int b = threadIdx.x + blockDim.x; b < fp.nal; b += blockDim.x) pq += fp.al[b];
   pq = block_sum<double>(pq, sh);
   if (!(pq > 0.0) || !isfinite(pq)) {  // the same decision in every workgroup
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -521,27 +583,26 @@ __global__ void __launch_bounds__(256) fold_q_kernel(const T* __restrict__ C, in
   }
   const T a = (T)(rho / pq);
   double rz = 0, rr = 0, wm = 0;
-  auto upd = [&](int ii, T vv) {
-    const T di = dvec[ii];
-    const T pi = z[ii] + bt * p[ii];
+  auto upd = [&](int ii, T vv, T di, T zi0, T pi0, T xi, T ri0, T wi) {
+    const T pi = zi0 + bt * pi0;
     const T qi = vv + di * pi;
     p[ii] = pi;
     q[ii] = qi;
-    x[ii] += a * pi;
-    const T ri = r[ii] - a * qi;
+    x[ii] = xi + a * pi;
+    const T ri = ri0 - a * qi;
     r[ii] = ri;
     rr += (double)ri * ri;
-    if (wts) wm = fmax(wm, fabs((double)wts[ii] * ri));
+    if (wts) wm = fmax(wm, fabs((double)wi * ri));
     if (prec != kPrecH) {
       const T zi = (prec == kPrecL) ? ri / di : ri;
       z[ii] = zi;
       rz += (double)ri * zi;
     }
   };
-  if (i < m2 && lane == 0) upd(i, v);
+  if (i < m2 && lane == 0) upd(i, v, e_d, e_z, e_p, e_x, e_r, e_w);
   for (i += stride; i < m2; i += stride) {
     v = dot(i);
-    if (lane == 0) upd(i, v);
+    if (lane == 0) upd(i, v, dvec[i], z[i], p[i], x[i], r[i], wts ? wts[i] : T(0));
   }
   block_sum2_max1(rz, rr, wm, sh3);
   if (threadIdx.x == 0) {
@@ -564,7 +625,7 @@ __global__ void __launch_bounds__(256) fold_test_kernel(PcgScalars* __restrict__
   if (sc->done || sc->fresh) return;
   const FoldState s{sc->rho, sc->tol2, sc->wtol, sc->iter, sc->maxit};
   double rz, rr, wm;
-  const int dn = fold_reduce_test(fp, s, rz, rr, wm, sh3);
+  const int dn = fold_reduce_test(fp, fold_load(fp), s, rz, rr, wm, sh3);
   if (dn && threadIdx.x == 0) {
     sc->rr = rr;
     sc->wmax = wm;
@@ -579,10 +640,13 @@ hipError_t fold_ct(hipStream_t st, const T* CT, int ldct, int n, int m2, const T
   if (n <= 0) return hipSuccess;
   const dim3 grid(gemv_rows_grid<T>(n));
   const int nt = tune().ld_nt & 1;
-  if (tune().rows_unroll >= 8)
-    QPG_LAUNCH((fold_ct_kernel<T, 8>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
-  else
-    QPG_LAUNCH((fold_ct_kernel<T, 4>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
+  const bool recur = tune().cg_fold & 4;
+  if (recur && tune().rows_unroll >= 8)
+    QPG_LAUNCH((fold_ct_kernel<T, 8, true>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
+  else if (recur)
+    QPG_LAUNCH((fold_ct_kernel<T, 4, true>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
+  else  // two dots per row: half the matrix loads in flight, the same registers
+    QPG_LAUNCH((fold_ct_kernel<T, 4, false>), grid, dim3(256), 0u, st, ev, CT, ldct, n, m2, z, p, u, sc, fp, nt);
   return hipGetLastError();
 }
 

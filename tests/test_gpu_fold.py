@@ -5,7 +5,9 @@ from u^T w + p^T D p (u = C^T p, w the K0 product), and for P_H the sum of the
 X_P apply's partials also forms r^T z.  It is the same preconditioned CG with
 those inner products summed differently, so both must reach the oracle's
 solution of K_F dnu = r at the solve tolerance, with step counts that differ by
-rounding only.  Bit 0 of the cg_fold key folds P_L solves, bit 1 P_H solves.
+rounding only.  Bit 0 of the cg_fold key folds P_L solves, bit 1 P_H solves; bit 2 takes
+C^T p_old in the folded C^T sweep from the previous step's u = C^T p, a recurrence
+whose rounding must not cost accuracy or steps either.
 """
 import numpy as np
 import pytest
@@ -43,7 +45,7 @@ def test_folded_pcg_matches_separate_update(gpu, table, prec, n, m1, m2):
     rhs = np.random.default_rng(n).standard_normal(m2)
     ref = sla.cho_solve(sla.cho_factor(reduced.kf_explicit(qp, dvec)), rhs)
     out = {}
-    for fold in (0, 3):
+    for fold in (0, 3, 7):
         qpgpu.tune_set(f"{base}\ndefault cg_fold={fold}")
         s = qpgpu.Solver(*qp.arrays(), prec=prec)
         s.factor()
@@ -52,14 +54,17 @@ def test_folded_pcg_matches_separate_update(gpu, table, prec, n, m1, m2):
         assert relerr(dnu, ref) <= 1e-8, fold
         assert info.rel_res <= 1e-11, fold
         out[fold] = info.iters
-    assert abs(out[3] - out[0]) <= max(2, out[0] // 10), out
+    for fold in (3, 7):
+        assert abs(out[fold] - out[0]) <= max(2, out[0] // 10), out
 
 
+@pytest.mark.parametrize("fold", [2, 6])
 @pytest.mark.parametrize("precision", [qpgpu.QP_FP64, qpgpu.QP_MIXED])
-def test_folded_ph_ipm_matches_oracle(gpu, table, precision):
-    """A whole P_H IPM with the folded step (the default for P_H) in both precisions."""
+def test_folded_ph_ipm_matches_oracle(gpu, table, precision, fold):
+    """A whole P_H IPM with the folded step in both precisions, with C^T p_old from
+    a second dot per row (cg_fold=2) and from the previous step's u (6)."""
     base = table.splitlines()[0]
-    qpgpu.tune_set(f"{base}\ndefault cg_fold=2")
+    qpgpu.tune_set(f"{base}\ndefault cg_fold={fold}")
     qp = synth.gaussian_qp(6301, 400, 60, 400)
     s = qpgpu.Solver(*qp.arrays(), prec=qpgpu.QP_PREC_FEW_EQ, precision=precision)
     s.factor()

@@ -124,6 +124,37 @@ def test_pipelined_one_pass_is_bitwise_the_two_row_sweep(gpu, table, sym_wg, n, 
         assert np.array_equal(out[key], out[0, 1]), key
 
 
+TEAM_SIZES = [(1025, 512, 100), (2049, 2049, 31), (1500, 700, 64), (4096, 3072, 257)]
+
+
+@pytest.mark.parametrize("sym_wg", [2, 4])
+@pytest.mark.parametrize("n,m1,m2", TEAM_SIZES)
+def test_two_team_one_pass_matches_one_team(gpu, table, sym_wg, n, m1, m2):
+    """Workgroups of two teams (each with its own rows and partial, added in team
+    order before the one partial is written) give the K_F product of the
+    one-team sweep up to the order of the additions, and the oracle's.  With
+    sym_units=1 every size here has enough units for two teams per CU."""
+    base = table.splitlines()[0]
+    qp = synth.gaussian_qp(5700 + n + m1, n, m1, m2)
+    s = qpgpu.Solver(*qp.arrays())
+    assert s.k0_one_pass()
+    s.factor()
+    dvec = synth.log_uniform(17, m2, 1e-3, 1e3)
+    p = np.random.default_rng(n + 11).standard_normal(m2)
+    out = {}
+    for teams in (1, 2):
+        for rows in (2, 4):
+            qpgpu.tune_set(f"{base}\ndefault sym_pipe=0,sym_units=1,sym_wg={sym_wg},sym_rows={rows},"
+                           f"sym_teams={teams}")
+            out[teams, rows] = s.kf_apply(dvec, p)
+    s.close()
+    ref = reduced.kf_apply(qp, dvec, p)
+    tol = k0_tol(qp)
+    for key, v in out.items():
+        assert relerr(v, ref) <= tol, key
+        assert relerr(v, out[1, 4]) <= tol, key
+
+
 def test_pipelined_one_pass_in_batches(gpu, table):
     """Batched one-pass sweep (every QP of the batch in one launch) with and
     without pipelining: bitwise the same IPM results."""
