@@ -105,7 +105,8 @@ ONE_PASS_SIZES = [(1, 1, 1), (3, 2, 5), (129, 65, 40), (513, 300, 64), (1025, 51
 @pytest.mark.parametrize("n,m1,m2", ONE_PASS_SIZES)
 def test_pipelined_one_pass_is_bitwise_the_two_row_sweep(gpu, table, sym_wg, n, m1, m2):
     """The pipelined one-pass sweep reads the same rows in the same order with the
-    same arithmetic as the two-rows-per-round sweep: K_F p is bitwise equal."""
+    same arithmetic as the two-rows-per-round sweep of one-team workgroups: K_F p
+    is bitwise equal."""
     base = table.splitlines()[0]
     qp = synth.gaussian_qp(5500 + n + m1, n, m1, m2)
     s = qpgpu.Solver(*qp.arrays())
@@ -116,7 +117,7 @@ def test_pipelined_one_pass_is_bitwise_the_two_row_sweep(gpu, table, sym_wg, n, 
     out = {}
     for pipe in (0, 1):
         for nt in (1, 3):
-            qpgpu.tune_set(f"{base}\ndefault sym_rows=2,sym_pipe={pipe},sym_wg={sym_wg},ld_nt={nt}")
+            qpgpu.tune_set(f"{base}\ndefault sym_rows=2,sym_pipe={pipe},sym_wg={sym_wg},ld_nt={nt},sym_teams=1")
             out[pipe, nt] = s.kf_apply(dvec, p)
     s.close()
     assert relerr(out[1, 1], reduced.kf_apply(qp, dvec, p)) <= k0_tol(qp)
