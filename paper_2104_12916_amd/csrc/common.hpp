@@ -62,6 +62,8 @@ struct Tune {
                         // (0: column sweeps with per-chunk partials, no extra memory)
   int k0_sym = 1;       // one pass over M for M^T Sigma M u (n small enough for register rows)
   int sym_wg = 2;       // one-pass sweep: workgroups per CU (each writes one partial of w)
+  int bsym_wave = 1;    // batched one-pass sweep: 1 lets each wavefront take whole rows when every
+                        // QP of the launch has rows of at most 4 x 64 lanes x 16 bytes
   int bsym_units = 16;  // batched one-pass sweep: row units per workgroup (buffer layout: the
                         // pooled partials are sized with it when a QP is admitted)
   int sym_units = 8;    // one-pass sweep: at least this many row units (about n entries

@@ -676,6 +676,107 @@ __device__ __forceinline__ void k0_sym_body_pipe(const T* __restrict__ M, int ld
   }
 }
 
+// Batched one-pass sweep of a QP with short rows (at most 4 x 64 lanes x 16 bytes:
+// n <= 512 in float64, 1024 in float32).  There a row spread over the 256 threads
+// of a workgroup leaves most lanes idle and every round waits at a barrier for a
+// few hundred bytes.  Here each wavefront takes whole rows: lane l
+// owns columns c*64*VE + l*VE .. + VE-1 (c < KW) of every row, the row's dot is a
+// wavefront sum (no barrier), and a wavefront keeps R rows' loads in flight; the
+// workgroup's rows (units [g U / G, (g+1) U / G) as above) are dealt to its four
+// wavefronts R at a time in turn.  At the end the four wavefronts' register partials
+// are added in wavefront order through LDS into the workgroup's one partial.  A
+// stopped QP's workgroups return before any matrix load.  KW is the QP's own
+// width, so its arithmetic does not depend on the other QPs of the launch.
+template <typename T, int KW, int R, bool NT>
+__device__ __forceinline__ void k0_sym_body_wave(const T* __restrict__ M, int ldm, int N, int n,
+                                                 const T* __restrict__ u, T* __restrict__ part, int ldp, int G,
+                                                 int g, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using V = typename Vec16<T>::type;
+  constexpr int VE = Vec16<T>::n;
+  constexpr int CW = kWave * VE;
+  constexpr int NW = 4;  // wavefronts of the 256-thread workgroup
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave), lane = (int)threadIdx.x % kWave;
+  const int P = n / 2, U = (n + 1) / 2 + (N - n);
+  const int u0 = (int)((long long)g * U / G), u1 = (int)((long long)(g + 1) * U / G);
+  const int np = max(0, min(u1, P) - u0);
+  const int us = max(u0, P);
+  const int nrows = 2 * np + max(0, u1 - us);
+  T xu[KW][VE], acc[KW][VE];
+#pragma unroll
+  for (int c = 0; c < KW; ++c) {
+    const int col = c * CW + lane * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      xu[c][e] = (col + e < n) ? u[col + e] : T(0);
+      acc[c][e] = T(0);
+    }
+  }
+  for (int q0 = wave * R; q0 < nrows; q0 += NW * R) {
+    V a[R][KW];
+    int rowi[R], lens[R];
+    // every lane issues every load (past a row's end it loads column 0 of a valid
+    // row and masks the value below), so the R rows' loads are one group
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = q0 + r;
+      int i = -1, len = 0;
+      if (q < nrows) {
+        i = sym_row(q, u0, np, us, n);
+        len = min(i + 1, n);
+      }
+      rowi[r] = i;
+      lens[r] = len;
+      const T* arow = M + (size_t)(i < 0 ? 0 : i) * ldm;
+#pragma unroll
+      for (int c = 0; c < KW; ++c) {
+        const int col = c * CW + lane * VE;
+        a[r][c] = ld16<V, NT>(reinterpret_cast<const V*>(arow + (col < len ? col : 0)));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T d = T(0);
+#pragma unroll
+      for (int c = 0; c < KW; ++c) {
+        const bool in = c * CW + lane * VE < lens[r];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) a[r][c][e] = in ? a[r][c][e] : T(0);
+        d += dot16<V, T>(a[r][c], xu[c]);
+      }
+      T v = wave_sum<T>(d);
+      if (rowi[r] >= n) v = -v;
+#pragma unroll
+      for (int c = 0; c < KW; ++c)
+#pragma unroll
+        for (int e = 0; e < VE; ++e) acc[c][e] += a[r][c][e] * v;
+    }
+  }
+  __shared__ T red[NW - 1][KW][VE][kWave];
+  if (wave > 0) {
+#pragma unroll
+    for (int c = 0; c < KW; ++c)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) red[wave - 1][c][e][lane] = acc[c][e];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w2 = 0; w2 < NW - 1; ++w2)
+#pragma unroll
+    for (int c = 0; c < KW; ++c)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[c][e] += red[w2][c][e][lane];
+  T* pg = part + (size_t)g * ldp;
+#pragma unroll
+  for (int c = 0; c < KW; ++c) {
+    const int col = c * CW + lane * VE;
+#pragma unroll
+    for (int e = 0; e < VE; ++e)
+      if (col + e < n) pg[col + e] = acc[c][e];
+  }
+}
+
 // w_j = sum over g of part[g][j]: 16 columns per workgroup, 16 lanes per column
 // take g = t, t + 16, ... with four loads in flight, then a fixed butterfly.
 template <typename T, int BT, int K, int R, bool NT, bool PIPE = false, int TM = 1>
@@ -688,11 +789,20 @@ __global__ void __launch_bounds__(BT * TM) k0_sym_kernel(const T* __restrict__ M
     k0_sym_body<T, BT, K, R, NT, TM>(M, ldm, N, n, u, part, ldp, G, blockIdx.x, skip);
 }
 
+// wave_rows: QPs with short rows take the wavefront-row form (k0_sym_body_wave)
 template <typename T, int BT, int K, int R, bool NT, bool PIPE = false>
 __global__ void __launch_bounds__(BT) bk0_sym_kernel(const SymDesc<T>* __restrict__ descs,
-                                                     const int* __restrict__ prefix, int ndesc) {
+                                                     const int* __restrict__ prefix, int ndesc, int wave_rows) {
   const DescBlock db = desc_of_block(prefix, ndesc, blockIdx.x);
   const SymDesc<T> d = descs[db.j];
+  if (wave_rows) {
+    static_assert(BT == 4 * kWave, "the wavefront-row form runs four wavefronts per workgroup");
+    constexpr int CW = kWave * Vec16<T>::n;
+    const int kc = (d.n + CW - 1) / CW;
+    if (kc <= 1) return k0_sym_body_wave<T, 1, 2, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
+    if (kc <= 2) return k0_sym_body_wave<T, 2, 2, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
+    if (kc <= 4) return k0_sym_body_wave<T, 4, 2, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
+  }
   if constexpr (PIPE)
     k0_sym_body_pipe<T, BT, K, R, NT>(d.M, d.ldm, d.N, d.n, d.u, d.part, d.ldp, d.G, db.local, d.skip);
   else
@@ -850,7 +960,7 @@ __global__ void __launch_bounds__(256) bk0_sym_reduce_kernel(const SymDesc<T>* _
   k0_sym_reduce_body<T>(d.part, d.ldp, d.G, d.n, d.w, d.skip, db.local);
 }
 
-constexpr int kSymBT = 256;  // threads per workgroup of the one-pass sweep (512 measured slower)
+constexpr int kSymBT = 256;  // threads of one team of the one-pass sweep (512 spanning the columns measured slower)
 int k0_sym_ldp(int n) { return (n + 63) / 64 * 64; }
 
 template <typename T>
@@ -978,11 +1088,12 @@ template <typename T, int R, bool NT, bool PIPE = false>
 static void launch_bsym_r(int K, dim3 grid, hipStream_t st, const EventPair* ev, const SymDesc<T>* d,
                           const int* prefix, int ndesc) {
   const dim3 blk(kSymBT);
+  const int wv = tune().bsym_wave;
   switch (K) {
-    case 1: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 1, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    case 2: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 2, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    case 4: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 4, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc); break;
-    default: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 8, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc);
+    case 1: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 1, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc, wv); break;
+    case 2: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 2, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc, wv); break;
+    case 4: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 4, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc, wv); break;
+    default: QPG_LAUNCH((bk0_sym_kernel<T, kSymBT, 8, R, NT, PIPE>), grid, blk, 0u, st, ev, d, prefix, ndesc, wv);
   }
 }
 

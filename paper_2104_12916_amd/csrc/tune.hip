@@ -57,6 +57,7 @@ bool parse_keys(const std::string& spec, Tune& t, bool alloc) {
     else if (k == "sym_wg") ok = v >= 1 && v <= kMaxSymWg, t.sym_wg = v;
     else if (k == "sym_units") ok = v >= 1 && v <= 64, t.sym_units = v;
     else if (k == "bsym_units") ok = v >= 1 && v <= 256, t.bsym_units = v;
+    else if (k == "bsym_wave") ok = v == 0 || v == 1, t.bsym_wave = v;
     else if (k == "sym_teams") ok = v == 1 || v == 2, t.sym_teams = v;
     else if (k == "sym_rows") ok = v == 2 || v == 4, t.sym_rows = v;
     else if (k == "sym_pipe") ok = v == 0 || v == 1, t.sym_pipe = v;
@@ -151,11 +152,11 @@ std::string format_tune(const Tune& t, bool alloc) {
   char b[512];
   snprintf(b, sizeof(b),
            "rows_bpc=%d,rows_unroll=%d,cols_bpc=%d,cols_unroll=%d,qe_stage=%d,rows_stage=%d,brows_stage=%d,"
-           "brows_unroll=%d,sym_wg=%d,sym_units=%d,bsym_units=%d,sym_teams=%d,sym_rows=%d,sym_pipe=%d,ld_nt=%d,"
-           "upd_threads=%d,mv_rt=%d,cg_fold=%d",
+           "brows_unroll=%d,sym_wg=%d,sym_units=%d,bsym_units=%d,bsym_wave=%d,sym_teams=%d,sym_rows=%d,sym_pipe=%d,"
+           "ld_nt=%d,upd_threads=%d,mv_rt=%d,cg_fold=%d",
            t.rows_bpc, t.rows_unroll, t.cols_bpc, t.cols_unroll, t.qe_stage, t.rows_stage, t.brows_stage,
-           t.brows_unroll, t.sym_wg, t.sym_units, t.bsym_units, t.sym_teams, t.sym_rows, t.sym_pipe, t.ld_nt,
-           t.upd_threads, t.mv_rt, t.cg_fold);
+           t.brows_unroll, t.sym_wg, t.sym_units, t.bsym_units, t.bsym_wave, t.sym_teams, t.sym_rows, t.sym_pipe,
+           t.ld_nt, t.upd_threads, t.mv_rt, t.cg_fold);
   std::string s(b);
   if (alloc) {
     snprintf(b, sizeof(b), ",ld_pad=%d,op_t=%d,k0_sym=%d", t.ld_pad, t.op_t, t.k0_sym);
