@@ -49,6 +49,7 @@ BATCH_SPACE = [
     ("brows_unroll", [4, 8]),
     ("brows_stage", [0, 1]),
     ("bsym_units", [8, 16, 32]),
+    ("bsym_wave", [0, 1]),
     ("sym_pipe", [0, 1]),
     ("sym_rows", [2, 4]),
     ("ld_nt", [0, 1, 2, 3]),
