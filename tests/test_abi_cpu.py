@@ -192,8 +192,13 @@ def test_tune_table_set_get_and_validation():
         assert t[0].startswith("default ") and "rows_bpc=2" in t[0]
         assert t[1].startswith("n<=256 ") and "sym_rows=2" in t[1] and "rows_bpc=2" in t[1]  # buckets sorted
         assert t[2].startswith("n<=512 ") and "sym_wg=1" in t[2] and "upd_threads=256" in t[2]
+        # the keys of the two-team one-pass sweep, the wavefront-row batched sweep and the fold bits
+        qpgpu.tune_set("default sym_teams=1,bsym_wave=0,cg_fold=7\nn<=512 sym_teams=2,cg_fold=0")
+        t = qpgpu.tune_get().splitlines()
+        assert all(k in t[0] for k in ("sym_teams=1", "bsym_wave=0", "cg_fold=7"))
+        assert "sym_teams=2" in t[1] and "cg_fold=0" in t[1] and "bsym_wave=0" in t[1]
         for bad in ("default ld_pad=0", "n<=100 ld_pad=128", "default rows_bpc=99", "default nosuchkey=1",
-                    "n<=0 rows_bpc=2"):
+                    "n<=0 rows_bpc=2", "default sym_teams=3", "default bsym_wave=2", "default cg_fold=8"):
             with pytest.raises(qpgpu.QpError):
                 qpgpu.tune_set(bad)
     finally:
