@@ -36,6 +36,10 @@ SWEEPS = {
     "M1": ("qpg::k0_sym_kernel<double,",),          # one pass over M: M^T Sigma M u
     "M1red": ("qpg::k0_sym_reduce_kernel<double>",),  # sum of its per-workgroup partials
     "q": ("qpg::pcg_q_kernel<double,",),
+    # the folded CG step's kernels (same matrices, with the vector update folded in)
+    "C^T fold": ("qpg::fold_ct_kernel<double,",),
+    "M1red fold": ("qpg::k0_sym_reduce_fold_kernel<double>",),
+    "q fold": ("qpg::fold_q_kernel<double,",),
 }
 
 
@@ -57,7 +61,7 @@ def algorithmic_bytes(n, m1, m2, elem=8):
     is the lower trapezoid of n(n+1)/2 + m1 n entries."""
     mm = n * (n + 1) // 2 + m1 * n
     return {"C^T": m2 * n * elem, "M": mm * elem, "M^T": mm * elem, "M1": mm * elem, "M1red": 0,
-            "q": m2 * n * elem}
+            "q": m2 * n * elem, "C^T fold": m2 * n * elem, "M1red fold": 0, "q fold": m2 * n * elem}
 
 
 def _short(name):
